@@ -1,0 +1,143 @@
+"""Algorithm 1: one implicit-Euler time step by Jacobi-preconditioned Dai-Kou
+nonlinear conjugate gradient (Sec. 4).
+
+Per iteration k (Algorithm 1, Sec. 4.1-4.4):
+  constraint set at x; gradient g_{k+1} and P_{k+1} = diag(H)^{-1};
+  beta = 0 on the first iteration, else the preconditioned Dai-Kou formula
+      beta = g^T P y / (y^T p) - (y^T P y / y^T p) (p^T g / y^T p),
+      y = g_{k+1} - g_k, p = the previous direction;
+  p_{k+1} = -P g_{k+1} + beta p_k;
+  alpha = min(dhat / (2 ||p||), -g^T p / p^T H p)     (equations upper, alpha)
+  x <- x + alpha p;  dE = -alpha g^T p - alpha^2/2 p^T H p;  dE_0 from the
+  first iteration; stop when dE < eps dE_0.
+
+Readings where the paper is silent or garbled:
+  * x_0 = x^t (not xt); prescribed vertices are set to their targets first.
+  * "If i = 0" in the listing means k = 0; beta uses only the previous
+    direction p_k.
+  * ||p|| in the step bound is the largest per-vertex Euclidean length
+    max_v ||p_v||_2, which keeps every vertex's displacement below dhat/2 as
+    the text requires ("component" reads it as the largest |p_i| instead).
+    The bound is infinite when the scene has no collision primitives.
+  * Guards: y^T p = 0 or a non-finite beta gives beta = 0; g^T p >= 0 restarts
+    with p = -P g; p^T H p <= 0 gives an unbounded Newton step; a step that is
+    still unbounded or not finite stops the iteration.
+  * Termination "delta_e": the rule above.  "grad_rel": stop at the top of an
+    iteration when ||g||_2 <= eps ||g_0||_2 (used for tight convergence).
+  * v^{t+1} = (x^{t+1} - x^t) / h.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class StepStats:
+    iters: int = 0
+    reason: str = ""
+    dE0: float = 0.0
+    last_dE: float = 0.0
+    g0: float = 0.0
+    gk: float = 0.0
+    alpha_upper_hits: int = 0
+    n_active: int = 0
+    n_plane: int = 0
+    energy_increase: int = 0
+    history: list = dataclasses.field(default_factory=list)
+
+
+def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
+         alpha_norm="vertex", fixed_targets=None, track_energy=False,
+         record=False):
+    """Returns (x_new, v_new, stats)."""
+    x_t = np.asarray(x_t, dtype=np.float64)
+    xt = prob.predictor(x_t, v_t, h)
+    x = x_t.copy()
+    if len(prob.fixed):
+        x[prob.fixed] = x_t[prob.fixed] if fixed_targets is None else fixed_targets
+    st = StepStats()
+    g_prev = p_prev = None
+    dE0 = None
+    g0n = None
+    E_prev = prob.energy(x, xt, h) if track_energy else None
+    k = 0
+    while k < iter_max:
+        aset = prob.active_set(x)
+        g = prob.gradient(x, xt, h, aset)
+        D = prob.diag(x, h, aset)
+        gn = float(np.sqrt(np.sum(g * g)))
+        if g0n is None:
+            g0n = gn
+            st.g0 = gn
+        st.gk = gn
+        if term == "grad_rel" and gn <= eps * g0n:
+            st.reason = "grad_rel"
+            break
+        P = 1.0 / D
+        if k == 0:
+            beta = 0.0
+        else:
+            y = g - g_prev
+            yp = float(np.sum(y * p_prev))
+            if yp == 0.0:
+                beta = 0.0
+            else:
+                gPy = float(np.sum(g * P * y))
+                yPy = float(np.sum(y * P * y))
+                pg = float(np.sum(p_prev * g))
+                beta = gPy / yp - (yPy / yp) * (pg / yp)
+                if not np.isfinite(beta):
+                    beta = 0.0
+        p = -P * g + (beta * p_prev if k > 0 else 0.0)
+        gp = float(np.sum(g * p))
+        if gp >= 0.0:
+            p = -P * g
+            gp = float(np.sum(g * p))
+        p[~prob.free] = 0.0
+        if gp == 0.0:
+            st.reason = "zero_gradient"
+            break
+        pHp = prob.pHp(x, p, h, aset)
+        a_bar = -gp / pHp if pHp > 0 else np.inf
+        if prob.has_collision_primitives:
+            pmax = float(np.max(np.linalg.norm(p, axis=1))) if alpha_norm == "vertex" \
+                else float(np.max(np.abs(p)))
+            a_up = prob.dhat / (2.0 * pmax) if pmax > 0 else np.inf
+        else:
+            a_up = np.inf
+        alpha = min(a_up, a_bar)
+        if not np.isfinite(alpha):
+            st.reason = "unbounded"
+            break
+        if a_up < a_bar:
+            st.alpha_upper_hits += 1
+        x = x + alpha * p
+        dE = -alpha * gp - 0.5 * alpha * alpha * pHp
+        if record:
+            st.history.append(dict(k=k, beta=beta, alpha=alpha, a_bar=a_bar, a_up=a_up,
+                                   gp=gp, pHp=pHp, dE=dE, gn=gn,
+                                   n_active=0 if aset is None else len(aset.d) + len(aset.pd)))
+        if aset is not None:
+            st.n_active = len(aset.d)
+            st.n_plane = len(aset.pd)
+        if track_energy:
+            E_new = prob.energy(x, xt, h)
+            if E_new > E_prev:
+                st.energy_increase += 1
+            E_prev = E_new
+        k += 1
+        if dE0 is None:
+            dE0 = dE
+            st.dE0 = dE
+        st.last_dE = dE
+        g_prev, p_prev = g, p
+        if term == "delta_e" and dE < eps * dE0:
+            st.reason = "delta_e"
+            break
+    if not st.reason:
+        st.reason = "iter_max"
+    st.iters = k
+    v = (x - x_t) / h
+    return x, v, st

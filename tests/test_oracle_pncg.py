@@ -1,0 +1,156 @@
+"""Pins for the oracle's Algorithm 1 driver (Sec. 4)."""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import scenes
+from oracle import barrier, pncg, problem
+
+
+class _Quadratic:
+    """E(x) = 1/2 x^T A x - b^T x in the Problem interface (no contact)."""
+
+    def __init__(self, A, b):
+        self.A, self.bv = A, b
+        n = b.size // 3
+        self.fixed = np.zeros(0, np.int64)
+        self.free = np.ones(n, bool)
+        self.has_collision_primitives = False
+        self.dhat = 1.0
+
+    def predictor(self, x_t, v_t, h):
+        return x_t
+
+    def active_set(self, x):
+        return None
+
+    def gradient(self, x, xt, h, aset=None):
+        return (self.A @ x.ravel() - self.bv).reshape(-1, 3)
+
+    def diag(self, x, h, aset=None):
+        return np.diag(self.A).reshape(-1, 3).copy()
+
+    def pHp(self, x, p, h, aset=None):
+        return float(p.ravel() @ self.A @ p.ravel())
+
+    def energy(self, x, xt, h, aset=None):
+        return 0.5 * x.ravel() @ self.A @ x.ravel() - self.bv @ x.ravel()
+
+
+def _textbook_pcg(A, b, x0, iters):
+    """Jacobi-preconditioned linear conjugate gradient (Hestenes-Stiefel form)."""
+    Minv = 1.0 / np.diag(A)
+    x = x0.copy()
+    r = b - A @ x
+    z = Minv * r
+    p = z.copy()
+    xs = []
+    for _ in range(iters):
+        Ap = A @ p
+        a = (r @ z) / (p @ Ap)
+        x = x + a * p
+        xs.append(x.copy())
+        r_new = r - a * Ap
+        z_new = Minv * r_new
+        beta = (r_new @ z_new) / (r @ z)
+        p = z_new + beta * p
+        r, z = r_new, z_new
+    return xs
+
+
+def test_dk_with_newton_step_is_jacobi_pcg_on_quadratics():
+    # With an exact line search p_k^T g_{k+1} = 0, so the preconditioned
+    # Dai-Kou beta reduces to preconditioned Hestenes-Stiefel, i.e. linear PCG.
+    rng = np.random.default_rng(0)
+    n = 30
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.diag(rng.uniform(0.5, 5, n))
+    b = rng.standard_normal(n)
+    qp = _Quadratic(A, b)
+    ref = _textbook_pcg(A, b, np.zeros(n), 12)
+    for k in range(1, 13):
+        x, _, st = pncg.step(qp, np.zeros((n // 3, 3)), np.zeros((n // 3, 3)), 1.0,
+                             iter_max=k, eps=0.0, term="delta_e")
+        assert st.iters == k
+        np.testing.assert_allclose(x.ravel(), ref[k - 1], rtol=1e-9, atol=1e-12)
+    # and it converges to the solution of A x = b
+    x, _, st = pncg.step(qp, np.zeros((n // 3, 3)), np.zeros((n // 3, 3)), 1.0,
+                         iter_max=200, eps=1e-13, term="grad_rel")
+    np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b), rtol=1e-10)
+
+
+def test_free_fall_converges_to_predictor():
+    # no contact: the minimiser of the incremental potential is the rigidly
+    # translated predictor x^t + h v + h^2 g (zero elastic energy there)
+    sc = scenes.tiny_scene()
+    P = problem.Problem.from_scene(sc)
+    v0 = np.tile([0.1, -0.2, 0.05], (sc.nV, 1))
+    x, v, st = pncg.step(P, sc.X, v0, sc.h, iter_max=2000, eps=1e-12, term="grad_rel")
+    xt = sc.X + sc.h * v0 + sc.h ** 2 * np.array([0, 0, -9.8])
+    np.testing.assert_allclose(x, xt, atol=1e-12)
+    np.testing.assert_allclose(v, (xt - sc.X) / sc.h, atol=1e-9)
+
+
+def test_vertices_resting_on_floor_match_scalar_root():
+    # a single tet with a negligible modulus over z = 0: each vertex solves
+    # m (z - zt) + kappa b'(z) = 0 on its own (lumped mass, plane barrier)
+    X = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0], [0, 0, 0.01]]) + np.array([0, 0, 8e-4])
+    tets = np.array([[0, 1, 2, 3]])
+    tris, edges, _ = scenes.surface_of(tets)
+    dhat, kappa, h = 1e-3, 1e-2, 1.0 / 60
+    P = problem.Problem(X, tets, tris, edges, E=1e-9, nu=0.3, rho=1000.0,
+                        planes=[[0, 0, 1, 0.0]], dhat=dhat, kappa=kappa)
+    v0 = np.zeros((4, 3))
+    v0[:, 2] = -0.05
+    x, _, st = pncg.step(P, X, v0, h, iter_max=5000, eps=1e-11, term="grad_rel")
+    zt = X[:, 2] + h * v0[:, 2] - h * h * 9.8
+    for i in range(4):
+        m = P.mass[i]
+        if zt[i] >= dhat:
+            ref = zt[i]
+        else:
+            f = lambda z: m * (z - zt[i]) + kappa * barrier.db(np.array([z]), dhat)[0]
+            ref = brentq(f, 1e-12, dhat, xtol=1e-16, rtol=1e-15)
+        assert np.isclose(x[i, 2], ref, rtol=1e-7), (i, x[i, 2], ref)
+        assert x[i, 2] > 0
+
+
+def test_cube_drop_invariants():
+    sc = scenes.cube_scene()
+    P = problem.Problem.from_scene(sc)
+    x, v = sc.x0.copy(), sc.v0.copy()
+    for s in range(2):
+        x, v, st = pncg.step(P, x, v, sc.h, iter_max=sc.iter_max, eps=sc.eps, term=sc.term,
+                             track_energy=True)
+        assert st.energy_increase == 0
+        dmin, jmin = P.min_distance(x)
+        assert dmin > 0 and jmin > 0
+
+
+def test_energy_decrease_matches_prediction_on_contact_scene():
+    # dE = -alpha g^T p - alpha^2/2 p^T H p is the exact decrease of the
+    # quadratic model; for small steps it tracks the true energy decrease
+    sc = scenes.small_contact_scene()
+    P = problem.Problem.from_scene(sc)
+    v0 = np.zeros_like(sc.X)
+    v0[sc.object_id == 1, 2] = -0.05
+    x, v, st = pncg.step(P, sc.X, v0, sc.h, iter_max=60, eps=1e-6, record=True, track_energy=True)
+    assert st.iters > 5
+    dmin, jmin = P.min_distance(x)
+    assert dmin > 0 and jmin > 0
+    assert st.energy_increase == 0
+    hist = st.history
+    assert all(hh["alpha"] > 0 and hh["dE"] > 0 for hh in hist)
+
+
+def test_alpha_upper_caps_vertex_displacement():
+    sc = scenes.small_contact_scene()
+    P = problem.Problem.from_scene(sc)
+    v0 = np.zeros_like(sc.X)
+    v0[sc.object_id == 1, 2] = -0.5
+    x_prev = sc.X.copy()
+    xt = P.predictor(sc.X, v0, sc.h)
+    x, _, st = pncg.step(P, sc.X, v0, sc.h, iter_max=1, eps=0.0)
+    assert st.alpha_upper_hits == 1
+    disp = np.linalg.norm(x - x_prev, axis=1).max()
+    assert disp <= 0.5 * sc.dhat * (1 + 1e-12)
