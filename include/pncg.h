@@ -1,0 +1,205 @@
+/*
+ * pncg.h - C ABI of libpncg, a gfx950 (MI355X) implementation of the
+ * Jacobi-preconditioned Dai-Kou nonlinear conjugate gradient (PNCG) solver
+ * for the IPC incremental potential of Shen et al., "Preconditioned
+ * Nonlinear Conjugate Gradient Method for Real-time Interior-point
+ * Hyperelasticity" (SIGGRAPH 2024).
+ *
+ * Problem (Sec. 3, equations E and Hessian): one implicit-Euler step
+ *     x^{t+1} = argmin_x 1/2 (x - xt)^T M (x - xt) + h^2 Psi(x)
+ *                        + kappa sum_k b(d_k(x)),
+ *     xt = x^t + h v^t + h^2 g,      v^{t+1} = (x^{t+1} - x^t) / h,
+ * Psi Neo-Hookean on linear tets (Sec. 3.1), b the IPC log barrier
+ * (Sec. 3, equation barrier) over point-triangle and edge-edge pairs
+ * (Sec. 3.2, equations PT and EE) and over surface-vertex/plane pairs,
+ * minimised by Algorithm 1 (Sec. 4) with the one-pass step bound
+ * (Sec. 4.3, equations upper and alpha) in place of continuous collision
+ * detection.
+ *
+ * Conventions for every entry point:
+ *  - Return value: PNCG_OK (0) on success, PNCG_W_* (> 0) for a warning
+ *    with valid outputs, PNCG_E_* (< 0) for an error; after an error the
+ *    outputs are unspecified and pncg_last_error() describes it.
+ *  - Indices are 0-based int32.  Positions, velocities and per-vertex
+ *    vectors are float64, shape (n, 3), row-major (x0 y0 z0 x1 ...).
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or a torch CUDA
+ *    tensor's data_ptr) on the context's device; all other pointers are host
+ *    pointers.  Inputs are only read during the call and never retained;
+ *    host inputs are copied.  Outputs are written before the call returns
+ *    (device outputs: ordered on the context's stream, which the call
+ *    synchronises before returning).
+ *  - The context owns all of its device memory and frees it in
+ *    pncg_destroy.  A context must not be used from two threads at once.
+ *  - Call order: pncg_create, pncg_set_mesh, pncg_set_material, then
+ *    optionally pncg_set_contact / pncg_set_solver / pncg_set_dirichlet,
+ *    then steps and queries.  Out-of-order calls return PNCG_E_STATE.
+ */
+#ifndef PNCG_H
+#define PNCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pncg_ctx pncg_ctx;
+
+/* status codes */
+#define PNCG_OK              0
+#define PNCG_W_MAXITER       1   /* iteration cap reached before the stop test */
+#define PNCG_E_INVAL        -1   /* bad argument (size, index, NaN in a parameter) */
+#define PNCG_E_NOMEM        -2   /* device or host allocation failed */
+#define PNCG_E_HIP          -3   /* a HIP runtime call failed */
+#define PNCG_E_STATE        -4   /* call out of order (e.g. step before set_mesh) */
+#define PNCG_E_PENETRATION  -5   /* some contact pair or plane distance is <= 0 */
+#define PNCG_E_INVERTED     -6   /* a tet with det F <= 0 (rest or deformed) */
+#define PNCG_E_NONFINITE    -7   /* NaN or Inf in an input or in the iterate */
+#define PNCG_E_CAPACITY     -8   /* an output buffer is too small (size reported) */
+
+/* arithmetic of the per-element and per-vertex work */
+#define PNCG_FP64   0   /* everything in float64 */
+#define PNCG_MIXED  1   /* float32 element math and vectors; float64 positions,
+                           distances, barrier terms and every reduction */
+
+/* termination (Algorithm 1 and Sec. 4.4) */
+#define PNCG_TERM_DELTA_E   0   /* stop after an update with dE < eps * dE_0 */
+#define PNCG_TERM_GRAD_REL  1   /* stop at the top of an iteration when
+                                   ||g||_2 <= eps * ||g_0||_2 */
+
+/* solver flags */
+#define PNCG_BARRIER_FULL        1u  /* use the pair Hessian of equation eq9
+                                        verbatim instead of its PSD projection */
+#define PNCG_ALPHA_INF_COMPONENT 2u  /* step bound with the largest |p_i|
+                                        instead of the largest per-vertex |p_v|_2 */
+
+/* contact flags */
+#define PNCG_CONTACT_SELF          1u  /* point-triangle and edge-edge pairs
+                                          (all objects, including self) */
+#define PNCG_CONTACT_REST_EXCLUDE  2u  /* drop same-object pairs closer than
+                                          1.5 dhat in the rest shape (Sec. 5.1) */
+
+/* candidate kinds for pncg_candidates */
+#define PNCG_KIND_PT 0   /* (surface vertex, surface triangle) */
+#define PNCG_KIND_EE 1   /* (surface edge e1, surface edge e2), e1 < e2 */
+#define PNCG_KIND_PG 2   /* (surface vertex, plane) */
+
+typedef struct {
+  int32_t device;      /* HIP device ordinal */
+  int32_t precision;   /* PNCG_FP64 or PNCG_MIXED */
+  void*   stream;      /* hipStream_t to run on; NULL = a stream the context creates */
+  int32_t block;       /* threads per block for element kernels; 0 = default (256) */
+  int32_t chunk;       /* iterations launched between host status reads; 0 = default */
+} pncg_opts;
+
+typedef struct {
+  int32_t iters;            /* position updates made in the step */
+  int32_t reason;           /* 0 dE rule, 1 gradient rule, 2 iteration cap,
+                               3 zero or unbounded direction */
+  double  dE0;              /* dE of the first iteration */
+  double  last_dE;          /* dE of the last iteration */
+  double  g0_norm;          /* ||g_0||_2 */
+  double  g_norm;           /* ||g||_2 at the last gradient evaluation */
+  int32_t alpha_upper_hits; /* iterations where dhat/(2|p|) was the smaller step */
+  int32_t rebuilds;         /* candidate-list rebuilds during the step */
+  int64_t n_candidates;     /* PT + EE candidates of the last list built */
+  int64_t n_active;         /* active PT + EE + plane pairs at the last evaluation */
+} pncg_stats;
+
+/* Create a context on opts->device (opts may be NULL: device 0, FP64).
+ * *out receives the context.  Errors: E_INVAL, E_HIP, E_NOMEM. */
+int pncg_create(pncg_ctx** out, const pncg_opts* opts);
+
+/* Free the context and all device memory it owns.  NULL is accepted. */
+void pncg_destroy(pncg_ctx* ctx);
+
+/* Message for the last error of this context (never NULL; "" if none).
+ * With ctx == NULL: the last error of pncg_create on this thread. */
+const char* pncg_last_error(const pncg_ctx* ctx);
+
+/* Rest mesh (Sec. 3.1: constant-strain tets, F = D_s D_m^{-1}).
+ *   X      [nV][3] rest positions
+ *   tets   [nT][4] vertex indices, positively oriented: det[X1-X0, X2-X0,
+ *          X3-X0] > 0, otherwise E_INVERTED
+ *   tris   [nF][3] boundary triangles (contact primitives; may be nF = 0)
+ *   edges  [nE][2] boundary edges (contact primitives; may be nE = 0)
+ *   object_id [nV] object index per vertex, or NULL (one object); used by
+ *          the rest-pose exclusion
+ * Every vertex must belong to at most 64 tets (E_INVAL otherwise).
+ * Resets material, contact, solver and prescribed vertices. */
+int pncg_set_mesh(pncg_ctx* ctx, int32_t nV, const double* X, int32_t nT,
+                  const int32_t* tets, int32_t nF, const int32_t* tris,
+                  int32_t nE, const int32_t* edges, const int32_t* object_id);
+
+/* Per-tet material: Young's modulus E > 0, Poisson ratio 0 <= nu < 0.5,
+ * density rho > 0, each [nT].  Lame parameters mu = E/(2(1+nu)),
+ * lam = E nu/((1+nu)(1-2nu)); lumped mass m_v = sum rho V_e / 4. */
+int pncg_set_material(pncg_ctx* ctx, const double* E, const double* nu,
+                      const double* rho);
+
+/* Barrier parameters (Sec. 3, equation barrier): dhat > 0, kappa >= 0;
+ * cell = spatial-hash cell size (> 0) or 0 for a size derived from the
+ * surface; planes [nP][4] rows (n0, n1, n2, o) with |n| = 1 describing the
+ * half-spaces n.x >= o; flags PNCG_CONTACT_*. */
+int pncg_set_contact(pncg_ctx* ctx, double dhat, double kappa, double cell,
+                     int32_t nP, const double* planes, uint32_t flags);
+
+/* Solver settings (Algorithm 1): iter_max >= 1, eps >= 0, term
+ * PNCG_TERM_*, gravity[3] (m/s^2, f_ext = m g), flags PNCG_BARRIER_FULL /
+ * PNCG_ALPHA_INF_COMPONENT.  Defaults: 100, 1e-3, DELTA_E, (0,0,-9.8), 0. */
+int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
+                    const double* gravity, uint32_t flags);
+
+/* Prescribed vertices for the following steps: idx [n] (distinct),
+ * target [n][3] positions they take at the start of the next step (their
+ * gradient, direction and update are zero during it).  n = 0 clears. */
+int pncg_set_dirichlet(pncg_ctx* ctx, int32_t n, const int32_t* idx,
+                       const double* target);
+
+/* One time step (Algorithm 1) from (x, v) with step size h > 0:
+ * x_out, v_out [nV][3] receive x^{t+1} and v^{t+1}; st (nullable) the step
+ * statistics.  Returns PNCG_W_MAXITER if the cap was hit, E_PENETRATION /
+ * E_INVERTED / E_NONFINITE if the input or the result is infeasible.
+ * x_out may alias x and v_out may alias v. */
+int pncg_step(pncg_ctx* ctx, const double* x, const double* v, double h,
+              double* x_out, double* v_out, pncg_stats* st);
+
+/* Same with device pointers (no host copies of the state). */
+int pncg_step_dev(pncg_ctx* ctx, const double* x_dev, const double* v_dev,
+                  double h, double* x_out_dev, double* v_out_dev,
+                  pncg_stats* st);
+
+/* Queries at a given x with the active set computed at x (Algorithm 1,
+ * ComputeConstraintSet), in the context's precision.  xt is the predictor.
+ *   pncg_energy:   E(x) of equation E
+ *   pncg_gradient: g = dE/dx and diag(H) (Sec. 3 and 4.2), [nV][3] each;
+ *                  prescribed rows: g = 0, diag = 1.  diag may be NULL.
+ *   pncg_hvp:      p^T H p (Sec. 3, with the PSD-projected pair Hessian
+ *                  unless PNCG_BARRIER_FULL) and optionally Hp [nV][3]
+ *                  (NULL to skip); p is treated as 0 on prescribed rows. */
+int pncg_energy(pncg_ctx* ctx, const double* x, const double* xt, double h,
+                double* energy);
+int pncg_gradient(pncg_ctx* ctx, const double* x, const double* xt, double h,
+                  double* g, double* diag);
+int pncg_hvp(pncg_ctx* ctx, const double* x, const double* p, double h,
+             double* Hp, double* pHp);
+
+/* Candidate pairs of the given kind at x with inflation r = dhat, by the
+ * inflated-AABB test in float64 (see the kinds above), after topology and
+ * rest-pose exclusions, sorted lexicographically: pairs [cap][2].  *n
+ * receives the count; if it exceeds cap the call returns E_CAPACITY and
+ * writes nothing. */
+int pncg_candidates(pncg_ctx* ctx, const double* x, int32_t kind,
+                    int32_t* pairs, int64_t cap, int64_t* n);
+
+/* Penetration audit (Sec. 6: discrete collision check per frame): smallest
+ * distance over all non-excluded point-triangle, edge-edge and
+ * surface-vertex/plane pairs within 10 dhat, and smallest det F. */
+int pncg_min_distance(pncg_ctx* ctx, const double* x, double* dmin,
+                      double* jmin);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNCG_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) PNCG solver for the IPC incremental potential.
+
+The compute path is libpncg.so (hand-written HIP); this package only binds
+it.  ``Context`` wraps one library context; its methods carry the C ABI names
+(``pncg_set_mesh``, ``pncg_step``, ...).  Importing the package raises if the
+library has not been built (``python -m paper_2405_08001_amd.build``).
+"""
+from ._lib import (Context, PncgError, pncg_create, FP64, MIXED, TERM_DELTA_E, TERM_GRAD_REL,  # noqa: F401
+                   BARRIER_FULL, ALPHA_INF_COMPONENT, CONTACT_SELF, CONTACT_REST_EXCLUDE,
+                   KIND_PT, KIND_EE, KIND_PG, W_MAXITER, E_INVAL, E_STATE, E_INVERTED, E_NONFINITE,
+                   E_PENETRATION, E_HIP, E_CAPACITY, EXPORTS, LIB_PATH)

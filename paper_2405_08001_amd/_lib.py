@@ -1,0 +1,226 @@
+"""ctypes binding of libpncg (include/pncg.h): argument marshalling only.
+
+Every function here converts NumPy arrays (or torch CUDA tensors for the
+``*_dev`` entry points) to the pointers and sizes of the C ABI and raises
+``PncgError`` on a negative status.  All computation happens in the HIP
+library; if it is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpncg.so")
+
+OK, W_MAXITER = 0, 1
+E_INVAL, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4
+E_PENETRATION, E_INVERTED, E_NONFINITE, E_CAPACITY = -5, -6, -7, -8
+FP64, MIXED = 0, 1
+TERM_DELTA_E, TERM_GRAD_REL = 0, 1
+BARRIER_FULL, ALPHA_INF_COMPONENT = 1, 2
+CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
+KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
+
+CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
+              -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY"}
+EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "pncg_set_material",
+           "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
+           "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance")
+
+
+class PncgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{CODE_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pncg_opts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("stream", C.c_void_p),
+                ("block", C.c_int32), ("chunk", C.c_int32)]
+
+
+class pncg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("reason", C.c_int32), ("dE0", C.c_double), ("last_dE", C.c_double),
+                ("g0_norm", C.c_double), ("g_norm", C.c_double), ("alpha_upper_hits", C.c_int32),
+                ("rebuilds", C.c_int32), ("n_candidates", C.c_int64), ("n_active", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2405_08001_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint32
+    sig = {
+        "pncg_create": (I32, [C.POINTER(P), C.POINTER(pncg_opts)]),
+        "pncg_destroy": (None, [P]),
+        "pncg_last_error": (C.c_char_p, [P]),
+        "pncg_set_mesh": (I32, [P, I32, P, I32, P, I32, P, I32, P, P]),
+        "pncg_set_material": (I32, [P, P, P, P]),
+        "pncg_set_contact": (I32, [P, D, D, D, I32, P, U32]),
+        "pncg_set_solver": (I32, [P, I32, D, I32, P, U32]),
+        "pncg_set_dirichlet": (I32, [P, I32, P, P]),
+        "pncg_step": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
+        "pncg_step_dev": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
+        "pncg_energy": (I32, [P, P, P, D, P]),
+        "pncg_gradient": (I32, [P, P, P, D, P, P]),
+        "pncg_hvp": (I32, [P, P, P, D, P, P]),
+        "pncg_candidates": (I32, [P, P, I32, P, I64, C.POINTER(I64)]),
+        "pncg_min_distance": (I32, [P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_L = _load()
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """One libpncg context (a device, a precision, a mesh)."""
+
+    def __init__(self, device=0, precision=FP64, stream=None, chunk=0):
+        opts = pncg_opts(device, precision, stream, 0, chunk)
+        h = C.c_void_p()
+        rc = _L.pncg_create(C.byref(h), C.byref(opts))
+        if rc < 0:
+            raise PncgError(rc, _L.pncg_last_error(None).decode())
+        self._h = h
+        self.precision = precision
+        self.nV = 0
+        self.nT = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.pncg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PncgError(rc, _L.pncg_last_error(self._h).decode())
+        return rc
+
+    # -------------------------------------------------------------- setup
+    def pncg_set_mesh(self, X, tets, tris=None, edges=None, object_id=None):
+        X = _f64(X)
+        tets = _i32(tets)
+        tris = _i32(np.zeros((0, 3)) if tris is None else tris)
+        edges = _i32(np.zeros((0, 2)) if edges is None else edges)
+        oid = None if object_id is None else _i32(object_id)
+        self._check(_L.pncg_set_mesh(self._h, X.shape[0], _ptr(X), tets.shape[0], _ptr(tets),
+                                     tris.shape[0], _ptr(tris), edges.shape[0], _ptr(edges), _ptr(oid)))
+        self.nV = X.shape[0]
+        self.nT = tets.shape[0]
+
+    def pncg_set_material(self, E, nu, rho):
+        n = max(self.nT, np.size(E))
+        E, nu, rho = (_f64(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))) for a in (E, nu, rho))
+        self._check(_L.pncg_set_material(self._h, _ptr(E), _ptr(nu), _ptr(rho)))
+
+    def pncg_set_contact(self, dhat, kappa, cell=0.0, planes=None, flags=0):
+        pl = _f64(np.zeros((0, 4)) if planes is None else np.asarray(planes, dtype=np.float64).reshape(-1, 4))
+        self._check(_L.pncg_set_contact(self._h, float(dhat), float(kappa), float(cell), pl.shape[0], _ptr(pl),
+                                        int(flags)))
+
+    def pncg_set_solver(self, iter_max=100, eps=1e-3, term=TERM_DELTA_E, gravity=(0.0, 0.0, -9.8), flags=0):
+        g = _f64(gravity)
+        self._check(_L.pncg_set_solver(self._h, int(iter_max), float(eps), int(term), _ptr(g), int(flags)))
+
+    def pncg_set_dirichlet(self, idx, target):
+        idx = _i32(idx)
+        target = _f64(target).reshape(-1, 3)
+        self._check(_L.pncg_set_dirichlet(self._h, idx.shape[0], _ptr(idx), _ptr(target)))
+
+    # -------------------------------------------------------------- steps
+    def pncg_step(self, x, v, h):
+        x = _f64(x, (self.nV, 3))
+        v = _f64(v, (self.nV, 3))
+        xo = np.empty_like(x)
+        vo = np.empty_like(v)
+        st = pncg_stats()
+        rc = self._check(_L.pncg_step(self._h, _ptr(x), _ptr(v), float(h), _ptr(xo), _ptr(vo), C.byref(st)))
+        d = st.as_dict()
+        d["status"] = rc
+        return xo, vo, d
+
+    def pncg_step_dev(self, x, v, h, x_out, v_out):
+        """x, v, x_out, v_out: float64 CUDA tensors of shape (nV, 3), contiguous."""
+        for t in (x, v, x_out, v_out):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+                    and tuple(t.shape) == (self.nV, 3)):
+                raise ValueError("step_dev needs contiguous float64 CUDA tensors of shape (nV, 3)")
+        st = pncg_stats()
+        rc = self._check(_L.pncg_step_dev(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), float(h),
+                                          C.c_void_p(x_out.data_ptr()), C.c_void_p(v_out.data_ptr()), C.byref(st)))
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    # ------------------------------------------------------------ queries
+    def pncg_energy(self, x, xt, h):
+        x = _f64(x, (self.nV, 3))
+        xt = _f64(xt, (self.nV, 3))
+        out = C.c_double()
+        self._check(_L.pncg_energy(self._h, _ptr(x), _ptr(xt), float(h), C.byref(out)))
+        return out.value
+
+    def pncg_gradient(self, x, xt, h, want_diag=True):
+        x = _f64(x, (self.nV, 3))
+        xt = _f64(xt, (self.nV, 3))
+        g = np.empty((self.nV, 3))
+        d = np.empty((self.nV, 3)) if want_diag else None
+        self._check(_L.pncg_gradient(self._h, _ptr(x), _ptr(xt), float(h), _ptr(g), _ptr(d)))
+        return g, d
+
+    def pncg_hvp(self, x, p, h, want_hp=True):
+        x = _f64(x, (self.nV, 3))
+        p = _f64(p, (self.nV, 3))
+        hp = np.empty((self.nV, 3)) if want_hp else None
+        out = C.c_double()
+        self._check(_L.pncg_hvp(self._h, _ptr(x), _ptr(p), float(h), _ptr(hp), C.byref(out)))
+        return hp, out.value
+
+    def pncg_candidates(self, x, kind):
+        x = _f64(x, (self.nV, 3))
+        n = C.c_int64()
+        rc = _L.pncg_candidates(self._h, _ptr(x), int(kind), None, 0, C.byref(n))
+        if rc < 0 and rc != E_CAPACITY:
+            self._check(rc)
+        out = np.empty((max(n.value, 1), 2), dtype=np.int32)
+        self._check(_L.pncg_candidates(self._h, _ptr(x), int(kind), _ptr(out), out.shape[0], C.byref(n)))
+        return out[:n.value]
+
+    def pncg_min_distance(self, x):
+        x = _f64(x, (self.nV, 3))
+        d, j = C.c_double(), C.c_double()
+        self._check(_L.pncg_min_distance(self._h, _ptr(x), C.byref(d), C.byref(j)))
+        return d.value, j.value
+
+
+def pncg_create(device=0, precision=FP64, stream=None, chunk=0):
+    return Context(device, precision, stream, chunk)

@@ -1,0 +1,944 @@
+// Host runtime and C ABI of libpncg (declared in include/pncg.h).
+//
+// The context keeps the mesh in the layouts the kernels want: one 64-byte
+// (mixed) or 112-byte (float64) record per tet holding its indices, the rows
+// of D_m^{-1} and V mu, V lam; positions as padded double4 (one load per
+// gathered vertex); per-vertex float32 or float64 vectors as padded 4-vectors;
+// and the vertex -> (tet, corner) incidence packed so that no vertex's lanes
+// straddle a 64-lane wave.  A time step runs entirely on the device: the host
+// launches chunks of iterations and reads a small status block between
+// chunks (to stop, or to rebuild the candidate list when the accumulated
+// displacement bound exceeds half the skin).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pncg.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace pncg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct pncg_ctx {
+  int device = 0;
+  int precision = PNCG_FP64;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool dev_ready = false;
+  int block = kBlock;
+  int chunk = 16;
+  std::string err;
+  int state = 0;  // 0 created, 1 mesh, 2 material
+
+  // host mesh
+  int nV = 0, nT = 0, nF = 0, nE = 0, nSV = 0;
+  std::vector<double> X;
+  std::vector<int> tets, tris, edges, surf, oid;
+  std::vector<double> vol, Bm;  // Bm: [nT][9] rows of D_m^{-1}
+  std::vector<double> E, nu, rho, mass;
+  std::vector<uint8_t> vflag;
+  std::vector<int> inc, inc_vert;
+  int nWaves = 0;
+
+  // contact / solver parameters
+  double dhat = 1e-3, kappa = 0.0, cell_user = 0.0, cell = 0.0, skin = 0.0;
+  Planes planes{};
+  unsigned cflags = 0;
+  int iter_max = 100, term = PNCG_TERM_DELTA_E;
+  double eps = 1e-3;
+  double grav[3] = {0.0, 0.0, -9.8};
+  unsigned sflags = 0;
+  std::vector<int> fixed;
+  std::vector<double> fixed_target;
+
+  // device memory
+  std::vector<void*> allocs;
+  void* d_elem = nullptr;
+  int* d_inc = nullptr;
+  int* d_inc_vert = nullptr;
+  double* d_mass = nullptr;
+  uint8_t* d_vflag = nullptr;
+  double4* d_target = nullptr;
+  double4 *d_x0 = nullptr, *d_x1 = nullptr, *d_xt = nullptr, *d_xstart = nullptr;
+  void *d_g = nullptr, *d_pg = nullptr, *d_p0 = nullptr, *d_p1 = nullptr;
+  double* d_acc = nullptr;
+  int *d_tris = nullptr, *d_edges = nullptr, *d_surf = nullptr, *d_oid = nullptr;
+  unsigned long long *d_excl_pt = nullptr, *d_excl_ee = nullptr;
+  int n_excl_pt = 0, n_excl_ee = 0;
+  int2* d_cand = nullptr;
+  long long cand_cap = 0;
+  long long* d_ncand = nullptr;
+  IterScal* d_scal = nullptr;
+  int scal_cap = 0;
+  StepStatus* d_status = nullptr;
+  StepStatus* h_status = nullptr;  // pinned
+  long long* h_n = nullptr;        // pinned [2]
+  double* d_part_grad = nullptr;
+  double* d_part_dir = nullptr;
+  double* d_part_narrow = nullptr;
+  double* d_io = nullptr;          // [3][nV][3] staging for host inputs/outputs
+  double* d_scalar = nullptr;      // [8]
+  // broad phase
+  int tsize = 0;
+  int *d_count = nullptr, *d_start = nullptr, *d_items = nullptr;
+  double* d_part_ext = nullptr;
+  long long *d_part_cnt = nullptr, *d_part_off = nullptr;
+  int grid = 1;
+};
+
+namespace {
+
+int fail(pncg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, PNCG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+template <typename T>
+int dmalloc(pncg_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(c, PNCG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return PNCG_OK;
+}
+
+void dfree(pncg_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+void free_all(pncg_ctx* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->h_n) (void)hipHostFree(c->h_n);
+  c->h_status = nullptr;
+  c->h_n = nullptr;
+}
+
+int ensure_device(pncg_ctx* c) {
+  if (c->dev_ready) return PNCG_OK;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(c, PNCG_E_HIP, "no HIP device available");
+  if (c->device < 0 || c->device >= n) return fail(c, PNCG_E_INVAL, "device ordinal out of range");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!c->stream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  HIPCHK(c, hipHostMalloc((void**)&c->h_status, sizeof(StepStatus), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->h_n, 4 * sizeof(long long), hipHostMallocDefault));
+  c->dev_ready = true;
+  return PNCG_OK;
+}
+
+int sync(pncg_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PNCG_OK;
+}
+
+template <typename R>
+Args<R> make_args(pncg_ctx* c, double h) {
+  Args<R> A{};
+  A.nV = c->nV;
+  A.nT = c->nT;
+  A.elem = reinterpret_cast<const ElemRec<R>*>(c->d_elem);
+  A.inc = c->d_inc;
+  A.inc_vert = c->d_inc_vert;
+  A.nWaves = c->nWaves;
+  A.mass = c->d_mass;
+  A.vflag = c->d_vflag;
+  A.target = c->d_target;
+  A.x0 = c->d_x0;
+  A.x1 = c->d_x1;
+  A.xt = c->d_xt;
+  A.xstart = c->d_xstart;
+  A.g = reinterpret_cast<R4<R>*>(c->d_g);
+  A.pg = reinterpret_cast<R4<R>*>(c->d_pg);
+  A.p0 = reinterpret_cast<R4<R>*>(c->d_p0);
+  A.p1 = reinterpret_cast<R4<R>*>(c->d_p1);
+  A.acc = c->d_acc;
+  A.self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0 ? 1 : 0;
+  A.cand = c->d_cand;
+  A.ncand = c->d_ncand;
+  A.tris = c->d_tris;
+  A.edges = c->d_edges;
+  A.planes = c->planes;
+  A.dhat = c->dhat;
+  A.kappa = c->kappa;
+  A.h = h;
+  A.h2 = h * h;
+  A.skin = c->skin;
+  A.has_prims = (c->planes.n > 0 || A.self) ? 1 : 0;
+  A.iter_max = c->iter_max;
+  A.term = c->term;
+  A.eps = c->eps;
+  A.flags = c->sflags;
+  A.scal = c->d_scal;
+  A.status = c->d_status;
+  A.part_grad = c->d_part_grad;
+  A.part_dir = c->d_part_dir;
+  A.part_narrow = c->d_part_narrow;
+  A.grid = c->grid;
+  return A;
+}
+
+Broad make_broad(pncg_ctx* c) {
+  Broad B{};
+  B.nV = c->nV;
+  B.nSV = c->nSV;
+  B.nF = c->nF;
+  B.nE = c->nE;
+  B.surf = c->d_surf;
+  B.tris = c->d_tris;
+  B.edges = c->d_edges;
+  B.oid = c->d_oid;
+  B.excl_pt = c->d_excl_pt;
+  B.n_excl_pt = c->n_excl_pt;
+  B.excl_ee = c->d_excl_ee;
+  B.n_excl_ee = c->n_excl_ee;
+  B.tsize = c->tsize;
+  B.count = c->d_count;
+  B.start = c->d_start;
+  B.items = c->d_items;
+  B.part_ext = c->d_part_ext;
+  B.part_cnt = c->d_part_cnt;
+  B.part_off = c->d_part_off;
+  B.grid = c->grid;
+  return B;
+}
+
+// Candidate pairs (PT then EE) at device positions x with inflation r into
+// c->d_cand; counts in c->d_ncand.  filter_d >= 0: same-object pairs closer
+// than filter_d only (rest-pose exclusion set).
+int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, long long* n_total, long long* n_pt) {
+  Broad B = make_broad(c);
+  broad_build(B, x, c->cell, c->stream);
+  broad_count(B, x, c->cell, r, filter_d, c->stream);
+  broad_scan(B, c->d_ncand, c->stream);
+  HIPCHK(c, hipMemcpyAsync(c->h_n, c->d_ncand, 2 * sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  int rc = sync(c);
+  if (rc) return rc;
+  const long long n = c->h_n[0];
+  if (n > c->cand_cap) {
+    long long cap = std::max<long long>(n + n / 2, 1024);
+    int2* nc = nullptr;
+    if ((rc = dmalloc(c, &nc, (size_t)cap))) return rc;
+    dfree(c, c->d_cand);
+    c->d_cand = nc;
+    c->cand_cap = cap;
+  }
+  broad_fill(B, x, c->cell, r, filter_d, c->d_cand, c->cand_cap, c->stream);
+  if (n_total) *n_total = n;
+  if (n_pt) *n_pt = c->h_n[1];
+  return PNCG_OK;
+}
+
+int upload_rows(pncg_ctx* c, const double* host, double* dev, int n) {
+  HIPCHK(c, hipMemcpyAsync(dev, host, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  return PNCG_OK;
+}
+
+__global__ void k_rows_to_x4(const double* a, double4* x, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    x[i] = make_double4(a[3 * i], a[3 * i + 1], a[3 * i + 2], 0.0);
+}
+
+int check_status_err(pncg_ctx* c, const StepStatus& st) {
+  if (st.err & kErrNonfinite) return fail(c, PNCG_E_NONFINITE, "non-finite value in positions or velocities");
+  if (st.err & kErrInverted) return fail(c, PNCG_E_INVERTED, "a tet has det F <= 0");
+  if (st.err & kErrPenetration) return fail(c, PNCG_E_PENETRATION, "a contact distance is <= 0");
+  return PNCG_OK;
+}
+
+int read_status(pncg_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(StepStatus), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+// ------------------------------------------------------------------ step
+template <typename R>
+int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, double* x_out, double* v_out,
+              pncg_stats* st) {
+  Args<R> A = make_args<R>(c, h);
+  const double3 grav = make_double3(c->grav[0], c->grav[1], c->grav[2]);
+  launch_predict<R>(A, x_dev, v_dev, grav, c->stream);
+  int rebuilds = 0;
+  long long ncand = 0;
+  const double r_build = c->dhat + c->skin;
+  int rc;
+  if (A.self) {
+    if ((rc = build_candidates(c, c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+    ++rebuilds;
+    A.cand = c->d_cand;
+  }
+  int k = 0;
+  int mode = 0;  // kModeNormal
+  while (true) {
+    const int kend = std::min(k + c->chunk, c->iter_max + 1);
+    for (int j = k; j < kend; ++j) {
+      if (j == c->iter_max) {
+        launch_iteration_first<R>(A, j, 1 /*finish*/, c->stream);
+        break;
+      }
+      launch_iteration_first<R>(A, j, (j == k) ? mode : 0, c->stream);
+      launch_iteration_rest<R>(A, j, c->stream);
+    }
+    mode = 0;
+    if ((rc = read_status(c))) return rc;
+    const StepStatus s = *c->h_status;
+    if ((rc = check_status_err(c, s))) return rc;
+    if (s.stopped) break;
+    if (s.paused_at >= 0) {
+      const int p = s.paused_at;
+      if ((rc = build_candidates(c, (p & 1) ? c->d_x1 : c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+      ++rebuilds;
+      A.cand = c->d_cand;
+      k = p;
+      mode = 2;  // kModeResume
+      continue;
+    }
+    if (kend > c->iter_max) break;  // cannot happen: the finish launch always stops
+    k = kend;
+  }
+  launch_finalize<R>(A, x_out, v_out, c->stream);
+  if ((rc = read_status(c))) return rc;
+  const StepStatus s = *c->h_status;
+  if ((rc = check_status_err(c, s))) return rc;
+  if (st) {
+    st->iters = s.iters;
+    st->reason = s.reason;
+    st->dE0 = s.dE0;
+    st->last_dE = s.last_dE;
+    st->g0_norm = s.g0;
+    st->g_norm = s.gk;
+    st->alpha_upper_hits = s.a_up_hits;
+    st->rebuilds = rebuilds;
+    st->n_candidates = ncand;
+    st->n_active = (long long)s.n_active;
+  }
+  return s.reason == 2 ? PNCG_W_MAXITER : PNCG_OK;
+}
+
+int ready(pncg_ctx* c) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 2) return fail(c, PNCG_E_STATE, "set_mesh and set_material must come first");
+  return PNCG_OK;
+}
+
+// Ensure the candidate buffer reflects r at device positions in d_x0.
+int query_candidates(pncg_ctx* c, double r) {
+  if (!((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0)) return PNCG_OK;
+  return build_candidates(c, c->d_x0, r, -1.0, nullptr, nullptr);
+}
+
+int stage_positions(pncg_ctx* c, const double* x) {
+  if (!finite_all(x, 3 * (size_t)c->nV)) return fail(c, PNCG_E_NONFINITE, "non-finite position");
+  int rc = upload_rows(c, x, c->d_io, c->nV);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rows_to_x4, dim3(c->grid), dim3(kBlock), 0, c->stream, (const double*)c->d_io, c->d_x0, c->nV);
+  return PNCG_OK;
+}
+
+template <typename R>
+int load_query(pncg_ctx* c, const double* x, const double* xt, const double* p) {
+  const size_t n3 = 3 * (size_t)c->nV;
+  if (!finite_all(x, n3) || (xt && !finite_all(xt, n3)) || (p && !finite_all(p, n3)))
+    return fail(c, PNCG_E_NONFINITE, "non-finite input");
+  int rc;
+  if ((rc = upload_rows(c, x, c->d_io, c->nV))) return rc;
+  if (xt && (rc = upload_rows(c, xt, c->d_io + n3, c->nV))) return rc;
+  if (p && (rc = upload_rows(c, p, c->d_io + 2 * n3, c->nV))) return rc;
+  Args<R> A = make_args<R>(c, 1.0);
+  launch_load_query<R>(A, c->d_io, xt ? c->d_io + n3 : nullptr, p ? c->d_io + 2 * n3 : nullptr, c->stream);
+  return query_candidates(c, c->dhat);
+}
+
+int finish_query(pncg_ctx* c) {
+  int rc = read_status(c);
+  if (rc) return rc;
+  return check_status_err(c, *c->h_status);
+}
+
+template <typename R>
+int energy_impl(pncg_ctx* c, const double* x, const double* xt, double h, double* out) {
+  int rc = load_query<R>(c, x, xt, nullptr);
+  if (rc) return rc;
+  Args<R> A = make_args<R>(c, h);
+  launch_query_energy<R>(A, c->d_scalar, c->stream);
+  HIPCHK(c, hipMemcpyAsync(out, c->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return finish_query(c);
+}
+
+template <typename R>
+int gradient_impl(pncg_ctx* c, const double* x, const double* xt, double h, double* g, double* d) {
+  int rc = load_query<R>(c, x, xt, nullptr);
+  if (rc) return rc;
+  Args<R> A = make_args<R>(c, h);
+  const size_t n3 = 3 * (size_t)c->nV;
+  double* dg = c->d_io;          // x staging is no longer needed
+  double* dd = c->d_io + 2 * n3;
+  launch_query_gradient<R>(A, dg, d ? dd : nullptr, c->stream);
+  HIPCHK(c, hipMemcpyAsync(g, dg, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  if (d) HIPCHK(c, hipMemcpyAsync(d, dd, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  return finish_query(c);
+}
+
+template <typename R>
+int hvp_impl(pncg_ctx* c, const double* x, const double* p, double h, double* hp, double* php) {
+  int rc = load_query<R>(c, x, nullptr, p);
+  if (rc) return rc;
+  Args<R> A = make_args<R>(c, h);
+  const size_t n3 = 3 * (size_t)c->nV;
+  double* dh = c->d_io + n3;
+  launch_query_hvp<R>(A, hp ? dh : nullptr, c->d_scalar, c->stream);
+  if (hp) HIPCHK(c, hipMemcpyAsync(hp, dh, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(php, c->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return finish_query(c);
+}
+
+template <typename R>
+int upload_elements(pncg_ctx* c) {
+  std::vector<ElemRec<R>> rec(c->nT);
+  for (int e = 0; e < c->nT; ++e) {
+    ElemRec<R>& r = rec[e];
+    for (int a = 0; a < 4; ++a) r.v[a] = c->tets[4 * e + a];
+    for (int j = 0; j < 9; ++j) r.B[j] = R(c->Bm[9 * e + j]);
+    const double mu = c->E[e] / (2.0 * (1.0 + c->nu[e]));
+    const double lam = c->E[e] * c->nu[e] / ((1.0 + c->nu[e]) * (1.0 - 2.0 * c->nu[e]));
+    r.vmu = R(c->vol[e] * mu);
+    r.vlam = R(c->vol[e] * lam);
+  }
+  if (!c->d_elem) {
+    int rc = dmalloc(c, reinterpret_cast<ElemRec<R>**>(&c->d_elem), (size_t)c->nT);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_elem, rec.data(), sizeof(ElemRec<R>) * (size_t)c->nT, hipMemcpyHostToDevice, c->stream));
+  return sync(c);
+}
+
+int upload_flags_targets(pncg_ctx* c) {
+  std::vector<uint8_t> fl(c->vflag);
+  std::vector<double4> tg(c->nV, make_double4(0, 0, 0, 0));
+  for (size_t i = 0; i < c->fixed.size(); ++i) {
+    const int v = c->fixed[i];
+    fl[v] |= kFixed;
+    tg[v] = make_double4(c->fixed_target[3 * i], c->fixed_target[3 * i + 1], c->fixed_target[3 * i + 2], 0.0);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_vflag, fl.data(), c->nV, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_target, tg.data(), sizeof(double4) * c->nV, hipMemcpyHostToDevice, c->stream));
+  return sync(c);
+}
+
+int grid_for(const pncg_ctx* c) {
+  long long work = std::max<long long>({(long long)c->nWaves * kWave, (long long)c->nT, (long long)c->nV, 1LL});
+  long long g = (work + kBlock - 1) / kBlock;
+  return (int)std::min<long long>(std::max<long long>(g, 1), kMaxGrid);
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int pncg_create(pncg_ctx** out, const pncg_opts* o) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return PNCG_E_INVAL;
+  }
+  *out = nullptr;
+  pncg_ctx* c = new (std::nothrow) pncg_ctx();
+  if (!c) {
+    g_create_error = "out of host memory";
+    return PNCG_E_NOMEM;
+  }
+  if (o) {
+    if (o->precision != PNCG_FP64 && o->precision != PNCG_MIXED) {
+      delete c;
+      g_create_error = "precision must be PNCG_FP64 or PNCG_MIXED";
+      return PNCG_E_INVAL;
+    }
+    if (o->device < 0 || o->block < 0 || o->chunk < 0) {
+      delete c;
+      g_create_error = "negative device, block or chunk";
+      return PNCG_E_INVAL;
+    }
+    if (o->block != 0 && o->block != kBlock) {
+      delete c;
+      g_create_error = "block must be 0 or 256";
+      return PNCG_E_INVAL;
+    }
+    c->device = o->device;
+    c->precision = o->precision;
+    c->stream = reinterpret_cast<hipStream_t>(o->stream);
+    if (o->chunk > 0) c->chunk = o->chunk;
+  }
+  *out = c;
+  return PNCG_OK;
+}
+
+void pncg_destroy(pncg_ctx* c) {
+  if (!c) return;
+  if (c->dev_ready) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+const char* pncg_last_error(const pncg_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const int32_t* tets, int32_t nF,
+                  const int32_t* tris, int32_t nE, const int32_t* edges, const int32_t* object_id) {
+  if (!c) return PNCG_E_INVAL;
+  if (nV <= 0 || nT <= 0 || nF < 0 || nE < 0 || !X || !tets || (nF > 0 && !tris) || (nE > 0 && !edges))
+    return fail(c, PNCG_E_INVAL, "bad mesh sizes or NULL arrays");
+  if (!finite_all(X, 3 * (size_t)nV)) return fail(c, PNCG_E_NONFINITE, "non-finite rest position");
+  for (long long i = 0; i < 4LL * nT; ++i)
+    if (tets[i] < 0 || tets[i] >= nV) return fail(c, PNCG_E_INVAL, "tet index out of range");
+  for (long long i = 0; i < 3LL * nF; ++i)
+    if (tris[i] < 0 || tris[i] >= nV) return fail(c, PNCG_E_INVAL, "triangle index out of range");
+  for (long long i = 0; i < 2LL * nE; ++i)
+    if (edges[i] < 0 || edges[i] >= nV) return fail(c, PNCG_E_INVAL, "edge index out of range");
+  for (int e = 0; e < nE; ++e)
+    if (edges[2 * e] == edges[2 * e + 1]) return fail(c, PNCG_E_INVAL, "degenerate edge");
+  std::vector<double> Bm(9 * (size_t)nT), vol(nT);
+  for (int e = 0; e < nT; ++e) {
+    const int* t = tets + 4 * e;
+    double D[3][3];
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) D[i][j] = X[3 * t[j + 1] + i] - X[3 * t[0] + i];
+    const double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
+                       D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                       D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+    if (!(det > 0.0)) return fail(c, PNCG_E_INVERTED, "rest tet " + std::to_string(e) + " has det <= 0");
+    const double id = 1.0 / det;
+    // inverse of D (rows of D^{-1} are the shape vectors b_1..b_3)
+    double Inv[3][3];
+    Inv[0][0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) * id;
+    Inv[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+    Inv[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+    Inv[1][0] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) * id;
+    Inv[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+    Inv[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+    Inv[2][0] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) * id;
+    Inv[2][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * id;
+    Inv[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+    for (int r = 0; r < 3; ++r)
+      for (int j = 0; j < 3; ++j) Bm[9 * (size_t)e + 3 * r + j] = Inv[r][j];
+    vol[e] = det / 6.0;
+  }
+  // vertex -> (tet, corner) incidence, packed into 64-lane waves
+  std::vector<int> deg(nV, 0);
+  for (long long i = 0; i < 4LL * nT; ++i) deg[tets[i]]++;
+  int maxdeg = 0;
+  for (int v = 0; v < nV; ++v) maxdeg = std::max(maxdeg, deg[v]);
+  if (maxdeg > kWave) return fail(c, PNCG_E_INVAL, "a vertex belongs to more than 64 tets");
+  std::vector<int> off(nV + 1, 0);
+  for (int v = 0; v < nV; ++v) off[v + 1] = off[v] + deg[v];
+  std::vector<int> lst(4 * (size_t)nT), fill(off.begin(), off.end() - 1);
+  for (int e = 0; e < nT; ++e)
+    for (int a = 0; a < 4; ++a) lst[fill[tets[4 * e + a]]++] = 4 * e + a;
+  std::vector<int> inc, incv;
+  inc.reserve(4 * (size_t)nT + nV);
+  int used = 0;
+  for (int v = 0; v < nV; ++v) {
+    const int d = std::max(deg[v], 1);
+    if (used + d > kWave) {
+      while (used < kWave) { inc.push_back(-1); incv.push_back(-1); ++used; }
+      used = 0;
+    }
+    if (deg[v] == 0) { inc.push_back(-2); incv.push_back(v); }
+    for (int i = off[v]; i < off[v + 1]; ++i) { inc.push_back(lst[i]); incv.push_back(v); }
+    used += d;
+  }
+  while (used % kWave) { inc.push_back(-1); incv.push_back(-1); ++used; }
+  // surface vertices and flags
+  std::vector<uint8_t> fl(nV, 0);
+  std::vector<int> surf;
+  for (long long i = 0; i < 3LL * nF; ++i) fl[tris[i]] |= kSurface;
+  for (int v = 0; v < nV; ++v)
+    if (fl[v] & kSurface) surf.push_back(v);
+
+  // commit host state
+  c->nV = nV; c->nT = nT; c->nF = nF; c->nE = nE; c->nSV = (int)surf.size();
+  c->X.assign(X, X + 3 * (size_t)nV);
+  c->tets.assign(tets, tets + 4 * (size_t)nT);
+  c->tris.assign(tris ? tris : tets, tris ? tris + 3 * (size_t)nF : tets);
+  c->edges.assign(edges ? edges : tets, edges ? edges + 2 * (size_t)nE : tets);
+  c->oid.assign(nV, 0);
+  if (object_id) c->oid.assign(object_id, object_id + nV);
+  c->surf = surf;
+  c->vol = vol;
+  c->Bm = Bm;
+  c->vflag = fl;
+  c->inc = inc;
+  c->inc_vert = incv;
+  c->nWaves = (int)(inc.size() / kWave);
+  c->fixed.clear();
+  c->fixed_target.clear();
+  c->cflags = 0;
+  c->planes.n = 0;
+  c->kappa = 0.0;
+  c->state = 1;
+  c->grid = grid_for(c);
+
+  int rc = ensure_device(c);
+  if (rc) { c->state = 0; return rc; }
+  HIPCHK(c, hipSetDevice(c->device));
+  // (re)allocate device state
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
+  c->d_excl_pt = c->d_excl_ee = nullptr; c->n_excl_pt = c->n_excl_ee = 0;
+  const size_t r4 = (c->precision == PNCG_MIXED) ? sizeof(float4) : sizeof(double4);
+  const int gmax = kMaxGrid;
+  if ((rc = dmalloc(c, &c->d_inc, inc.size())) || (rc = dmalloc(c, &c->d_inc_vert, incv.size())) ||
+      (rc = dmalloc(c, &c->d_mass, nV)) || (rc = dmalloc(c, &c->d_vflag, nV)) ||
+      (rc = dmalloc(c, &c->d_target, nV)) || (rc = dmalloc(c, &c->d_x0, nV)) || (rc = dmalloc(c, &c->d_x1, nV)) ||
+      (rc = dmalloc(c, &c->d_xt, nV)) || (rc = dmalloc(c, &c->d_xstart, nV)) ||
+      (rc = dmalloc(c, (char**)&c->d_g, r4 * nV)) || (rc = dmalloc(c, (char**)&c->d_pg, r4 * nV)) ||
+      (rc = dmalloc(c, (char**)&c->d_p0, r4 * nV)) || (rc = dmalloc(c, (char**)&c->d_p1, r4 * nV)) ||
+      (rc = dmalloc(c, &c->d_acc, 8 * (size_t)nV)) || (rc = dmalloc(c, &c->d_tris, 3 * (size_t)nF)) ||
+      (rc = dmalloc(c, &c->d_edges, 2 * (size_t)nE)) || (rc = dmalloc(c, &c->d_surf, surf.size())) ||
+      (rc = dmalloc(c, &c->d_oid, nV)) || (rc = dmalloc(c, &c->d_ncand, 4)) ||
+      (rc = dmalloc(c, &c->d_status, 1)) || (rc = dmalloc(c, &c->d_part_grad, 8 * (size_t)gmax)) ||
+      (rc = dmalloc(c, &c->d_part_dir, 4 * (size_t)gmax)) || (rc = dmalloc(c, &c->d_part_narrow, gmax)) ||
+      (rc = dmalloc(c, &c->d_io, 9 * (size_t)nV)) || (rc = dmalloc(c, &c->d_scalar, 8)) ||
+      (rc = dmalloc(c, &c->d_part_ext, 3 * (size_t)gmax)) ||
+      (rc = dmalloc(c, &c->d_part_cnt, 2 * (size_t)gmax * kBlock)) ||
+      (rc = dmalloc(c, &c->d_part_off, 2 * (size_t)gmax * kBlock + 4096)))
+    return rc;
+  c->scal_cap = 0;
+  c->d_scal = nullptr;
+  // hash table sized to the surface items
+  int ts = 1024;
+  while (ts < 2 * (c->nSV + nE)) ts <<= 1;
+  c->tsize = ts;
+  if ((rc = dmalloc(c, &c->d_count, ts)) || (rc = dmalloc(c, &c->d_start, ts + 1)) ||
+      (rc = dmalloc(c, &c->d_items, std::max(c->nSV + nE, 1))))
+    return rc;
+  HIPCHK(c, hipMemsetAsync(c->d_ncand, 0, 4 * sizeof(long long), c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_inc, inc.data(), sizeof(int) * inc.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_inc_vert, incv.data(), sizeof(int) * incv.size(), hipMemcpyHostToDevice, c->stream));
+  if (nF) HIPCHK(c, hipMemcpyAsync(c->d_tris, tris, sizeof(int) * 3 * (size_t)nF, hipMemcpyHostToDevice, c->stream));
+  if (nE) HIPCHK(c, hipMemcpyAsync(c->d_edges, edges, sizeof(int) * 2 * (size_t)nE, hipMemcpyHostToDevice, c->stream));
+  if (!surf.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_surf, surf.data(), sizeof(int) * surf.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_oid, c->oid.data(), sizeof(int) * nV, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_acc, 0, sizeof(double) * 8 * (size_t)nV, c->stream));
+  if ((rc = upload_flags_targets(c))) return rc;
+  return sync(c);
+}
+
+int pncg_set_material(pncg_ctx* c, const double* E, const double* nu, const double* rho) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  if (!E || !nu || !rho) return fail(c, PNCG_E_INVAL, "NULL material array");
+  for (int e = 0; e < c->nT; ++e) {
+    if (!std::isfinite(E[e]) || !std::isfinite(nu[e]) || !std::isfinite(rho[e]))
+      return fail(c, PNCG_E_NONFINITE, "non-finite material parameter");
+    if (!(E[e] > 0.0) || !(nu[e] >= 0.0 && nu[e] < 0.5) || !(rho[e] > 0.0))
+      return fail(c, PNCG_E_INVAL, "material out of range (E > 0, 0 <= nu < 0.5, rho > 0)");
+  }
+  c->E.assign(E, E + c->nT);
+  c->nu.assign(nu, nu + c->nT);
+  c->rho.assign(rho, rho + c->nT);
+  c->mass.assign(c->nV, 0.0);
+  for (int e = 0; e < c->nT; ++e)
+    for (int a = 0; a < 4; ++a) c->mass[c->tets[4 * e + a]] += rho[e] * c->vol[e] / 4.0;
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = (c->precision == PNCG_MIXED) ? upload_elements<float>(c) : upload_elements<double>(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->d_mass, c->mass.data(), sizeof(double) * c->nV, hipMemcpyHostToDevice, c->stream));
+  c->state = 2;
+  return sync(c);
+}
+
+int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_t nP, const double* planes,
+                     uint32_t flags) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 2) return fail(c, PNCG_E_STATE, "set_mesh and set_material must come first");
+  if (!std::isfinite(dhat) || !std::isfinite(kappa) || !std::isfinite(cell) || !(dhat > 0.0) || kappa < 0.0 ||
+      cell < 0.0)
+    return fail(c, PNCG_E_INVAL, "need dhat > 0, kappa >= 0, cell >= 0");
+  if (nP < 0 || nP > kMaxPlanes || (nP > 0 && !planes)) return fail(c, PNCG_E_INVAL, "0 <= nP <= 8 planes");
+  if (flags & ~3u) return fail(c, PNCG_E_INVAL, "unknown contact flag");
+  Planes P{};
+  P.n = nP;
+  for (int j = 0; j < nP; ++j) {
+    if (!finite_all(planes + 4 * j, 4)) return fail(c, PNCG_E_NONFINITE, "non-finite plane");
+    const double n2 = planes[4 * j] * planes[4 * j] + planes[4 * j + 1] * planes[4 * j + 1] +
+                      planes[4 * j + 2] * planes[4 * j + 2];
+    if (std::fabs(std::sqrt(n2) - 1.0) > 1e-6) return fail(c, PNCG_E_INVAL, "plane normal must have unit length");
+    for (int i = 0; i < 4; ++i) P.p[j][i] = planes[4 * j + i];
+  }
+  c->dhat = dhat;
+  c->kappa = kappa;
+  c->cell_user = cell;
+  c->planes = P;
+  c->cflags = flags;
+  c->skin = 4.0 * dhat;
+  // hash cell: the caller's, or the longest surface edge (>= 2 r) so a query
+  // visits at most a few cells per axis
+  double lmax = 0.0;
+  for (int e = 0; e < c->nE; ++e) {
+    const int a = c->edges[2 * e], b = c->edges[2 * e + 1];
+    double l2 = 0.0;
+    for (int i = 0; i < 3; ++i) l2 += (c->X[3 * a + i] - c->X[3 * b + i]) * (c->X[3 * a + i] - c->X[3 * b + i]);
+    lmax = std::max(lmax, std::sqrt(l2));
+  }
+  c->cell = cell > 0.0 ? cell : std::max(lmax, 2.0 * (dhat + c->skin));
+  c->n_excl_pt = c->n_excl_ee = 0;
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((flags & PNCG_CONTACT_SELF) && (flags & PNCG_CONTACT_REST_EXCLUDE) && c->nF + c->nE > 0) {
+    // same-object pairs closer than 1.5 dhat in the rest shape (Sec. 5.1)
+    int rc = stage_positions(c, c->X.data());
+    if (rc) return rc;
+    const double r = 1.5 * dhat;
+    long long n = 0, npt = 0;
+    if ((rc = build_candidates(c, c->d_x0, r, r, &n, &npt))) return rc;
+    std::vector<int2> pairs(n);
+    if (n) HIPCHK(c, hipMemcpyAsync(pairs.data(), c->d_cand, sizeof(int2) * n, hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync(c))) return rc;
+    std::vector<unsigned long long> kp, ke;
+    for (long long i = 0; i < n; ++i) {
+      const unsigned long long key = ((unsigned long long)(unsigned)pairs[i].x << 32) | (unsigned)pairs[i].y;
+      (i < npt ? kp : ke).push_back(key);
+    }
+    std::sort(kp.begin(), kp.end());
+    std::sort(ke.begin(), ke.end());
+    if (!kp.empty()) {
+      if ((rc = dmalloc(c, &c->d_excl_pt, kp.size()))) return rc;
+      HIPCHK(c, hipMemcpyAsync(c->d_excl_pt, kp.data(), 8 * kp.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    if (!ke.empty()) {
+      if ((rc = dmalloc(c, &c->d_excl_ee, ke.size()))) return rc;
+      HIPCHK(c, hipMemcpyAsync(c->d_excl_ee, ke.data(), 8 * ke.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    c->n_excl_pt = (int)kp.size();
+    c->n_excl_ee = (int)ke.size();
+    if ((rc = sync(c))) return rc;
+  }
+  return PNCG_OK;
+}
+
+int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, const double* gravity, uint32_t flags) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  if (iter_max < 1 || !std::isfinite(eps) || eps < 0.0 || (term != PNCG_TERM_DELTA_E && term != PNCG_TERM_GRAD_REL))
+    return fail(c, PNCG_E_INVAL, "need iter_max >= 1, eps >= 0, term DELTA_E or GRAD_REL");
+  if (gravity && !finite_all(gravity, 3)) return fail(c, PNCG_E_NONFINITE, "non-finite gravity");
+  if (flags & ~3u) return fail(c, PNCG_E_INVAL, "unknown solver flag");
+  c->iter_max = iter_max;
+  c->eps = eps;
+  c->term = term;
+  if (gravity) for (int i = 0; i < 3; ++i) c->grav[i] = gravity[i];
+  c->sflags = flags;
+  return PNCG_OK;
+}
+
+int pncg_set_dirichlet(pncg_ctx* c, int32_t n, const int32_t* idx, const double* target) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  if (n < 0 || (n > 0 && (!idx || !target))) return fail(c, PNCG_E_INVAL, "bad prescribed-vertex arrays");
+  std::vector<char> seen(c->nV, 0);
+  for (int i = 0; i < n; ++i) {
+    if (idx[i] < 0 || idx[i] >= c->nV) return fail(c, PNCG_E_INVAL, "prescribed index out of range");
+    if (seen[idx[i]]) return fail(c, PNCG_E_INVAL, "prescribed index repeated");
+    seen[idx[i]] = 1;
+  }
+  if (n > 0 && !finite_all(target, 3 * (size_t)n)) return fail(c, PNCG_E_NONFINITE, "non-finite target");
+  c->fixed.assign(idx, idx + n);
+  c->fixed_target.assign(target, target + 3 * (size_t)n);
+  HIPCHK(c, hipSetDevice(c->device));
+  return upload_flags_targets(c);
+}
+
+static int ensure_scal(pncg_ctx* c) {
+  if (c->scal_cap >= c->iter_max + 2) return PNCG_OK;
+  if (c->d_scal) dfree(c, c->d_scal);
+  c->d_scal = nullptr;
+  int rc = dmalloc(c, &c->d_scal, (size_t)c->iter_max + 2);
+  if (rc) return rc;
+  c->scal_cap = c->iter_max + 2;
+  HIPCHK(c, hipMemsetAsync(c->d_scal, 0, sizeof(IterScal) * c->scal_cap, c->stream));
+  return PNCG_OK;
+}
+
+int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
+                  pncg_stats* st) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !v || !x_out || !v_out) return fail(c, PNCG_E_INVAL, "NULL state pointer");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = ensure_scal(c))) return rc;
+  if (st) std::memset(st, 0, sizeof(*st));
+  return c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)
+                                    : step_impl<double>(c, x, v, h, x_out, v_out, st);
+}
+
+int pncg_step(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
+              pncg_stats* st) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !v || !x_out || !v_out) return fail(c, PNCG_E_INVAL, "NULL state pointer");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  const size_t n3 = 3 * (size_t)c->nV;
+  if (!finite_all(x, n3) || !finite_all(v, n3)) return fail(c, PNCG_E_NONFINITE, "non-finite x or v");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = upload_rows(c, x, c->d_io, c->nV)) || (rc = upload_rows(c, v, c->d_io + n3, c->nV))) return rc;
+  double* xo = c->d_io + 2 * n3;
+  double* vo = c->d_io + n3;  // v is consumed by the predictor before finalize writes here
+  rc = pncg_step_dev(c, c->d_io, c->d_io + n3, h, xo, vo, st);
+  if (rc < 0) return rc;
+  HIPCHK(c, hipMemcpyAsync(x_out, xo, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(v_out, vo, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  int rs = sync(c);
+  return rs ? rs : rc;
+}
+
+int pncg_energy(pncg_ctx* c, const double* x, const double* xt, double h, double* out) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !xt || !out) return fail(c, PNCG_E_INVAL, "NULL argument");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  return c->precision == PNCG_MIXED ? energy_impl<float>(c, x, xt, h, out) : energy_impl<double>(c, x, xt, h, out);
+}
+
+int pncg_gradient(pncg_ctx* c, const double* x, const double* xt, double h, double* g, double* diag) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !xt || !g) return fail(c, PNCG_E_INVAL, "NULL argument");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  return c->precision == PNCG_MIXED ? gradient_impl<float>(c, x, xt, h, g, diag)
+                                    : gradient_impl<double>(c, x, xt, h, g, diag);
+}
+
+int pncg_hvp(pncg_ctx* c, const double* x, const double* p, double h, double* hp, double* php) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !p || !php) return fail(c, PNCG_E_INVAL, "NULL argument");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  return c->precision == PNCG_MIXED ? hvp_impl<float>(c, x, p, h, hp, php) : hvp_impl<double>(c, x, p, h, hp, php);
+}
+
+int pncg_candidates(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, int64_t cap, int64_t* n) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !n || cap < 0 || (cap > 0 && !pairs)) return fail(c, PNCG_E_INVAL, "bad arguments");
+  if (kind < PNCG_KIND_PT || kind > PNCG_KIND_PG) return fail(c, PNCG_E_INVAL, "unknown kind");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = stage_positions(c, x))) return rc;
+  std::vector<int2> out;
+  if (kind == PNCG_KIND_PG) {
+    const long long capd = (long long)c->nSV * std::max(c->planes.n, 1);
+    if (capd > c->cand_cap) {
+      int2* nc = nullptr;
+      if ((rc = dmalloc(c, &nc, (size_t)std::max<long long>(capd, 1024)))) return rc;
+      dfree(c, c->d_cand);
+      c->d_cand = nc;
+      c->cand_cap = std::max<long long>(capd, 1024);
+    }
+    Broad B = make_broad(c);
+    plane_candidates(B, c->d_x0, c->planes, c->dhat, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->h_n, c->d_ncand, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync(c))) return rc;
+    const long long m = c->h_n[0];
+    out.resize(m);
+    if (m) HIPCHK(c, hipMemcpyAsync(out.data(), c->d_cand, sizeof(int2) * m, hipMemcpyDeviceToHost, c->stream));
+  } else if ((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0) {
+    long long m = 0, mpt = 0;
+    if ((rc = build_candidates(c, c->d_x0, c->dhat, -1.0, &m, &mpt))) return rc;
+    const long long a = kind == PNCG_KIND_PT ? 0 : mpt, b = kind == PNCG_KIND_PT ? mpt : m;
+    out.resize(b - a);
+    if (b > a) HIPCHK(c, hipMemcpyAsync(out.data(), c->d_cand + a, sizeof(int2) * (b - a), hipMemcpyDeviceToHost, c->stream));
+  }
+  if ((rc = sync(c))) return rc;
+  std::sort(out.begin(), out.end(), [](const int2& p, const int2& q) { return p.x < q.x || (p.x == q.x && p.y < q.y); });
+  *n = (int64_t)out.size();
+  if ((int64_t)out.size() > cap) return fail(c, PNCG_E_CAPACITY, "pairs buffer too small; *n holds the size needed");
+  for (size_t i = 0; i < out.size(); ++i) {
+    pairs[2 * i] = out[i].x;
+    pairs[2 * i + 1] = out[i].y;
+  }
+  return PNCG_OK;
+}
+
+int pncg_min_distance(pncg_ctx* c, const double* x, double* dmin, double* jmin) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !dmin || !jmin) return fail(c, PNCG_E_INVAL, "NULL argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = stage_positions(c, x))) return rc;
+  const bool self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0;
+  if (self) {
+    if ((rc = build_candidates(c, c->d_x0, 10.0 * c->dhat, -1.0, nullptr, nullptr))) return rc;
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->d_ncand, 0, 2 * sizeof(long long), c->stream));
+  }
+  std::vector<double> part(2 * (size_t)c->grid);
+  if (c->precision == PNCG_MIXED) {
+    Args<float> A = make_args<float>(c, 1.0);
+    A.self = self;
+    launch_audit<float>(A, c->d_part_dir, c->stream);
+  } else {
+    Args<double> A = make_args<double>(c, 1.0);
+    A.self = self;
+    launch_audit<double>(A, c->d_part_dir, c->stream);
+  }
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->d_part_dir, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+  if ((rc = sync(c))) return rc;
+  double d = HUGE_VAL, j = HUGE_VAL;
+  for (int b = 0; b < c->grid; ++b) {
+    d = std::min(d, part[2 * b]);
+    j = std::min(j, part[2 * b + 1]);
+  }
+  *dmin = d;
+  *jmin = j;
+  return PNCG_OK;
+}
+
+}  // extern "C"

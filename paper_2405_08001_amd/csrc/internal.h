@@ -1,0 +1,106 @@
+// Internal layout shared by the kernels and the host runtime of libpncg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "device_math.h"
+
+namespace pncg {
+
+constexpr int kMaxPlanes = 8;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per block of every kernel
+constexpr int kMaxGrid = 512;        // blocks of the grid-stride kernels (= partial count)
+
+// per-vertex flags
+constexpr uint8_t kFixed = 1;
+constexpr uint8_t kSurface = 2;
+
+// error bits raised by kernels
+constexpr int kErrInverted = 1;
+constexpr int kErrPenetration = 2;
+constexpr int kErrNonfinite = 4;
+constexpr int kErrCapacity = 8;
+
+template <typename R> struct R4T;
+template <> struct R4T<float> { using type = float4; };
+template <> struct R4T<double> { using type = double4; };
+template <typename R> using R4 = typename R4T<R>::type;
+
+struct Planes {
+  int n;
+  double p[kMaxPlanes][4];   // n0 n1 n2 o  (half-space n.x >= o)
+};
+
+// Scalars of iteration k.  Each field has one writer kernel (block 0 of it):
+//   first kernel of k: alpha, dE, dE0, D, stop, pause, a_up
+//   direction kernel of k: beta, gTp, gnorm, dir_stop, restart, n_active
+// and is read only by kernels launched after its writer.
+struct IterScal {
+  double alpha, dE, dE0, D;
+  double beta, gTp, gnorm;
+  double n_active;
+  int stop, pause, a_up, dir_stop, restart, pad;
+};
+
+// Step status, written when the step ends or pauses (one writer at a time).
+struct StepStatus {
+  int stopped;      // the step has ended
+  int final_k;      // iteration whose x buffer (final_k & 1) holds x^{t+1}
+  int iters;        // position updates made
+  int reason;       // 0 dE rule, 1 gradient rule, 2 cap, 3 zero/unbounded
+  int paused_at;    // -1, or iteration whose candidate list must be rebuilt
+  int err;          // kErr* bits
+  int a_up_hits;
+  int pad;
+  double g0, gk, dE0, last_dE;
+  double n_active;
+  long long n_cand;   // candidates of the last list (written by the list builder)
+  long long n_pt;     // of which point-triangle
+};
+
+// Everything a solver kernel touches.  Passed by value.
+template <typename R>
+struct Args {
+  // mesh
+  int nV, nT;
+  const ElemRec<R>* elem;
+  const int* inc;          // per lane: e * 4 + a, -1 padding, -2 vertex without tets
+  const int* inc_vert;     // per lane: vertex, -1 padding
+  int nWaves;
+  const double* mass;
+  const uint8_t* vflag;
+  const double4* target;   // prescribed positions (valid where kFixed)
+  // state
+  double4* x0;             // x buffer of even iterations
+  double4* x1;             // x buffer of odd iterations
+  double4* xt;             // predictor
+  double4* xstart;         // x^t
+  R4<R>* g;                // gradient of the last evaluation
+  R4<R>* pg;               // P g
+  R4<R>* p0;               // direction buffers (p_k lives in p[k & 1])
+  R4<R>* p1;
+  double* acc;             // [nV][8] contact accumulators: g xyz, diag xyz
+  // contact
+  int self;                // point-triangle / edge-edge barriers on
+  const int2* cand;        // candidate pairs: (v, f) point-triangle then (e1, e2) edge-edge
+  const long long* ncand;  // device: [0] total, [1] point-triangle count
+  const int* tris;         // [nF][3]
+  const int* edges;        // [nE][2]
+  Planes planes;
+  double dhat, kappa, h, h2, skin;
+  int has_prims;           // any collision primitive (planes or self contact)
+  // solver
+  int iter_max, term;
+  double eps;
+  unsigned flags;
+  IterScal* scal;
+  StepStatus* status;
+  double* part_grad;       // [kMaxGrid][8]
+  double* part_dir;        // [kMaxGrid][4]
+  double* part_narrow;     // [kMaxGrid]
+  int grid;
+};
+
+}  // namespace pncg

@@ -1,0 +1,929 @@
+// Per-iteration kernels of the PNCG time step (Algorithm 1, Sec. 4) and the
+// query kernels built from the same pieces.
+//
+// One iteration k is two launches (three with point-triangle / edge-edge
+// contact):
+//   [narrow]  candidate pairs at x_k -> barrier gradient and diagonal,
+//             scattered with float64 atomics into per-vertex accumulators
+//   grad      vertex-centric element sweep: every lane evaluates one
+//             (tet, corner) incidence, a wave-segmented sum gives each
+//             vertex its complete gradient and diag(H) without atomics;
+//             the vertex's lane adds inertia, planes and contact terms and
+//             the dot products for beta (Sec. 4.1-4.2)
+//   dir       beta from the grad partials; p_{k+1} = -P g + beta p_k is
+//             recomputed on the fly wherever a tet or pair needs it, so the
+//             element and pair parts of p^T H p run in the same launch as
+//             the per-vertex update of p (Sec. 4.3)
+// The first launch of iteration k + 1 reduces the dir partials into alpha
+// (equations upper, alpha), applies x_{k+1} = x_k + alpha p while reading
+// positions lazily, and evaluates the stop test (Sec. 4.4).
+//
+// Grid-wide reductions never use atomics on one address: each block writes
+// its partial sums and the next launch's blocks re-reduce them in a fixed
+// order, which is deterministic and costs no extra launch.
+#include <cfloat>
+#include <climits>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace pncg {
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
+  return v;
+}
+
+// Sum (kind 0) or max (kind 1) of N per-thread values over the block; the
+// result is returned to every thread.  sh must hold 4 * N doubles.
+template <int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kind)[N], double* sh) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = kind[i] ? wave_max(v[i]) : wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[w * N + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double r = sh[i];
+    for (int j = 1; j < kBlock / kWave; ++j) r = kind[i] ? fmax(r, sh[j * N + i]) : r + sh[j * N + i];
+    v[i] = r;
+  }
+  __syncthreads();
+}
+
+// Re-reduce the per-block partials [n][stride] of the previous launch.
+template <int N>
+__device__ __forceinline__ void reduce_partials(const double* part, int stride, int n, const int (&kind)[N],
+                                                double (&out)[N], double* sh) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = kind[i] ? 0.0 : 0.0;
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double v = part[j * stride + i];
+      out[i] = kind[i] ? fmax(out[i], v) : out[i] + v;
+    }
+  }
+  block_reduce<N>(out, kind, sh);
+}
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ V3<double> ld3(const double4* a, int i) {
+  double4 v = a[i];
+  return mk3(v.x, v.y, v.z);
+}
+__device__ __forceinline__ void st3(double4* a, int i, V3<double> v) { a[i] = make_double4(v.x, v.y, v.z, 0.0); }
+
+template <typename R>
+__device__ __forceinline__ V3<R> ldr(const R4<R>* a, int i) {
+  R4<R> v = a[i];
+  return mk3(v.x, v.y, v.z);
+}
+template <typename R>
+__device__ __forceinline__ void str(R4<R>* a, int i, V3<R> v) {
+  R4<R> o;
+  o.x = v.x; o.y = v.y; o.z = v.z; o.w = R(0);
+  a[i] = o;
+}
+
+// the direction p_{k+1} = -P g + beta p_k, one rounding per component
+template <typename R>
+__device__ __forceinline__ V3<R> direction(V3<R> pg, V3<R> pprev, R beta) {
+  return mk3(fma(beta, pprev.x, -pg.x), fma(beta, pprev.y, -pg.y), fma(beta, pprev.z, -pg.z));
+}
+
+__device__ __forceinline__ double plane_dist(const double* pl, V3<double> x) {
+#pragma clang fp contract(off)
+  return ((pl[0] * x.x + pl[1] * x.y) + pl[2] * x.z) - pl[3];
+}
+
+__device__ __forceinline__ void raise_err(StepStatus* st, int bit) { atomicOr(&st->err, bit); }
+
+// x of iteration k, either materialised in x[k & 1] or, inside the launch
+// that applies the update, lazily as x_{k-1} + alpha p_k.
+template <typename R>
+struct PosReader {
+  const double4* xsrc;   // x_{k-1} (lazy) or x_k (direct)
+  const R4<R>* p;        // p_k (lazy only)
+  double alpha;
+  int lazy;
+  __device__ __forceinline__ V3<double> operator()(int v) const {
+    V3<double> x = ld3(xsrc, v);
+    if (lazy) {
+      R4<R> q = p[v];
+      x = mk3(fma(alpha, double(q.x), x.x), fma(alpha, double(q.y), x.y), fma(alpha, double(q.z), x.z));
+    }
+    return x;
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ double4* xbuf(const Args<R>& A, int k) { return (k & 1) ? A.x1 : A.x0; }
+template <typename R>
+__device__ __forceinline__ R4<R>* pbuf(const Args<R>& A, int k) { return (k & 1) ? A.p1 : A.p0; }
+
+// --------------------------------------------------------------- predict
+// xt = x^t + h v^t + h^2 g (Sec. 3); x_0 = x^t with prescribed vertices at
+// their targets (Algorithm 1, first line).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_predict(Args<R> A, const double* x_in, const double* v_in, double3 grav) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    StepStatus* s = A.status;
+    s->stopped = 0; s->final_k = 0; s->iters = 0; s->reason = 2; s->paused_at = -1; s->err = 0;
+    s->a_up_hits = 0; s->g0 = 0; s->gk = 0; s->dE0 = 0; s->last_dE = 0; s->n_active = 0;
+  }
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+    V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
+    V3<double> vel = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
+    if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(vel.x) && isfinite(vel.y) && isfinite(vel.z)))
+      raise_err(A.status, kErrNonfinite);
+    st3(A.xstart, v, x);
+    V3<double> xt = x + A.h * vel;
+    xt = xt + A.h2 * mk3(grav.x, grav.y, grav.z);
+    st3(A.xt, v, xt);
+    if (A.vflag[v] & kFixed) x = ld3(A.target, v);
+    st3(A.x0, v, x);
+    str<R>(A.g, v, mk3(R(0), R(0), R(0)));
+    str<R>(A.p0, v, mk3(R(0), R(0), R(0)));
+    if (A.self) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) A.acc[8 * v + j] = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------ first-launch prologue
+enum FirstMode { kModeNormal = 0, kModeFinish = 1, kModeResume = 2 };
+
+struct FirstPro {
+  double alpha;
+  int materialize;   // apply x_k = x_{k-1} + alpha p_k in this launch
+  int work;          // evaluate the iteration's terms at x_k
+};
+
+template <typename R>
+__device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh) {
+  FirstPro fp{0.0, 0, 1};
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  if (k == 0 || mode == kModeResume) {
+    if (leader) {
+      IterScal& s = A.scal[k];
+      if (k == 0) {
+        s.alpha = 0; s.dE = 0; s.dE0 = 0; s.a_up = 0;
+      }
+      s.D = 0; s.stop = 0; s.pause = 0;
+      A.status->paused_at = -1;
+    }
+    return fp;
+  }
+  const IterScal prev = A.scal[k - 1];
+  if (prev.stop || prev.dir_stop || prev.pause) {
+    if (leader) { A.scal[k].stop = 1; A.scal[k].pause = 0; }
+    fp.work = 0;
+    return fp;
+  }
+  const int kind[3] = {0, 1, 1};
+  double r[3];
+  reduce_partials<3>(A.part_dir, 4, A.grid, kind, r, sh);
+  const double pHp = r[0], pmv = r[1], pmc = r[2];
+  const double gTp = prev.gTp;
+  const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
+  const double pm = (A.flags & 2u) ? pmc : pmv;
+  const double aup = (A.has_prims && pm > 0.0) ? A.dhat / (2.0 * pm) : HUGE_VAL;
+  const double alpha = fmin(aup, abar);
+  IterScal s{};
+  s.a_up = prev.a_up + (aup < abar ? 1 : 0);
+  if (!isfinite(alpha)) {
+    if (leader) {
+      s.alpha = 0; s.dE = 0; s.dE0 = prev.dE0; s.D = prev.D; s.stop = 1; s.pause = 0;
+      A.scal[k].alpha = s.alpha; A.scal[k].dE = 0; A.scal[k].dE0 = s.dE0; A.scal[k].D = s.D;
+      A.scal[k].stop = 1; A.scal[k].pause = 0; A.scal[k].a_up = s.a_up;
+      StepStatus* st = A.status;
+      st->stopped = 1; st->final_k = k - 1; st->iters = k - 1; st->reason = 3;
+      st->gk = prev.gnorm; st->dE0 = prev.dE0; st->last_dE = prev.dE; st->a_up_hits = prev.a_up;
+      st->n_active = prev.n_active;
+    }
+    fp.work = 0;
+    return fp;
+  }
+  const double dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
+  const double dE0 = (k == 1) ? dE : prev.dE0;
+  const double D = prev.D + alpha * pmv;
+  int stop = 0, reason = 0;
+  if (A.term == 0 && dE < A.eps * dE0) { stop = 1; reason = 0; }
+  else if (mode == kModeFinish) { stop = 1; reason = 2; }
+  const int pause = (!stop && A.self && D > 0.5 * A.skin) ? 1 : 0;
+  if (leader) {
+    IterScal& o = A.scal[k];
+    o.alpha = alpha; o.dE = dE; o.dE0 = dE0; o.D = D; o.stop = stop; o.pause = pause; o.a_up = s.a_up;
+    o.dir_stop = 0;
+    if (stop) {
+      StepStatus* st = A.status;
+      st->stopped = 1; st->final_k = k; st->iters = k; st->reason = reason;
+      st->gk = prev.gnorm; st->dE0 = dE0; st->last_dE = dE; st->a_up_hits = s.a_up;
+      st->n_active = prev.n_active;
+    }
+    if (pause) A.status->paused_at = k;
+  }
+  fp.alpha = alpha;
+  fp.materialize = 1;
+  fp.work = (stop || pause) ? 0 : 1;
+  return fp;
+}
+
+// ----------------------------------------------------------- narrow phase
+// One candidate pair at positions from `pos`: closest points (Sec. 3.2),
+// returns false if inactive.  Penetration raises the error bit.
+template <typename R, typename Pos>
+__device__ __forceinline__ bool pair_closest(const Args<R>& A, int q, const Pos& pos, int (&iv)[4], Closest& c,
+                                             long long npt) {
+  int2 pr = A.cand[q];
+  V3<double> X[4];
+  if (q < npt) {
+    iv[0] = pr.x;
+    iv[1] = A.tris[3 * pr.y]; iv[2] = A.tris[3 * pr.y + 1]; iv[3] = A.tris[3 * pr.y + 2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = pos(iv[i]);
+    c = closest_pt(X[0], X[1], X[2], X[3]);
+  } else {
+    iv[0] = A.edges[2 * pr.x]; iv[1] = A.edges[2 * pr.x + 1];
+    iv[2] = A.edges[2 * pr.y]; iv[3] = A.edges[2 * pr.y + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = pos(iv[i]);
+    c = closest_ee(X[0], X[1], X[2], X[3]);
+  }
+  if (!(c.d > 0.0)) {
+    raise_err(A.status, kErrPenetration);
+    return false;
+  }
+  return c.d < A.dhat;
+}
+
+// coefficient of (J t)(J t)^T and of J J^T in kappa * d2b/dx2 (eq9, or its
+// PSD projection (b''/d^2)(J t)(J t)^T when not BARRIER_FULL)
+template <typename R>
+__device__ __forceinline__ void pair_hess_coefs(const Args<R>& A, double d, double& ca, double& cb) {
+  const double b1 = barrier_db(d, A.dhat), b2 = barrier_d2b(d, A.dhat);
+  if (A.flags & 1u) {
+    ca = A.kappa * (b2 / (d * d) - b1 / (d * d * d));
+    cb = A.kappa * b1 / d;
+  } else {
+    ca = A.kappa * b2 / (d * d);
+    cb = 0.0;
+  }
+}
+
+// First launch of an iteration with self contact: apply the pending update,
+// then barrier gradient + diagonal of every active pair into acc (eq8,
+// eq10, eq11).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_narrow(Args<R> A, int k, int mode) {
+  __shared__ double sh[4 * 8];
+  FirstPro fp = first_prologue(A, k, mode, sh);
+  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  double4* xcur = xbuf(A, k);
+  const double4* xprev = xbuf(A, k - 1);
+  const R4<R>* pk = pbuf(A, k);
+  if (fp.materialize) {
+    for (int v = tid; v < A.nV; v += stride) {
+      V3<double> x = ld3(xprev, v);
+      R4<R> q = pk[v];
+      st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
+    }
+  }
+  if (!fp.work) return;
+  PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
+  const long long nq = A.ncand[0], npt = A.ncand[1];
+  double nact = 0.0;
+  for (long long q = tid; q < nq; q += stride) {
+    int iv[4];
+    Closest c;
+    if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+    nact += 1.0;
+    const double d = c.d;
+    const double cg = A.kappa * barrier_db(d, A.dhat) / d;
+    double ca, cb;
+    pair_hess_coefs(A, d, ca, cb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double ci = c.c[i];
+      double* a = A.acc + 8 * iv[i];
+      const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
+      atomicAdd(a + 0, cg * tx);
+      atomicAdd(a + 1, cg * ty);
+      atomicAdd(a + 2, cg * tz);
+      const double dj = cb * ci * ci;
+      atomicAdd(a + 3, ca * tx * tx + dj);
+      atomicAdd(a + 4, ca * ty * ty + dj);
+      atomicAdd(a + 5, ca * tz * tz + dj);
+    }
+  }
+  double v[1] = {nact};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) A.part_narrow[blockIdx.x] = v[0];
+}
+
+// ---------------------------------------------------- vertex-centric sweep
+// Wave-segmented suffix sum: lanes of one vertex are contiguous inside a
+// wave; afterwards the vertex's first lane holds the segment total.
+template <typename R>
+__device__ __forceinline__ void seg_sum(int myv, R (&s)[6]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int off = 1; off < kWave; off <<= 1) {
+    int ov = __shfl_down(myv, off, kWave);
+    R o[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) o[i] = __shfl_down(s[i], off, kWave);
+    if (lane + off < kWave && ov == myv) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) s[i] += o[i];
+    }
+  }
+}
+
+enum GradMode { kGradFirst = 0, kGradDirect = 1, kGradQuery = 2 };
+
+// Element gradient and diagonal of one (tet, corner) lane; false if the lane
+// holds no tet.  Without the h^2 factor.
+template <typename R, typename Pos>
+__device__ __forceinline__ bool lane_elem(const Args<R>& A, int code, const Pos& pos, V3<R>& g, V3<R>& dg) {
+  if (code < 0) return false;
+  const int e = code >> 2, a = code & 3;
+  const ElemRec<R> rec = A.elem[e];
+  Kin<R> kin = kinematics<R>(rec.B, pos(rec.v[0]), pos(rec.v[1]), pos(rec.v[2]), pos(rec.v[3]));
+  if (!(kin.J > R(0))) {
+    raise_err(A.status, kErrInverted);
+    g = mk3(R(0), R(0), R(0));
+    dg = g;
+    return true;
+  }
+  nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, a), g, dg);
+  return true;
+}
+
+// Vertex terms at x_v: inertia m (x - xt), plane barriers (surface
+// vertices), contact accumulators; returns g and diag in float64.
+template <typename R>
+__device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double> x, double (&gd)[3], double (&dd)[3],
+                                             double& nplane, bool zero_acc) {
+  const double m = A.mass[v];
+  V3<double> xt = ld3(A.xt, v);
+  gd[0] += m * (x.x - xt.x); gd[1] += m * (x.y - xt.y); gd[2] += m * (x.z - xt.z);
+  dd[0] += m; dd[1] += m; dd[2] += m;
+  const uint8_t fl = A.vflag[v];
+  if (fl & kSurface) {
+    for (int j = 0; j < A.planes.n; ++j) {
+      const double* pl = A.planes.p[j];
+      const double d = plane_dist(pl, x);
+      if (d < A.dhat) {
+        if (!(d > 0.0)) { raise_err(A.status, kErrPenetration); continue; }
+        const double b1 = A.kappa * barrier_db(d, A.dhat), b2 = A.kappa * barrier_d2b(d, A.dhat);
+        gd[0] += b1 * pl[0]; gd[1] += b1 * pl[1]; gd[2] += b1 * pl[2];
+        dd[0] += b2 * pl[0] * pl[0]; dd[1] += b2 * pl[1] * pl[1]; dd[2] += b2 * pl[2] * pl[2];
+        nplane += 1.0;
+      }
+    }
+  }
+  if (A.self) {
+    double* a = A.acc + 8 * v;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { gd[j] += a[j]; dd[j] += a[3 + j]; }
+    if (zero_acc) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a[j] = 0.0;
+    }
+  }
+}
+
+// Gradient, diag(H) and the dot products for beta (Sec. 4.1-4.2).
+// Mode kGradFirst: first launch of the iteration (no self contact): applies
+// the pending update lazily.  kGradDirect: x_k already materialised.
+// kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kBlock) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
+  __shared__ double sh[4 * 8];
+  FirstPro fp{0.0, 0, 1};
+  if (MODE == kGradFirst) {
+    fp = first_prologue(A, k, mode, sh);
+  } else if (MODE == kGradDirect) {
+    const IterScal s = A.scal[k];
+    if (s.stop || s.pause) return;
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * kBlock) >> 6;
+  double4* xcur = MODE == kGradQuery ? A.x0 : xbuf(A, k);
+  const double4* xprev = xbuf(A, k - 1);
+  const R4<R>* pk = pbuf(A, k);
+  if (MODE == kGradFirst && fp.materialize && !fp.work) {
+    // stop test passed: only apply the last update
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+      V3<double> x = ld3(xprev, v);
+      R4<R> q = pk[v];
+      st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
+    }
+    return;
+  }
+  if (!fp.work) return;
+  PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
+  double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int w = wid; w < A.nWaves; w += nw) {
+    const int idx = w * kWave + lane;
+    const int code = A.inc[idx];
+    const int myv = A.inc_vert[idx];
+    V3<R> g, dg;
+    R s[6];
+    if (lane_elem(A, code, pos, g, dg)) {
+      s[0] = g.x; s[1] = g.y; s[2] = g.z; s[3] = dg.x; s[4] = dg.y; s[5] = dg.z;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) s[i] = R(0);
+    }
+    seg_sum<R>(myv, s);
+    const int upv = __shfl_up(myv, 1, kWave);
+    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    // this lane is the vertex's first lane
+    const int v = myv;
+    const V3<double> x = pos(v);
+    if (MODE == kGradFirst && fp.materialize) st3(xcur, v, x);
+    double gd[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
+    double dd[3] = {A.h2 * double(s[3]), A.h2 * double(s[4]), A.h2 * double(s[5])};
+    vertex_terms(A, v, x, gd, dd, dots[6], MODE != kGradQuery);
+    if (A.vflag[v] & kFixed) {
+      gd[0] = gd[1] = gd[2] = 0.0;
+      dd[0] = dd[1] = dd[2] = 1.0;
+    }
+    if (MODE == kGradQuery) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { out_g[3 * v + j] = gd[j]; if (out_d) out_d[3 * v + j] = dd[j]; }
+      continue;
+    }
+    V3<R> gR = mk3(R(gd[0]), R(gd[1]), R(gd[2]));
+    V3<R> pgR = mk3(R(gd[0] / dd[0]), R(gd[1] / dd[1]), R(gd[2] / dd[2]));
+    V3<R> gpR = ldr<R>(A.g, v);
+    V3<R> ppR = ldr<R>(pk, v);
+    str<R>(A.g, v, gR);
+    str<R>(A.pg, v, pgR);
+    const double g3[3] = {double(gR.x), double(gR.y), double(gR.z)};
+    const double pg3[3] = {double(pgR.x), double(pgR.y), double(pgR.z)};
+    const double gp3[3] = {double(gpR.x), double(gpR.y), double(gpR.z)};
+    const double pp3[3] = {double(ppR.x), double(ppR.y), double(ppR.z)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double P = 1.0 / dd[j];
+      const double y = g3[j] - gp3[j];
+      dots[0] += g3[j] * g3[j];
+      dots[1] += g3[j] * pg3[j];
+      dots[2] += g3[j] * P * y;
+      dots[3] += y * pp3[j];
+      dots[4] += y * P * y;
+      dots[5] += pp3[j] * g3[j];
+    }
+  }
+  if (MODE == kGradQuery) return;
+  const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  block_reduce<8>(dots, kind, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) A.part_grad[blockIdx.x * 8 + i] = dots[i];
+  }
+}
+
+// ------------------------------------------------------ direction + pHp
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
+  __shared__ double sh[4 * 8];
+  const IterScal s = A.scal[k];
+  if (s.stop || s.pause) return;
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  double r[8];
+  {
+    const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    reduce_partials<8>(A.part_grad, 8, A.grid, kind, r, sh);
+  }
+  double nact = r[6];
+  if (A.self) {
+    const int kind[1] = {0};
+    double q[1];
+    reduce_partials<1>(A.part_narrow, 1, A.grid, kind, q, sh);
+    nact += q[0];
+  }
+  const double gg = r[0], gPg = r[1], gPy = r[2], yp = r[3], yPy = r[4], pg = r[5];
+  const double gnorm = sqrt(gg);
+  const double g0 = k == 0 ? gnorm : A.status->g0;
+  int dir_stop = 0, reason = 0, restart = 0;
+  double beta = 0.0;
+  if (A.term == 1 && gnorm <= A.eps * g0) { dir_stop = 1; reason = 1; }
+  if (k > 0 && yp != 0.0) {
+    beta = gPy / yp - (yPy / yp) * (pg / yp);
+    if (!isfinite(beta)) beta = 0.0;
+  }
+  double gTp = -gPg + beta * pg;
+  if (!(gTp < 0.0)) {
+    restart = 1;
+    beta = 0.0;
+    gTp = -gPg;
+  }
+  if (!dir_stop && gTp == 0.0) { dir_stop = 1; reason = 3; }
+  if (leader) {
+    IterScal& o = A.scal[k];
+    o.beta = beta; o.gTp = gTp; o.gnorm = gnorm; o.dir_stop = dir_stop; o.restart = restart; o.n_active = nact;
+    if (k == 0) A.status->g0 = gnorm;
+    if (dir_stop) {
+      StepStatus* st = A.status;
+      st->stopped = 1; st->final_k = k; st->iters = k; st->reason = reason;
+      st->gk = gnorm; st->dE0 = s.dE0; st->last_dE = s.dE; st->a_up_hits = s.a_up; st->n_active = nact;
+    }
+  }
+  if (dir_stop) return;
+  const R rb = R(beta);
+  const double4* xk = xbuf(A, k);
+  const R4<R>* pk = pbuf(A, k);
+  R4<R>* pn = pbuf(A, k + 1);
+  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  double acc_pHp = 0.0, pmv = 0.0, pmc = 0.0;
+  // tets: element p^T H p with p recomputed at the four corners
+  double el = 0.0;
+  for (int e = tid; e < A.nT; e += stride) {
+    const ElemRec<R> rec = A.elem[e];
+    V3<R> P[4];
+    V3<double> X[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = rec.v[i];
+      X[i] = ld3(xk, v);
+      P[i] = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), rb);
+    }
+    Kin<R> kin = kinematics<R>(rec.B, X[0], X[1], X[2], X[3]);
+    V3<R> d[3];
+    dF_cols(rec.B, P[0], P[1], P[2], P[3], d);
+    el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+  }
+  acc_pHp += A.h2 * el;
+  // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
+  for (int v = tid; v < A.nV; v += stride) {
+    V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), rb);
+    str<R>(pn, v, p);
+    const double px = p.x, py = p.y, pz = p.z;
+    const double p2 = px * px + py * py + pz * pz;
+    acc_pHp += A.mass[v] * p2;
+    pmv = fmax(pmv, sqrt(p2));
+    pmc = fmax(pmc, fmax(fabs(px), fmax(fabs(py), fabs(pz))));
+    if ((A.vflag[v] & kSurface) && A.planes.n > 0) {
+      const V3<double> x = ld3(xk, v);
+      for (int j = 0; j < A.planes.n; ++j) {
+        const double* pl = A.planes.p[j];
+        const double d = plane_dist(pl, x);
+        if (d > 0.0 && d < A.dhat) {
+          const double np = pl[0] * px + pl[1] * py + pl[2] * pz;
+          acc_pHp += A.kappa * barrier_d2b(d, A.dhat) * np * np;
+        }
+      }
+    }
+  }
+  // pairs: kappa [ca (sum_i c_i p_i . t)^2 + cb |sum_i c_i p_i|^2] (eq12, eq13)
+  if (A.self) {
+    PosReader<R> pos{xk, pk, 0.0, 0};
+    const long long nq = A.ncand[0], npt = A.ncand[1];
+    for (long long q = tid; q < nq; q += stride) {
+      int iv[4];
+      Closest c;
+      if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+      double ca, cb;
+      pair_hess_coefs(A, c.d, ca, cb);
+      V3<double> sp = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        V3<R> p = direction(ldr<R>(A.pg, iv[i]), ldr<R>(pk, iv[i]), rb);
+        sp = sp + c.c[i] * cast3<double>(p);
+      }
+      const double st = dot(sp, c.t);
+      acc_pHp += ca * st * st + cb * dot(sp, sp);
+    }
+  }
+  double v[3] = {acc_pHp, pmv, pmc};
+  const int kind[3] = {0, 1, 1};
+  block_reduce<3>(v, kind, sh);
+  if (threadIdx.x == 0) {
+    A.part_dir[blockIdx.x * 4 + 0] = v[0];
+    A.part_dir[blockIdx.x * 4 + 1] = v[1];
+    A.part_dir[blockIdx.x * 4 + 2] = v[2];
+  }
+}
+
+// --------------------------------------------------------------- finalize
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_finalize(Args<R> A, double* x_out, double* v_out) {
+  const int fk = A.status->final_k;
+  const double4* xf = xbuf(A, fk);
+  const double ih = 1.0 / A.h;
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+    V3<double> x = ld3(xf, v), x0 = ld3(A.xstart, v);
+    if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z))) raise_err(A.status, kErrNonfinite);
+    x_out[3 * v] = x.x; x_out[3 * v + 1] = x.y; x_out[3 * v + 2] = x.z;
+    v_out[3 * v] = (x.x - x0.x) * ih; v_out[3 * v + 1] = (x.y - x0.y) * ih; v_out[3 * v + 2] = (x.z - x0.z) * ih;
+  }
+}
+
+// ----------------------------------------------------------------- queries
+// Load query positions (row-major [nV][3]) into x0 and the predictor into xt.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_load_query(Args<R> A, const double* x, const double* xt, const double* p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.status->err = 0;
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+    V3<double> xv = mk3(x[3 * v], x[3 * v + 1], x[3 * v + 2]);
+    if (!(isfinite(xv.x) && isfinite(xv.y) && isfinite(xv.z))) raise_err(A.status, kErrNonfinite);
+    st3(A.x0, v, xv);
+    if (xt) st3(A.xt, v, mk3(xt[3 * v], xt[3 * v + 1], xt[3 * v + 2]));
+    if (p) {
+      const bool fixed = A.vflag[v] & kFixed;
+      str<R>(A.p0, v, fixed ? mk3(R(0), R(0), R(0)) : mk3(R(p[3 * v]), R(p[3 * v + 1]), R(p[3 * v + 2])));
+    }
+    if (A.self) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) A.acc[8 * v + j] = 0.0;
+    }
+  }
+}
+
+// Pair terms at x0 for queries: WHAT = 0 gradient + diag into acc, 1 energy
+// partials, 2 H p into acc (acc[0..2]) and p^T H p partials (p in p0).
+template <typename R, int WHAT>
+__global__ void __launch_bounds__(kBlock) k_pairs_query(Args<R> A, double* part) {
+  __shared__ double sh[4 * 2];
+  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  PosReader<R> pos{A.x0, A.p0, 0.0, 0};
+  const long long nq = A.ncand[0], npt = A.ncand[1];
+  double sum = 0.0;
+  for (long long q = tid; q < nq; q += stride) {
+    int iv[4];
+    Closest c;
+    if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+    const double d = c.d;
+    if (WHAT == 1) {
+      sum += A.kappa * barrier_b(d, A.dhat);
+      continue;
+    }
+    double ca, cb;
+    pair_hess_coefs(A, d, ca, cb);
+    if (WHAT == 0) {
+      const double cg = A.kappa * barrier_db(d, A.dhat) / d;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double ci = c.c[i];
+        double* a = A.acc + 8 * iv[i];
+        const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
+        atomicAdd(a + 0, cg * tx); atomicAdd(a + 1, cg * ty); atomicAdd(a + 2, cg * tz);
+        const double dj = cb * ci * ci;
+        atomicAdd(a + 3, ca * tx * tx + dj); atomicAdd(a + 4, ca * ty * ty + dj); atomicAdd(a + 5, ca * tz * tz + dj);
+      }
+    } else {
+      V3<double> sp = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sp = sp + c.c[i] * cast3<double>(ldr<R>(A.p0, iv[i]));
+      const double st = dot(sp, c.t);
+      sum += ca * st * st + cb * dot(sp, sp);
+      // (H p)_i = c_i [ca (t . sp) t + cb sp]
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double ci = c.c[i];
+        double* a = A.acc + 8 * iv[i];
+        atomicAdd(a + 0, ci * (ca * st * c.t.x + cb * sp.x));
+        atomicAdd(a + 1, ci * (ca * st * c.t.y + cb * sp.y));
+        atomicAdd(a + 2, ci * (ca * st * c.t.z + cb * sp.z));
+      }
+    }
+  }
+  double v[1] = {sum};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Energy of elements, inertia and planes at x0 (partials per block).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_energy(Args<R> A, double* part) {
+  __shared__ double sh[4 * 2];
+  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  double el = 0.0, vt = 0.0;
+  for (int e = tid; e < A.nT; e += stride) {
+    const ElemRec<R> rec = A.elem[e];
+    Kin<R> kin = kinematics<R>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]), ld3(A.x0, rec.v[3]));
+    if (!(kin.J > R(0))) { raise_err(A.status, kErrInverted); continue; }
+    el += double(nh_energy(kin, rec.vmu, rec.vlam));
+  }
+  for (int v = tid; v < A.nV; v += stride) {
+    V3<double> x = ld3(A.x0, v), xt = ld3(A.xt, v);
+    V3<double> dx = x - xt;
+    vt += 0.5 * A.mass[v] * dot(dx, dx);
+    if (A.vflag[v] & kSurface) {
+      for (int j = 0; j < A.planes.n; ++j) {
+        const double d = plane_dist(A.planes.p[j], x);
+        if (d < A.dhat) {
+          if (!(d > 0.0)) { raise_err(A.status, kErrPenetration); continue; }
+          vt += A.kappa * barrier_b(d, A.dhat);
+        }
+      }
+    }
+  }
+  double v[1] = {A.h2 * el + vt};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// H p by the vertex-centric sweep (p in p0, prescribed rows zero) and the
+// per-block partials of p^T H p.  Pair contributions must already be in acc.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
+  __shared__ double sh[4 * 2];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * kBlock) >> 6;
+  double php = 0.0;
+  for (int w = wid; w < A.nWaves; w += nw) {
+    const int idx = w * kWave + lane;
+    const int code = A.inc[idx];
+    const int myv = A.inc_vert[idx];
+    R s[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (code >= 0) {
+      const int e = code >> 2, a = code & 3;
+      const ElemRec<R> rec = A.elem[e];
+      Kin<R> kin = kinematics<R>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]), ld3(A.x0, rec.v[3]));
+      if (kin.J > R(0)) {
+        V3<R> d[3];
+        dF_cols(rec.B, ldr<R>(A.p0, rec.v[0]), ldr<R>(A.p0, rec.v[1]), ldr<R>(A.p0, rec.v[2]), ldr<R>(A.p0, rec.v[3]), d);
+        V3<R> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, a));
+        s[0] = hp.x; s[1] = hp.y; s[2] = hp.z;
+      } else {
+        raise_err(A.status, kErrInverted);
+      }
+    }
+    seg_sum<R>(myv, s);
+    const int upv = __shfl_up(myv, 1, kWave);
+    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const int v = myv;
+    V3<R> pr = ldr<R>(A.p0, v);
+    const double p3[3] = {double(pr.x), double(pr.y), double(pr.z)};
+    double hv[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
+    const double m = A.mass[v];
+    for (int j = 0; j < 3; ++j) hv[j] += m * p3[j];
+    if (A.vflag[v] & kSurface) {
+      const V3<double> x = ld3(A.x0, v);
+      for (int j = 0; j < A.planes.n; ++j) {
+        const double* pl = A.planes.p[j];
+        const double d = plane_dist(pl, x);
+        if (d > 0.0 && d < A.dhat) {
+          const double c = A.kappa * barrier_d2b(d, A.dhat) * (pl[0] * p3[0] + pl[1] * p3[1] + pl[2] * p3[2]);
+          hv[0] += c * pl[0]; hv[1] += c * pl[1]; hv[2] += c * pl[2];
+        }
+      }
+    }
+    if (A.self) {
+      for (int j = 0; j < 3; ++j) hv[j] += A.acc[8 * v + j];
+    }
+    if (A.vflag[v] & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
+    php += hv[0] * p3[0] + hv[1] * p3[1] + hv[2] * p3[2];
+    if (out_hp) {
+      for (int j = 0; j < 3; ++j) out_hp[3 * v + j] = hv[j];
+    }
+  }
+  double v[1] = {php};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Sum of n partials (one block), optionally plus `extra` partials.
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const double* a, int na, const double* b, int nb, double* out) {
+  __shared__ double sh[4 * 1];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < na; j += kBlock) s += a[j];
+  if (b)
+    for (int j = threadIdx.x; j < nb; j += kBlock) s += b[j];
+  double v[1] = {s};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) out[0] = v[0];
+}
+
+// ----------------------------------------------------------------- audit
+// Minimum distance over candidate pairs (positions x0) and surface-vertex
+// plane distances, and minimum det F; partials [grid][2] (min d, min J).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_audit(Args<R> A, double* part) {
+  __shared__ double sh[4 * 2];
+  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  double dmin = HUGE_VAL, jmin = HUGE_VAL;
+  const long long nq = A.ncand[0], npt = A.ncand[1];
+  for (long long q = tid; q < nq; q += stride) {
+    int2 pr = A.cand[q];
+    Closest c;
+    if (q < npt) {
+      c = closest_pt(ld3(A.x0, pr.x), ld3(A.x0, A.tris[3 * pr.y]), ld3(A.x0, A.tris[3 * pr.y + 1]),
+                     ld3(A.x0, A.tris[3 * pr.y + 2]));
+    } else {
+      c = closest_ee(ld3(A.x0, A.edges[2 * pr.x]), ld3(A.x0, A.edges[2 * pr.x + 1]), ld3(A.x0, A.edges[2 * pr.y]),
+                     ld3(A.x0, A.edges[2 * pr.y + 1]));
+    }
+    dmin = fmin(dmin, c.d);
+  }
+  for (int v = tid; v < A.nV; v += stride) {
+    if (!(A.vflag[v] & kSurface)) continue;
+    const V3<double> x = ld3(A.x0, v);
+    for (int j = 0; j < A.planes.n; ++j) dmin = fmin(dmin, plane_dist(A.planes.p[j], x));
+  }
+  for (int e = tid; e < A.nT; e += stride) {
+    const ElemRec<R> rec = A.elem[e];
+    // det F in float64 regardless of R
+    V3<double> X0 = ld3(A.x0, rec.v[0]);
+    V3<double> e1 = ld3(A.x0, rec.v[1]) - X0, e2 = ld3(A.x0, rec.v[2]) - X0, e3 = ld3(A.x0, rec.v[3]) - X0;
+    V3<double> f[3];
+    for (int j = 0; j < 3; ++j) f[j] = double(rec.B[j]) * e1 + double(rec.B[3 + j]) * e2 + double(rec.B[6 + j]) * e3;
+    jmin = fmin(jmin, dot(f[0], cross(f[1], f[2])));
+  }
+  double v[2] = {-dmin, -jmin};
+  const int kind[2] = {1, 1};
+  block_reduce<2>(v, kind, sh);
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = -v[0]; part[2 * blockIdx.x + 1] = -v[1]; }
+}
+
+// ============================================================== launchers
+template <typename R>
+void launch_predict(const Args<R>& A, const double* x, const double* v, double3 grav, hipStream_t s) {
+  hipLaunchKernelGGL(k_predict<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x, v, grav);
+}
+template <typename R>
+void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
+  if (A.self)
+    hipLaunchKernelGGL(k_narrow<R>, dim3(A.grid), dim3(kBlock), 0, s, A, k, mode);
+  else
+    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kBlock), 0, s, A, k, mode, (double*)nullptr,
+                       (double*)nullptr);
+}
+template <typename R>
+void launch_iteration_rest(const Args<R>& A, int k, hipStream_t s) {
+  if (A.self)
+    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kBlock), 0, s, A, k, 0, (double*)nullptr,
+                       (double*)nullptr);
+  hipLaunchKernelGGL(k_dir<R>, dim3(A.grid), dim3(kBlock), 0, s, A, k);
+}
+template <typename R>
+void launch_finalize(const Args<R>& A, double* x_out, double* v_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x_out, v_out);
+}
+template <typename R>
+void launch_load_query(const Args<R>& A, const double* x, const double* xt, const double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_load_query<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x, xt, p);
+}
+template <typename R>
+void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kBlock), 0, s, A, 0, 0, g, d);
+}
+template <typename R>
+void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy<R>, dim3(A.grid), dim3(kBlock), 0, s, A, A.part_dir);
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 1>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, A.part_dir, A.grid,
+                     A.self ? A.part_narrow : (const double*)nullptr, A.grid, out);
+}
+template <typename R>
+void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) {
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL(k_hvp<R>, dim3(A.grid), dim3(kBlock), 0, s, A, hp, A.part_dir);
+  // pair p^T H p is already inside H p at the vertices, so only k_hvp's partials are summed
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
+}
+template <typename R>
+void launch_audit(const Args<R>& A, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_audit<R>, dim3(A.grid), dim3(kBlock), 0, s, A, part);
+}
+
+#define PNCG_INSTANTIATE(R)                                                                          \
+  template void launch_predict<R>(const Args<R>&, const double*, const double*, double3, hipStream_t); \
+  template void launch_iteration_first<R>(const Args<R>&, int, int, hipStream_t);                     \
+  template void launch_iteration_rest<R>(const Args<R>&, int, hipStream_t);                           \
+  template void launch_finalize<R>(const Args<R>&, double*, double*, hipStream_t);                    \
+  template void launch_load_query<R>(const Args<R>&, const double*, const double*, const double*,     \
+                                     hipStream_t);                                                    \
+  template void launch_query_gradient<R>(const Args<R>&, double*, double*, hipStream_t);              \
+  template void launch_query_energy<R>(const Args<R>&, double*, hipStream_t);                         \
+  template void launch_query_hvp<R>(const Args<R>&, double*, double*, hipStream_t);                   \
+  template void launch_audit<R>(const Args<R>&, double*, hipStream_t);
+
+PNCG_INSTANTIATE(float)
+PNCG_INSTANTIATE(double)
+
+}  // namespace pncg

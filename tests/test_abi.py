@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every symbol include/pncg.h declares, and
+rejects bad input on the host before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pncg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pncg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2405_08001_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_header_compiles_as_c():
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no gcc")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        open(src, "w").write('#include "pncg.h"\nint main(void){pncg_opts o={0,PNCG_MIXED,0,0,0};(void)o;return 0;}\n')
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), src, "-o",
+                            os.path.join(d, "t")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def _ctx():
+    import paper_2405_08001_amd as P
+    return P.Context(0, P.FP64)
+
+
+def test_create_rejects_bad_precision():
+    import paper_2405_08001_amd as P
+    with pytest.raises(P.PncgError) as e:
+        P.Context(0, 7)
+    assert e.value.code == P.E_INVAL
+
+
+def test_call_order_is_enforced():
+    import paper_2405_08001_amd as P
+    c = _ctx()
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_material([1e5], [0.3], [1e3])
+    assert e.value.code == P.E_STATE
+    c.nV = 4
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_step(np.zeros((4, 3)), np.zeros((4, 3)), 0.01)
+    assert e.value.code == P.E_STATE
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_energy(np.zeros((4, 3)), np.zeros((4, 3)), 0.01)
+    assert e.value.code == P.E_STATE
+
+
+def test_set_mesh_validation():
+    import paper_2405_08001_amd as P
+    sc = scenes.tiny_scene()
+    c = _ctx()
+    bad = sc.tets.copy()
+    bad[0, 0] = sc.nV            # index out of range
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(sc.X, bad, sc.tris, sc.edges)
+    assert e.value.code == P.E_INVAL
+    inv = sc.tets.copy()
+    inv[3, [1, 2]] = inv[3, [2, 1]]   # negative orientation
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(sc.X, inv, sc.tris, sc.edges)
+    assert e.value.code == P.E_INVERTED
+    X = sc.X.copy()
+    X[2, 1] = np.nan
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(X, sc.tets, sc.tris, sc.edges)
+    assert e.value.code == P.E_NONFINITE
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(sc.X, sc.tets, sc.tris, np.array([[0, 0]]))
+    assert e.value.code == P.E_INVAL
+
+
+def test_vertex_degree_limit():
+    import paper_2405_08001_amd as P
+    # a fan of 65 tets around vertex 0
+    n = 65
+    ang = np.linspace(0, 2 * np.pi, n, endpoint=False)
+    ring = np.stack([np.cos(ang), np.sin(ang), np.zeros(n)], 1)
+    X = np.concatenate([[[0, 0, 0.0]], [[0, 0, 1.0]], ring])
+    tets = np.array([[0, 2 + i, 2 + (i + 1) % n, 1] for i in range(n)])
+    c = _ctx()
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(X, tets)
+    assert e.value.code == P.E_INVAL and "64" in str(e.value)
+
+
+def test_valid_mesh_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_2405_08001_amd as P
+    sc = scenes.tiny_scene()
+    c = _ctx()
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges)
+    assert e.value.code == P.E_HIP
