@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the PNCG time step on one MI355X.
+
+Workload: the ~110k-tet pile (24 voxelised spheres and tori dropped into a
+0.4 m box; synthetic, seeded; dhat = 5e-4 m, h = 1/30 s, at most 25 PNCG
+iterations per frame, dE tolerance 1e-3), stepped in the mixed float32 /
+float64 form, with the plain float64 form timed on the same frames for
+comparison.  W untimed warm-up frames bring the shapes into contact; the
+timed region is K frames.  The primary value is PNCG iterations per second
+(summed over the K frames); ms per frame is reported beside it.
+
+One JSON line is printed.  Besides the throughput it carries:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time (HIP events on the library's stream,
+                from a separate profiled pass), against 8 TB/s
+  iter_roofline the whole iteration's algorithmic bytes (per-tet, per-vertex,
+                per-contact byte model) times iterations/s, against 8 TB/s
+  cpu_baseline  the float64 CPU oracle timed on a bounded sample of the same
+                workload (one PNCG iteration from the state after warm-up)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+# algorithmic bytes (compulsory traffic, each array touched once per pass)
+BYTES = {
+    # per tet, per vertex, per active contact, per candidate, for one iteration
+    "iter": {"mixed": (120, 232, 144, 8), "fp64": (208, 344, 144, 8)},
+}
+# per-launch algorithmic bytes of each kernel: per tet, per vertex, per candidate
+KERNEL_BYTES = {
+    # dir: tet record; x (24), P g, p_prev, p_new, mass (8); candidate pair (8)
+    "dir": {"mixed": (60, 24 + 12 + 12 + 12 + 8, 8), "fp64": (104, 24 + 24 + 24 + 24 + 8, 8)},
+    # grad: tet record; x, xt, mass, g_prev, p_prev, g, P g, contact accumulators (48)
+    "grad": {"mixed": (60, 24 + 24 + 8 + 12 * 4 + 48, 0), "fp64": (104, 24 + 24 + 8 + 24 * 4 + 48, 0)},
+    # narrow: pending update (x_prev, p, x) per vertex; candidate pair (8)
+    "narrow": {"mixed": (0, 24 + 12 + 24, 8), "fp64": (0, 24 + 24 + 24, 8)},
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def setup_ctx(sc, precision):
+    import paper_2405_08001_amd as P
+    ctx = P.Context(0, P.MIXED if precision == "mixed" else P.FP64)
+    ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
+    ctx.pncg_set_material(sc.E, sc.nu, sc.rho)
+    ctx.pncg_set_contact(sc.dhat, sc.kappa, sc.cell, sc.planes,
+                         (P.CONTACT_SELF if sc.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
+    ctx.pncg_set_solver(sc.iter_max, sc.eps, P.TERM_DELTA_E, sc.gravity, 0)
+    return ctx
+
+
+def run(sc, precision, warmup, steps, profile_frames):
+    import torch
+    ctx = setup_ctx(sc, precision)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(sc.x0, dtype=torch.float64, device=dev)
+    v = torch.tensor(sc.v0, dtype=torch.float64, device=dev)
+    x2 = torch.empty_like(x)
+    v2 = torch.empty_like(v)
+    for _ in range(warmup):
+        ctx.pncg_step_dev(x, v, sc.h, x2, v2)
+        x, x2, v, v2 = x2, x, v2, v
+    state = (x.cpu().numpy().copy(), v.cpu().numpy().copy())
+    iters = 0
+    act = cand = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = ctx.pncg_step_dev(x, v, sc.h, x2, v2)
+        x, x2, v, v2 = x2, x, v2, v
+        iters += st["iters"]
+        act += st["n_active"]
+        cand += st["n_candidates"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # profiled pass (events around every launch) on further frames
+    ctx.pncg_set_profiling(True)
+    for _ in range(profile_frames):
+        ctx.pncg_step_dev(x, v, sc.h, x2, v2)
+        x, x2, v, v2 = x2, x, v2, v
+    prof = ctx.pncg_get_profile()
+    ctx.pncg_set_profiling(False)
+    dmin, jmin = ctx.pncg_min_distance(x.cpu().numpy())
+    ctx.close()
+    return dict(seconds=dt, iters=iters, frames=steps, mean_active=act / steps, mean_cand=cand / steps,
+                prof=prof, dmin=dmin, jmin=jmin, state=state)
+
+
+def cpu_baseline(sc, state, budget_iters=1):
+    """The float64 oracle, single-threaded, on one PNCG iteration from the
+    same state (the rest-pose exclusion set of this scene is empty, so it is
+    skipped in the oracle's setup)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:      # pragma: no cover
+        threadpool_limits = None
+    from oracle import pncg, problem
+    prob = problem.Problem.from_scene(sc, rest_exclude=False)
+    x, v = state
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        t0 = time.perf_counter()
+        _, _, st = pncg.step(prob, x, v, sc.h, iter_max=budget_iters, eps=0.0, term="delta_e")
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    return dict(value=st.iters / dt, unit="iters/s", cores=1, kind="oracle",
+                sample=f"{st.iters} PNCG iteration(s) of the 110k-tet pile from the state after warm-up "
+                       f"(float64 NumPy oracle, 1 thread, {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed frames before timing")
+    ap.add_argument("--profile-frames", type=int, default=10)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-GPU workload is one scene or one batch)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import scenes
+    sc = scenes.pile_scene()
+    log(f"pile: {sc.nT} tets, {sc.nV} vertices, {len(sc.tris)} surface triangles")
+
+    res = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        log(f"running {prec}: warmup {args.warmup}, timed {args.steps}")
+        res[prec] = run(sc, prec, args.warmup, args.steps, args.profile_frames)
+        r = res[prec]
+        log(f"  {prec}: {r['iters']} iterations in {r['seconds'] * 1e3:.1f} ms "
+            f"({r['iters'] / r['seconds']:.0f} it/s), dmin={r['dmin']:.3e} jmin={r['jmin']:.3f}")
+
+    m = res["mixed"]
+    ips = m["iters"] / m["seconds"]
+    ms_frame = 1e3 * m["seconds"] / m["frames"]
+    bt, bv, ba, bq = BYTES["iter"]["mixed"]
+    bytes_iter = bt * sc.nT + bv * sc.nV + ba * m["mean_active"] + bq * m["mean_cand"]
+    # dominant kernel of the profiled pass
+    prof = {k: v for k, v in m["prof"].items() if v[1] > 0}
+    kern = max((k for k in prof if k in KERNEL_BYTES), key=lambda k: prof[k][0])
+    avg_us = prof[kern][0] / prof[kern][1]
+    kt, kv, kq = KERNEL_BYTES[kern]["mixed"]
+    kbytes = kt * sc.nT + kv * sc.nV + kq * m["mean_cand"]
+    achieved = kbytes / (avg_us * 1e-6) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            tj = json.load(open(tpath))
+            traffic = tj.get("pile", {}).get(kern)
+        except (OSError, ValueError):
+            traffic = None
+    out = {
+        "metric": "PNCG iterations/s, 110k-tet pile, mixed float32/float64",
+        "value": round(ips, 1),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_frame, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "pile-110k", "tets": sc.nT, "vertices": sc.nV, "h": sc.h,
+                   "iter_max": sc.iter_max, "eps": sc.eps, "dhat": sc.dhat,
+                   "frames_timed": args.steps, "frames_warmup": args.warmup,
+                   "mean_iters_per_frame": round(m["iters"] / m["frames"], 2),
+                   "mean_active_pairs": round(m["mean_active"], 1),
+                   "mean_candidates": round(m["mean_cand"], 1)},
+        "ms_per_frame": round(ms_frame, 4),
+        "us_per_iter": round(1e6 / ips, 3),
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": round(achieved * 1e9 / HBM_PEAK, 4),
+                     "bytes_per_launch": int(kbytes), "avg_launch_us": round(avg_us, 3),
+                     "traffic": traffic},
+        "iter_roofline": {"bytes_per_iter": int(bytes_iter),
+                          "achieved_GBps": round(bytes_iter * ips / 1e9, 1),
+                          "frac": round(bytes_iter * ips / HBM_PEAK, 4)},
+        "kernels_us_avg": {k: round(v[0] / v[1], 3) for k, v in prof.items()},
+        "kernels_launches": {k: v[1] for k, v in prof.items()},
+        "min_distance_after": m["dmin"],
+        "min_detF_after": m["jmin"],
+    }
+    if "fp64" in res:
+        f = res["fp64"]
+        fips = f["iters"] / f["seconds"]
+        out["fp64"] = {"iters_per_s": round(fips, 1), "ms_per_frame": round(1e3 * f["seconds"] / f["frames"], 4),
+                       "us_per_iter": round(1e6 / fips, 3)}
+        out["mixed_vs_fp64_speedup"] = round(ips / fips, 3)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one iteration ...")
+        out["cpu_baseline"] = cpu_baseline(sc, m["state"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

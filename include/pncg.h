@@ -198,6 +198,29 @@ int pncg_candidates(pncg_ctx* ctx, const double* x, int32_t kind,
 int pncg_min_distance(pncg_ctx* ctx, const double* x, double* dmin,
                       double* jmin);
 
+/* Per-kernel timing of steps (tracing aid).  With profiling on, every
+ * launch a step makes is bracketed by HIP events recorded on the context's
+ * stream; durations are summed per kind:
+ *   PNCG_PROF_NARROW  first launch of an iteration with self contact
+ *                     (update + pair gradient/diagonal)
+ *   PNCG_PROF_GRAD    element gradient/diag sweep + dot products
+ *   PNCG_PROF_DIR     direction + p^T H p sweep
+ *   PNCG_PROF_REBUILD candidate-list rebuild (hash build + pair queries,
+ *                     including its host synchronisation)
+ *   PNCG_PROF_PREDICT predictor and end-of-step launches
+ * pncg_set_profiling(ctx, on) resets the totals; pncg_get_profile fills
+ * total_us[PNCG_PROF_KINDS] (microseconds) and launches[PNCG_PROF_KINDS].
+ * Event recording adds a little time to each launch, so timed runs that
+ * report throughput keep profiling off. */
+#define PNCG_PROF_NARROW  0
+#define PNCG_PROF_GRAD    1
+#define PNCG_PROF_DIR     2
+#define PNCG_PROF_REBUILD 3
+#define PNCG_PROF_PREDICT 4
+#define PNCG_PROF_KINDS   5
+int pncg_set_profiling(pncg_ctx* ctx, int32_t on);
+int pncg_get_profile(pncg_ctx* ctx, double* total_us, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,9 @@ CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP"
               -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY"}
 EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "pncg_set_material",
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
-           "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance")
+           "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
+           "pncg_set_profiling", "pncg_get_profile")
+PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
 class PncgError(RuntimeError):
@@ -72,6 +74,8 @@ def _load():
         "pncg_hvp": (I32, [P, P, P, D, P, P]),
         "pncg_candidates": (I32, [P, P, I32, P, I64, C.POINTER(I64)]),
         "pncg_min_distance": (I32, [P, P, P, P]),
+        "pncg_set_profiling": (I32, [P, I32]),
+        "pncg_get_profile": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -220,6 +224,18 @@ class Context:
         d, j = C.c_double(), C.c_double()
         self._check(_L.pncg_min_distance(self._h, _ptr(x), C.byref(d), C.byref(j)))
         return d.value, j.value
+
+
+    # ---------------------------------------------------------- profiling
+    def pncg_set_profiling(self, on):
+        self._check(_L.pncg_set_profiling(self._h, 1 if on else 0))
+
+    def pncg_get_profile(self):
+        """{kind: (total_us, launches)} for the kinds in PROF_KINDS."""
+        us = np.zeros(len(PROF_KINDS))
+        n = np.zeros(len(PROF_KINDS), dtype=np.int64)
+        self._check(_L.pncg_get_profile(self._h, _ptr(us), _ptr(n)))
+        return {k: (float(us[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
 
 
 def pncg_create(device=0, precision=FP64, stream=None, chunk=0):

@@ -98,6 +98,13 @@ struct pncg_ctx {
   double* d_part_ext = nullptr;
   long long *d_part_cnt = nullptr, *d_part_off = nullptr;
   int grid = 1;
+  // optional per-launch timing (HIP events on the context stream)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;  // (kind, index of the start event)
+  int ev_used = 0;
+  double prof_us[PNCG_PROF_KINDS] = {0};
+  long long prof_n[PNCG_PROF_KINDS] = {0};
 };
 
 namespace {
@@ -283,9 +290,44 @@ int check_status_err(pncg_ctx* c, const StepStatus& st) {
   return PNCG_OK;
 }
 
+// ------------------------------------------------------------- profiling
+int prof_begin(pncg_ctx* c, int kind) {
+  if (!c->profiling) return -1;
+  if (c->ev_used + 2 > (int)c->ev_pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->ev_pool.push_back(e);
+    }
+  }
+  const int i = c->ev_used;
+  c->ev_used += 2;
+  (void)hipEventRecord(c->ev_pool[i], c->stream);
+  c->ev_pending.push_back({kind, i});
+  return i;
+}
+void prof_end(pncg_ctx* c, int i) {
+  if (i < 0) return;
+  (void)hipEventRecord(c->ev_pool[i + 1], c->stream);
+}
+// after a stream synchronisation: fold the recorded pairs into the totals
+void prof_collect(pncg_ctx* c) {
+  for (auto& pe : c->ev_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[pe.second], c->ev_pool[pe.second + 1]) == hipSuccess) {
+      c->prof_us[pe.first] += 1000.0 * ms;
+      c->prof_n[pe.first] += 1;
+    }
+  }
+  c->ev_pending.clear();
+  c->ev_used = 0;
+}
+
 int read_status(pncg_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(StepStatus), hipMemcpyDeviceToHost, c->stream));
-  return sync(c);
+  int rc = sync(c);
+  if (c->profiling) prof_collect(c);
+  return rc;
 }
 
 // ------------------------------------------------------------------ step
@@ -294,13 +336,17 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
               pncg_stats* st) {
   Args<R> A = make_args<R>(c, h);
   const double3 grav = make_double3(c->grav[0], c->grav[1], c->grav[2]);
+  int ev = prof_begin(c, PNCG_PROF_PREDICT);
   launch_predict<R>(A, x_dev, v_dev, grav, c->stream);
+  prof_end(c, ev);
   int rebuilds = 0;
   long long ncand = 0;
   const double r_build = c->dhat + c->skin;
   int rc;
   if (A.self) {
+    ev = prof_begin(c, PNCG_PROF_REBUILD);
     if ((rc = build_candidates(c, c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+    prof_end(c, ev);
     ++rebuilds;
     A.cand = c->d_cand;
   }
@@ -308,13 +354,25 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   int mode = 0;  // kModeNormal
   while (true) {
     const int kend = std::min(k + c->chunk, c->iter_max + 1);
+    const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
     for (int j = k; j < kend; ++j) {
       if (j == c->iter_max) {
+        ev = prof_begin(c, kind_first);
         launch_iteration_first<R>(A, j, 1 /*finish*/, c->stream);
+        prof_end(c, ev);
         break;
       }
+      ev = prof_begin(c, kind_first);
       launch_iteration_first<R>(A, j, (j == k) ? mode : 0, c->stream);
-      launch_iteration_rest<R>(A, j, c->stream);
+      prof_end(c, ev);
+      if (A.self) {
+        ev = prof_begin(c, PNCG_PROF_GRAD);
+        launch_iteration_grad<R>(A, j, c->stream);
+        prof_end(c, ev);
+      }
+      ev = prof_begin(c, PNCG_PROF_DIR);
+      launch_iteration_dir<R>(A, j, c->stream);
+      prof_end(c, ev);
     }
     mode = 0;
     if ((rc = read_status(c))) return rc;
@@ -323,7 +381,9 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if (s.stopped) break;
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
+      ev = prof_begin(c, PNCG_PROF_REBUILD);
       if ((rc = build_candidates(c, (p & 1) ? c->d_x1 : c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+      prof_end(c, ev);
       ++rebuilds;
       A.cand = c->d_cand;
       k = p;
@@ -333,7 +393,9 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if (kend > c->iter_max) break;  // cannot happen: the finish launch always stops
     k = kend;
   }
+  ev = prof_begin(c, PNCG_PROF_PREDICT);
   launch_finalize<R>(A, x_out, v_out, c->stream);
+  prof_end(c, ev);
   if ((rc = read_status(c))) return rc;
   const StepStatus s = *c->h_status;
   if ((rc = check_status_err(c, s))) return rc;
@@ -515,6 +577,7 @@ void pncg_destroy(pncg_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -903,6 +966,27 @@ int pncg_candidates(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, 
   for (size_t i = 0; i < out.size(); ++i) {
     pairs[2 * i] = out[i].x;
     pairs[2 * i + 1] = out[i].y;
+  }
+  return PNCG_OK;
+}
+
+int pncg_set_profiling(pncg_ctx* c, int32_t on) {
+  if (!c) return PNCG_E_INVAL;
+  c->profiling = on != 0;
+  for (int i = 0; i < PNCG_PROF_KINDS; ++i) {
+    c->prof_us[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  c->ev_pending.clear();
+  c->ev_used = 0;
+  return PNCG_OK;
+}
+
+int pncg_get_profile(pncg_ctx* c, double* total_us, int64_t* launches) {
+  if (!c || !total_us || !launches) return PNCG_E_INVAL;
+  for (int i = 0; i < PNCG_PROF_KINDS; ++i) {
+    total_us[i] = c->prof_us[i];
+    launches[i] = c->prof_n[i];
   }
   return PNCG_OK;
 }

@@ -9,7 +9,8 @@ namespace pncg {
 
 template <typename R> void launch_predict(const Args<R>& A, const double* x, const double* v, double3 grav, hipStream_t s);
 template <typename R> void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s);
-template <typename R> void launch_iteration_rest(const Args<R>& A, int k, hipStream_t s);
+template <typename R> void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s);
+template <typename R> void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s);
 template <typename R> void launch_finalize(const Args<R>& A, double* x_out, double* v_out, hipStream_t s);
 template <typename R> void launch_load_query(const Args<R>& A, const double* x, const double* xt, const double* p, hipStream_t s);
 template <typename R> void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s);

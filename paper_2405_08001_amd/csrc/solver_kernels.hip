@@ -873,10 +873,12 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
                        (double*)nullptr);
 }
 template <typename R>
-void launch_iteration_rest(const Args<R>& A, int k, hipStream_t s) {
-  if (A.self)
-    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kBlock), 0, s, A, k, 0, (double*)nullptr,
-                       (double*)nullptr);
+void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
+  hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kBlock), 0, s, A, k, 0, (double*)nullptr,
+                     (double*)nullptr);
+}
+template <typename R>
+void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_dir<R>, dim3(A.grid), dim3(kBlock), 0, s, A, k);
 }
 template <typename R>
@@ -914,7 +916,8 @@ void launch_audit(const Args<R>& A, double* part, hipStream_t s) {
 #define PNCG_INSTANTIATE(R)                                                                          \
   template void launch_predict<R>(const Args<R>&, const double*, const double*, double3, hipStream_t); \
   template void launch_iteration_first<R>(const Args<R>&, int, int, hipStream_t);                     \
-  template void launch_iteration_rest<R>(const Args<R>&, int, hipStream_t);                           \
+  template void launch_iteration_grad<R>(const Args<R>&, int, hipStream_t);                           \
+  template void launch_iteration_dir<R>(const Args<R>&, int, hipStream_t);                            \
   template void launch_finalize<R>(const Args<R>&, double*, double*, hipStream_t);                    \
   template void launch_load_query<R>(const Args<R>&, const double*, const double*, const double*,     \
                                      hipStream_t);                                                    \
