@@ -94,9 +94,16 @@ struct pncg_ctx {
   double* d_scalar = nullptr;      // [8]
   // broad phase
   int tsize = 0;
-  int *d_count = nullptr, *d_start = nullptr, *d_items = nullptr;
-  double* d_part_ext = nullptr;
-  long long *d_part_cnt = nullptr, *d_part_off = nullptr;
+  int *d_count = nullptr, *d_start = nullptr;
+  double4 *d_item_lo = nullptr, *d_item_hi = nullptr;
+  long long *d_item_cnt = nullptr, *d_item_off = nullptr;
+  long long ent_cap = 0;
+  unsigned long long *d_ent_key = nullptr, *d_bkt_key = nullptr;
+  int *d_ent_item = nullptr, *d_bkt_item = nullptr;
+  double4 *d_bkt_lo = nullptr, *d_bkt_hi = nullptr;
+  int4* d_bkt_ids = nullptr;
+  long long *d_part_cnt = nullptr, *d_part_off = nullptr, *d_totals = nullptr;
+  long long work_cap = 0;
   int grid = 1;
   // optional per-launch timing (HIP events on the context stream)
   bool profiling = false;
@@ -108,6 +115,8 @@ struct pncg_ctx {
 };
 
 namespace {
+
+constexpr long long kTileScan = 4096;   // scan tile of the broad phase (kBlock * 16)
 
 int fail(pncg_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -236,29 +245,80 @@ Broad make_broad(pncg_ctx* c) {
   B.n_excl_pt = c->n_excl_pt;
   B.excl_ee = c->d_excl_ee;
   B.n_excl_ee = c->n_excl_ee;
+  B.item_lo = c->d_item_lo;
+  B.item_hi = c->d_item_hi;
+  B.item_cnt = c->d_item_cnt;
+  B.item_off = c->d_item_off;
+  B.ent_cap = c->ent_cap;
+  B.ent_key = c->d_ent_key;
+  B.ent_item = c->d_ent_item;
+  B.bkt_key = c->d_bkt_key;
+  B.bkt_item = c->d_bkt_item;
+  B.bkt_lo = c->d_bkt_lo;
+  B.bkt_hi = c->d_bkt_hi;
+  B.bkt_ids = c->d_bkt_ids;
   B.tsize = c->tsize;
   B.count = c->d_count;
   B.start = c->d_start;
-  B.items = c->d_items;
-  B.part_ext = c->d_part_ext;
+  B.work_cap = c->work_cap;
   B.part_cnt = c->d_part_cnt;
   B.part_off = c->d_part_off;
+  B.totals = c->d_totals;
   B.grid = c->grid;
   return B;
 }
 
+// (Re)allocate the cell-entry arrays for `ent` entries and the hash table and
+// work arrays that depend on it.
+int alloc_grid(pncg_ctx* c, long long ent) {
+  int rc;
+  for (void* p : {(void*)c->d_ent_key, (void*)c->d_ent_item, (void*)c->d_bkt_key, (void*)c->d_bkt_item,
+                  (void*)c->d_bkt_lo, (void*)c->d_bkt_hi, (void*)c->d_bkt_ids, (void*)c->d_count,
+                  (void*)c->d_start, (void*)c->d_part_cnt, (void*)c->d_part_off})
+    dfree(c, p);
+  c->ent_cap = std::max<long long>(ent, 4096);
+  int ts = 1024;
+  while (ts < c->ent_cap / 4 && ts < (1 << 24)) ts <<= 1;
+  c->tsize = ts;
+  c->work_cap = (long long)c->nSV + c->ent_cap;
+  if ((rc = dmalloc(c, &c->d_ent_key, c->ent_cap)) || (rc = dmalloc(c, &c->d_ent_item, c->ent_cap)) ||
+      (rc = dmalloc(c, &c->d_bkt_key, c->ent_cap)) || (rc = dmalloc(c, &c->d_bkt_item, c->ent_cap)) ||
+      (rc = dmalloc(c, &c->d_bkt_lo, c->ent_cap)) || (rc = dmalloc(c, &c->d_bkt_hi, c->ent_cap)) ||
+      (rc = dmalloc(c, &c->d_bkt_ids, c->ent_cap)) ||
+      (rc = dmalloc(c, &c->d_count, ts)) || (rc = dmalloc(c, &c->d_start, ts + 1)) ||
+      (rc = dmalloc(c, &c->d_part_cnt, c->work_cap)) || (rc = dmalloc(c, &c->d_part_off, c->work_cap + 4096)))
+    return rc;
+  return PNCG_OK;
+}
+
+__global__ void k_copy_counts(const long long* totals, long long* ncand) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ncand[0] = totals[1];
+    ncand[1] = totals[2];
+  }
+}
+
 // Candidate pairs (PT then EE) at device positions x with inflation r into
 // c->d_cand; counts in c->d_ncand.  filter_d >= 0: same-object pairs closer
-// than filter_d only (rest-pose exclusion set).
-int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, long long* n_total, long long* n_pt) {
-  Broad B = make_broad(c);
-  broad_build(B, x, c->cell, c->stream);
-  broad_count(B, x, c->cell, r, filter_d, c->stream);
-  broad_scan(B, c->d_ncand, c->stream);
-  HIPCHK(c, hipMemcpyAsync(c->h_n, c->d_ncand, 2 * sizeof(long long), hipMemcpyDeviceToHost, c->stream));
-  int rc = sync(c);
-  if (rc) return rc;
-  const long long n = c->h_n[0];
+// than filter_d only (rest-pose exclusion set).  One host synchronisation
+// (to size the pair list); the grid is rebuilt larger if its entry capacity
+// was too small.
+int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, int filter_obj, long long* n_total,
+                     long long* n_pt) {
+  int rc;
+  long long n = 0;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    Broad B = make_broad(c);
+    broad_build_count(B, x, c->cell, r, filter_d, filter_obj, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->h_n, c->d_totals, 3 * sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync(c))) return rc;
+    if (c->h_n[0] <= c->ent_cap) break;
+    if ((rc = alloc_grid(c, c->h_n[0] + c->h_n[0] / 4))) return rc;
+  }
+  if (c->h_n[0] > c->ent_cap) return fail(c, PNCG_E_NOMEM, "spatial grid did not fit");
+  n = c->h_n[1];
+  const long long npt = c->h_n[2];
+  hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, c->stream, (const long long*)c->d_totals, c->d_ncand);
   if (n > c->cand_cap) {
     long long cap = std::max<long long>(n + n / 2, 1024);
     int2* nc = nullptr;
@@ -267,9 +327,9 @@ int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, l
     c->d_cand = nc;
     c->cand_cap = cap;
   }
-  broad_fill(B, x, c->cell, r, filter_d, c->d_cand, c->cand_cap, c->stream);
+  broad_fill(make_broad(c), x, c->cell, r, filter_d, filter_obj, c->d_cand, c->cand_cap, c->stream);
   if (n_total) *n_total = n;
-  if (n_pt) *n_pt = c->h_n[1];
+  if (n_pt) *n_pt = npt;
   return PNCG_OK;
 }
 
@@ -341,19 +401,33 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   prof_end(c, ev);
   int rebuilds = 0;
   long long ncand = 0;
+  // the solver's list: pairs within dhat + skin at the build positions (a
+  // pair's distance changes by at most twice the per-vertex displacement,
+  // which stays below skin / 2 until the next build)
   const double r_build = c->dhat + c->skin;
   int rc;
   if (A.self) {
     ev = prof_begin(c, PNCG_PROF_REBUILD);
-    if ((rc = build_candidates(c, c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+    if ((rc = build_candidates(c, c->d_x0, r_build, r_build, 0, &ncand, nullptr))) return rc;
     prof_end(c, ev);
     ++rebuilds;
     A.cand = c->d_cand;
   }
   int k = 0;
   int mode = 0;  // kModeNormal
+  // With self contact the chunk length is chosen so that the displacement
+  // bound is expected to stay inside half the skin (observed growth per
+  // iteration, starting from the worst case dhat / 2); the device pauses the
+  // chunk if the prediction fails.
+  double D = 0.0, rate = 0.5 * c->dhat;
   while (true) {
-    const int kend = std::min(k + c->chunk, c->iter_max + 1);
+    int m = c->chunk;
+    if (A.self) {
+      const double room = 0.5 * c->skin - D;
+      const double want = room / std::max(rate, 1e-300);
+      m = (int)std::min<double>(std::max<double>(std::floor(want), 1.0), (double)c->chunk);
+    }
+    const int kend = std::min(k + m, c->iter_max + 1);
     const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
     for (int j = k; j < kend; ++j) {
       if (j == c->iter_max) {
@@ -382,15 +456,18 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
       ev = prof_begin(c, PNCG_PROF_REBUILD);
-      if ((rc = build_candidates(c, (p & 1) ? c->d_x1 : c->d_x0, r_build, -1.0, &ncand, nullptr))) return rc;
+      if ((rc = build_candidates(c, (p & 1) ? c->d_x1 : c->d_x0, r_build, r_build, 0, &ncand, nullptr))) return rc;
       prof_end(c, ev);
       ++rebuilds;
       A.cand = c->d_cand;
+      if (p > k) rate = std::max(rate, (s.D - D) / (p - k + 1));
+      D = 0.0;
       k = p;
       mode = 2;  // kModeResume
       continue;
     }
-    if (kend > c->iter_max) break;  // cannot happen: the finish launch always stops
+    if (kend > k) rate = std::max(0.0, (s.D - D) / (kend - k));
+    D = s.D;
     k = kend;
   }
   ev = prof_begin(c, PNCG_PROF_PREDICT);
@@ -423,7 +500,7 @@ int ready(pncg_ctx* c) {
 // Ensure the candidate buffer reflects r at device positions in d_x0.
 int query_candidates(pncg_ctx* c, double r) {
   if (!((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0)) return PNCG_OK;
-  return build_candidates(c, c->d_x0, r, -1.0, nullptr, nullptr);
+  return build_candidates(c, c->d_x0, r, r, 0, nullptr, nullptr);
 }
 
 int stage_positions(pncg_ctx* c, const double* x) {
@@ -706,19 +783,18 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
       (rc = dmalloc(c, &c->d_status, 1)) || (rc = dmalloc(c, &c->d_part_grad, 8 * (size_t)gmax)) ||
       (rc = dmalloc(c, &c->d_part_dir, 4 * (size_t)gmax)) || (rc = dmalloc(c, &c->d_part_narrow, gmax)) ||
       (rc = dmalloc(c, &c->d_io, 9 * (size_t)nV)) || (rc = dmalloc(c, &c->d_scalar, 8)) ||
-      (rc = dmalloc(c, &c->d_part_ext, 3 * (size_t)gmax)) ||
-      (rc = dmalloc(c, &c->d_part_cnt, 2 * (size_t)gmax * kBlock)) ||
-      (rc = dmalloc(c, &c->d_part_off, 2 * (size_t)gmax * kBlock + 4096)))
+      (rc = dmalloc(c, &c->d_item_lo, (size_t)nF + nE)) || (rc = dmalloc(c, &c->d_item_hi, (size_t)nF + nE)) ||
+      (rc = dmalloc(c, &c->d_item_cnt, (size_t)nF + nE + surf.size())) ||
+      (rc = dmalloc(c, &c->d_item_off, (size_t)nF + nE + surf.size() + 1)) ||
+      (rc = dmalloc(c, &c->d_totals, 4)))
     return rc;
   c->scal_cap = 0;
   c->d_scal = nullptr;
-  // hash table sized to the surface items
-  int ts = 1024;
-  while (ts < 2 * (c->nSV + nE)) ts <<= 1;
-  c->tsize = ts;
-  if ((rc = dmalloc(c, &c->d_count, ts)) || (rc = dmalloc(c, &c->d_start, ts + 1)) ||
-      (rc = dmalloc(c, &c->d_items, std::max(c->nSV + nE, 1))))
-    return rc;
+  c->d_ent_key = nullptr; c->d_ent_item = nullptr; c->d_bkt_key = nullptr; c->d_bkt_item = nullptr;
+  c->d_bkt_lo = nullptr; c->d_bkt_hi = nullptr; c->d_bkt_ids = nullptr;
+  c->d_count = nullptr; c->d_start = nullptr; c->d_part_cnt = nullptr; c->d_part_off = nullptr;
+  // grid entries: start with eight cells per primitive; grown on demand
+  if ((rc = alloc_grid(c, 8LL * (nF + nE) + (long long)surf.size() + 4096))) return rc;
   HIPCHK(c, hipMemsetAsync(c->d_ncand, 0, 4 * sizeof(long long), c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_inc, inc.data(), sizeof(int) * inc.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_inc_vert, incv.data(), sizeof(int) * incv.size(), hipMemcpyHostToDevice, c->stream));
@@ -780,16 +856,17 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
   c->planes = P;
   c->cflags = flags;
   c->skin = 4.0 * dhat;
-  // hash cell: the caller's, or the longest surface edge (>= 2 r) so a query
-  // visits at most a few cells per axis
-  double lmax = 0.0;
+  // grid cell: the caller's, or the mean rest length of the surface edges
+  // (at least the candidate inflation), so each primitive touches a few cells
+  double lsum = 0.0;
   for (int e = 0; e < c->nE; ++e) {
     const int a = c->edges[2 * e], b = c->edges[2 * e + 1];
     double l2 = 0.0;
     for (int i = 0; i < 3; ++i) l2 += (c->X[3 * a + i] - c->X[3 * b + i]) * (c->X[3 * a + i] - c->X[3 * b + i]);
-    lmax = std::max(lmax, std::sqrt(l2));
+    lsum += std::sqrt(l2);
   }
-  c->cell = cell > 0.0 ? cell : std::max(lmax, 2.0 * (dhat + c->skin));
+  const double lmean = c->nE > 0 ? lsum / c->nE : 0.0;
+  c->cell = cell > 0.0 ? cell : std::max(lmean, dhat + c->skin);
   c->n_excl_pt = c->n_excl_ee = 0;
   HIPCHK(c, hipSetDevice(c->device));
   if ((flags & PNCG_CONTACT_SELF) && (flags & PNCG_CONTACT_REST_EXCLUDE) && c->nF + c->nE > 0) {
@@ -798,7 +875,7 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
     if (rc) return rc;
     const double r = 1.5 * dhat;
     long long n = 0, npt = 0;
-    if ((rc = build_candidates(c, c->d_x0, r, r, &n, &npt))) return rc;
+    if ((rc = build_candidates(c, c->d_x0, r, r, 1, &n, &npt))) return rc;
     std::vector<int2> pairs(n);
     if (n) HIPCHK(c, hipMemcpyAsync(pairs.data(), c->d_cand, sizeof(int2) * n, hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync(c))) return rc;
@@ -954,7 +1031,7 @@ int pncg_candidates(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, 
     if (m) HIPCHK(c, hipMemcpyAsync(out.data(), c->d_cand, sizeof(int2) * m, hipMemcpyDeviceToHost, c->stream));
   } else if ((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0) {
     long long m = 0, mpt = 0;
-    if ((rc = build_candidates(c, c->d_x0, c->dhat, -1.0, &m, &mpt))) return rc;
+    if ((rc = build_candidates(c, c->d_x0, c->dhat, -1.0, 0, &m, &mpt))) return rc;
     const long long a = kind == PNCG_KIND_PT ? 0 : mpt, b = kind == PNCG_KIND_PT ? mpt : m;
     out.resize(b - a);
     if (b > a) HIPCHK(c, hipMemcpyAsync(out.data(), c->d_cand + a, sizeof(int2) * (b - a), hipMemcpyDeviceToHost, c->stream));
@@ -999,7 +1076,7 @@ int pncg_min_distance(pncg_ctx* c, const double* x, double* dmin, double* jmin) 
   if ((rc = stage_positions(c, x))) return rc;
   const bool self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0;
   if (self) {
-    if ((rc = build_candidates(c, c->d_x0, 10.0 * c->dhat, -1.0, nullptr, nullptr))) return rc;
+    if ((rc = build_candidates(c, c->d_x0, 10.0 * c->dhat, -1.0, 0, nullptr, nullptr))) return rc;
   } else {
     HIPCHK(c, hipMemsetAsync(c->d_ncand, 0, 2 * sizeof(long long), c->stream));
   }

@@ -1,24 +1,30 @@
 // Broad phase: candidate point-triangle and edge-edge pairs by an inflated
-// axis-aligned box test in float64 over a uniform-grid spatial hash (the
-// paper culls with a grid hash, Sec. 6; the hash changes speed, not the set).
+// axis-aligned box test in float64 over a uniform grid (the paper culls with
+// a grid hash, Sec. 6; the grid changes speed, not the set).
 //
 //   PT (v, f): v a surface vertex not in f, and on every axis
 //              min_f - r <= x_v <= max_f + r
 //   EE (e1 < e2) without a shared vertex, on every axis
 //              min_e1 - r <= max_e2  and  min_e2 <= max_e1 + r
 //
-// Surface vertices are hashed by their cell; edges by the cell of their
-// lower box corner.  A triangle visits the cells its inflated box covers; an
-// edge e2 visits the cells where the lower corner of a qualifying e1 can lie
-// (widened by the largest edge extent).  Each pair is found exactly once:
-// a vertex or edge lives in one cell, and a visit only accepts items whose
-// own cell is the visited cell (hash collisions are filtered).
+// Grid entries (cell, item): every surface vertex in its cell, every
+// triangle in each cell its r-inflated box touches, every edge in each cell
+// its (r/2 + margin)-inflated box touches.  Entries are grouped by a hash of
+// the cell; each entry's record (cell, item, exact float64 box, vertex ids)
+// is stored contiguously per bucket.  One thread per entry scans its bucket
+// for entries of the same cell with a larger item id, so each pair sharing a
+// cell is seen once per shared cell, and lanes of a wave read the same bucket
+// (broadcast loads).  A vertex lies in one cell, which is among the
+// triangle's cells whenever the PT test holds; an edge pair is reported only
+// in the cell holding the lower corner of the intersection of the two
+// inflated boxes, which both edges touch.  So every pair is found exactly
+// once, and the exact test above makes the final decision.
 //
 // Output is produced without any global counter: a counting pass stores the
-// number of pairs of every thread, an exclusive scan turns the counts into
-// offsets (point-triangle counts first, then edge-edge), and a second pass
-// writes the pairs.  Buckets are sorted by item index, so the list order is
-// deterministic.
+// pair counts of every entry, an exclusive scan turns them into offsets
+// (point-triangle counts of all entries first, then edge-edge), and a second
+// pass writes the pairs.
+#include <algorithm>
 #include <climits>
 
 #include "kernels.h"
@@ -28,23 +34,33 @@ namespace pncg {
 namespace {
 
 constexpr int kTile = kBlock * 16;
+constexpr double kEdgeMargin = 1e-9;   // absolute slack of the edge culling boxes (m)
 
 __device__ __forceinline__ int cell_coord(double p, double inv) {
   double c = floor(p * inv);
-  c = fmin(fmax(c, -1048576.0), 1048576.0);
+  c = fmin(fmax(c, -1048575.0), 1048575.0);
   return (int)c;
 }
 __device__ __forceinline__ int3 cell_of(V3<double> p, double inv) {
   return make_int3(cell_coord(p.x, inv), cell_coord(p.y, inv), cell_coord(p.z, inv));
 }
-__device__ __forceinline__ unsigned hash_cell(int cx, int cy, int cz, int tsize) {
-  unsigned h = ((unsigned)cx * 73856093u) ^ ((unsigned)cy * 19349663u) ^ ((unsigned)cz * 83492791u);
-  return h & (unsigned)(tsize - 1);
+__device__ __forceinline__ unsigned long long cell_key(int cx, int cy, int cz) {
+  return ((unsigned long long)(cx + 1048576) << 42) | ((unsigned long long)(cy + 1048576) << 21) |
+         (unsigned long long)(cz + 1048576);
+}
+// bucket of a cell in one half of the table: triangles use [0, tsize/2),
+// edges [tsize/2, tsize)
+__device__ __forceinline__ unsigned hash_key(unsigned long long k, int tsize, bool edge) {
+  const unsigned cx = (unsigned)(k >> 42), cy = (unsigned)((k >> 21) & 0x1FFFFF), cz = (unsigned)(k & 0x1FFFFF);
+  unsigned h = (cx * 73856093u) ^ (cy * 19349663u) ^ (cz * 83492791u);
+  const unsigned half = (unsigned)tsize >> 1;
+  return (h & (half - 1)) + (edge ? half : 0u);
 }
 __device__ __forceinline__ V3<double> ldx(const double4* x, int i) {
   double4 v = x[i];
   return mk3(v.x, v.y, v.z);
 }
+__device__ __forceinline__ V3<double> v4(double4 v) { return mk3(v.x, v.y, v.z); }
 __device__ __forceinline__ V3<double> vmin3(V3<double> a, V3<double> b) { return mk3(fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)); }
 __device__ __forceinline__ V3<double> vmax3(V3<double> a, V3<double> b) { return mk3(fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)); }
 
@@ -142,189 +158,318 @@ void scan_exclusive(const T* in, long long n, T* out, T* total, T* scratch, hipS
   hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(kBlock), 0, s, in, n, (const T*)scratch, out, total);
 }
 
-// ------------------------------------------------------------ hash build
+// ------------------------------------------------------------ grid build
 __global__ void __launch_bounds__(kBlock) k_zero_int(int* a, int n) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) a[i] = 0;
 }
 
-__device__ __forceinline__ V3<double> item_key_point(const Broad& B, const double4* x, int it) {
-  if (it < B.nSV) return ldx(x, B.surf[it]);
-  const int e = it - B.nSV;
-  return vmin3(ldx(x, B.edges[2 * e]), ldx(x, B.edges[2 * e + 1]));
+// culling box of primitive i (0..nF-1 triangles, nF.. edges): what is
+// inserted into the grid
+__device__ __forceinline__ void cull_box(const Broad& B, int i, double r, V3<double>& lo, V3<double>& hi) {
+  lo = v4(B.item_lo[i]);
+  hi = v4(B.item_hi[i]);
+  if (i >= B.nF) {
+    const double q = 0.5 * r + kEdgeMargin;
+    lo = mk3(lo.x - q, lo.y - q, lo.z - q);
+    hi = mk3(hi.x + q, hi.y + q, hi.z + q);
+  }
 }
 
-__global__ void __launch_bounds__(kBlock) k_hash_count(Broad B, const double4* x, double inv) {
-  __shared__ double sh[3][kBlock / kWave];
-  const int n = B.nSV + B.nE;
-  double ext[3] = {0.0, 0.0, 0.0};
-  for (int it = blockIdx.x * kBlock + threadIdx.x; it < n; it += gridDim.x * kBlock) {
-    V3<double> k = item_key_point(B, x, it);
-    int3 c = cell_of(k, inv);
-    atomicAdd(&B.count[hash_cell(c.x, c.y, c.z, B.tsize)], 1);
-    if (it >= B.nSV) {
-      const int e = it - B.nSV;
-      V3<double> a = ldx(x, B.edges[2 * e]), b = ldx(x, B.edges[2 * e + 1]);
-      V3<double> mx = vmax3(a, b);
-      ext[0] = fmax(ext[0], mx.x - k.x);
-      ext[1] = fmax(ext[1], mx.y - k.y);
-      ext[2] = fmax(ext[2], mx.z - k.z);
+__global__ void __launch_bounds__(kBlock) k_items(Broad B, const double4* x, double inv, double r) {
+  const int n = B.nF + B.nE;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    V3<double> lo, hi;
+    if (i < B.nF) {
+      const V3<double> a = ldx(x, B.tris[3 * i]), b = ldx(x, B.tris[3 * i + 1]), c = ldx(x, B.tris[3 * i + 2]);
+      const V3<double> mn = vmin3(vmin3(a, b), c), mx = vmax3(vmax3(a, b), c);
+      lo = mk3(mn.x - r, mn.y - r, mn.z - r);
+      hi = mk3(mx.x + r, mx.y + r, mx.z + r);
+    } else {
+      const int e = i - B.nF;
+      const V3<double> a = ldx(x, B.edges[2 * e]), b = ldx(x, B.edges[2 * e + 1]);
+      lo = vmin3(a, b);
+      hi = vmax3(a, b);
     }
+    B.item_lo[i] = make_double4(lo.x, lo.y, lo.z, 0.0);
+    B.item_hi[i] = make_double4(hi.x, hi.y, hi.z, 0.0);
+    V3<double> cl, ch;
+    cull_box(B, i, r, cl, ch);
+    const int3 c0 = cell_of(cl, inv), c1 = cell_of(ch, inv);
+    B.item_cnt[i] = (long long)(c1.x - c0.x + 1) * (c1.y - c0.y + 1) * (c1.z - c0.z + 1);
   }
-  for (int j = 0; j < 3; ++j) {
-    double v = ext[j];
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
-    if ((threadIdx.x & 63) == 0) sh[j][threadIdx.x >> 6] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_emit(Broad B, const double4* x, double inv, double r) {
+  const int n = B.nF + B.nE;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    V3<double> cl, ch;
+    cull_box(B, i, r, cl, ch);
+    const int3 c0 = cell_of(cl, inv), c1 = cell_of(ch, inv);
+    long long o = B.item_off[i];
+    for (int cx = c0.x; cx <= c1.x; ++cx)
+      for (int cy = c0.y; cy <= c1.y; ++cy)
+        for (int cz = c0.z; cz <= c1.z; ++cz, ++o) {
+          if (o >= B.ent_cap) break;
+          const unsigned long long k = cell_key(cx, cy, cz);
+          B.ent_key[o] = k;
+          B.ent_item[o] = B.nSV + i;
+          atomicAdd(&B.count[hash_key(k, B.tsize, i >= B.nF)], 1);
+        }
+  }
+}
+
+// Group the entries by bucket and store each entry's full record there.
+__global__ void __launch_bounds__(kBlock) k_bucket_fill(Broad B, const double4* x) {
+  const long long n = min(B.totals[0], B.ent_cap);
+  const int vbase = B.nSV, ebase = B.nSV + B.nF;
+  for (long long j = blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock) {
+    const unsigned long long k = B.ent_key[j];
+    const int it = B.ent_item[j];
+    const unsigned h = hash_key(k, B.tsize, it >= B.nSV + B.nF);
+    const int slot = B.start[h] + atomicAdd(&B.count[h], 1);
+    double4 lo, hi;
+    int4 ids = make_int4(-1, -1, -1, 0);
+    if (it < vbase) {
+      ids.x = B.surf[it];
+      lo = hi = x[ids.x];
+    } else if (it < ebase) {
+      const int f = it - vbase;
+      ids = make_int4(B.tris[3 * f], B.tris[3 * f + 1], B.tris[3 * f + 2], 0);
+      lo = B.item_lo[f];
+      hi = B.item_hi[f];
+    } else {
+      const int e = it - ebase;
+      ids.x = B.edges[2 * e];
+      ids.y = B.edges[2 * e + 1];
+      lo = B.item_lo[B.nF + e];
+      hi = B.item_hi[B.nF + e];
+    }
+    B.bkt_key[slot] = k;
+    B.bkt_item[slot] = it;
+    B.bkt_lo[slot] = lo;
+    B.bkt_hi[slot] = hi;
+    B.bkt_ids[slot] = ids;
+  }
+}
+
+// ------------------------------------------------------------------ pairs
+// item ids: [0, nSV) surface vertices (surf order), [nSV, nSV + nF)
+// triangles, [nSV + nF, ...) edges.
+struct PairCtx {
+  const double4* x;
+  double inv, r, filter_d;
+  int filter_obj;
+};
+
+// Records of a contiguous run of bucket slots held in LDS.
+constexpr int kSpan = 512;
+struct SlotSpan {
+  unsigned long long key[kSpan];
+  int item[kSpan];
+  int4 ids[kSpan];
+  double lo[3][kSpan];
+  double hi[3][kSpan];
+};
+
+// Record accessors: all slots from the LDS span, or all from global memory.
+struct LdsRec {
+  const SlotSpan& L;
+  int base;
+  __device__ __forceinline__ unsigned long long key(int t) const { return L.key[t - base]; }
+  __device__ __forceinline__ int item(int t) const { return L.item[t - base]; }
+  __device__ __forceinline__ int4 ids(int t) const { return L.ids[t - base]; }
+  __device__ __forceinline__ V3<double> lo(int t) const {
+    return mk3(L.lo[0][t - base], L.lo[1][t - base], L.lo[2][t - base]);
+  }
+  __device__ __forceinline__ V3<double> hi(int t) const {
+    return mk3(L.hi[0][t - base], L.hi[1][t - base], L.hi[2][t - base]);
+  }
+};
+struct GlobalRec {
+  const Broad& B;
+  __device__ __forceinline__ unsigned long long key(int t) const { return B.bkt_key[t]; }
+  __device__ __forceinline__ int item(int t) const { return B.bkt_item[t]; }
+  __device__ __forceinline__ int4 ids(int t) const { return B.bkt_ids[t]; }
+  __device__ __forceinline__ V3<double> lo(int t) const { return v4(B.bkt_lo[t]); }
+  __device__ __forceinline__ V3<double> hi(int t) const { return v4(B.bkt_hi[t]); }
+};
+
+// Point-triangle test of surface vertex v (position p, cell key) against
+// the triangle entry in slot t.
+__device__ __forceinline__ bool vertex_slot_pair(const Broad& B, const PairCtx& P, int v, V3<double> p,
+                                                 unsigned long long key, int t, int2& out) {
+  if (B.bkt_key[t] != key) return false;
+  const int4 idB = B.bkt_ids[t];
+  if (v == idB.x || v == idB.y || v == idB.z) return false;
+  const V3<double> lo = v4(B.bkt_lo[t]), hi = v4(B.bkt_hi[t]);
+  if (!(lo.x <= p.x && p.x <= hi.x && lo.y <= p.y && p.y <= hi.y && lo.z <= p.z && p.z <= hi.z)) return false;
+  const int f = B.bkt_item[t] - B.nSV;
+  const unsigned long long pk = ((unsigned long long)(unsigned)v << 32) | (unsigned)f;
+  if (B.n_excl_pt && in_sorted(B.excl_pt, B.n_excl_pt, pk)) return false;
+  if (P.filter_d >= 0.0) {
+    if (P.filter_obj && B.oid[v] != B.oid[idB.x]) return false;
+    if (!(closest_pt(p, ldx(P.x, idB.x), ldx(P.x, idB.y), ldx(P.x, idB.z)).d < P.filter_d)) return false;
+  }
+  out = make_int2(v, f);
+  return true;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int& total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int x = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(x, o, kWave);
+    if (lane >= o) x += u;
+  }
+  total = __shfl(x, kWave - 1, kWave);
+  return x - v;
+}
+
+// Point-triangle pairs of surface vertex w: one wave per vertex, one lane per
+// slot of the vertex's triangle bucket.  FILL = false returns the count (in
+// every lane); FILL = true writes the pairs from offset `o` in slot order.
+template <bool FILL>
+__device__ __forceinline__ int vertex_pairs_wave(const Broad& B, const PairCtx& P, int w, long long o, int2* out,
+                                                 long long cap) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int v = B.surf[w];
+  const V3<double> p = ldx(P.x, v);
+  const int3 c = cell_of(p, P.inv);
+  const unsigned long long key = cell_key(c.x, c.y, c.z);
+  const unsigned h = hash_key(key, B.tsize, false);
+  const int s0 = B.start[h], s1 = B.start[h + 1];
+  int count = 0;
+  for (int t0 = s0; t0 < s1; t0 += kWave) {
+    const int t = t0 + lane;
+    int2 pr;
+    const int hit = (t < s1 && vertex_slot_pair(B, P, v, p, key, t, pr)) ? 1 : 0;
+    int tot;
+    const int before = wave_excl_scan(hit, tot);
+    if (FILL && hit) {
+      const long long k = o + count + before;
+      if (k < cap) out[k] = pr;
+    }
+    count += tot;
+  }
+  return count;
+}
+
+// Edge-edge pairs of edge slot s with the later edges of its cell.
+template <typename Rec, typename Emit>
+__device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, const Rec& R, int s, Emit&& emit) {
+  const int ebase = B.nSV + B.nF;
+  const int ia = R.item(s);
+  const unsigned long long key = R.key(s);
+  const unsigned h = hash_key(key, B.tsize, true);
+  const int s0 = B.start[h], s1 = B.start[h + 1];
+  const V3<double> loA = R.lo(s), hiA = R.hi(s);
+  const int4 idA = R.ids(s);
+  const double r = P.r, q = 0.5 * P.r + kEdgeMargin;
+  for (int t = s0; t < s1; ++t) {
+    const int ib = R.item(t);
+    if (ib <= ia || R.key(t) != key) continue;
+    const int4 idB = R.ids(t);
+    if (idA.x == idB.x || idA.x == idB.y || idA.y == idB.x || idA.y == idB.y) continue;
+    const V3<double> lo = R.lo(t), hi = R.hi(t);
+    // exact test with e1 = this (smaller) edge
+    if (!((loA.x - r) <= hi.x && (loA.y - r) <= hi.y && (loA.z - r) <= hi.z)) continue;
+    if (!(lo.x <= (hiA.x + r) && lo.y <= (hiA.y + r) && lo.z <= (hiA.z + r))) continue;
+    // report only in the cell of the lower corner of the culling-box intersection
+    const V3<double> corner = mk3(fmax(loA.x - q, lo.x - q), fmax(loA.y - q, lo.y - q), fmax(loA.z - q, lo.z - q));
+    const int3 cc = cell_of(corner, P.inv);
+    if (cell_key(cc.x, cc.y, cc.z) != key) continue;
+    const int e1 = ia - ebase, e2 = ib - ebase;
+    const unsigned long long pk = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
+    if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, pk)) continue;
+    if (P.filter_d >= 0.0) {
+      if (P.filter_obj && B.oid[idA.x] != B.oid[idB.x]) continue;
+      if (!(closest_ee(ldx(P.x, idA.x), ldx(P.x, idA.y), ldx(P.x, idB.x), ldx(P.x, idB.y)).d < P.filter_d)) continue;
+    }
+    emit(make_int2(e1, e2));
+  }
+}
+
+// Load the edge buckets covering slots [S, S + kBlock) into LDS; returns the
+// first slot of the span, or -1 if the span does not fit.
+__device__ __forceinline__ int load_span(const Broad& B, SlotSpan& L, long long S, long long E) {
+  const int lo = B.start[hash_key(B.bkt_key[S], B.tsize, true)];
+  const int hi = B.start[hash_key(B.bkt_key[E - 1], B.tsize, true) + 1];
+  const bool fits = hi - lo <= kSpan;
+  if (fits) {
+    for (int t = threadIdx.x; t < hi - lo; t += kBlock) {
+      L.key[t] = B.bkt_key[lo + t];
+      L.item[t] = B.bkt_item[lo + t];
+      L.ids[t] = B.bkt_ids[lo + t];
+      const double4 a = B.bkt_lo[lo + t], b = B.bkt_hi[lo + t];
+      L.lo[0][t] = a.x; L.lo[1][t] = a.y; L.lo[2][t] = a.z;
+      L.hi[0][t] = b.x; L.hi[1][t] = b.y; L.hi[2][t] = b.z;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < 3; ++j) {
-      double m = 0.0;
-      for (int w = 0; w < kBlock / kWave; ++w) m = fmax(m, sh[j][w]);
-      B.part_ext[3 * blockIdx.x + j] = m;
-    }
-  }
+  return fits ? lo : -1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_hash_fill(Broad B, const double4* x, double inv) {
-  const int n = B.nSV + B.nE;
-  for (int it = blockIdx.x * kBlock + threadIdx.x; it < n; it += gridDim.x * kBlock) {
-    int3 c = cell_of(item_key_point(B, x, it), inv);
-    const unsigned h = hash_cell(c.x, c.y, c.z, B.tsize);
-    const int slot = atomicAdd(&B.count[h], 1);
-    B.items[B.start[h] + slot] = it;
-  }
-}
-
-// insertion sort of every bucket by item index
-__global__ void __launch_bounds__(kBlock) k_hash_sort(Broad B) {
-  for (int h = blockIdx.x * kBlock + threadIdx.x; h < B.tsize; h += gridDim.x * kBlock) {
-    const int s0 = B.start[h], s1 = B.start[h + 1];
-    for (int i = s0 + 1; i < s1; ++i) {
-      const int v = B.items[i];
-      int j = i - 1;
-      while (j >= s0 && B.items[j] > v) {
-        B.items[j + 1] = B.items[j];
-        --j;
-      }
-      B.items[j + 1] = v;
-    }
-  }
-}
-
-// --------------------------------------------------------------- queries
-// Visit every candidate of query `q` (a triangle when q < nF, else an edge
-// e2 = q - nF) and call emit(a, b) for each pair in a fixed order.
 template <typename Emit>
-__device__ __forceinline__ void visit_query(const Broad& B, const double4* x, double inv, double r, double filter_d,
-                                            const double ext[3], int q, Emit&& emit) {
-  const int tsize = B.tsize;
-  if (q < B.nF) {
-    const int f = q;
-    const int a = B.tris[3 * f], b = B.tris[3 * f + 1], c = B.tris[3 * f + 2];
-    const V3<double> pa = ldx(x, a), pb = ldx(x, b), pc = ldx(x, c);
-    const V3<double> mn = vmin3(vmin3(pa, pb), pc), mx = vmax3(vmax3(pa, pb), pc);
-    const V3<double> lo = mk3(mn.x - r, mn.y - r, mn.z - r);
-    const V3<double> hi = mk3(mx.x + r, mx.y + r, mx.z + r);
-    const int3 c0 = cell_of(lo, inv), c1 = cell_of(hi, inv);
-    for (int cx = c0.x; cx <= c1.x; ++cx)
-      for (int cy = c0.y; cy <= c1.y; ++cy)
-        for (int cz = c0.z; cz <= c1.z; ++cz) {
-          const unsigned h = hash_cell(cx, cy, cz, tsize);
-          const int s1 = B.start[h + 1];
-          for (int s = B.start[h]; s < s1; ++s) {
-            const int it = B.items[s];
-            if (it >= B.nSV) break;   // buckets are sorted: edge items follow vertex items
-            const int v = B.surf[it];
-            if (v == a || v == b || v == c) continue;
-            const V3<double> p = ldx(x, v);
-            const int3 pc3 = cell_of(p, inv);
-            if (pc3.x != cx || pc3.y != cy || pc3.z != cz) continue;
-            if (!(lo.x <= p.x && p.x <= hi.x && lo.y <= p.y && p.y <= hi.y && lo.z <= p.z && p.z <= hi.z)) continue;
-            const unsigned long long key = ((unsigned long long)(unsigned)v << 32) | (unsigned)f;
-            if (B.n_excl_pt && in_sorted(B.excl_pt, B.n_excl_pt, key)) continue;
-            if (filter_d >= 0.0) {
-              if (B.oid[v] != B.oid[a]) continue;
-              if (!(closest_pt(p, pa, pb, pc).d < filter_d)) continue;
-            }
-            emit(0, v, f);
-          }
-        }
-  } else {
-    const int e2 = q - B.nF;
-    const int a2 = B.edges[2 * e2], b2 = B.edges[2 * e2 + 1];
-    const V3<double> pa2 = ldx(x, a2), pb2 = ldx(x, b2);
-    const V3<double> mn2 = vmin3(pa2, pb2), mx2 = vmax3(pa2, pb2);
-    // the lower corner of a qualifying e1 lies in [mn2 - r - ext, mx2 + r]
-    const double marg = 1e-9;
-    const V3<double> lo = mk3(mn2.x - r - ext[0] - marg, mn2.y - r - ext[1] - marg, mn2.z - r - ext[2] - marg);
-    const V3<double> hi = mk3(mx2.x + r + marg, mx2.y + r + marg, mx2.z + r + marg);
-    const int3 c0 = cell_of(lo, inv), c1 = cell_of(hi, inv);
-    for (int cx = c0.x; cx <= c1.x; ++cx)
-      for (int cy = c0.y; cy <= c1.y; ++cy)
-        for (int cz = c0.z; cz <= c1.z; ++cz) {
-          const unsigned h = hash_cell(cx, cy, cz, tsize);
-          const int s1 = B.start[h + 1];
-          for (int s = B.start[h]; s < s1; ++s) {
-            const int it = B.items[s];
-            if (it < B.nSV) continue;
-            const int e1 = it - B.nSV;
-            if (e1 >= e2) break;      // sorted bucket: no smaller edge index follows
-            const int a1 = B.edges[2 * e1], b1 = B.edges[2 * e1 + 1];
-            if (a1 == a2 || a1 == b2 || b1 == a2 || b1 == b2) continue;
-            const V3<double> pa1 = ldx(x, a1), pb1 = ldx(x, b1);
-            const V3<double> mn1 = vmin3(pa1, pb1), mx1 = vmax3(pa1, pb1);
-            const int3 k3 = cell_of(mn1, inv);
-            if (k3.x != cx || k3.y != cy || k3.z != cz) continue;
-            if (!((mn1.x - r) <= mx2.x && (mn1.y - r) <= mx2.y && (mn1.z - r) <= mx2.z)) continue;
-            if (!(mn2.x <= (mx1.x + r) && mn2.y <= (mx1.y + r) && mn2.z <= (mx1.z + r))) continue;
-            const unsigned long long key = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
-            if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, key)) continue;
-            if (filter_d >= 0.0) {
-              if (B.oid[a1] != B.oid[a2]) continue;
-              if (!(closest_ee(pa1, pb1, pa2, pb2).d < filter_d)) continue;
-            }
-            emit(1, e1, e2);
-          }
-        }
+__device__ __forceinline__ void edge_slot_pairs(const Broad& B, const PairCtx& P, const SlotSpan& L, int base, int s,
+                                                Emit&& emit) {
+  if (base >= 0) edge_pairs(B, P, LdsRec{L, base}, s, emit);
+  else edge_pairs(B, P, GlobalRec{B}, s, emit);
+}
+
+// Work items: [0, nSV) surface vertices (point-triangle), then the edge slots
+// [start[tsize/2], start[tsize]) (edge-edge).  part_cnt[w] = pairs of item w;
+// every slot below work_cap is written, so no stale count survives.
+__global__ void __launch_bounds__(kBlock) k_pairs_count(Broad B, PairCtx P) {
+  __shared__ SlotSpan L;
+  const long long e0 = B.start[B.tsize >> 1], e1 = B.start[B.tsize];
+  const long long nw = B.nSV + (e1 - e0);
+  // vertices: one wave each
+  {
+    const long long wid = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const long long nwv = ((long long)gridDim.x * kBlock) >> 6;
+    for (long long w = wid; w < B.nSV; w += nwv) {
+      const int c = vertex_pairs_wave<false>(B, P, (int)w, 0, nullptr, 0);
+      if ((threadIdx.x & (kWave - 1)) == 0) B.part_cnt[w] = c;
+    }
+  }
+  // edge slots: a block takes kBlock consecutive slots and their buckets in LDS
+  for (long long S = e0 + (long long)blockIdx.x * kBlock; S < e1; S += (long long)gridDim.x * kBlock) {
+    const long long s = S + threadIdx.x;
+    const int base = load_span(B, L, S, min(S + (long long)kBlock, e1));
+    int c = 0;
+    if (s < e1) edge_slot_pairs(B, P, L, base, (int)s, [&](int2) { ++c; });
+    __syncthreads();
+    if (s < e1) B.part_cnt[B.nSV + (s - e0)] = c;
+  }
+  for (long long w = nw + blockIdx.x * kBlock + threadIdx.x; w < B.work_cap; w += (long long)gridDim.x * kBlock)
+    B.part_cnt[w] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pairs_fill(Broad B, PairCtx P, int2* out, long long cap) {
+  __shared__ SlotSpan L;
+  const long long e0 = B.start[B.tsize >> 1], e1 = B.start[B.tsize];
+  {
+    const long long wid = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const long long nwv = ((long long)gridDim.x * kBlock) >> 6;
+    for (long long w = wid; w < B.nSV; w += nwv) vertex_pairs_wave<true>(B, P, (int)w, B.part_off[w], out, cap);
+  }
+  for (long long S = e0 + (long long)blockIdx.x * kBlock; S < e1; S += (long long)gridDim.x * kBlock) {
+    const long long s = S + threadIdx.x;
+    const int base = load_span(B, L, S, min(S + (long long)kBlock, e1));
+    if (s < e1) {
+      long long o = B.part_off[B.nSV + (s - e0)];
+      edge_slot_pairs(B, P, L, base, (int)s, [&](int2 pr) {
+        if (o < cap) out[o] = pr;
+        ++o;
+      });
+    }
+    __syncthreads();
   }
 }
 
-__device__ __forceinline__ void reduce_ext(const Broad& B, double ext[3]) {
-  ext[0] = ext[1] = ext[2] = 0.0;
-  for (int j = 0; j < B.grid; ++j) {
-    ext[0] = fmax(ext[0], B.part_ext[3 * j]);
-    ext[1] = fmax(ext[1], B.part_ext[3 * j + 1]);
-    ext[2] = fmax(ext[2], B.part_ext[3 * j + 2]);
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_query_count(Broad B, const double4* x, double inv, double r, double filter_d) {
-  double ext[3];
-  reduce_ext(B, ext);
-  const int tid = blockIdx.x * kBlock + threadIdx.x, nth = gridDim.x * kBlock;
-  long long cpt = 0, cee = 0;
-  const int nq = B.nF + B.nE;
-  for (int q = tid; q < nq; q += nth)
-    visit_query(B, x, inv, r, filter_d, ext, q, [&](int kind, int, int) {
-      if (kind == 0) ++cpt; else ++cee;
-    });
-  B.part_cnt[tid] = cpt;
-  B.part_cnt[nth + tid] = cee;
-}
-
-__global__ void __launch_bounds__(kBlock) k_query_fill(Broad B, const double4* x, double inv, double r, double filter_d,
-                                                       int2* out, long long cap) {
-  double ext[3];
-  reduce_ext(B, ext);
-  const int tid = blockIdx.x * kBlock + threadIdx.x, nth = gridDim.x * kBlock;
-  long long opt = B.part_off[tid], oee = B.part_off[nth + tid];
-  const int nq = B.nF + B.nE;
-  for (int q = tid; q < nq; q += nth)
-    visit_query(B, x, inv, r, filter_d, ext, q, [&](int kind, int a, int b) {
-      long long& o = kind == 0 ? opt : oee;
-      if (o < cap) out[o] = make_int2(a, b);
-      ++o;
-    });
+// totals[2] = number of point-triangle pairs = offset of the first edge-edge slot
+__global__ void k_pt_total(Broad B) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) B.totals[2] = B.part_off[B.nSV];
 }
 
 __global__ void __launch_bounds__(kBlock) k_plane_cand(Broad B, const double4* x, Planes P, double r, int2* out,
@@ -349,32 +494,29 @@ __global__ void __launch_bounds__(kBlock) k_plane_cand(Broad B, const double4* x
 
 }  // namespace
 
-void broad_build(const Broad& B, const double4* x, double cell, hipStream_t s) {
+void broad_build_count(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj,
+                       hipStream_t s) {
   const double inv = 1.0 / cell;
+  const int n = B.nF + B.nE;
   hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
-  hipLaunchKernelGGL(k_hash_count, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv);
-  // start = exclusive scan of count (start[tsize] = total); part_off serves as scratch
-  scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)B.part_off, s);
+  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
+  hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
   hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
-  hipLaunchKernelGGL(k_hash_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv);
-  hipLaunchKernelGGL(k_hash_sort, dim3(B.grid), dim3(kBlock), 0, s, B);
+  hipLaunchKernelGGL(k_bucket_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x);
+  PairCtx P{x, inv, r, filter_d, filter_obj};
+  const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_pairs_count, dim3(nb), dim3(kBlock), 0, s, B, P);
+  scan_exclusive<long long>(B.part_cnt, B.work_cap, B.part_off, B.totals + 1, B.part_off + B.work_cap, s);
+  hipLaunchKernelGGL(k_pt_total, dim3(1), dim3(64), 0, s, B);
 }
 
-void broad_count(const Broad& B, const double4* x, double cell, double r, double filter_d, hipStream_t s) {
-  hipLaunchKernelGGL(k_query_count, dim3(B.grid), dim3(kBlock), 0, s, B, x, 1.0 / cell, r, filter_d);
-}
-
-void broad_scan(const Broad& B, long long* n_out, hipStream_t s) {
-  const long long n = 2LL * B.grid * kBlock;
-  // scratch for block sums: the tail of part_off beyond the 2n offsets
-  scan_exclusive<long long>(B.part_cnt, n, B.part_off, n_out, B.part_off + n, s);
-  // n_out[1] = offset of the first edge-edge pair = number of point-triangle pairs
-  (void)hipMemcpyAsync(n_out + 1, B.part_off + (long long)B.grid * kBlock, sizeof(long long), hipMemcpyDeviceToDevice, s);
-}
-
-void broad_fill(const Broad& B, const double4* x, double cell, double r, double filter_d, int2* out, long long cap,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_query_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x, 1.0 / cell, r, filter_d, out, cap);
+void broad_fill(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj, int2* out,
+                long long cap, hipStream_t s) {
+  PairCtx P{x, 1.0 / cell, r, filter_d, filter_obj};
+  const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_pairs_fill, dim3(nb), dim3(kBlock), 0, s, B, P, out, cap);
 }
 
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,

@@ -56,6 +56,7 @@ struct StepStatus {
   int pad;
   double g0, gk, dE0, last_dE;
   double n_active;
+  double D;           // displacement bound since the last list build (first launch of each iteration)
   long long n_cand;   // candidates of the last list (written by the list builder)
   long long n_pt;     // of which point-triangle
 };

@@ -19,40 +19,56 @@ template <typename R> void launch_query_hvp(const Args<R>& A, double* hp, double
 template <typename R> void launch_audit(const Args<R>& A, double* part, hipStream_t s);
 
 // ------------------------------------------------------------ broad phase
-// Candidate lists by the inflated-AABB test (float64, no contraction) with a
-// uniform-grid spatial hash.  Point items are the surface vertices; edge
-// items are keyed by the cell of their lower box corner.
+// Candidate lists by the inflated-AABB test (float64, no contraction) over a
+// uniform grid.  Triangles (boxes inflated by r) and edges (boxes inflated by
+// r/2) are inserted into every cell their box touches; a surface vertex
+// visits its own cell, edge pairs are tested per shared cell.
 struct Broad {
   // static
   int nV, nSV, nF, nE;
-  const int* surf;       // [nSV] surface vertices
+  const int* surf;       // [nSV] surface vertices (ascending)
   const int* tris;       // [nF][3]
   const int* edges;      // [nE][2]
   const int* oid;        // [nV] object id (rest exclusion)
   // rest-pose exclusion keys (sorted)
   const unsigned long long* excl_pt; int n_excl_pt;
   const unsigned long long* excl_ee; int n_excl_ee;
-  // hash table: items 0..nSV-1 surface vertices, nSV.. edges
+  // items 0..nF-1 triangles, nF.. edges
+  double4* item_lo;      // [nF + nE] triangle: min - r; edge: min
+  double4* item_hi;      // [nF + nE] triangle: max + r; edge: max
+  long long* item_cnt;   // [nF + nE + nSV] cells touched (primitives, then vertices)
+  long long* item_off;   // [nF + nE + nSV + 1]
+  // cell entries (item, cell key), then grouped by hash bucket
+  long long ent_cap;
+  unsigned long long* ent_key;   // [ent_cap]
+  int* ent_item;                 // [ent_cap]
+  unsigned long long* bkt_key;   // [ent_cap] records grouped by bucket
+  int* bkt_item;                 // [ent_cap]
+  double4* bkt_lo;               // [ent_cap] vertex: position; triangle: inflated box; edge: box
+  double4* bkt_hi;               // [ent_cap]
+  int4* bkt_ids;                 // [ent_cap] vertex ids of the item (-1 unused)
   int tsize;             // power of two
   int* count;            // [tsize]
   int* start;            // [tsize + 1]
-  int* items;            // [nSV + nE]
-  double* part_ext;      // [kMaxGrid][3] max edge extent per block
-  long long* part_cnt;   // [kMaxGrid * kBlock] per-thread pair counts (pt, ee interleaved)
-  long long* part_off;   // [kMaxGrid * kBlock * 2]
+  // pair counting: PT and EE counts per entry
+  long long work_cap;    // = 2 * ent_cap
+  long long* part_cnt;   // [work_cap]
+  long long* part_off;   // [work_cap + 4096]
+  long long* totals;     // device: [0] entries, [1] pairs, [2] point-triangle pairs
   int grid;
 };
 
-// Build the hash at positions x (double4 [nV]) with cell size `cell`.
-void broad_build(const Broad& B, const double4* x, double cell, hipStream_t s);
-// Count pairs (pass 1); writes per-thread counts.  filter_d >= 0 keeps only
-// pairs closer than filter_d (exact distance) from the same object.
-void broad_count(const Broad& B, const double4* x, double cell, double r, double filter_d, hipStream_t s);
-// Exclusive scan of the per-thread counts; totals to n_out[0] (all), n_out[1] (PT).
-void broad_scan(const Broad& B, long long* n_out, hipStream_t s);
-// Emit pairs (pass 2) into out[cap] (PT first, then EE); cap checked on device.
-void broad_fill(const Broad& B, const double4* x, double cell, double r, double filter_d, int2* out, long long cap,
-                hipStream_t s);
+// Rebuild the grid at positions x with cell size `cell` and inflation r,
+// count the pairs and scan the counts.  totals[0] receives the number of
+// cell entries (the build is valid only if it is <= ent_cap), totals[1] and
+// totals[2] the pair counts.  filter_d >= 0 keeps only pairs closer than
+// filter_d (exact distance), and with filter_obj only pairs of one object.
+void broad_build_count(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj,
+                       hipStream_t s);
+// Emit the pairs counted above into out[cap] (point-triangle first, sorted by
+// (v, f); then edge-edge).
+void broad_fill(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj, int2* out,
+                long long cap, hipStream_t s);
 // Plane candidates ((n0 x0 + n1 x1) + n2 x2) - o <= r for surface vertices.
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,
                       long long cap, hipStream_t s);

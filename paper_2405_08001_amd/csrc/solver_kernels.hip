@@ -183,6 +183,7 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
       }
       s.D = 0; s.stop = 0; s.pause = 0;
       A.status->paused_at = -1;
+      A.status->D = 0.0;
     }
     return fp;
   }
@@ -234,6 +235,7 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
       st->n_active = prev.n_active;
     }
     if (pause) A.status->paused_at = k;
+    A.status->D = D;
   }
   fp.alpha = alpha;
   fp.materialize = 1;
