@@ -603,8 +603,9 @@ int upload_flags_targets(pncg_ctx* c) {
 
 int grid_for(const pncg_ctx* c) {
   long long work = std::max<long long>({(long long)c->nWaves * kWave, (long long)c->nT, (long long)c->nV, 1LL});
-  long long g = (work + kBlock - 1) / kBlock;
-  return (int)std::min<long long>(std::max<long long>(g, 1), kMaxGrid);
+  long long g = (work + kSBlock - 1) / kSBlock;
+  g = std::min<long long>(std::max<long long>(g, 1), kMaxGrid);
+  return (int)(((g + kXcds - 1) / kXcds) * kXcds);   // whole rounds over the XCDs
 }
 
 }  // namespace

@@ -10,8 +10,10 @@ namespace pncg {
 
 constexpr int kMaxPlanes = 8;
 constexpr int kWave = 64;
-constexpr int kBlock = 256;          // threads per block of every kernel
-constexpr int kMaxGrid = 512;        // blocks of the grid-stride kernels (= partial count)
+constexpr int kBlock = 256;          // threads per block of the broad-phase kernels
+constexpr int kSBlock = 256;         // threads per block of the solver kernels
+constexpr int kXcds = 8;             // accelerator complex dies; workgroups are dealt round-robin over them
+constexpr int kMaxGrid = 512;        // blocks of the solver kernels (= partial count)
 
 // per-vertex flags
 constexpr uint8_t kFixed = 1;

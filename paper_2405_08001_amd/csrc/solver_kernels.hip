@@ -29,6 +29,8 @@
 
 namespace pncg {
 
+constexpr int kSWaves = kSBlock / kWave;
+
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
@@ -40,7 +42,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Sum (kind 0) or max (kind 1) of N per-thread values over the block; the
-// result is returned to every thread.  sh must hold 4 * N doubles.
+// result is returned to every thread.  sh must hold kSWaves * N doubles.
 template <int N>
 __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kind)[N], double* sh) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
@@ -55,7 +57,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kind)[N
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double r = sh[i];
-    for (int j = 1; j < kBlock / kWave; ++j) r = kind[i] ? fmax(r, sh[j * N + i]) : r + sh[j * N + i];
+    for (int j = 1; j < kSBlock / kWave; ++j) r = kind[i] ? fmax(r, sh[j * N + i]) : r + sh[j * N + i];
     v[i] = r;
   }
   __syncthreads();
@@ -67,7 +69,7 @@ __device__ __forceinline__ void reduce_partials(const double* part, int stride, 
                                                 double (&out)[N], double* sh) {
 #pragma unroll
   for (int i = 0; i < N; ++i) out[i] = kind[i] ? 0.0 : 0.0;
-  for (int j = threadIdx.x; j < n; j += kBlock) {
+  for (int j = threadIdx.x; j < n; j += kSBlock) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       double v = part[j * stride + i];
@@ -75,6 +77,26 @@ __device__ __forceinline__ void reduce_partials(const double* part, int stride, 
     }
   }
   block_reduce<N>(out, kind, sh);
+}
+
+// ------------------------------------------------------- work partitioning
+// Workgroups are dispatched round-robin over the XCDs, each with its own L2.
+// The logical block index below gives every XCD a contiguous range of
+// logical blocks (the grid is a multiple of kXcds), and every logical block
+// a contiguous slice of each work range, so an XCD touches one contiguous
+// eighth of the mesh and its L2 holds that eighth's tets and vertices.
+__device__ __forceinline__ int logical_block() {
+  const int per = gridDim.x / kXcds;
+  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+struct Slice {
+  long long begin, end;
+};
+// slice of [0, n) for this block, in units of `unit` items
+__device__ __forceinline__ Slice block_slice(long long n) {
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  const long long b = (long long)logical_block() * per;
+  return Slice{b, b + per < n ? b + per : n};
 }
 
 // ---------------------------------------------------------------- helpers
@@ -136,13 +158,13 @@ __device__ __forceinline__ R4<R>* pbuf(const Args<R>& A, int k) { return (k & 1)
 // xt = x^t + h v^t + h^2 g (Sec. 3); x_0 = x^t with prescribed vertices at
 // their targets (Algorithm 1, first line).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_predict(Args<R> A, const double* x_in, const double* v_in, double3 grav) {
+__global__ void __launch_bounds__(kSBlock) k_predict(Args<R> A, const double* x_in, const double* v_in, double3 grav) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     StepStatus* s = A.status;
     s->stopped = 0; s->final_k = 0; s->iters = 0; s->reason = 2; s->paused_at = -1; s->err = 0;
     s->a_up_hits = 0; s->g0 = 0; s->gk = 0; s->dE0 = 0; s->last_dE = 0; s->n_active = 0;
   }
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+  for (int v = blockIdx.x * kSBlock + threadIdx.x; v < A.nV; v += gridDim.x * kSBlock) {
     V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
     V3<double> vel = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
     if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(vel.x) && isfinite(vel.y) && isfinite(vel.z)))
@@ -289,15 +311,15 @@ __device__ __forceinline__ void pair_hess_coefs(const Args<R>& A, double d, doub
 // then barrier gradient + diagonal of every active pair into acc (eq8,
 // eq10, eq11).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_narrow(Args<R> A, int k, int mode) {
-  __shared__ double sh[4 * 8];
+__global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) {
+  __shared__ double sh[kSWaves * 8];
   FirstPro fp = first_prologue(A, k, mode, sh);
-  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
   double4* xcur = xbuf(A, k);
   const double4* xprev = xbuf(A, k - 1);
   const R4<R>* pk = pbuf(A, k);
   if (fp.materialize) {
-    for (int v = tid; v < A.nV; v += stride) {
+    const Slice sv = block_slice(A.nV);
+    for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
       V3<double> x = ld3(xprev, v);
       R4<R> q = pk[v];
       st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
@@ -307,7 +329,8 @@ __global__ void __launch_bounds__(kBlock) k_narrow(Args<R> A, int k, int mode) {
   PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
   const long long nq = A.ncand[0], npt = A.ncand[1];
   double nact = 0.0;
-  for (long long q = tid; q < nq; q += stride) {
+  const Slice sq = block_slice(nq);
+  for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
     int iv[4];
     Closest c;
     if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
@@ -413,8 +436,8 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // the pending update lazily.  kGradDirect: x_k already materialised.
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 template <typename R, int MODE>
-__global__ void __launch_bounds__(kBlock) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
-  __shared__ double sh[4 * 8];
+__global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
+  __shared__ double sh[kSWaves * 8];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
     fp = first_prologue(A, k, mode, sh);
@@ -423,14 +446,14 @@ __global__ void __launch_bounds__(kBlock) k_grad(Args<R> A, int k, int mode, dou
     if (s.stop || s.pause) return;
   }
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nw = (gridDim.x * kBlock) >> 6;
+  const Slice swv = block_slice(A.nWaves);
   double4* xcur = MODE == kGradQuery ? A.x0 : xbuf(A, k);
   const double4* xprev = xbuf(A, k - 1);
   const R4<R>* pk = pbuf(A, k);
   if (MODE == kGradFirst && fp.materialize && !fp.work) {
     // stop test passed: only apply the last update
-    for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+    const Slice sv = block_slice(A.nV);
+    for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
       V3<double> x = ld3(xprev, v);
       R4<R> q = pk[v];
       st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
@@ -440,7 +463,7 @@ __global__ void __launch_bounds__(kBlock) k_grad(Args<R> A, int k, int mode, dou
   if (!fp.work) return;
   PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
   double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int w = wid; w < A.nWaves; w += nw) {
+  for (int w = (int)swv.begin + (threadIdx.x >> 6); w < swv.end; w += kSWaves) {
     const int idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
@@ -504,8 +527,8 @@ __global__ void __launch_bounds__(kBlock) k_grad(Args<R> A, int k, int mode, dou
 
 // ------------------------------------------------------ direction + pHp
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
-  __shared__ double sh[4 * 8];
+__global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
+  __shared__ double sh[kSWaves * 8];
   const IterScal s = A.scal[k];
   if (s.stop || s.pause) return;
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -553,11 +576,11 @@ __global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
   const double4* xk = xbuf(A, k);
   const R4<R>* pk = pbuf(A, k);
   R4<R>* pn = pbuf(A, k + 1);
-  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
   double acc_pHp = 0.0, pmv = 0.0, pmc = 0.0;
   // tets: element p^T H p with p recomputed at the four corners
   double el = 0.0;
-  for (int e = tid; e < A.nT; e += stride) {
+  const Slice st = block_slice(A.nT);
+  for (int e = (int)st.begin + threadIdx.x; e < st.end; e += kSBlock) {
     const ElemRec<R> rec = A.elem[e];
     V3<R> P[4];
     V3<double> X[4];
@@ -574,7 +597,8 @@ __global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
   }
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
-  for (int v = tid; v < A.nV; v += stride) {
+  const Slice sv = block_slice(A.nV);
+  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
     V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), rb);
     str<R>(pn, v, p);
     const double px = p.x, py = p.y, pz = p.z;
@@ -598,7 +622,8 @@ __global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
   if (A.self) {
     PosReader<R> pos{xk, pk, 0.0, 0};
     const long long nq = A.ncand[0], npt = A.ncand[1];
-    for (long long q = tid; q < nq; q += stride) {
+    const Slice sq = block_slice(nq);
+    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
       int iv[4];
       Closest c;
       if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
@@ -626,11 +651,11 @@ __global__ void __launch_bounds__(kBlock) k_dir(Args<R> A, int k) {
 
 // --------------------------------------------------------------- finalize
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_finalize(Args<R> A, double* x_out, double* v_out) {
+__global__ void __launch_bounds__(kSBlock) k_finalize(Args<R> A, double* x_out, double* v_out) {
   const int fk = A.status->final_k;
   const double4* xf = xbuf(A, fk);
   const double ih = 1.0 / A.h;
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+  for (int v = blockIdx.x * kSBlock + threadIdx.x; v < A.nV; v += gridDim.x * kSBlock) {
     V3<double> x = ld3(xf, v), x0 = ld3(A.xstart, v);
     if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z))) raise_err(A.status, kErrNonfinite);
     x_out[3 * v] = x.x; x_out[3 * v + 1] = x.y; x_out[3 * v + 2] = x.z;
@@ -641,9 +666,9 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Args<R> A, double* x_out, d
 // ----------------------------------------------------------------- queries
 // Load query positions (row-major [nV][3]) into x0 and the predictor into xt.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_load_query(Args<R> A, const double* x, const double* xt, const double* p) {
+__global__ void __launch_bounds__(kSBlock) k_load_query(Args<R> A, const double* x, const double* xt, const double* p) {
   if (blockIdx.x == 0 && threadIdx.x == 0) A.status->err = 0;
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < A.nV; v += gridDim.x * kBlock) {
+  for (int v = blockIdx.x * kSBlock + threadIdx.x; v < A.nV; v += gridDim.x * kSBlock) {
     V3<double> xv = mk3(x[3 * v], x[3 * v + 1], x[3 * v + 2]);
     if (!(isfinite(xv.x) && isfinite(xv.y) && isfinite(xv.z))) raise_err(A.status, kErrNonfinite);
     st3(A.x0, v, xv);
@@ -662,9 +687,9 @@ __global__ void __launch_bounds__(kBlock) k_load_query(Args<R> A, const double* 
 // Pair terms at x0 for queries: WHAT = 0 gradient + diag into acc, 1 energy
 // partials, 2 H p into acc (acc[0..2]) and p^T H p partials (p in p0).
 template <typename R, int WHAT>
-__global__ void __launch_bounds__(kBlock) k_pairs_query(Args<R> A, double* part) {
-  __shared__ double sh[4 * 2];
-  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+__global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part) {
+  __shared__ double sh[kSWaves * 2];
+  const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   PosReader<R> pos{A.x0, A.p0, 0.0, 0};
   const long long nq = A.ncand[0], npt = A.ncand[1];
   double sum = 0.0;
@@ -715,9 +740,9 @@ __global__ void __launch_bounds__(kBlock) k_pairs_query(Args<R> A, double* part)
 
 // Energy of elements, inertia and planes at x0 (partials per block).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_energy(Args<R> A, double* part) {
-  __shared__ double sh[4 * 2];
-  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+__global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
+  __shared__ double sh[kSWaves * 2];
+  const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   double el = 0.0, vt = 0.0;
   for (int e = tid; e < A.nT; e += stride) {
     const ElemRec<R> rec = A.elem[e];
@@ -748,11 +773,11 @@ __global__ void __launch_bounds__(kBlock) k_energy(Args<R> A, double* part) {
 // H p by the vertex-centric sweep (p in p0, prescribed rows zero) and the
 // per-block partials of p^T H p.  Pair contributions must already be in acc.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
-  __shared__ double sh[4 * 2];
+__global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
+  __shared__ double sh[kSWaves * 2];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nw = (gridDim.x * kBlock) >> 6;
+  const int wid = (blockIdx.x * kSBlock + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * kSBlock) >> 6;
   double php = 0.0;
   for (int w = wid; w < A.nWaves; w += nw) {
     const int idx = w * kWave + lane;
@@ -808,12 +833,12 @@ __global__ void __launch_bounds__(kBlock) k_hvp(Args<R> A, double* out_hp, doubl
 }
 
 // Sum of n partials (one block), optionally plus `extra` partials.
-__global__ void __launch_bounds__(kBlock) k_sum_partials(const double* a, int na, const double* b, int nb, double* out) {
-  __shared__ double sh[4 * 1];
+__global__ void __launch_bounds__(kSBlock) k_sum_partials(const double* a, int na, const double* b, int nb, double* out) {
+  __shared__ double sh[kSWaves * 1];
   double s = 0.0;
-  for (int j = threadIdx.x; j < na; j += kBlock) s += a[j];
+  for (int j = threadIdx.x; j < na; j += kSBlock) s += a[j];
   if (b)
-    for (int j = threadIdx.x; j < nb; j += kBlock) s += b[j];
+    for (int j = threadIdx.x; j < nb; j += kSBlock) s += b[j];
   double v[1] = {s};
   const int kind[1] = {0};
   block_reduce<1>(v, kind, sh);
@@ -824,9 +849,9 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* a, int na
 // Minimum distance over candidate pairs (positions x0) and surface-vertex
 // plane distances, and minimum det F; partials [grid][2] (min d, min J).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_audit(Args<R> A, double* part) {
-  __shared__ double sh[4 * 2];
-  const int tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+__global__ void __launch_bounds__(kSBlock) k_audit(Args<R> A, double* part) {
+  __shared__ double sh[kSWaves * 2];
+  const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   double dmin = HUGE_VAL, jmin = HUGE_VAL;
   const long long nq = A.ncand[0], npt = A.ncand[1];
   for (long long q = tid; q < nq; q += stride) {
@@ -864,55 +889,55 @@ __global__ void __launch_bounds__(kBlock) k_audit(Args<R> A, double* part) {
 // ============================================================== launchers
 template <typename R>
 void launch_predict(const Args<R>& A, const double* x, const double* v, double3 grav, hipStream_t s) {
-  hipLaunchKernelGGL(k_predict<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x, v, grav);
+  hipLaunchKernelGGL(k_predict<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, x, v, grav);
 }
 template <typename R>
 void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
   if (A.self)
-    hipLaunchKernelGGL(k_narrow<R>, dim3(A.grid), dim3(kBlock), 0, s, A, k, mode);
+    hipLaunchKernelGGL(k_narrow<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
   else
-    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kBlock), 0, s, A, k, mode, (double*)nullptr,
+    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode, (double*)nullptr,
                        (double*)nullptr);
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
-  hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kBlock), 0, s, A, k, 0, (double*)nullptr,
+  hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0, (double*)nullptr,
                      (double*)nullptr);
 }
 template <typename R>
 void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_dir<R>, dim3(A.grid), dim3(kBlock), 0, s, A, k);
+  hipLaunchKernelGGL(k_dir<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, k);
 }
 template <typename R>
 void launch_finalize(const Args<R>& A, double* x_out, double* v_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x_out, v_out);
+  hipLaunchKernelGGL(k_finalize<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, x_out, v_out);
 }
 template <typename R>
 void launch_load_query(const Args<R>& A, const double* x, const double* xt, const double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_load_query<R>, dim3(A.grid), dim3(kBlock), 0, s, A, x, xt, p);
+  hipLaunchKernelGGL(k_load_query<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, x, xt, p);
 }
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
-  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kBlock), 0, s, A, 0, 0, g, d);
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kSBlock), 0, s, A, 0, 0, g, d);
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy<R>, dim3(A.grid), dim3(kBlock), 0, s, A, A.part_dir);
-  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 1>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, A.part_dir, A.grid,
+  hipLaunchKernelGGL(k_energy<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_dir);
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 1>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid,
                      A.self ? A.part_narrow : (const double*)nullptr, A.grid, out);
 }
 template <typename R>
 void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) {
-  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL(k_hvp<R>, dim3(A.grid), dim3(kBlock), 0, s, A, hp, A.part_dir);
+  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  hipLaunchKernelGGL(k_hvp<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir);
   // pair p^T H p is already inside H p at the vertices, so only k_hvp's partials are summed
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
 }
 template <typename R>
 void launch_audit(const Args<R>& A, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_audit<R>, dim3(A.grid), dim3(kBlock), 0, s, A, part);
+  hipLaunchKernelGGL(k_audit<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, part);
 }
 
 #define PNCG_INSTANTIATE(R)                                                                          \
