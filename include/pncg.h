@@ -221,6 +221,89 @@ int pncg_min_distance(pncg_ctx* ctx, const double* x, double* dmin,
 int pncg_set_profiling(pncg_ctx* ctx, int32_t on);
 int pncg_get_profile(pncg_ctx* ctx, double* total_us, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many small independent scenes stepped together on one
+ * device.  Each scene is one workgroup that runs a whole time step of
+ * Algorithm 1 (predictor, every PNCG iteration with its own beta, alpha and
+ * stop test, end of step) without returning to the host; the workgroups of a
+ * persistent grid take scenes largest first.  A scene has elasticity,
+ * inertia, gravity and at most one contact plane (barrier against a
+ * half-space, Sec. 3 equation barrier with d the signed plane distance);
+ * there are no point-triangle or edge-edge pairs between or within scenes.
+ * The step size bound (Sec. 4.3) is per scene, in the spirit of the
+ * per-object step sizes of Sec. 5.2.  All arithmetic is the single-scene
+ * path's for a scene with one plane and no self contact.
+ * ---------------------------------------------------------------------- */
+typedef struct pncg_batch pncg_batch;
+
+/* Create a batch of nScenes scenes from concatenated arrays (host pointers,
+ * copied).  Scene s owns vertices [vert_off[s], vert_off[s+1]), tets
+ * [tet_off[s], tet_off[s+1]) and surface triangles [tri_off[s],
+ * tri_off[s+1]) (surface triangles only mark the vertices that feel the
+ * plane).  Offsets have nScenes + 1 entries starting at 0; every scene has
+ * at least one vertex and one tet.  X [nV][3] rest positions; tets [nT][4]
+ * and tris [nF][3] hold vertex indices LOCAL to their scene, tets
+ * positively oriented (E_INVERTED otherwise); E, nu, rho [nT] as in
+ * pncg_set_material; planes [nScenes][4] (n0, n1, n2, o) with |n| = 1, or
+ * a zero normal for no plane, or planes = NULL for none at all.
+ * opts: device, precision and stream as for pncg_create (block and chunk
+ * are ignored).  Errors: E_INVAL, E_INVERTED, E_NONFINITE, E_HIP, E_NOMEM;
+ * pncg_batch_last_error(NULL) then describes the failure. */
+int pncg_batch_create(pncg_batch** out, const pncg_opts* opts, int32_t nScenes,
+                      const int32_t* vert_off, const double* X,
+                      const int32_t* tet_off, const int32_t* tets,
+                      const int32_t* tri_off, const int32_t* tris,
+                      const double* E, const double* nu, const double* rho,
+                      const double* planes);
+
+/* Free the batch and its device memory.  NULL is accepted. */
+void pncg_batch_destroy(pncg_batch* b);
+
+/* Message for the last error of b (never NULL); b == NULL: the last
+ * pncg_batch_create failure on this thread. */
+const char* pncg_batch_last_error(const pncg_batch* b);
+
+/* Parameters shared by all scenes: dhat > 0, kappa >= 0 (plane barrier),
+ * iter_max >= 1, eps >= 0, term PNCG_TERM_*, gravity[3] (NULL keeps the
+ * current value), flags PNCG_BARRIER_FULL / PNCG_ALPHA_INF_COMPONENT (the
+ * plane Hessian is the same in both barrier modes).  Defaults: dhat 1e-3,
+ * kappa 1e4, 100, 1e-3, DELTA_E, (0, 0, -9.8), 0. */
+int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa,
+                          int32_t iter_max, double eps, int32_t term,
+                          const double* gravity, uint32_t flags);
+
+/* Threads per workgroup of the step kernel: 256, 512 or 1024 (default
+ * 512); pncg_batch_autotune picks one by timing. */
+int pncg_batch_set_block(pncg_batch* b, int32_t block);
+
+/* One time step of every scene with step size h > 0.  Device pointers on the
+ * batch's device: x_dev, v_dev [nV][3] the state, x_out_dev, v_out_dev
+ * [nV][3] the result (must not alias the inputs).  Ordered on the batch's
+ * stream; the call synchronises it.  E_PENETRATION / E_INVERTED if some
+ * scene's state is infeasible. */
+int pncg_batch_step(pncg_batch* b, const double* x_dev, const double* v_dev,
+                    double h, double* x_out_dev, double* v_out_dev);
+
+/* nsteps >= 1 consecutive steps in place on x_dev, v_dev (device
+ * pointers), launched as one HIP graph that the batch captures on first use
+ * and replays while (x_dev, v_dev, h, nsteps, block size, parameters) stay
+ * the same.  The call synchronises the stream. */
+int pncg_batch_run(pncg_batch* b, double* x_dev, double* v_dev, double h,
+                   int32_t nsteps);
+
+/* Per-scene statistics of the last step (host arrays [nScenes], each
+ * nullable): iterations, stop reason (as pncg_stats.reason), and iterations
+ * summed over every step since creation. */
+int pncg_batch_stats(pncg_batch* b, int32_t* iters, int32_t* reason,
+                     int64_t* iters_total);
+
+/* Time reps steps from (x_dev, v_dev) at each workgroup size and keep the
+ * fastest (written to *block_out if non-NULL).  The state is not modified;
+ * iters_total advances by the timed steps. */
+int pncg_batch_autotune(pncg_batch* b, const double* x_dev,
+                        const double* v_dev, double h, int32_t reps,
+                        int32_t* block_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,10 @@ CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP"
 EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "pncg_set_material",
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
            "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
-           "pncg_set_profiling", "pncg_get_profile")
+           "pncg_set_profiling", "pncg_get_profile",
+           "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
+           "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
+           "pncg_batch_autotune")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -76,6 +79,15 @@ def _load():
         "pncg_min_distance": (I32, [P, P, P, P]),
         "pncg_set_profiling": (I32, [P, I32]),
         "pncg_get_profile": (I32, [P, P, P]),
+        "pncg_batch_create": (I32, [C.POINTER(P), C.POINTER(pncg_opts), I32, P, P, P, P, P, P, P, P, P, P]),
+        "pncg_batch_destroy": (None, [P]),
+        "pncg_batch_last_error": (C.c_char_p, [P]),
+        "pncg_batch_set_params": (I32, [P, D, D, I32, D, I32, P, U32]),
+        "pncg_batch_set_block": (I32, [P, I32]),
+        "pncg_batch_step": (I32, [P, P, P, D, P, P]),
+        "pncg_batch_run": (I32, [P, P, P, D, I32]),
+        "pncg_batch_stats": (I32, [P, P, P, P]),
+        "pncg_batch_autotune": (I32, [P, P, P, D, I32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +248,89 @@ class Context:
         n = np.zeros(len(PROF_KINDS), dtype=np.int64)
         self._check(_L.pncg_get_profile(self._h, _ptr(us), _ptr(n)))
         return {k: (float(us[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
+
+
+def _dev_ptr(t, n, what):
+    if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+            and tuple(t.shape) == (n, 3)):
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor of shape ({n}, 3)")
+    return C.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """A batch of independent scenes (pncg_batch_*): concatenated meshes
+    with per-scene offsets and scene-local indices."""
+
+    def __init__(self, vert_off, X, tet_off, tets, tri_off, tris, E, nu, rho, planes=None,
+                 device=0, precision=FP64, stream=None):
+        vert_off, tet_off, tri_off = _i32(vert_off), _i32(tet_off), _i32(tri_off)
+        X, E, nu, rho = _f64(X), _f64(E), _f64(nu), _f64(rho)
+        tets, tris = _i32(tets), _i32(tris)
+        S = vert_off.shape[0] - 1
+        if tet_off.shape[0] != S + 1 or tri_off.shape[0] != S + 1:
+            raise ValueError("offset arrays must all have nScenes + 1 entries")
+        nV, nT, nF = int(vert_off[-1]), int(tet_off[-1]), int(tri_off[-1])
+        if X.shape != (nV, 3) or tets.shape != (nT, 4) or tris.reshape(-1, 3).shape[0] != nF:
+            raise ValueError("array sizes do not match the offsets")
+        if E.shape != (nT,) or nu.shape != (nT,) or rho.shape != (nT,):
+            raise ValueError("E, nu, rho need one value per tet")
+        pl = None if planes is None else _f64(planes).reshape(S, 4)
+        opts = pncg_opts(device, precision, stream, 0, 0)
+        h = C.c_void_p()
+        rc = _L.pncg_batch_create(C.byref(h), C.byref(opts), S, _ptr(vert_off), _ptr(X), _ptr(tet_off), _ptr(tets),
+                                  _ptr(tri_off), _ptr(tris), _ptr(E), _ptr(nu), _ptr(rho), _ptr(pl))
+        if rc < 0:
+            raise PncgError(rc, _L.pncg_batch_last_error(None).decode())
+        self._h = h
+        self.nScenes, self.nV, self.nT = S, nV, nT
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.pncg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PncgError(rc, _L.pncg_batch_last_error(self._h).decode())
+        return rc
+
+    def pncg_batch_set_params(self, dhat, kappa, iter_max=100, eps=1e-3, term=TERM_DELTA_E,
+                              gravity=(0.0, 0.0, -9.8), flags=0):
+        g = _f64(gravity)
+        self._check(_L.pncg_batch_set_params(self._h, float(dhat), float(kappa), int(iter_max), float(eps), int(term),
+                                             _ptr(g), int(flags)))
+
+    def pncg_batch_set_block(self, block):
+        self._check(_L.pncg_batch_set_block(self._h, int(block)))
+
+    def pncg_batch_step(self, x, v, h, x_out, v_out):
+        """float64 CUDA tensors (nV, 3); x_out/v_out must not alias x/v."""
+        n = self.nV
+        self._check(_L.pncg_batch_step(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h),
+                                       _dev_ptr(x_out, n, "x_out"), _dev_ptr(v_out, n, "v_out")))
+
+    def pncg_batch_run(self, x, v, h, nsteps):
+        """nsteps steps in place on the float64 CUDA tensors x, v (nV, 3)."""
+        n = self.nV
+        self._check(_L.pncg_batch_run(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(nsteps)))
+
+    def pncg_batch_stats(self):
+        it = np.zeros(self.nScenes, dtype=np.int32)
+        rs = np.zeros(self.nScenes, dtype=np.int32)
+        tot = np.zeros(self.nScenes, dtype=np.int64)
+        self._check(_L.pncg_batch_stats(self._h, _ptr(it), _ptr(rs), _ptr(tot)))
+        return it, rs, tot
+
+    def pncg_batch_autotune(self, x, v, h, reps=3):
+        n = self.nV
+        out = C.c_int32()
+        self._check(_L.pncg_batch_autotune(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(reps),
+                                           C.byref(out)))
+        return out.value
 
 
 def pncg_create(device=0, precision=FP64, stream=None, chunk=0):

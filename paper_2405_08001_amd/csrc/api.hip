@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pncg.h"
+#include "host_mesh.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -680,57 +681,11 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
     if (edges[i] < 0 || edges[i] >= nV) return fail(c, PNCG_E_INVAL, "edge index out of range");
   for (int e = 0; e < nE; ++e)
     if (edges[2 * e] == edges[2 * e + 1]) return fail(c, PNCG_E_INVAL, "degenerate edge");
-  std::vector<double> Bm(9 * (size_t)nT), vol(nT);
-  for (int e = 0; e < nT; ++e) {
-    const int* t = tets + 4 * e;
-    double D[3][3];
-    for (int j = 0; j < 3; ++j)
-      for (int i = 0; i < 3; ++i) D[i][j] = X[3 * t[j + 1] + i] - X[3 * t[0] + i];
-    const double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
-                       D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
-                       D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
-    if (!(det > 0.0)) return fail(c, PNCG_E_INVERTED, "rest tet " + std::to_string(e) + " has det <= 0");
-    const double id = 1.0 / det;
-    // inverse of D (rows of D^{-1} are the shape vectors b_1..b_3)
-    double Inv[3][3];
-    Inv[0][0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) * id;
-    Inv[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
-    Inv[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
-    Inv[1][0] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) * id;
-    Inv[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
-    Inv[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
-    Inv[2][0] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) * id;
-    Inv[2][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * id;
-    Inv[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
-    for (int r = 0; r < 3; ++r)
-      for (int j = 0; j < 3; ++j) Bm[9 * (size_t)e + 3 * r + j] = Inv[r][j];
-    vol[e] = det / 6.0;
-  }
-  // vertex -> (tet, corner) incidence, packed into 64-lane waves
-  std::vector<int> deg(nV, 0);
-  for (long long i = 0; i < 4LL * nT; ++i) deg[tets[i]]++;
-  int maxdeg = 0;
-  for (int v = 0; v < nV; ++v) maxdeg = std::max(maxdeg, deg[v]);
-  if (maxdeg > kWave) return fail(c, PNCG_E_INVAL, "a vertex belongs to more than 64 tets");
-  std::vector<int> off(nV + 1, 0);
-  for (int v = 0; v < nV; ++v) off[v + 1] = off[v] + deg[v];
-  std::vector<int> lst(4 * (size_t)nT), fill(off.begin(), off.end() - 1);
-  for (int e = 0; e < nT; ++e)
-    for (int a = 0; a < 4; ++a) lst[fill[tets[4 * e + a]]++] = 4 * e + a;
+  std::vector<double> Bm, vol;
+  int bad = rest_shape(X, tets, nT, Bm, vol);
+  if (bad >= 0) return fail(c, PNCG_E_INVERTED, "rest tet " + std::to_string(bad) + " has det <= 0");
   std::vector<int> inc, incv;
-  inc.reserve(4 * (size_t)nT + nV);
-  int used = 0;
-  for (int v = 0; v < nV; ++v) {
-    const int d = std::max(deg[v], 1);
-    if (used + d > kWave) {
-      while (used < kWave) { inc.push_back(-1); incv.push_back(-1); ++used; }
-      used = 0;
-    }
-    if (deg[v] == 0) { inc.push_back(-2); incv.push_back(v); }
-    for (int i = off[v]; i < off[v + 1]; ++i) { inc.push_back(lst[i]); incv.push_back(v); }
-    used += d;
-  }
-  while (used % kWave) { inc.push_back(-1); incv.push_back(-1); ++used; }
+  if (!pack_incidence(nV, tets, nT, 0, inc, incv)) return fail(c, PNCG_E_INVAL, "a vertex belongs to more than 64 tets");
   // surface vertices and flags
   std::vector<uint8_t> fl(nV, 0);
   std::vector<int> surf;

@@ -1,0 +1,226 @@
+// Batched form: many independent scenes (concatenated meshes), each stepped
+// by one workgroup that runs the whole time step of Algorithm 1 (Sec. 4) on
+// its own: predictor, every PNCG iteration with its per-scene beta, alpha and
+// stop test, and the end-of-step velocity.  The grid-wide reductions of the
+// single-scene path become block reductions, so an iteration costs no kernel
+// launch; the grid is persistent (workgroups loop over scenes, largest
+// first).  Scenes have plane contact only (one optional plane each); the
+// per-scene scalars follow the separate-step-size-per-object idea of Sec. 5.2.
+#include "batch.h"
+#include "sweep_common.h"
+
+namespace pncg {
+
+template <typename R, int BS>
+__global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double* x_in, const double* v_in,
+                                                   double* x_out, double* v_out) {
+  constexpr int NW = BS / kWave;
+  __shared__ double sh[NW * 8];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  for (int si = blockIdx.x; si < A.nScenes; si += gridDim.x) {
+    const int s = A.order[si];
+    const int v0 = A.vert_off[s], v1 = A.vert_off[s + 1];
+    const int t0 = A.tet_off[s], t1 = A.tet_off[s + 1];
+    const int w0 = A.wave_off[s], w1 = A.wave_off[s + 1];
+    const double* pl = A.planes + 4 * s;
+    const bool has_plane = pl[0] != 0.0 || pl[1] != 0.0 || pl[2] != 0.0;
+    // predictor: xt = x + h v + h^2 g; x_0 = x^t
+    for (int v = v0 + tid; v < v1; v += BS) {
+      const V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
+      const V3<double> u = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
+      st3(A.xstart, v, x);
+      st3(A.x, v, x);
+      V3<double> xt = x + A.h * u;
+      xt = xt + A.h2 * A.grav;
+      st3(A.xt, v, xt);
+      str<R>(A.g, v, mk3(R(0), R(0), R(0)));
+      str<R>(A.p, v, mk3(R(0), R(0), R(0)));
+    }
+    __syncthreads();
+    int k = 0, reason = 2;
+    double g0 = 0.0, dE0 = 0.0;
+    PosReader<R> pos{A.x, A.p, 0.0, 0};
+    for (;;) {
+      // ---- gradient, diag(H), dot products (vertex-centric sweep)
+      double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int w = w0 + wave; w < w1; w += NW) {
+        const int idx = w * kWave + lane;
+        const int code = A.inc[idx];
+        const int myv = A.inc_vert[idx];
+        R sv[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        if (code >= 0) {
+          const ElemRec<R> rec = A.elem[code >> 2];
+          Kin<R> kin = kinematics<R>(rec.B, pos(rec.v[0]), pos(rec.v[1]), pos(rec.v[2]), pos(rec.v[3]));
+          if (kin.J > R(0)) {
+            V3<R> g, dg;
+            nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg);
+            sv[0] = g.x; sv[1] = g.y; sv[2] = g.z; sv[3] = dg.x; sv[4] = dg.y; sv[5] = dg.z;
+          } else {
+            atomicOr(A.err, kErrInverted);
+          }
+        }
+        seg_sum<R>(myv, sv);
+        const int upv = __shfl_up(myv, 1, kWave);
+        if (myv < 0 || (lane > 0 && upv == myv)) continue;
+        const int v = myv;
+        const V3<double> x = ld3(A.x, v), xt = ld3(A.xt, v);
+        const double m = A.mass[v];
+        double gd[3] = {A.h2 * double(sv[0]) + m * (x.x - xt.x), A.h2 * double(sv[1]) + m * (x.y - xt.y),
+                        A.h2 * double(sv[2]) + m * (x.z - xt.z)};
+        double dd[3] = {A.h2 * double(sv[3]) + m, A.h2 * double(sv[4]) + m, A.h2 * double(sv[5]) + m};
+        if (has_plane && (A.vflag[v] & kSurface)) {
+          const double d = plane_dist(pl, x);
+          if (d < A.dhat) {
+            if (!(d > 0.0)) {
+              atomicOr(A.err, kErrPenetration);
+            } else {
+              const double b1 = A.kappa * barrier_db(d, A.dhat), b2 = A.kappa * barrier_d2b(d, A.dhat);
+              for (int j = 0; j < 3; ++j) {
+                gd[j] += b1 * pl[j];
+                dd[j] += b2 * pl[j] * pl[j];
+              }
+            }
+          }
+        }
+        const V3<R> gR = mk3(R(gd[0]), R(gd[1]), R(gd[2]));
+        const V3<R> pgR = mk3(R(gd[0] / dd[0]), R(gd[1] / dd[1]), R(gd[2] / dd[2]));
+        const V3<R> gpR = ldr<R>(A.g, v), ppR = ldr<R>(A.p, v);
+        str<R>(A.g, v, gR);
+        str<R>(A.pg, v, pgR);
+        const double g3[3] = {double(gR.x), double(gR.y), double(gR.z)};
+        const double pg3[3] = {double(pgR.x), double(pgR.y), double(pgR.z)};
+        const double gp3[3] = {double(gpR.x), double(gpR.y), double(gpR.z)};
+        const double pp3[3] = {double(ppR.x), double(ppR.y), double(ppR.z)};
+        for (int j = 0; j < 3; ++j) {
+          const double P = 1.0 / dd[j], y = g3[j] - gp3[j];
+          dots[0] += g3[j] * g3[j];
+          dots[1] += g3[j] * pg3[j];
+          dots[2] += g3[j] * P * y;
+          dots[3] += y * pp3[j];
+          dots[4] += y * P * y;
+          dots[5] += pp3[j] * g3[j];
+        }
+      }
+      {
+        const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        block_reduce<8, BS>(dots, kind, sh);
+      }
+      const double gnorm = sqrt(dots[0]);
+      if (k == 0) g0 = gnorm;
+      if (A.term == 1 && gnorm <= A.eps * g0) { reason = 1; break; }
+      double beta = 0.0;
+      if (k > 0 && dots[3] != 0.0) {
+        beta = dots[2] / dots[3] - (dots[4] / dots[3]) * (dots[5] / dots[3]);
+        if (!isfinite(beta)) beta = 0.0;
+      }
+      double gTp = -dots[1] + beta * dots[5];
+      if (!(gTp < 0.0)) {
+        beta = 0.0;
+        gTp = -dots[1];
+      }
+      if (gTp == 0.0) { reason = 3; break; }
+      // ---- direction p = -P g + beta p (in place), inertia and plane parts of p^T H p
+      const R rb = R(beta);
+      double php = 0.0, pmv = 0.0, pmc = 0.0;
+      for (int v = v0 + tid; v < v1; v += BS) {
+        const V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(A.p, v), rb);
+        str<R>(A.p, v, p);
+        const double px = p.x, py = p.y, pz = p.z, p2 = px * px + py * py + pz * pz;
+        php += A.mass[v] * p2;
+        pmv = fmax(pmv, sqrt(p2));
+        pmc = fmax(pmc, fmax(fabs(px), fmax(fabs(py), fabs(pz))));
+        if (has_plane && (A.vflag[v] & kSurface)) {
+          const double d = plane_dist(pl, ld3(A.x, v));
+          if (d > 0.0 && d < A.dhat) {
+            const double np = pl[0] * px + pl[1] * py + pl[2] * pz;
+            php += A.kappa * barrier_d2b(d, A.dhat) * np * np;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- element p^T H p
+      double el = 0.0;
+      for (int e = t0 + tid; e < t1; e += BS) {
+        const ElemRec<R> rec = A.elem[e];
+        Kin<R> kin = kinematics<R>(rec.B, ld3(A.x, rec.v[0]), ld3(A.x, rec.v[1]), ld3(A.x, rec.v[2]),
+                                   ld3(A.x, rec.v[3]));
+        V3<R> d[3];
+        dF_cols(rec.B, ldr<R>(A.p, rec.v[0]), ldr<R>(A.p, rec.v[1]), ldr<R>(A.p, rec.v[2]), ldr<R>(A.p, rec.v[3]), d);
+        el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+      }
+      double red[3] = {php + A.h2 * el, pmv, pmc};
+      {
+        const int kind[3] = {0, 1, 1};
+        block_reduce<3, BS>(red, kind, sh);
+      }
+      const double pHp = red[0];
+      const double pm = (A.flags & 2u) ? red[2] : red[1];
+      const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
+      const double aup = (has_plane && pm > 0.0) ? A.dhat / (2.0 * pm) : HUGE_VAL;
+      const double alpha = fmin(aup, abar);
+      if (!isfinite(alpha)) { reason = 3; break; }
+      // ---- update
+      for (int v = v0 + tid; v < v1; v += BS) {
+        const V3<double> x = ld3(A.x, v);
+        const R4<R> q = A.p[v];
+        st3(A.x, v, mk3(fma(alpha, double(q.x), x.x), fma(alpha, double(q.y), x.y), fma(alpha, double(q.z), x.z)));
+      }
+      const double dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
+      if (k == 0) dE0 = dE;
+      ++k;
+      __syncthreads();
+      if (A.term == 0 && dE < A.eps * dE0) { reason = 0; break; }
+      if (k >= A.iter_max) { reason = 2; break; }
+    }
+    // end of step: v = (x - x^t) / h
+    const double ih = 1.0 / A.h;
+    for (int v = v0 + tid; v < v1; v += BS) {
+      const V3<double> x = ld3(A.x, v), xs = ld3(A.xstart, v);
+      x_out[3 * v] = x.x; x_out[3 * v + 1] = x.y; x_out[3 * v + 2] = x.z;
+      v_out[3 * v] = (x.x - xs.x) * ih; v_out[3 * v + 1] = (x.y - xs.y) * ih; v_out[3 * v + 2] = (x.z - xs.z) * ih;
+    }
+    if (tid == 0) {
+      A.iters[s] = k;
+      A.reason[s] = reason;
+      A.iters_total[s] += k;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R>
+void launch_batch_step(const BatchArgs<R>& A, int block, int grid, const double* x, const double* v, double* xo,
+                       double* vo, hipStream_t s) {
+  switch (block) {
+    case 256:
+      hipLaunchKernelGGL((k_batch_step<R, 256>), dim3(grid), dim3(256), 0, s, A, x, v, xo, vo);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_batch_step<R, 512>), dim3(grid), dim3(512), 0, s, A, x, v, xo, vo);
+      break;
+    default:
+      hipLaunchKernelGGL((k_batch_step<R, 1024>), dim3(grid), dim3(1024), 0, s, A, x, v, xo, vo);
+      break;
+  }
+}
+
+template <typename R>
+hipError_t batch_occupancy(int block, int* per_cu) {
+  switch (block) {
+    case 256:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 256>, 256, 0);
+    case 512:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 512>, 512, 0);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 1024>, 1024, 0);
+  }
+}
+
+template hipError_t batch_occupancy<float>(int, int*);
+template hipError_t batch_occupancy<double>(int, int*);
+template void launch_batch_step<float>(const BatchArgs<float>&, int, int, const double*, const double*, double*,
+                                       double*, hipStream_t);
+template void launch_batch_step<double>(const BatchArgs<double>&, int, int, const double*, const double*, double*,
+                                        double*, hipStream_t);
+
+}  // namespace pncg

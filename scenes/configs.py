@@ -216,6 +216,36 @@ def batched_scenes(seed=3, n_scenes=256, t_lo=500, t_hi=8000, drop=0.05):
     return out
 
 
+def pack_batch(scs, x=None, v=None):
+    """Concatenate scenes for the batched entry points: per-scene offsets,
+    scene-local indices, one plane row per scene (zero normal if none).
+    ``x``/``v`` (lists of per-scene states, default x0/v0) are stacked too."""
+    nv = [s.nV for s in scs]
+    nt = [s.nT for s in scs]
+    nf = [len(s.tris) for s in scs]
+    planes = np.zeros((len(scs), 4))
+    for i, s in enumerate(scs):
+        if len(s.planes) > 1:
+            raise ValueError("a batched scene has at most one plane")
+        if len(s.planes):
+            planes[i] = s.planes[0]
+    cat = lambda arrs, shape: (np.concatenate(arrs) if arrs else np.zeros(shape))
+    return dict(
+        vert_off=np.concatenate([[0], np.cumsum(nv)]).astype(np.int32),
+        tet_off=np.concatenate([[0], np.cumsum(nt)]).astype(np.int32),
+        tri_off=np.concatenate([[0], np.cumsum(nf)]).astype(np.int32),
+        X=cat([s.X for s in scs], (0, 3)),
+        tets=cat([s.tets for s in scs], (0, 4)).astype(np.int32),
+        tris=cat([s.tris for s in scs], (0, 3)).astype(np.int32),
+        E=cat([np.broadcast_to(s.E, (s.nT,)) for s in scs], (0,)),
+        nu=cat([np.broadcast_to(s.nu, (s.nT,)) for s in scs], (0,)),
+        rho=cat([np.broadcast_to(s.rho, (s.nT,)) for s in scs], (0,)),
+        planes=planes,
+        x=cat([s.x0 for s in scs] if x is None else list(x), (0, 3)),
+        v=cat([s.v0 for s in scs] if v is None else list(v), (0, 3)),
+    )
+
+
 def diff_bar_scene(seed=4, nx=50, ny=10, nz=10, dx=0.01, lift=0.01):
     """Bar whose per-tet Young's modulus is E = 1e5 * exp(0.5 z), z ~ N(0,1),
     starting ``lift`` metres above the ground plane."""

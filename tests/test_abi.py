@@ -119,3 +119,49 @@ def test_valid_mesh_without_gpu_fails_loudly():
     with pytest.raises(P.PncgError) as e:
         c.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges)
     assert e.value.code == P.E_HIP
+
+
+def _batch_args(n=3):
+    scs = scenes.batched_scenes(n_scenes=n, t_lo=30, t_hi=200)
+    b = scenes.pack_batch(scs)
+    return {k: b[k] for k in ("vert_off", "X", "tet_off", "tets", "tri_off", "tris", "E", "nu", "rho", "planes")}
+
+
+def test_batch_create_validation():
+    """Host-side checks of pncg_batch_create run before any device call."""
+    import paper_2405_08001_amd as P
+    a = _batch_args()
+    bad = dict(a, tets=a["tets"].copy())
+    bad["tets"][a["tet_off"][1], 0] = a["vert_off"][2] - a["vert_off"][1]   # local index past scene 1's vertices
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**bad)
+    assert e.value.code == P.E_INVAL and "scene 1" in str(e.value)
+    bad = dict(a, tets=a["tets"].copy())
+    bad["tets"][0, [0, 1]] = bad["tets"][0, [1, 0]]                          # negative orientation
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**bad)
+    assert e.value.code == P.E_INVERTED
+    bad = dict(a, E=a["E"].copy())
+    bad["E"][5] = -1.0
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**bad)
+    assert e.value.code == P.E_INVAL
+    bad = dict(a, planes=a["planes"] * 2.0)                                  # non-unit normal
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**bad)
+    assert e.value.code == P.E_INVAL
+    bad = dict(a, tet_off=a["tet_off"].copy())
+    bad["tet_off"][2] = bad["tet_off"][1]                                    # a scene without tets
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**bad)
+    assert e.value.code == P.E_INVAL
+
+
+def test_batch_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_2405_08001_amd as P
+    with pytest.raises(P.PncgError) as e:
+        P.Batch(**_batch_args())
+    assert e.value.code == P.E_HIP

@@ -1,0 +1,213 @@
+"""Batched form on the GPU: every scene of a batch against the oracle run on
+that scene alone, the batch against the single-scene path, multi-step graph
+replays against eager steps, and the autotuner."""
+import sys
+
+import numpy as np
+import pytest
+
+import scenes
+from helpers import make_ctx, make_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _states(scs, seed):
+    """Even scenes start 1.2 mm above their floor moving down at 0.1 m/s (the
+    plane barrier engages within the step); odd scenes start as configured
+    (free fall from 5 cm, no contact)."""
+    rng = np.random.default_rng(seed)
+    xs, vs = [], []
+    for i, s in enumerate(scs):
+        x = s.x0.copy()
+        v = s.v0.copy()
+        if i % 2 == 0:
+            x[:, 2] -= x[:, 2].min() - 1.2e-3
+            x += rng.uniform(-5e-5, 5e-5, x.shape)
+            v[:, 2] = -0.1
+        xs.append(x)
+        vs.append(v)
+    return xs, vs
+
+
+def _small_batch():
+    scs = scenes.batched_scenes(seed=5, n_scenes=8, t_lo=30, t_hi=4000)
+    return scs
+
+
+def _make_batch(scs, precision, iter_max, eps, term):
+    import paper_2405_08001_amd as P
+    b = scenes.pack_batch(scs)
+    bt = P.Batch(b["vert_off"], b["X"], b["tet_off"], b["tets"], b["tri_off"], b["tris"], b["E"], b["nu"],
+                 b["rho"], b["planes"], precision=precision)
+    s0 = scs[0]
+    bt.pncg_batch_set_params(s0.dhat, s0.kappa, iter_max, eps,
+                             {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL}[term], s0.gravity, 0)
+    return bt, b
+
+
+def _step(bt, x, v, h):
+    import torch
+    dev = torch.device("cuda:0")
+    xd = torch.tensor(x, dtype=torch.float64, device=dev)
+    vd = torch.tensor(v, dtype=torch.float64, device=dev)
+    xo = torch.empty_like(xd)
+    vo = torch.empty_like(vd)
+    bt.pncg_batch_step(xd, vd, h, xo, vo)
+    return xo.cpu().numpy(), vo.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("K", [1, 3, 12])
+def test_batch_fixed_iterations_match_oracle(K, precision):
+    """K iterations of Algorithm 1 in every scene (no early stop), each scene
+    against the oracle stepping that scene alone."""
+    from oracle import pncg
+    scs = _small_batch()
+    _say(f"batch fixed K={K} precision={precision}: tets {[s.nT for s in scs]}")
+    xs, vs = _states(scs, 1)
+    bt, b = _make_batch(scs, precision, K, 0.0, "delta_e")
+    xg, vg = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
+    it, rs, tot = bt.pncg_batch_stats()
+    off = b["vert_off"]
+    for i, s in enumerate(scs):
+        P = make_problem(s)
+        xo, vo, st = pncg.step(P, xs[i], vs[i], s.h, iter_max=K, eps=0.0, term="delta_e")
+        sl = slice(off[i], off[i + 1])
+        rx, rdx = rel(xg[sl], xo), rel(xg[sl] - xs[i], xo - xs[i])
+        bx, bdx = (1e-12, 1e-9) if precision == 0 else (1e-6, 1e-3)
+        if precision == 1 and K > 3:
+            # float32 element arithmetic perturbs every gradient by about one
+            # float32 rounding; after several nonlinear CG iterations some
+            # scenes amplify that.  The oracle's own spread under a 2^-24
+            # relative perturbation of the start state measures how much.
+            xq = xs[i] * (1.0 + 2.0 ** -24)
+            xp, _, _ = pncg.step(P, xq, vs[i], s.h, iter_max=K, eps=0.0, term="delta_e")
+            bx = max(bx, 4.0 * rel(xp, xo))
+            bdx = max(bdx, 4.0 * rel(xp - xq, xo - xs[i]))
+        _say(f"  scene {i} ({s.nT} tets): iters {it[i]}/{st.iters} rel_x={rx:.3e} (bar {bx:.1e}) "
+             f"rel_dx={rdx:.3e} (bar {bdx:.1e})")
+        assert it[i] == st.iters == K
+        assert rx <= bx
+        assert rdx <= bdx
+        assert rel(vg[sl], vo) <= bdx
+    assert np.all(tot == K)
+
+
+def test_batch_converged_matches_oracle():
+    """Tightly converged steps (gradient rule, 1e-9): both sides reach the same
+    minimiser in every scene."""
+    from oracle import pncg
+    scs = _small_batch()
+    _say("batch converged fp64")
+    xs, vs = _states(scs, 2)
+    bt, b = _make_batch(scs, 0, 4000, 1e-9, "grad_rel")
+    xg, _ = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
+    it, rs, _ = bt.pncg_batch_stats()
+    off = b["vert_off"]
+    assert np.all(rs == 1)
+    for i, s in enumerate(scs):
+        if s.nT > 2500:          # the oracle needs ~40 s for the 4374-tet scene
+            continue
+        xo, _, st = pncg.step(make_problem(s), xs[i], vs[i], s.h, iter_max=4000, eps=1e-9, term="grad_rel")
+        sl = slice(off[i], off[i + 1])
+        rx = rel(xg[sl], xo)
+        _say(f"  scene {i}: iters {it[i]}/{st.iters} reason {rs[i]}/{st.reason} rel_x={rx:.3e}")
+        assert rs[i] == 1
+        assert rx <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_single_scene_path(precision):
+    """Fixed 6 iterations per scene: the batched kernel and the single-scene
+    entry points (one context per scene, same plane, no self contact) agree
+    to rounding."""
+    scs = _small_batch()[:4]
+    _say(f"batch vs single-scene precision={precision}")
+    xs, vs = _states(scs, 3)
+    bt, b = _make_batch(scs, precision, 6, 0.0, "delta_e")
+    xg, vg = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
+    off = b["vert_off"]
+    for i, s in enumerate(scs):
+        ctx = make_ctx(s, precision, iter_max=6, eps=0.0, term="delta_e")
+        xc, vc, sc = ctx.pncg_step(xs[i], vs[i], s.h)
+        sl = slice(off[i], off[i + 1])
+        rdx = rel(xg[sl] - xs[i], xc - xs[i])
+        _say(f"  scene {i}: rel_dx={rdx:.3e}")
+        assert sc["iters"] == 6
+        assert rdx <= (1e-9 if precision == 0 else 1e-3)
+
+
+def test_batch_graph_replays_equal_eager_steps():
+    """pncg_batch_run (a captured graph of 3 steps, replayed) gives the same
+    bits as 3 eager pncg_batch_step calls, on every replay."""
+    import torch
+    scs = _small_batch()
+    _say("batch graph replay vs eager")
+    xs, vs = _states(scs, 4)
+    bt, b = _make_batch(scs, 0, 100, 1e-3, "delta_e")
+    h = scs[0].h
+    dev = torch.device("cuda:0")
+    x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
+    xe, ve = x.clone(), v.clone()
+    xn, vn = torch.empty_like(x), torch.empty_like(v)
+    for rep in range(3):
+        bt.pncg_batch_run(x, v, h, 3)
+        for _ in range(3):
+            bt.pncg_batch_step(xe, ve, h, xn, vn)
+            xe, xn, ve, vn = xn, xe, vn, ve
+        torch.cuda.synchronize()
+        same = bool(torch.equal(x, xe) and torch.equal(v, ve))
+        _say(f"  replay {rep}: identical={same}")
+        assert same
+        assert bool(torch.isfinite(x).all())
+
+
+def test_batch_autotune_keeps_state_and_result():
+    import torch
+    import paper_2405_08001_amd as P
+    scs = _small_batch()
+    xs, vs = _states(scs, 5)
+    bt, b = _make_batch(scs, 1, 100, 1e-3, "delta_e")
+    h = scs[0].h
+    dev = torch.device("cuda:0")
+    x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
+    x0, v0 = x.clone(), v.clone()
+    blk = bt.pncg_batch_autotune(x, v, h, 2)
+    _say(f"autotune picked {blk}")
+    assert blk in (256, 512, 1024)
+    assert torch.equal(x, x0) and torch.equal(v, v0)
+    with pytest.raises(P.PncgError):
+        bt.pncg_batch_set_block(300)
+
+
+def test_batch_full_size_sampled_scenes():
+    """The 256-scene batch (about 720k tets) in one launch: all scenes end
+    feasible, and four sampled scenes (the largest, the smallest and two
+    others) match the oracle after 3 fixed iterations."""
+    from oracle import pncg
+    scs = scenes.batched_scenes()
+    _say(f"full batch: {len(scs)} scenes, {sum(s.nT for s in scs)} tets")
+    xs, vs = _states(scs, 6)
+    bt, b = _make_batch(scs, 0, 3, 0.0, "delta_e")
+    xg, _ = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
+    it, _, _ = bt.pncg_batch_stats()
+    assert np.all(it == 3)
+    off = b["vert_off"]
+    assert np.all(xg[:, 2] > 0.0)
+    sizes = np.array([s.nT for s in scs])
+    picks = [int(np.argmax(sizes)), int(np.argmin(sizes)), 17, 128]
+    for i in picks:
+        s = scs[i]
+        xo, _, st = pncg.step(make_problem(s), xs[i], vs[i], s.h, iter_max=3, eps=0.0, term="delta_e")
+        sl = slice(off[i], off[i + 1])
+        rx, rdx = rel(xg[sl], xo), rel(xg[sl] - xs[i], xo - xs[i])
+        _say(f"  scene {i} ({s.nT} tets): rel_x={rx:.3e} rel_dx={rdx:.3e}")
+        assert rx <= 1e-12 and rdx <= 1e-9
