@@ -56,6 +56,8 @@ typedef struct pncg_ctx pncg_ctx;
 #define PNCG_E_INVERTED     -6   /* a tet with det F <= 0 (rest or deformed) */
 #define PNCG_E_NONFINITE    -7   /* NaN or Inf in an input or in the iterate */
 #define PNCG_E_CAPACITY     -8   /* an output buffer is too small (size reported) */
+#define PNCG_E_INDEFINITE   -9   /* the adjoint CG met p^T H p <= 0 (H not positive
+                                    definite at the given state) */
 
 /* arithmetic of the per-element and per-vertex work */
 #define PNCG_FP64   0   /* everything in float64 */
@@ -220,6 +222,43 @@ int pncg_min_distance(pncg_ctx* ctx, const double* x, double* dmin,
 #define PNCG_PROF_KINDS   5
 int pncg_set_profiling(pncg_ctx* ctx, int32_t on);
 int pncg_get_profile(pncg_ctx* ctx, double* total_us, int64_t* launches);
+
+/* ------------------------------------------------------------------------
+ * Adjoint of one time step (implicit differentiation; the paper notes only
+ * that the IPC formulation is differentiable, Sec. 1).  x1 = x^{t+1} must be
+ * a converged step result (gradient of equation E zero to the accuracy
+ * wanted, e.g. PNCG_TERM_GRAD_REL with eps 1e-10), since the adjoint uses
+ * the optimality condition G(x^{t+1}) = 0.  For a loss L with adjoints
+ * xbar = dL/dx^{t+1}, vbar = dL/dv^{t+1} ([nV][3]):
+ *     H lambda = xbar + vbar / h   (H = Hessian of equation E at x1:
+ *              inertia, exact Neo-Hookean Hessian (Sec. 3.1), plane barrier
+ *              kappa b''(d) n n^T, pair barrier as the solver's pair Hessian
+ *              model; prescribed rows removed)
+ *     xbar_t = M lambda - vbar / h          (= dL/dx^t)   [nV][3]
+ *     vbar_t = h M lambda                   (= dL/dv^t)   [nV][3]
+ *     Ebar[e] -= lambda . dG/dE_e           (dL/dE_e, ACCUMULATED) [nT]
+ * solved by Jacobi-preconditioned linear CG on the device until
+ * |r| <= cg_tol |b| or cg_max iterations (then PNCG_W_MAXITER).  Needs a
+ * PNCG_FP64 context (E_STATE otherwise); the material, contact and
+ * prescribed vertices are the context's current ones.  Outputs may alias
+ * inputs.  E_INDEFINITE if CG meets p^T H p <= 0. */
+typedef struct {
+  int32_t cg_iters;       /* CG iterations (updates of lambda) */
+  int32_t reason;         /* 0 residual rule, 1 cap, 2 p^T H p <= 0 */
+  double  rel_residual;   /* |r| / |b| at the end */
+} pncg_adjoint_stats;
+
+/* host pointers */
+int pncg_adjoint_step(pncg_ctx* ctx, const double* x1, double h,
+                      const double* xbar, const double* vbar, double cg_tol,
+                      int32_t cg_max, double* xbar_t, double* vbar_t,
+                      double* Ebar, pncg_adjoint_stats* st);
+/* device pointers on the context's device */
+int pncg_adjoint_step_dev(pncg_ctx* ctx, const double* x1_dev, double h,
+                          const double* xbar_dev, const double* vbar_dev,
+                          double cg_tol, int32_t cg_max, double* xbar_t_dev,
+                          double* vbar_t_dev, double* Ebar_dev,
+                          pncg_adjoint_stats* st);
 
 /* ------------------------------------------------------------------------
  * Batched form: many small independent scenes stepped together on one

@@ -103,6 +103,21 @@ def trajectory(prob, x0, v0, h, steps, tol=1e-10):
     return xs, vs
 
 
+def step_adjoint(prob, x1, h, xbar, vbar):
+    """One backward step at the converged x^{t+1} = x1, given the loss
+    adjoints xbar = dL/dx^{t+1}, vbar = dL/dv^{t+1}: returns
+    (dL/dx^t, dL/dv^t, this step's contribution to dL/dE, lambda)."""
+    H = prob.hessian_matrix(x1, h, mode="full")
+    rhs = (np.asarray(xbar, dtype=np.float64) + np.asarray(vbar, dtype=np.float64) / h).copy()
+    rhs[~prob.free] = 0.0
+    lam = spla.spsolve(H.tocsc(), rhs.ravel()).reshape(-1, 3)
+    lam[~prob.free] = 0.0
+    dE = -(param_gradient_matrix(prob, x1, h).T @ lam.ravel())
+    Ml = prob.mass[:, None] * lam
+    # prescribed vertices of x^{t+1} do not depend on x^t, v^t
+    return Ml - vbar / h, h * Ml, dE, lam
+
+
 def loss_and_gradient(prob, x0, v0, h, steps, x_target, tol=1e-10):
     """L = ||x_T - x_target||^2 and dL/dE (T,) by the adjoint recursion."""
     xs, vs = trajectory(prob, x0, v0, h, steps, tol)
@@ -111,16 +126,6 @@ def loss_and_gradient(prob, x0, v0, h, steps, x_target, tol=1e-10):
     vbar = np.zeros_like(xbar)
     Ebar = np.zeros(prob.tets.shape[0])
     for t in range(steps, 0, -1):
-        x1 = xs[t]
-        H = prob.hessian_matrix(x1, h, mode="full")
-        rhs = (xbar + vbar / h).copy()
-        rhs[~prob.free] = 0.0
-        lam = spla.spsolve(H.tocsc(), rhs.ravel()).reshape(-1, 3)
-        lam[~prob.free] = 0.0
-        Ebar -= param_gradient_matrix(prob, x1, h).T @ lam.ravel()
-        Ml = prob.mass[:, None] * lam
-        # prescribed vertices of x^{t+1} do not depend on x^t, v^t
-        xbar_new = Ml - vbar / h
-        vbar = h * Ml
-        xbar = xbar_new
+        xbar, vbar, dE, _ = step_adjoint(prob, xs[t], h, xbar, vbar)
+        Ebar += dE
     return L, Ebar, xs

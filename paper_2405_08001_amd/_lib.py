@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpncg.so")
 
 OK, W_MAXITER = 0, 1
 E_INVAL, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4
-E_PENETRATION, E_INVERTED, E_NONFINITE, E_CAPACITY = -5, -6, -7, -8
+E_PENETRATION, E_INVERTED, E_NONFINITE, E_CAPACITY, E_INDEFINITE = -5, -6, -7, -8, -9
 FP64, MIXED = 0, 1
 TERM_DELTA_E, TERM_GRAD_REL = 0, 1
 BARRIER_FULL, ALPHA_INF_COMPONENT = 1, 2
@@ -25,11 +25,11 @@ CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
 
 CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
-              -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY"}
+              -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY", -9: "E_INDEFINITE"}
 EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "pncg_set_material",
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
            "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
-           "pncg_set_profiling", "pncg_get_profile",
+           "pncg_set_profiling", "pncg_get_profile", "pncg_adjoint_step", "pncg_adjoint_step_dev",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune")
@@ -51,6 +51,13 @@ class pncg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("reason", C.c_int32), ("dE0", C.c_double), ("last_dE", C.c_double),
                 ("g0_norm", C.c_double), ("g_norm", C.c_double), ("alpha_upper_hits", C.c_int32),
                 ("rebuilds", C.c_int32), ("n_candidates", C.c_int64), ("n_active", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class pncg_adjoint_stats(C.Structure):
+    _fields_ = [("cg_iters", C.c_int32), ("reason", C.c_int32), ("rel_residual", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -79,6 +86,8 @@ def _load():
         "pncg_min_distance": (I32, [P, P, P, P]),
         "pncg_set_profiling": (I32, [P, I32]),
         "pncg_get_profile": (I32, [P, P, P]),
+        "pncg_adjoint_step": (I32, [P, P, D, P, P, D, I32, P, P, P, C.POINTER(pncg_adjoint_stats)]),
+        "pncg_adjoint_step_dev": (I32, [P, P, D, P, P, D, I32, P, P, P, C.POINTER(pncg_adjoint_stats)]),
         "pncg_batch_create": (I32, [C.POINTER(P), C.POINTER(pncg_opts), I32, P, P, P, P, P, P, P, P, P, P]),
         "pncg_batch_destroy": (None, [P]),
         "pncg_batch_last_error": (C.c_char_p, [P]),
@@ -237,6 +246,36 @@ class Context:
         self._check(_L.pncg_min_distance(self._h, _ptr(x), C.byref(d), C.byref(j)))
         return d.value, j.value
 
+
+    # ------------------------------------------------------------ adjoint
+    def pncg_adjoint_step(self, x1, h, xbar, vbar, Ebar=None, cg_tol=1e-10, cg_max=10000):
+        """Host arrays; returns (xbar_t, vbar_t, Ebar (accumulated copy), stats)."""
+        x1 = _f64(x1, (self.nV, 3))
+        xbar = _f64(xbar, (self.nV, 3))
+        vbar = _f64(vbar, (self.nV, 3))
+        Eb = np.zeros(self.nT) if Ebar is None else np.array(Ebar, dtype=np.float64).reshape(self.nT)
+        xo = np.empty_like(x1)
+        vo = np.empty_like(x1)
+        st = pncg_adjoint_stats()
+        rc = self._check(_L.pncg_adjoint_step(self._h, _ptr(x1), float(h), _ptr(xbar), _ptr(vbar), float(cg_tol),
+                                              int(cg_max), _ptr(xo), _ptr(vo), _ptr(Eb), C.byref(st)))
+        d = st.as_dict()
+        d["status"] = rc
+        return xo, vo, Eb, d
+
+    def pncg_adjoint_step_dev(self, x1, h, xbar, vbar, xbar_t, vbar_t, Ebar, cg_tol=1e-10, cg_max=10000):
+        """float64 CUDA tensors: x1, xbar, vbar, xbar_t, vbar_t (nV, 3); Ebar (nT,) accumulated."""
+        n = self.nV
+        if not (Ebar.is_cuda and Ebar.element_size() == 8 and Ebar.is_contiguous() and Ebar.numel() == self.nT):
+            raise ValueError(f"Ebar must be a contiguous float64 CUDA tensor of {self.nT} values")
+        st = pncg_adjoint_stats()
+        rc = self._check(_L.pncg_adjoint_step_dev(
+            self._h, _dev_ptr(x1, n, "x1"), float(h), _dev_ptr(xbar, n, "xbar"), _dev_ptr(vbar, n, "vbar"),
+            float(cg_tol), int(cg_max), _dev_ptr(xbar_t, n, "xbar_t"), _dev_ptr(vbar_t, n, "vbar_t"),
+            C.c_void_p(Ebar.data_ptr()), C.byref(st)))
+        d = st.as_dict()
+        d["status"] = rc
+        return d
 
     # ---------------------------------------------------------- profiling
     def pncg_set_profiling(self, on):

@@ -1,0 +1,316 @@
+// Adjoint of one converged time step by implicit differentiation (not in
+// the paper; the paper only notes that the IPC formulation is
+// differentiable, Sec. 1).
+//
+// x^{t+1} solves G(x) = grad E(x) = 0 (Sec. 3, equation E) with
+// xt = x^t + h v^t + h^2 g and v^{t+1} = (x^{t+1} - x^t) / h.  For adjoints
+// xbar = dL/dx^{t+1}, vbar = dL/dv^{t+1}:
+//     H lambda = xbar + vbar / h          (H = dG/dx at x^{t+1})
+//     dL/dx^t  = M lambda - vbar / h,    dL/dv^t = h M lambda,
+//     dL/dE_e -= lambda . dG/dE_e.
+// H is applied matrix-free: the element term is the exact Neo-Hookean
+// Hessian-vector product h^2 V dP(dF) b_a (Sec. 3.1), inertia M, the plane
+// barrier kappa b''(d) n n^T (exact), and the pair terms as the solver's
+// pair Hessian model (Sec. 3.2, equations eq9/eq12).  The system is solved by
+// Jacobi-preconditioned linear CG; each iteration is two launches: the Hv
+// sweep (vertex-centric, the new direction formed on the fly from z and the
+// previous direction) and the update of lambda, r, z.  Global scalars are
+// per-block partials re-reduced by the next launch in a fixed order, so every
+// block takes the same decisions.
+#include "adjoint.h"
+#include "kernels.h"
+#include "sweep_common.h"
+
+namespace pncg {
+
+namespace {
+
+__device__ __forceinline__ int read_stopped(const CgStatus* st) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = *reinterpret_cast<const volatile int*>(&st->stopped);
+  __syncthreads();
+  const int r = s_stop;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ V3<double> row3(const double* a, int v) {
+  return mk3(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
+}
+
+// Reduce the update partials of iteration k-1 (or of the initialisation),
+// apply the stop rule and compute beta.  Returns false if CG has ended.
+__device__ __forceinline__ bool cg_begin(const Args<double>& A, const AdjArgs& C, int k, double& beta, double* sh) {
+  double red[2];
+  const int kind[2] = {0, 0};
+  reduce_partials<2>(C.part_rz, 2, A.grid, kind, red, sh);
+  const double rz = red[0], rr = red[1];
+  const double bb = (k == 0) ? rr : C.status->bb;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (k == 0 && lead) C.status->bb = rr;
+  const bool conv = rr <= C.tol2 * bb;
+  if (conv || k >= C.max_iter) {
+    if (lead) {
+      C.status->iters = k;
+      C.status->reason = conv ? 0 : 1;
+      C.status->rr = rr;
+      C.status->stopped = 1;
+    }
+    return false;
+  }
+  beta = (k == 0) ? 0.0 : rz / C.scal[k - 1].rz;
+  if (lead) {
+    C.scal[k].rz = rz;
+    C.scal[k].beta = beta;
+  }
+  return true;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C, const double* xbar,
+                                                      const double* vbar) {
+  __shared__ double sh[kSWaves * 2];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    C.status->stopped = 0;
+    C.status->iters = 0;
+    C.status->reason = 0;
+    C.status->bb = 0.0;
+    C.status->rr = 0.0;
+  }
+  const double ih = 1.0 / A.h;
+  double rz = 0.0, rr = 0.0;
+  const Slice sl = block_slice(A.nV);
+  for (long long i = sl.begin + threadIdx.x; i < sl.end; i += kSBlock) {
+    const int v = (int)i;
+    const bool fixed = A.vflag[v] & kFixed;
+    V3<double> b = mk3(0.0, 0.0, 0.0);
+    if (!fixed) b = row3(xbar, v) + ih * row3(vbar, v);
+    const V3<double> d = row3(C.diag, v);
+    const V3<double> z = mk3(b.x / d.x, b.y / d.y, b.z / d.z);
+    st3(C.r, v, b);
+    st3(C.z, v, z);
+    st3(C.lam, v, mk3(0.0, 0.0, 0.0));
+    rz += dot(b, z);
+    rr += dot(b, b);
+  }
+  double red[2] = {rz, rr};
+  const int kind[2] = {0, 0};
+  block_reduce<2>(red, kind, sh);
+  if (threadIdx.x == 0) {
+    C.part_rz[2 * blockIdx.x] = red[0];
+    C.part_rz[2 * blockIdx.x + 1] = red[1];
+  }
+}
+
+// Direction launch of the non-lazy form: p_k = z_k + beta p_{k-1}
+// materialised, pair accumulators cleared for the pair H p launch.
+__global__ void __launch_bounds__(kSBlock) k_cg_dir(Args<double> A, AdjArgs C, int k) {
+  __shared__ double sh[kSWaves * 2];
+  if (read_stopped(C.status)) return;
+  double beta = 0.0;
+  if (!cg_begin(A, C, k, beta, sh)) return;
+  const double4* pprev = C.pbuf[(k + 1) & 1];
+  double4* pk = C.pbuf[k & 1];
+  const Slice sl = block_slice(A.nV);
+  for (long long i = sl.begin + threadIdx.x; i < sl.end; i += kSBlock) {
+    const int v = (int)i;
+    V3<double> p = ld3(C.z, v);
+    if (k > 0) {
+      const V3<double> pp = ld3(pprev, v);
+      p = mk3(fma(beta, pp.x, p.x), fma(beta, pp.y, p.y), fma(beta, pp.z, p.z));
+    }
+    st3(pk, v, p);
+    A.acc[8 * v] = 0.0;
+    A.acc[8 * v + 1] = 0.0;
+    A.acc[8 * v + 2] = 0.0;
+  }
+}
+
+// q = H p_k by the vertex-centric sweep; partials of p_k . q.
+template <bool LAZY>
+__global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, int k) {
+  __shared__ double sh[kSWaves * 2];
+  if (read_stopped(C.status)) return;
+  double beta = 0.0;
+  if (LAZY && !cg_begin(A, C, k, beta, sh)) return;
+  const double4* pprev = C.pbuf[(k + 1) & 1];
+  double4* pk = C.pbuf[k & 1];
+  auto pget = [&](int v) -> V3<double> {
+    if (!LAZY) return ld3(pk, v);
+    V3<double> p = ld3(C.z, v);
+    if (k > 0) {
+      const V3<double> pp = ld3(pprev, v);
+      p = mk3(fma(beta, pp.x, p.x), fma(beta, pp.y, p.y), fma(beta, pp.z, p.z));
+    }
+    return p;
+  };
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const Slice sl = block_slice(A.nWaves);
+  double pq = 0.0;
+  for (long long w = sl.begin + wave; w < sl.end; w += kSWaves) {
+    const long long idx = w * kWave + lane;
+    const int code = A.inc[idx];
+    const int myv = A.inc_vert[idx];
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (code >= 0) {
+      const ElemRec<double> rec = A.elem[code >> 2];
+      Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
+                                           ld3(A.x0, rec.v[3]));
+      if (kin.J > 0.0) {
+        V3<double> d[3];
+        dF_cols(rec.B, pget(rec.v[0]), pget(rec.v[1]), pget(rec.v[2]), pget(rec.v[3]), d);
+        const V3<double> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3));
+        s[0] = hp.x;
+        s[1] = hp.y;
+        s[2] = hp.z;
+      } else {
+        raise_err(A.status, kErrInverted);
+      }
+    }
+    seg_sum<double>(myv, s);
+    const int upv = __shfl_up(myv, 1, kWave);
+    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const int v = myv;
+    const V3<double> p = pget(v);
+    const double m = A.mass[v];
+    double hv[3] = {fma(A.h2, s[0], m * p.x), fma(A.h2, s[1], m * p.y), fma(A.h2, s[2], m * p.z)};
+    const uint8_t fl = A.vflag[v];
+    if (fl & kSurface) {
+      const V3<double> x = ld3(A.x0, v);
+      for (int j = 0; j < A.planes.n; ++j) {
+        const double* pl = A.planes.p[j];
+        const double d = plane_dist(pl, x);
+        if (d > 0.0 && d < A.dhat) {
+          const double c = A.kappa * barrier_d2b(d, A.dhat) * (pl[0] * p.x + pl[1] * p.y + pl[2] * p.z);
+          hv[0] += c * pl[0];
+          hv[1] += c * pl[1];
+          hv[2] += c * pl[2];
+        }
+      }
+    }
+    if (!LAZY && A.self) {
+      hv[0] += A.acc[8 * v];
+      hv[1] += A.acc[8 * v + 1];
+      hv[2] += A.acc[8 * v + 2];
+    }
+    if (fl & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
+    if (LAZY) st3(pk, v, p);
+    st3(C.q, v, mk3(hv[0], hv[1], hv[2]));
+    pq += hv[0] * p.x + hv[1] * p.y + hv[2] * p.z;
+  }
+  double red[1] = {pq};
+  const int kind[1] = {0};
+  block_reduce<1>(red, kind, sh);
+  if (threadIdx.x == 0) C.part_pq[blockIdx.x] = red[0];
+}
+
+// alpha = rz_k / p_k . H p_k; lambda += alpha p, r -= alpha q, z = r / diag.
+__global__ void __launch_bounds__(kSBlock) k_cg_update(Args<double> A, AdjArgs C, int k) {
+  __shared__ double sh[kSWaves * 2];
+  if (read_stopped(C.status)) return;
+  double red1[1];
+  const int kind1[1] = {0};
+  reduce_partials<1>(C.part_pq, 1, A.grid, kind1, red1, sh);
+  const double pq = red1[0];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (lead) {
+      C.status->iters = k;
+      C.status->reason = 2;
+      C.status->rr = 0.0;
+      C.status->stopped = 1;
+    }
+    return;
+  }
+  const double alpha = C.scal[k].rz / pq;
+  if (lead) {
+    C.scal[k].alpha = alpha;
+    C.scal[k].pq = pq;
+  }
+  const double4* pk = C.pbuf[k & 1];
+  double rz = 0.0, rr = 0.0;
+  const Slice sl = block_slice(A.nV);
+  for (long long i = sl.begin + threadIdx.x; i < sl.end; i += kSBlock) {
+    const int v = (int)i;
+    const V3<double> p = ld3(pk, v), q = ld3(C.q, v), l = ld3(C.lam, v), r0 = ld3(C.r, v);
+    const V3<double> d = row3(C.diag, v);
+    st3(C.lam, v, mk3(fma(alpha, p.x, l.x), fma(alpha, p.y, l.y), fma(alpha, p.z, l.z)));
+    const V3<double> r = mk3(fma(-alpha, q.x, r0.x), fma(-alpha, q.y, r0.y), fma(-alpha, q.z, r0.z));
+    const V3<double> z = mk3(r.x / d.x, r.y / d.y, r.z / d.z);
+    st3(C.r, v, r);
+    st3(C.z, v, z);
+    rz += dot(r, z);
+    rr += dot(r, r);
+  }
+  double red[2] = {rz, rr};
+  const int kind[2] = {0, 0};
+  block_reduce<2>(red, kind, sh);
+  if (threadIdx.x == 0) {
+    C.part_rz[2 * blockIdx.x] = red[0];
+    C.part_rz[2 * blockIdx.x + 1] = red[1];
+  }
+}
+
+// Adjoints of x^t, v^t and the per-tet moduli (accumulated into Ebar).
+__global__ void __launch_bounds__(kSBlock) k_adj_out(Args<double> A, AdjArgs C, const double* vbar, const double* E,
+                                                     double* xbar_t, double* vbar_t, double* Ebar) {
+  const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
+  const double ih = 1.0 / A.h;
+  for (int v = tid; v < A.nV; v += stride) {
+    const V3<double> l = ld3(C.lam, v), vb = row3(vbar, v);
+    const double m = A.mass[v];
+    const V3<double> ml = m * l;
+    xbar_t[3 * v] = ml.x - vb.x * ih;
+    xbar_t[3 * v + 1] = ml.y - vb.y * ih;
+    xbar_t[3 * v + 2] = ml.z - vb.z * ih;
+    vbar_t[3 * v] = A.h * ml.x;
+    vbar_t[3 * v + 1] = A.h * ml.y;
+    vbar_t[3 * v + 2] = A.h * ml.z;
+  }
+  for (int e = tid; e < A.nT; e += stride) {
+    const ElemRec<double> rec = A.elem[e];
+    Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
+                                         ld3(A.x0, rec.v[3]));
+    if (!(kin.J > 0.0)) {
+      raise_err(A.status, kErrInverted);
+      continue;
+    }
+    // mu and lam are linear in E: d(V mu)/dE = V mu / E, likewise for lam
+    const double iE = 1.0 / E[e];
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const V3<double> dg = nh_dgdE(kin, rec.vmu * iE, rec.vlam * iE, shape_vec(rec.B, a));
+      s += dot(ld3(C.lam, rec.v[a]), dg);
+    }
+    Ebar[e] -= A.h2 * s;
+  }
+}
+
+void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_init, dim3(A.grid), dim3(kSBlock), 0, s, A, C, xbar, vbar);
+}
+
+void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool lazy, hipStream_t s) {
+  if (lazy) {
+    hipLaunchKernelGGL(k_cg_hv<true>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+  } else {
+    hipLaunchKernelGGL(k_cg_dir, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+    if (A.self) {
+      Args<double> B = A;
+      B.p0 = C.pbuf[k & 1];
+      launch_pairs_hvp<double>(B, s);
+    }
+    hipLaunchKernelGGL(k_cg_hv<false>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+  }
+  hipLaunchKernelGGL(k_cg_update, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+}
+
+void launch_adj_out(const Args<double>& A, const AdjArgs& C, const double* vbar, const double* E, double* xbar_t,
+                    double* vbar_t, double* Ebar, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_out, dim3(A.grid), dim3(kSBlock), 0, s, A, C, vbar, E, xbar_t, vbar_t, Ebar);
+}
+
+}  // namespace pncg

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pncg.h"
+#include "adjoint.h"
 #include "host_mesh.h"
 #include "internal.h"
 #include "kernels.h"
@@ -106,6 +107,17 @@ struct pncg_ctx {
   long long *d_part_cnt = nullptr, *d_part_off = nullptr, *d_totals = nullptr;
   long long work_cap = 0;
   int grid = 1;
+  // adjoint (allocated on first use)
+  bool adj_ready = false;
+  double4 *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_pa = nullptr, *d_pb = nullptr, *d_q = nullptr;
+  double *d_adiag = nullptr, *d_agrad = nullptr, *d_E = nullptr;
+  double *d_part_rz = nullptr, *d_part_pq = nullptr;
+  double* d_aio = nullptr;         // [2][nV][3] + [nT] staging for host adjoint outputs
+  CgScal* d_cgs = nullptr;
+  int cgs_cap = 0;
+  CgStatus* d_cgst = nullptr;
+  CgStatus* h_cgst = nullptr;      // pinned
+  bool E_uploaded = false;
   // optional per-launch timing (HIP events on the context stream)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -160,8 +172,10 @@ void free_all(pncg_ctx* c) {
   c->allocs.clear();
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_n) (void)hipHostFree(c->h_n);
+  if (c->h_cgst) (void)hipHostFree(c->h_cgst);
   c->h_status = nullptr;
   c->h_n = nullptr;
+  c->h_cgst = nullptr;
 }
 
 int ensure_device(pncg_ctx* c) {
@@ -602,6 +616,99 @@ int upload_flags_targets(pncg_ctx* c) {
   return sync(c);
 }
 
+// ---------------------------------------------------------------- adjoint
+int ensure_adjoint(pncg_ctx* c, int cg_max) {
+  int rc;
+  if (!c->adj_ready) {
+    const size_t nV = c->nV, nT = c->nT;
+    if ((rc = dmalloc(c, &c->d_lam, nV)) || (rc = dmalloc(c, &c->d_r, nV)) || (rc = dmalloc(c, &c->d_z, nV)) ||
+        (rc = dmalloc(c, &c->d_pa, nV)) || (rc = dmalloc(c, &c->d_pb, nV)) || (rc = dmalloc(c, &c->d_q, nV)) ||
+        (rc = dmalloc(c, &c->d_adiag, 3 * nV)) || (rc = dmalloc(c, &c->d_agrad, 3 * nV)) ||
+        (rc = dmalloc(c, &c->d_E, nT)) || (rc = dmalloc(c, &c->d_part_rz, 2 * (size_t)kMaxGrid)) ||
+        (rc = dmalloc(c, &c->d_part_pq, (size_t)kMaxGrid)) || (rc = dmalloc(c, &c->d_aio, 6 * nV + nT)) ||
+        (rc = dmalloc(c, &c->d_cgst, 1)))
+      return rc;
+    if (!c->h_cgst) HIPCHK(c, hipHostMalloc((void**)&c->h_cgst, sizeof(CgStatus), hipHostMallocDefault));
+    c->adj_ready = true;
+  }
+  if (c->cgs_cap < cg_max + 1) {
+    if (c->d_cgs) dfree(c, c->d_cgs);
+    c->d_cgs = nullptr;
+    if ((rc = dmalloc(c, &c->d_cgs, (size_t)cg_max + 1))) return rc;
+    c->cgs_cap = cg_max + 1;
+  }
+  if (!c->E_uploaded) {
+    HIPCHK(c, hipMemcpyAsync(c->d_E, c->E.data(), sizeof(double) * c->nT, hipMemcpyHostToDevice, c->stream));
+    c->E_uploaded = true;
+  }
+  return PNCG_OK;
+}
+
+// All pointers are device pointers.  Ebar is accumulated.
+int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, const double* vbar, double cg_tol,
+                 int cg_max, double* xbar_t, double* vbar_t, double* Ebar, pncg_adjoint_stats* st) {
+  int rc;
+  if ((rc = ensure_adjoint(c, cg_max))) return rc;
+  Args<double> A = make_args<double>(c, h);
+  launch_load_query<double>(A, x1, nullptr, nullptr, c->stream);
+  if ((rc = query_candidates(c, c->dhat))) return rc;
+  A.cand = c->d_cand;
+  // Jacobi diagonal of H at x^{t+1} (the gradient written alongside is
+  // unused; the predictor is taken as x^{t+1} so that it stays finite)
+  A.xt = c->d_x0;
+  launch_query_gradient<double>(A, c->d_agrad, c->d_adiag, c->stream);
+  A.xt = c->d_xt;
+  AdjArgs C{};
+  C.lam = c->d_lam;
+  C.r = c->d_r;
+  C.z = c->d_z;
+  C.pbuf[0] = c->d_pa;
+  C.pbuf[1] = c->d_pb;
+  C.q = c->d_q;
+  C.diag = c->d_adiag;
+  C.part_rz = c->d_part_rz;
+  C.part_pq = c->d_part_pq;
+  C.scal = c->d_cgs;
+  C.status = c->d_cgst;
+  C.tol2 = cg_tol * cg_tol;
+  C.max_iter = cg_max;
+  launch_adj_init(A, C, xbar, vbar, c->stream);
+  const bool lazy = !A.self;
+  int k = 0, chunk = 16;
+  while (true) {
+    const int kend = std::min(k + chunk, cg_max + 1);
+    for (int j = k; j < kend; ++j) launch_cg_iteration(A, C, j, lazy, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->h_cgst, c->d_cgst, sizeof(CgStatus), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync(c))) return rc;
+    if (c->h_cgst->stopped) break;
+    if (kend > cg_max) return fail(c, PNCG_E_HIP, "adjoint CG did not report its end");
+    k = kend;
+    chunk = std::min(chunk * 2, 256);
+  }
+  const CgStatus cs = *c->h_cgst;
+  if (st) {
+    st->cg_iters = cs.iters;
+    st->reason = cs.reason;
+    st->rel_residual = cs.bb > 0.0 ? std::sqrt(cs.rr / cs.bb) : 0.0;
+  }
+  if (cs.reason == 2) return fail(c, PNCG_E_INDEFINITE, "p^T H p <= 0 or not finite in the adjoint CG");
+  launch_adj_out(A, C, vbar, c->d_E, xbar_t, vbar_t, Ebar, c->stream);
+  if ((rc = read_status(c))) return rc;
+  if ((rc = check_status_err(c, *c->h_status))) return rc;
+  return cs.reason == 1 ? PNCG_W_MAXITER : PNCG_OK;
+}
+
+int adjoint_checks(pncg_ctx* c, const void* x1, double h, const void* xbar, const void* vbar, double cg_tol,
+                   int cg_max, const void* xbar_t, const void* vbar_t, const void* Ebar) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (c->precision != PNCG_FP64) return fail(c, PNCG_E_STATE, "the adjoint needs a PNCG_FP64 context");
+  if (!x1 || !xbar || !vbar || !xbar_t || !vbar_t || !Ebar) return fail(c, PNCG_E_INVAL, "NULL argument");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  if (!(cg_tol >= 0.0) || !std::isfinite(cg_tol) || cg_max < 1) return fail(c, PNCG_E_INVAL, "need cg_tol >= 0, cg_max >= 1");
+  return PNCG_OK;
+}
+
 int grid_for(const pncg_ctx* c) {
   long long work = std::max<long long>({(long long)c->nWaves * kWave, (long long)c->nT, (long long)c->nV, 1LL});
   long long g = (work + kSBlock - 1) / kSBlock;
@@ -724,6 +831,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
+  c->adj_ready = false; c->d_cgs = nullptr; c->cgs_cap = 0; c->E_uploaded = false;
   c->d_excl_pt = c->d_excl_ee = nullptr; c->n_excl_pt = c->n_excl_ee = 0;
   const size_t r4 = (c->precision == PNCG_MIXED) ? sizeof(float4) : sizeof(double4);
   const int gmax = kMaxGrid;
@@ -784,6 +892,7 @@ int pncg_set_material(pncg_ctx* c, const double* E, const double* nu, const doub
   int rc = (c->precision == PNCG_MIXED) ? upload_elements<float>(c) : upload_elements<double>(c);
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(c->d_mass, c->mass.data(), sizeof(double) * c->nV, hipMemcpyHostToDevice, c->stream));
+  c->E_uploaded = false;
   c->state = 2;
   return sync(c);
 }
@@ -1056,6 +1165,48 @@ int pncg_min_distance(pncg_ctx* c, const double* x, double* dmin, double* jmin) 
   *dmin = d;
   *jmin = j;
   return PNCG_OK;
+}
+
+
+int pncg_adjoint_step_dev(pncg_ctx* c, const double* x1, double h, const double* xbar, const double* vbar,
+                          double cg_tol, int32_t cg_max, double* xbar_t, double* vbar_t, double* Ebar,
+                          pncg_adjoint_stats* st) {
+  int rc = adjoint_checks(c, x1, h, xbar, vbar, cg_tol, cg_max, xbar_t, vbar_t, Ebar);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (st) std::memset(st, 0, sizeof(*st));
+  return adjoint_impl(c, x1, h, xbar, vbar, cg_tol, cg_max, xbar_t, vbar_t, Ebar, st);
+}
+
+int pncg_adjoint_step(pncg_ctx* c, const double* x1, double h, const double* xbar, const double* vbar,
+                      double cg_tol, int32_t cg_max, double* xbar_t, double* vbar_t, double* Ebar,
+                      pncg_adjoint_stats* st) {
+  int rc = adjoint_checks(c, x1, h, xbar, vbar, cg_tol, cg_max, xbar_t, vbar_t, Ebar);
+  if (rc) return rc;
+  const size_t n3 = 3 * (size_t)c->nV;
+  if (!finite_all(x1, n3) || !finite_all(xbar, n3) || !finite_all(vbar, n3) || !finite_all(Ebar, c->nT))
+    return fail(c, PNCG_E_NONFINITE, "non-finite input");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = ensure_adjoint(c, cg_max))) return rc;
+  if (st) std::memset(st, 0, sizeof(*st));
+  // inputs in d_io (x1, xbar, vbar), outputs in d_aio (xbar_t, vbar_t, Ebar)
+  double* dx = c->d_io;
+  double* dxb = c->d_io + n3;
+  double* dvb = c->d_io + 2 * n3;
+  double* oxb = c->d_aio;
+  double* ovb = c->d_aio + n3;
+  double* oE = c->d_aio + 2 * n3;
+  if ((rc = upload_rows(c, x1, dx, c->nV)) || (rc = upload_rows(c, xbar, dxb, c->nV)) ||
+      (rc = upload_rows(c, vbar, dvb, c->nV)))
+    return rc;
+  HIPCHK(c, hipMemcpyAsync(oE, Ebar, sizeof(double) * c->nT, hipMemcpyHostToDevice, c->stream));
+  rc = adjoint_impl(c, dx, h, dxb, dvb, cg_tol, cg_max, oxb, ovb, oE, st);
+  if (rc < 0) return rc;
+  HIPCHK(c, hipMemcpyAsync(xbar_t, oxb, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(vbar_t, ovb, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(Ebar, oE, sizeof(double) * c->nT, hipMemcpyDeviceToHost, c->stream));
+  int rs = sync(c);
+  return rs ? rs : rc;
 }
 
 }  // extern "C"

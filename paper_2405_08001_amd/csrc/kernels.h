@@ -16,6 +16,8 @@ template <typename R> void launch_load_query(const Args<R>& A, const double* x, 
 template <typename R> void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s);
 template <typename R> void launch_query_energy(const Args<R>& A, double* out, hipStream_t s);
 template <typename R> void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s);
+// H p of the active pairs into acc[0..2] (p in A.p0, acc zeroed beforehand)
+template <typename R> void launch_pairs_hvp(const Args<R>& A, hipStream_t s);
 template <typename R> void launch_audit(const Args<R>& A, double* part, hipStream_t s);
 
 // ------------------------------------------------------------ broad phase

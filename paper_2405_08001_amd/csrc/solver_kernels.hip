@@ -800,6 +800,10 @@ void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) 
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
 }
 template <typename R>
+void launch_pairs_hvp(const Args<R>& A, hipStream_t s) {
+  hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+}
+template <typename R>
 void launch_audit(const Args<R>& A, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_audit<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, part);
 }
@@ -815,6 +819,7 @@ void launch_audit(const Args<R>& A, double* part, hipStream_t s) {
   template void launch_query_gradient<R>(const Args<R>&, double*, double*, hipStream_t);              \
   template void launch_query_energy<R>(const Args<R>&, double*, hipStream_t);                         \
   template void launch_query_hvp<R>(const Args<R>&, double*, double*, hipStream_t);                   \
+  template void launch_pairs_hvp<R>(const Args<R>&, hipStream_t);                                    \
   template void launch_audit<R>(const Args<R>&, double*, hipStream_t);
 
 PNCG_INSTANTIATE(float)
