@@ -17,6 +17,11 @@ One JSON line is printed.  Besides the throughput it carries:
                 per-contact byte model) times iterations/s, against 8 TB/s
   cpu_baseline  the float64 CPU oracle timed on a bounded sample of the same
                 workload (one PNCG iteration from the state after warm-up)
+  batched       256 independent scenes (500-8000 tets each, 721k tets in
+                all) stepped together by the batched kernel, several steps per
+                captured graph: scene-steps/s and the kernel's byte rate
+  adjoint       the differentiable rollout of the 30,000-tet bar (30 steps,
+                checkpoints every 5): backward wall time per step
 """
 from __future__ import annotations
 
@@ -124,6 +129,88 @@ def cpu_baseline(sc, state, budget_iters=1):
                        f"(float64 NumPy oracle, 1 thread, {dt:.1f} s)")
 
 
+def run_batched(steps, warmup):
+    """The 256-scene batch, mixed precision: W eager steps (the scenes fall
+    onto their planes), then K steps as one captured graph."""
+    import torch
+    import paper_2405_08001_amd as P
+    import scenes
+    scs = scenes.batched_scenes()
+    b = scenes.pack_batch(scs)
+    bt = P.Batch(b["vert_off"], b["X"], b["tet_off"], b["tets"], b["tri_off"], b["tris"], b["E"], b["nu"], b["rho"],
+                 b["planes"], precision=P.MIXED)
+    s0 = scs[0]
+    bt.pncg_batch_set_params(s0.dhat, s0.kappa, s0.iter_max, s0.eps, P.TERM_DELTA_E, s0.gravity, 0)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(b["x"], dtype=torch.float64, device=dev)
+    v = torch.tensor(b["v"], dtype=torch.float64, device=dev)
+    block = bt.pncg_batch_autotune(x, v, s0.h, 2)
+    bt.pncg_batch_run(x, v, s0.h, warmup)
+    _, _, tot0 = bt.pncg_batch_stats()
+    bt.pncg_batch_run(x, v, s0.h, steps)      # captures the graph
+    _, _, tot1 = bt.pncg_batch_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.pncg_batch_run(x, v, s0.h, steps)      # replays it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, _, tot2 = bt.pncg_batch_stats()
+    it = (tot2 - tot1).astype(np.float64)
+    T = np.diff(b["tet_off"]).astype(np.float64)
+    V = np.diff(b["vert_off"]).astype(np.float64)
+    bt_, bv_, _, _ = BYTES["iter"]["mixed"]
+    nbytes = float(np.sum(it * (bt_ * T + bv_ * V)))
+    xz = x[:, 2].min().item()
+    bt.close()
+    return {"scenes": len(scs), "tets": int(T.sum()), "steps_timed": steps, "steps_warmup": warmup,
+            "block": block, "scene_steps_per_s": round(len(scs) * steps / dt, 1),
+            "ms_per_batch_step": round(1e3 * dt / steps, 4),
+            "mean_iters_per_scene_step": round(float(it.sum()) / (len(scs) * steps), 2),
+            "iters_per_s": round(float(it.sum()) / dt, 1),
+            "roofline": {"bound": "hbm", "kernel": "batch_step", "achieved": round(nbytes / dt / 1e9, 1),
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(nbytes / dt / HBM_PEAK, 4),
+                         "bytes_per_launch": int(nbytes / steps)},
+            "min_z_after": xz, "dtype": "f32+f64"}
+
+
+def run_adjoint(steps=30, checkpoint=5):
+    """Loss ||x_T - x_target||^2 of the 30,000-tet bar over 30 steps; the
+    target is the forward result under a second seeded modulus field."""
+    import torch
+    import paper_2405_08001_amd as P
+    import scenes
+    sc = scenes.diff_bar_scene(seed=4)
+    tgt = scenes.diff_bar_scene(seed=5)
+    ctx = setup_ctx(sc, "fp64")
+    ctx.pncg_set_solver(sc.iter_max, sc.eps, P.TERM_GRAD_ABS, sc.gravity, 0)
+    sim = P.Simulation(ctx, sc.nu, sc.rho, sc.h, steps, checkpoint=checkpoint, cg_tol=1e-10, cg_max=20000)
+    dev = torch.device("cuda:0")
+    x0 = torch.tensor(sc.x0, dtype=torch.float64, device=dev)
+    v0 = torch.tensor(sc.v0, dtype=torch.float64, device=dev)
+    with torch.no_grad():
+        x_tgt, _ = P.simulate(torch.tensor(tgt.E), x0, v0, sim)
+    E = torch.tensor(sc.E, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xT, _ = P.simulate(E, x0, v0, sim)
+    loss = ((xT - x_tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd_iters = [s["iters"] for s in sim.forward_stats]
+    cg = [s["cg_iters"] for s in sim.adjoint_stats]
+    ctx.close()
+    return {"workload": "bar-50x10x10 (30000 tets), 30 steps, h=1/60, checkpoint 5",
+            "adjoint_ms_per_step": round(1e3 * (t2 - t1) / steps, 3),
+            "forward_ms_per_step": round(1e3 * (t1 - t0) / steps, 3),
+            "backward_s": round(t2 - t1, 4), "forward_s": round(t1 - t0, 4),
+            "recomputed_steps": sim.recomputed_steps, "mean_forward_iters": round(float(np.mean(fwd_iters)), 1),
+            "mean_cg_iters": round(float(np.mean(cg)), 1), "max_cg_iters": int(max(cg)),
+            "loss": float(loss.detach()), "grad_norm": float(E.grad.norm()), "dtype": "f64"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +219,10 @@ def main():
     ap.add_argument("--profile-frames", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-scene batched run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
+    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--batched-warmup", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -213,6 +304,14 @@ def main():
         out["fp64"] = {"iters_per_s": round(fips, 1), "ms_per_frame": round(1e3 * f["seconds"] / f["frames"], 4),
                        "us_per_iter": round(1e6 / fips, 3)}
         out["mixed_vs_fp64_speedup"] = round(ips / fips, 3)
+    if not args.no_batched:
+        log("batched: 256 scenes ...")
+        out["batched"] = run_batched(args.batched_steps, args.batched_warmup)
+        log(f"  {out['batched']['scene_steps_per_s']} scene-steps/s")
+    if not args.no_adjoint:
+        log("adjoint: 30,000-tet bar, 30 steps ...")
+        out["adjoint"] = run_adjoint()
+        log(f"  {out['adjoint']['adjoint_ms_per_step']} ms/step backward")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(sc, m["state"])

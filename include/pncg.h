@@ -68,6 +68,10 @@ typedef struct pncg_ctx pncg_ctx;
 #define PNCG_TERM_DELTA_E   0   /* stop after an update with dE < eps * dE_0 */
 #define PNCG_TERM_GRAD_REL  1   /* stop at the top of an iteration when
                                    ||g||_2 <= eps * ||g_0||_2 */
+#define PNCG_TERM_GRAD_ABS  2   /* stop at the top of an iteration when
+                                   ||g||_2 <= eps (absolute; for steps that
+                                   start near equilibrium, where ||g_0|| is
+                                   itself near the gradient's rounding floor) */
 
 /* solver flags */
 #define PNCG_BARRIER_FULL        1u  /* use the pair Hessian of equation eq9

@@ -23,7 +23,9 @@ Readings where the paper is silent or garbled:
     with p = -P g; p^T H p <= 0 gives an unbounded Newton step; a step that is
     still unbounded or not finite stops the iteration.
   * Termination "delta_e": the rule above.  "grad_rel": stop at the top of an
-    iteration when ||g||_2 <= eps ||g_0||_2 (used for tight convergence).
+    iteration when ||g||_2 <= eps ||g_0||_2 (used for tight convergence);
+    "grad_abs": the same test against eps itself (steps that start near
+    equilibrium have ||g_0|| near the gradient's rounding floor).
   * v^{t+1} = (x^{t+1} - x^t) / h.
 """
 from __future__ import annotations
@@ -72,8 +74,8 @@ def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
             g0n = gn
             st.g0 = gn
         st.gk = gn
-        if term == "grad_rel" and gn <= eps * g0n:
-            st.reason = "grad_rel"
+        if (term == "grad_rel" and gn <= eps * g0n) or (term == "grad_abs" and gn <= eps):
+            st.reason = term
             break
         P = 1.0 / D
         if k == 0:

@@ -19,7 +19,7 @@ OK, W_MAXITER = 0, 1
 E_INVAL, E_NOMEM, E_HIP, E_STATE = -1, -2, -3, -4
 E_PENETRATION, E_INVERTED, E_NONFINITE, E_CAPACITY, E_INDEFINITE = -5, -6, -7, -8, -9
 FP64, MIXED = 0, 1
-TERM_DELTA_E, TERM_GRAD_REL = 0, 1
+TERM_DELTA_E, TERM_GRAD_REL, TERM_GRAD_ABS = 0, 1, 2
 BARRIER_FULL, ALPHA_INF_COMPONENT = 1, 2
 CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2

@@ -969,8 +969,9 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
 int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, const double* gravity, uint32_t flags) {
   if (!c) return PNCG_E_INVAL;
   if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
-  if (iter_max < 1 || !std::isfinite(eps) || eps < 0.0 || (term != PNCG_TERM_DELTA_E && term != PNCG_TERM_GRAD_REL))
-    return fail(c, PNCG_E_INVAL, "need iter_max >= 1, eps >= 0, term DELTA_E or GRAD_REL");
+  if (iter_max < 1 || !std::isfinite(eps) || eps < 0.0 ||
+      (term != PNCG_TERM_DELTA_E && term != PNCG_TERM_GRAD_REL && term != PNCG_TERM_GRAD_ABS))
+    return fail(c, PNCG_E_INVAL, "need iter_max >= 1, eps >= 0, term DELTA_E, GRAD_REL or GRAD_ABS");
   if (gravity && !finite_all(gravity, 3)) return fail(c, PNCG_E_NONFINITE, "non-finite gravity");
   if (flags & ~3u) return fail(c, PNCG_E_INVAL, "unknown solver flag");
   c->iter_max = iter_max;

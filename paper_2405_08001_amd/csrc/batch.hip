@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       }
       const double gnorm = sqrt(dots[0]);
       if (k == 0) g0 = gnorm;
-      if (A.term == 1 && gnorm <= A.eps * g0) { reason = 1; break; }
+      if ((A.term == 1 && gnorm <= A.eps * g0) || (A.term == 2 && gnorm <= A.eps)) { reason = 1; break; }
       double beta = 0.0;
       if (k > 0 && dots[3] != 0.0) {
         beta = dots[2] / dots[3] - (dots[4] / dots[3]) * (dots[5] / dots[3]);

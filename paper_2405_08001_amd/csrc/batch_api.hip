@@ -324,7 +324,7 @@ const char* pncg_batch_last_error(const pncg_batch* b) { return b ? b->err.c_str
 int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa, int32_t iter_max, double eps, int32_t term,
                           const double* gravity, uint32_t flags) {
   if (!b) return PNCG_E_INVAL;
-  if (!(dhat > 0.0) || !(kappa >= 0.0) || iter_max < 1 || !(eps >= 0.0) || (term != 0 && term != 1) ||
+  if (!(dhat > 0.0) || !(kappa >= 0.0) || iter_max < 1 || !(eps >= 0.0) || (term < 0 || term > 2) ||
       (flags & ~3u))
     return bfail(b, PNCG_E_INVAL, "bad batch parameters");
   b->dhat = dhat;

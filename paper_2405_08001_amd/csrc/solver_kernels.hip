@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   const double g0 = k == 0 ? gnorm : A.status->g0;
   int dir_stop = 0, reason = 0, restart = 0;
   double beta = 0.0;
-  if (A.term == 1 && gnorm <= A.eps * g0) { dir_stop = 1; reason = 1; }
+  if ((A.term == 1 && gnorm <= A.eps * g0) || (A.term == 2 && gnorm <= A.eps)) { dir_stop = 1; reason = 1; }
   if (k > 0 && yp != 0.0) {
     beta = gPy / yp - (yPy / yp) * (pg / yp);
     if (!isfinite(beta)) beta = 0.0;

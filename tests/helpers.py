@@ -11,7 +11,8 @@ def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_ma
     ctx.pncg_set_material(sc.E, sc.nu, sc.rho)
     flags = (P.CONTACT_SELF if sc.self_contact else 0) | (P.CONTACT_REST_EXCLUDE if rest_exclude else 0)
     ctx.pncg_set_contact(sc.dhat, sc.kappa, sc.cell if cell is None else cell, sc.planes, flags)
-    term = {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL}[sc.term if term is None else term]
+    term = {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL,
+            "grad_abs": P.TERM_GRAD_ABS}[sc.term if term is None else term]
     sflags = (P.BARRIER_FULL if barrier_full else 0) | (P.ALPHA_INF_COMPONENT if alpha_component else 0)
     ctx.pncg_set_solver(sc.iter_max if iter_max is None else iter_max, sc.eps if eps is None else eps, term,
                         sc.gravity, sflags)

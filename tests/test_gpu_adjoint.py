@@ -25,7 +25,7 @@ def _bar(nx, ny, nz, lift=0.0012):
 
 def _sim(sc, steps, checkpoint=5, cg_tol=1e-12):
     import paper_2405_08001_amd as P
-    ctx = make_ctx(sc, 0, iter_max=20000, eps=1e-10, term="grad_rel")
+    ctx = make_ctx(sc, 0)                   # converged steps: absolute gradient rule of the scene
     return P.Simulation(ctx, sc.nu, sc.rho, sc.h, steps, checkpoint=checkpoint, cg_tol=cg_tol, cg_max=20000)
 
 
@@ -78,7 +78,7 @@ def test_adjoint_step_matches_oracle():
 
 def test_trajectory_gradient_matches_oracle():
     """4 steps of the small bar falling onto the floor: dL/dE through the GPU
-    forward (PNCG, gradient rule 1e-10) and adjoint versus the oracle's Newton
+    forward (PNCG, absolute gradient rule) and adjoint versus the oracle's Newton
     trajectory and direct-solve adjoint recursion."""
     from oracle import adjoint, problem
     sc = _bar(4, 2, 2)

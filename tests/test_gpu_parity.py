@@ -179,3 +179,18 @@ def test_cube_configured_step_within_rounding_envelope():
     _say(f"  envelope={env:.3e} gpu rel_x={rel(xg, xo):.3e} iters={sg['iters']}/{st.iters}")
     assert sg["iters"] == st.iters
     assert rel(xg, xo) <= max(20 * env, 1e-9)
+
+
+def test_grad_abs_rule_matches_scaled_grad_rel():
+    """The absolute gradient rule with eps * ||g_0|| stops at the same
+    iteration, with the same result, as the relative rule with eps."""
+    _say("grad_abs vs grad_rel")
+    sc, x0, v0 = _cube_drop()
+    cr = make_ctx(sc, 0, iter_max=4000, eps=1e-8, term="grad_rel")
+    xr, _, sr = cr.pncg_step(x0, v0, sc.h)
+    ca = make_ctx(sc, 0, iter_max=4000, eps=1e-8 * sr["g0_norm"], term="grad_abs")
+    xa, _, sa = ca.pncg_step(x0, v0, sc.h)
+    _say(f"  iters {sr['iters']}/{sa['iters']} reasons {sr['reason']}/{sa['reason']}")
+    assert sr["reason"] == sa["reason"] == 1
+    assert sa["iters"] == sr["iters"]
+    assert np.array_equal(xa, xr)

@@ -154,3 +154,20 @@ def test_alpha_upper_caps_vertex_displacement():
     assert st.alpha_upper_hits == 1
     disp = np.linalg.norm(x - x_prev, axis=1).max()
     assert disp <= 0.5 * sc.dhat * (1 + 1e-12)
+
+
+def test_grad_abs_rule_is_grad_rel_scaled_by_g0():
+    """The absolute gradient rule with eps * ||g_0|| stops exactly where the
+    relative rule with eps does; with eps >= ||g_0|| it stops before any
+    update."""
+    from helpers import make_problem
+    sc = scenes.tiny_scene()
+    P = make_problem(sc)
+    v0 = np.zeros_like(sc.X)
+    v0[:, 0] = 0.3
+    xr, _, sr = pncg.step(P, sc.X, v0, sc.h, iter_max=500, eps=1e-6, term="grad_rel")
+    xa, _, sa = pncg.step(P, sc.X, v0, sc.h, iter_max=500, eps=1e-6 * sr.g0, term="grad_abs")
+    assert sr.reason == "grad_rel" and sa.reason == "grad_abs"
+    assert sa.iters == sr.iters and np.array_equal(xa, xr)
+    x0, _, s0 = pncg.step(P, sc.X, v0, sc.h, iter_max=500, eps=2.0 * sr.g0, term="grad_abs")
+    assert s0.iters == 0 and np.array_equal(x0, sc.X)
