@@ -53,6 +53,83 @@ KERNEL_BYTES = {
 }
 
 
+# kernels of the mixed single-scene path, by the name rocprofv3 records
+KERNEL_NAMES = {"grad": "k_grad<float", "dir": "k_dir<float", "narrow": "k_narrow<float"}
+CALIB_BYTES = 256 << 20          # the calibration copy reads and writes this many bytes
+SOLVER_SOURCES = ("solver_kernels.hip", "sweep_common.h", "device_math.h", "internal.h")
+
+
+def solver_source_hash():
+    """sha256 over the sources of the single-scene solver kernels: traffic
+    figures measured on other sources are not reported."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in SOLVER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_08001_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def traffic_from_csv(fetch_csv, write_csv, out_path):
+    """HBM bytes per launch of each solver kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by the
+    ratio of the calibration copy's known bytes to what the counter read for
+    it."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = None
+                for k, pat in KERNEL_NAMES.items():
+                    if pat in name:
+                        key = k
+                if key is None and re.search(r"copyBuffer|elementwise", name):
+                    key = "copy"
+                if key is not None:
+                    vals.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
+        out = {}
+        for k, v in vals.items():
+            v = np.sort(np.asarray(v))
+            # the calibration copies are the three largest copy dispatches; a
+            # solver kernel's launches vary little except those that return
+            # at once after the step has stopped, so its median is taken
+            out[k] = float(np.mean(v[-3:])) if k == "copy" else float(np.median(v))
+        return out, {k: len(v) for k, v in vals.items()}
+
+    fetch, nf = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, nw = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale = CALIB_BYTES / fetch["copy"]
+    w_scale = CALIB_BYTES / write["copy"]
+    out = {"source_sha256": solver_source_hash(),
+           "calibration": {"copy_bytes_each_way": CALIB_BYTES, "fetch_counter_bytes": fetch["copy"],
+                           "write_counter_bytes": write["copy"], "fetch_scale": f_scale, "write_scale": w_scale},
+           "pile": {}, "detail": {}}
+    for k in KERNEL_NAMES:
+        if k in fetch and k in write:
+            fb, wb = fetch[k] * f_scale, write[k] * w_scale
+            out["pile"][k] = int(round(fb + wb))
+            out["detail"][k] = {"fetch_bytes": int(round(fb)), "write_bytes": int(round(wb)),
+                                "dispatches": [nf[k], nw[k]]}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def calibration_copy():
+    import torch
+    src = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -221,9 +298,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-scene batched run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--calibrate-copy run into profiles/traffic.json")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--batched-warmup", type=int, default=10)
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from_csv(args.traffic_from[0], args.traffic_from[1],
+                                          os.path.join(ROOT, "profiles", "traffic.json"))))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is one scene or one batch)", file=sys.stderr)
@@ -233,6 +319,8 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibration_copy()
     import scenes
     sc = scenes.pile_scene()
     log(f"pile: {sc.nT} tets, {sc.nV} vertices, {len(sc.tris)} surface triangles")
@@ -262,7 +350,8 @@ def main():
     if os.path.exists(tpath):
         try:
             tj = json.load(open(tpath))
-            traffic = tj.get("pile", {}).get(kern)
+            if tj.get("source_sha256") == solver_source_hash():
+                traffic = tj.get("pile", {}).get(kern)
         except (OSError, ValueError):
             traffic = None
     out = {
