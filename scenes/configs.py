@@ -74,6 +74,25 @@ def twisted_bar_scene(nx=40, ny=8, nz=8, dx=0.01, steps_per_turn=120):
                         "length": L, "steps_per_turn": steps_per_turn})
 
 
+def stacked_bars_scene(gap=6e-4, angle=0.03, nx=40, ny=8, nz=8, dx=0.01):
+    """Two copies of the twisted-bar mesh, the second one turned by ``angle``
+    about the vertical axis and resting ``gap`` above the first: point-
+    triangle and edge-edge barriers are active over the whole overlap (the
+    self-contact state of the twist scene at its own scale, without the
+    120 twist steps needed to reach it)."""
+    Xa, Ta = hex_grid(nx, ny, nz, dx)
+    Xb, Tb = hex_grid(nx, ny, nz, dx)
+    c = np.array([nx * dx / 2, ny * dx / 2, 0.0])
+    R = rotation_matrix([0.0, 0.0, 1.0], angle)
+    Xb = (Xb - c) @ R.T + c + np.array([0.0, 0.0, nz * dx + gap])
+    X, tets, oid = merge_meshes([(Xa, Ta), (Xb, Tb)])
+    fixed = np.nonzero((oid == 0) & ((X[:, 0] < 0.25 * dx) | (X[:, 0] > nx * dx - 0.25 * dx)))[0].astype(np.int32)
+    return _scene(X, tets, E=5e5, nu=0.45, rho=1000.0, dhat=1e-3, kappa=1e4,
+                  h=1.0 / 30.0, fixed=fixed, object_id=oid, self_contact=True,
+                  name="stackedbars", iter_max=150, eps=1e-3, cell=2e-3,
+                  meta={"length": nx * dx})
+
+
 def twist_targets(scene, step):
     """Prescribed positions of the bar's end faces at ``step`` (1-based):
     the end x=0 turns by +2*pi*step/steps_per_turn about the bar axis, the

@@ -194,3 +194,144 @@ def test_grad_abs_rule_matches_scaled_grad_rel():
     assert sr["reason"] == sa["reason"] == 1
     assert sa["iters"] == sr["iters"]
     assert np.array_equal(xa, xr)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_twisted_bar_first_step_matches_oracle(precision):
+    """The 15,360-tet bar, first twist step (end faces prescribed, rotated by
+    3 degrees each way), 12 fixed iterations against the oracle."""
+    from oracle import pncg
+    _say(f"twisted bar step precision={precision}")
+    sc = scenes.twisted_bar_scene()
+    tgt = scenes.twist_targets(sc, 1)
+    P = make_problem(sc)
+    v0 = np.zeros_like(sc.X)
+    xo, vo, st = pncg.step(P, sc.X, v0, sc.h, iter_max=12, eps=0.0, term="delta_e", fixed_targets=tgt)
+    ctx = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e")
+    ctx.pncg_set_dirichlet(sc.fixed, tgt)
+    xg, vg, sg = ctx.pncg_step(sc.X, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - sc.X, xo - sc.X)
+    _say(f"  iters {sg['iters']}/{st.iters} rel_x={rx:.3e} rel_dx={rdx:.3e}")
+    assert sg["iters"] == st.iters == 12
+    assert np.array_equal(xg[sc.fixed], tgt)
+    assert rx <= (1e-12 if precision == 0 else 1e-6)
+    assert rdx <= (1e-9 if precision == 0 else 1e-3)
+
+
+def _stacked():
+    sc = scenes.stacked_bars_scene()
+    x0 = sc.X.copy()
+    v0 = np.zeros_like(x0)
+    v0[sc.object_id == 1, 2] = -0.02
+    return sc, x0, v0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stacked_bars_self_contact_step_matches_oracle(precision):
+    """Two twisted-bar meshes (30,720 tets) stacked with a 0.6 mm gap, the
+    upper one moving down: point-triangle and edge-edge barriers active over
+    the whole overlap (about 5,400 pairs), 2 fixed iterations."""
+    from oracle import pncg
+    _say(f"stacked bars step precision={precision}")
+    sc, x0, v0 = _stacked()
+    P = make_problem(sc)
+    xo, vo, st = pncg.step(P, x0, v0, sc.h, iter_max=2, eps=0.0, term="delta_e", fixed_targets=x0[sc.fixed])
+    ctx = make_ctx(sc, precision, iter_max=2, eps=0.0, term="delta_e")
+    xg, vg, sg = ctx.pncg_step(x0, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - x0, xo - x0)
+    bdx = 1e-9
+    if precision == 1:
+        xq = x0 * (1.0 + 2.0 ** -24)
+        xp, _, _ = pncg.step(P, xq, v0, sc.h, iter_max=2, eps=0.0, term="delta_e", fixed_targets=xq[sc.fixed])
+        bdx = max(1e-3, 4.0 * rel(xp - xq, xo - x0))
+    _say(f"  iters {sg['iters']}/{st.iters} active {sg['n_active']} cand {sg['n_candidates']} "
+         f"rel_x={rx:.3e} rel_dx={rdx:.3e} (bar {bdx:.1e}) hits {sg['alpha_upper_hits']}/{st.alpha_upper_hits}")
+    assert sg["iters"] == st.iters == 2
+    assert sg["n_active"] > 1000
+    assert sg["alpha_upper_hits"] == st.alpha_upper_hits
+    assert rx <= (1e-12 if precision == 0 else 1e-6)
+    assert rdx <= bdx
+    dmin, jmin = ctx.pncg_min_distance(xg)
+    assert dmin > 0 and jmin > 0
+
+
+def test_stacked_bars_four_iterations_within_rounding_envelope():
+    """With ~5,500 stiff barriers active, each further iteration amplifies
+    rounding differences several hundred times (the oracle's own result
+    after 4 iterations moves by ~1e-4 in the step displacement under a
+    1e-15 relative perturbation of the start state).  The float64 GPU result
+    after 4 iterations must lie within 20x that envelope."""
+    from oracle import pncg
+    _say("stacked bars, 4 iterations vs rounding envelope")
+    sc, x0, v0 = _stacked()
+    P = make_problem(sc)
+    xo, _, st = pncg.step(P, x0, v0, sc.h, iter_max=4, eps=0.0, term="delta_e", fixed_targets=x0[sc.fixed])
+    xq = x0 * (1.0 + 1e-15)
+    xp, _, _ = pncg.step(P, xq, v0, sc.h, iter_max=4, eps=0.0, term="delta_e", fixed_targets=xq[sc.fixed])
+    env = rel(xp - xq, xo - x0)
+    ctx = make_ctx(sc, 0, iter_max=4, eps=0.0, term="delta_e")
+    xg, _, sg = ctx.pncg_step(x0, v0, sc.h)
+    rdx = rel(xg - x0, xo - x0)
+    _say(f"  envelope rel_dx={env:.3e} gpu rel_dx={rdx:.3e}")
+    assert sg["iters"] == 4
+    assert rdx <= max(20.0 * env, 1e-9)
+    dmin, jmin = ctx.pncg_min_distance(xg)
+    assert dmin > 0 and jmin > 0
+
+
+_PILE = {}
+
+
+def _pile():
+    """The pile scene and its oracle problem (built once: the rest-pose
+    exclusion over 110k tets takes the oracle about 20 s)."""
+    if not _PILE:
+        sc = scenes.pile_scene()
+        _PILE["sc"] = sc
+        _PILE["P"] = make_problem(sc)
+    return _PILE["sc"], _PILE["P"]
+
+
+def test_pile_candidates_bit_exact_full_size():
+    """The 110k-tet pile squashed to 40% of its height about the floor (the
+    24 shapes' boxes overlap in many places; the state need not be
+    feasible for the AABB test): the sorted point-triangle, edge-edge and
+    vertex-plane lists equal the oracle's bit for bit."""
+    _say("pile candidates (squashed)")
+    sc, P = _pile()
+    x = sc.x0.copy()
+    x[:, 2] *= 0.4
+    pt, ee, pg = P.candidate_lists(x)
+    ctx = make_ctx(sc, 1)
+    import paper_2405_08001_amd as L
+    g_pt = ctx.pncg_candidates(x, L.KIND_PT)
+    g_ee = ctx.pncg_candidates(x, L.KIND_EE)
+    g_pg = ctx.pncg_candidates(x, L.KIND_PG)
+    _say(f"  pt {len(g_pt)}/{len(pt)} ee {len(g_ee)}/{len(ee)} pg {len(g_pg)}/{len(pg)}")
+    assert len(pt) > 1000 and len(ee) > 1000
+    assert np.array_equal(g_pt, pt)
+    assert np.array_equal(g_ee, ee)
+    assert np.array_equal(g_pg, pg)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_pile_two_iterations_match_oracle(precision):
+    """The 110k-tet pile at its start state moving down at 0.1 m/s (the
+    bottom shapes reach the floor barrier), 2 fixed iterations in the
+    bench's configuration against the oracle."""
+    from oracle import pncg
+    _say(f"pile 2 iterations precision={precision}")
+    sc, P = _pile()
+    v0 = np.zeros_like(sc.x0)
+    v0[:, 2] = -0.1
+    if "step" not in _PILE:
+        _PILE["step"] = pncg.step(P, sc.x0, v0, sc.h, iter_max=2, eps=0.0, term="delta_e")
+    xo, vo, st = _PILE["step"]
+    ctx = make_ctx(sc, precision, iter_max=2, eps=0.0, term="delta_e")
+    xg, vg, sg = ctx.pncg_step(sc.x0, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - sc.x0, xo - sc.x0)
+    _say(f"  iters {sg['iters']}/{st.iters} active {sg['n_active']} rel_x={rx:.3e} rel_dx={rdx:.3e} "
+         f"hits {sg['alpha_upper_hits']}/{st.alpha_upper_hits}")
+    assert sg["iters"] == st.iters == 2
+    assert rx <= (1e-12 if precision == 0 else 1e-6)
+    assert rdx <= (1e-9 if precision == 0 else 1e-3)
