@@ -156,6 +156,18 @@ int pncg_set_contact(pncg_ctx* ctx, double dhat, double kappa, double cell,
 int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
                     const double* gravity, uint32_t flags);
 
+/* Performance settings (results do not depend on them beyond rounding
+ * order).  skin > 0: the solver keeps the pairs within dhat + skin at the
+ * last list build and rebuilds the list when the accumulated displacement
+ * bound exceeds skin / 2 (Algorithm 1's per-iteration constraint set is the
+ * active subset of that list); 0 = the default, 0.4 x the mean surface-edge
+ * rest length less dhat, clamped to [2, 8] dhat.  If the contact cell was left to
+ * the library (cell = 0), it becomes max(mean surface edge, dhat + skin).
+ * chunk > 0: iterations launched between reads of the device status (0
+ * keeps the current value; default 16).  Call after pncg_set_contact, which
+ * keeps a skin set here. */
+int pncg_set_tuning(pncg_ctx* ctx, double skin, int32_t chunk);
+
 /* Prescribed vertices for the following steps: idx [n] (distinct),
  * target [n][3] positions they take at the start of the next step (their
  * gradient, direction and update are zero during it).  n = 0 clears. */

@@ -57,7 +57,7 @@ struct pncg_ctx {
   int nWaves = 0;
 
   // contact / solver parameters
-  double dhat = 1e-3, kappa = 0.0, cell_user = 0.0, cell = 0.0, skin = 0.0;
+  double dhat = 1e-3, kappa = 0.0, cell_user = 0.0, cell = 0.0, skin = 0.0, skin_user = 0.0, lmean = 0.0;
   Planes planes{};
   unsigned cflags = 0;
   int iter_max = 100, term = PNCG_TERM_DELTA_E;
@@ -75,6 +75,7 @@ struct pncg_ctx {
   double* d_mass = nullptr;
   uint8_t* d_vflag = nullptr;
   double4* d_target = nullptr;
+  double4* d_xbuild = nullptr;
   double4 *d_x0 = nullptr, *d_x1 = nullptr, *d_xt = nullptr, *d_xstart = nullptr;
   void *d_g = nullptr, *d_pg = nullptr, *d_p0 = nullptr, *d_p1 = nullptr;
   double* d_acc = nullptr;
@@ -212,6 +213,7 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.mass = c->d_mass;
   A.vflag = c->d_vflag;
   A.target = c->d_target;
+  A.xbuild = c->d_xbuild;
   A.x0 = c->d_x0;
   A.x1 = c->d_x1;
   A.xt = c->d_xt;
@@ -424,6 +426,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   if (A.self) {
     ev = prof_begin(c, PNCG_PROF_REBUILD);
     if ((rc = build_candidates(c, c->d_x0, r_build, r_build, 0, &ncand, nullptr))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_xbuild, c->d_x0, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
     prof_end(c, ev);
     ++rebuilds;
     A.cand = c->d_cand;
@@ -471,7 +474,9 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
       ev = prof_begin(c, PNCG_PROF_REBUILD);
-      if ((rc = build_candidates(c, (p & 1) ? c->d_x1 : c->d_x0, r_build, r_build, 0, &ncand, nullptr))) return rc;
+      const double4* xb = (p & 1) ? c->d_x1 : c->d_x0;
+      if ((rc = build_candidates(c, xb, r_build, r_build, 0, &ncand, nullptr))) return rc;
+      HIPCHK(c, hipMemcpyAsync(c->d_xbuild, xb, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
       prof_end(c, ev);
       ++rebuilds;
       A.cand = c->d_cand;
@@ -709,6 +714,15 @@ int adjoint_checks(pncg_ctx* c, const void* x1, double h, const void* xbar, cons
   return PNCG_OK;
 }
 
+// Verlet skin of the solver's candidate list: large enough that the list
+// lasts many iterations, small against the mesh spacing so that neighbouring
+// primitives of one surface (never active, a fraction of an edge apart) stay
+// out of it: 0.4 of the mean surface edge less dhat, within [2, 8] dhat.
+double default_skin(double dhat, double lmean) {
+  if (!(lmean > 0.0)) return 4.0 * dhat;
+  return std::min(8.0 * dhat, std::max(2.0 * dhat, 0.4 * lmean - dhat));
+}
+
 int grid_for(const pncg_ctx* c) {
   long long work = std::max<long long>({(long long)c->nWaves * kWave, (long long)c->nT, (long long)c->nV, 1LL});
   long long g = (work + kSBlock - 1) / kSBlock;
@@ -838,6 +852,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   if ((rc = dmalloc(c, &c->d_inc, inc.size())) || (rc = dmalloc(c, &c->d_inc_vert, incv.size())) ||
       (rc = dmalloc(c, &c->d_mass, nV)) || (rc = dmalloc(c, &c->d_vflag, nV)) ||
       (rc = dmalloc(c, &c->d_target, nV)) || (rc = dmalloc(c, &c->d_x0, nV)) || (rc = dmalloc(c, &c->d_x1, nV)) ||
+      (rc = dmalloc(c, &c->d_xbuild, nV)) ||
       (rc = dmalloc(c, &c->d_xt, nV)) || (rc = dmalloc(c, &c->d_xstart, nV)) ||
       (rc = dmalloc(c, (char**)&c->d_g, r4 * nV)) || (rc = dmalloc(c, (char**)&c->d_pg, r4 * nV)) ||
       (rc = dmalloc(c, (char**)&c->d_p0, r4 * nV)) || (rc = dmalloc(c, (char**)&c->d_p1, r4 * nV)) ||
@@ -920,7 +935,6 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
   c->cell_user = cell;
   c->planes = P;
   c->cflags = flags;
-  c->skin = 4.0 * dhat;
   // grid cell: the caller's, or the mean rest length of the surface edges
   // (at least the candidate inflation), so each primitive touches a few cells
   double lsum = 0.0;
@@ -931,6 +945,8 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
     lsum += std::sqrt(l2);
   }
   const double lmean = c->nE > 0 ? lsum / c->nE : 0.0;
+  c->lmean = lmean;
+  c->skin = c->skin_user > 0.0 ? c->skin_user : default_skin(dhat, lmean);
   c->cell = cell > 0.0 ? cell : std::max(lmean, dhat + c->skin);
   c->n_excl_pt = c->n_excl_ee = 0;
   HIPCHK(c, hipSetDevice(c->device));
@@ -979,6 +995,18 @@ int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, con
   c->term = term;
   if (gravity) for (int i = 0; i < 3; ++i) c->grav[i] = gravity[i];
   c->sflags = flags;
+  return PNCG_OK;
+}
+
+int pncg_set_tuning(pncg_ctx* c, double skin, int32_t chunk) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 2) return fail(c, PNCG_E_STATE, "set_mesh and set_material must come first");
+  if (!std::isfinite(skin) || skin < 0.0 || chunk < 0) return fail(c, PNCG_E_INVAL, "need skin >= 0, chunk >= 0");
+  c->skin_user = skin;
+  c->skin = skin > 0.0 ? skin : default_skin(c->dhat, c->lmean);
+  if (c->cell_user <= 0.0 && c->lmean > 0.0) c->cell = std::max(c->lmean, c->dhat + c->skin);
+  else if (c->cell_user <= 0.0) c->cell = c->dhat + c->skin;
+  if (chunk > 0) c->chunk = chunk;
   return PNCG_OK;
 }
 

@@ -37,12 +37,13 @@ struct Planes {
 
 // Scalars of iteration k.  Each field has one writer kernel (block 0 of it):
 //   first kernel of k: alpha, dE, dE0, D, stop, pause, a_up
-//   direction kernel of k: beta, gTp, gnorm, dir_stop, restart, n_active
+//   direction kernel of k: beta, gTp, gnorm, dir_stop, restart, n_active, Dx
 // and is read only by kernels launched after its writer.
 struct IterScal {
   double alpha, dE, dE0, D;
   double beta, gTp, gnorm;
   double n_active;
+  double Dx;         // max over surface vertices of |x_k - x at the last list build|
   int stop, pause, a_up, dir_stop, restart, pad;
 };
 
@@ -75,6 +76,7 @@ struct Args {
   const double* mass;
   const uint8_t* vflag;
   const double4* target;   // prescribed positions (valid where kFixed)
+  const double4* xbuild;   // positions at the last candidate-list build
   // state
   double4* x0;             // x buffer of even iterations
   double4* x1;             // x buffer of odd iterations

@@ -122,7 +122,9 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
   }
   const double dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
   const double dE0 = (k == 1) ? dE : prev.dE0;
-  const double D = prev.D + alpha * pmv;
+  // displacement of any surface vertex since the list build: exact at x_{k-1}
+  // (measured by the gradient sweep) plus at most alpha |p|_max this update
+  const double D = (A.self ? prev.Dx : prev.D) + alpha * pmv;
   int stop = 0, reason = 0;
   if (A.term == 0 && dE < A.eps * dE0) { stop = 1; reason = 0; }
   else if (mode == kModeFinish) { stop = 1; reason = 2; }
@@ -349,6 +351,11 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
     double gd[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
     double dd[3] = {A.h2 * double(s[3]), A.h2 * double(s[4]), A.h2 * double(s[5])};
     vertex_terms(A, v, x, gd, dd, dots[6], MODE != kGradQuery);
+    if (MODE == kGradDirect && A.self && (A.vflag[v] & kSurface)) {
+      const V3<double> xb = ld3(A.xbuild, v);
+      const double ex = x.x - xb.x, ey = x.y - xb.y, ez = x.z - xb.z;
+      dots[7] = fmax(dots[7], sqrt(ex * ex + ey * ey + ez * ez));
+    }
     if (A.vflag[v] & kFixed) {
       gd[0] = gd[1] = gd[2] = 0.0;
       dd[0] = dd[1] = dd[2] = 1.0;
@@ -381,7 +388,7 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
     }
   }
   if (MODE == kGradQuery) return;
-  const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 1};
   block_reduce<8>(dots, kind, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -398,7 +405,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   double r[8];
   {
-    const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 1};
     reduce_partials<8>(A.part_grad, 8, A.grid, kind, r, sh);
   }
   double nact = r[6];
@@ -428,6 +435,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   if (leader) {
     IterScal& o = A.scal[k];
     o.beta = beta; o.gTp = gTp; o.gnorm = gnorm; o.dir_stop = dir_stop; o.restart = restart; o.n_active = nact;
+    o.Dx = r[7];
     if (k == 0) A.status->g0 = gnorm;
     if (dir_stop) {
       StepStatus* st = A.status;
