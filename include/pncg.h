@@ -162,7 +162,7 @@ int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
  * bound exceeds skin / 2 (Algorithm 1's per-iteration constraint set is the
  * active subset of that list); 0 = the default, 0.4 x the mean surface-edge
  * rest length less dhat, clamped to [2, 8] dhat.  If the contact cell was left to
- * the library (cell = 0), it becomes max(mean surface edge, dhat + skin).
+ * the library (cell = 0), it becomes max(1.5 x mean surface edge, dhat + skin).
  * chunk > 0: iterations launched between reads of the device status (0
  * keeps the current value; default 16).  Call after pncg_set_contact, which
  * keeps a skin set here. */

@@ -226,6 +226,7 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0 ? 1 : 0;
   A.cand = c->d_cand;
   A.ncand = c->d_ncand;
+  A.cand_cap = c->cand_cap;
   A.tris = c->d_tris;
   A.edges = c->d_edges;
   A.planes = c->planes;
@@ -350,6 +351,48 @@ int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, i
   return PNCG_OK;
 }
 
+constexpr int kRestart = 1000;   // internal: a capacity was exceeded, run the step again
+
+// The solver's candidate list at device positions x (pairs within
+// dhat + skin, unordered, kind in the pair), built without host
+// synchronisation; a grid or list that did not fit raises kErrCapacity in
+// the step status, which the step loop turns into a rerun with larger
+// buffers.  Also records the build positions.
+int build_solver_list(pncg_ctx* c, const double4* x) {
+  const long long want = std::max<long long>(4096, 2LL * c->nSV);
+  if (c->cand_cap < want) {
+    int2* nc = nullptr;
+    int rc = dmalloc(c, &nc, (size_t)want);
+    if (rc) return rc;
+    dfree(c, c->d_cand);
+    c->d_cand = nc;
+    c->cand_cap = want;
+  }
+  broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, c->d_cand, c->cand_cap, c->d_ncand,
+                    &c->d_status->err, &c->d_status->n_cand, c->stream);
+  HIPCHK(c, hipMemcpyAsync(c->d_xbuild, x, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
+  return PNCG_OK;
+}
+
+// After a kRestart: size the grid and the list for what the last build found.
+int grow_solver_buffers(pncg_ctx* c) {
+  long long cnt[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&cnt[0], c->d_totals, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&cnt[1], c->d_ncand, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  int rc = sync(c);
+  if (rc) return rc;
+  if (cnt[0] > c->ent_cap && (rc = alloc_grid(c, cnt[0] + cnt[0] / 2))) return rc;
+  if (cnt[1] > c->cand_cap) {
+    const long long cap = cnt[1] + cnt[1] / 2 + 1024;
+    int2* nc = nullptr;
+    if ((rc = dmalloc(c, &nc, (size_t)cap))) return rc;
+    dfree(c, c->d_cand);
+    c->d_cand = nc;
+    c->cand_cap = cap;
+  }
+  return PNCG_OK;
+}
+
 int upload_rows(pncg_ctx* c, const double* host, double* dev, int n) {
   HIPCHK(c, hipMemcpyAsync(dev, host, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream));
   return PNCG_OK;
@@ -417,19 +460,17 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   launch_predict<R>(A, x_dev, v_dev, grav, c->stream);
   prof_end(c, ev);
   int rebuilds = 0;
-  long long ncand = 0;
   // the solver's list: pairs within dhat + skin at the build positions (a
   // pair's distance changes by at most twice the per-vertex displacement,
   // which stays below skin / 2 until the next build)
-  const double r_build = c->dhat + c->skin;
   int rc;
   if (A.self) {
     ev = prof_begin(c, PNCG_PROF_REBUILD);
-    if ((rc = build_candidates(c, c->d_x0, r_build, r_build, 0, &ncand, nullptr))) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->d_xbuild, c->d_x0, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = build_solver_list(c, c->d_x0))) return rc;
     prof_end(c, ev);
     ++rebuilds;
     A.cand = c->d_cand;
+    A.cand_cap = c->cand_cap;
   }
   int k = 0;
   int mode = 0;  // kModeNormal
@@ -469,17 +510,17 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     mode = 0;
     if ((rc = read_status(c))) return rc;
     const StepStatus s = *c->h_status;
+    if (s.err & kErrCapacity) return kRestart;
     if ((rc = check_status_err(c, s))) return rc;
     if (s.stopped) break;
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
       ev = prof_begin(c, PNCG_PROF_REBUILD);
-      const double4* xb = (p & 1) ? c->d_x1 : c->d_x0;
-      if ((rc = build_candidates(c, xb, r_build, r_build, 0, &ncand, nullptr))) return rc;
-      HIPCHK(c, hipMemcpyAsync(c->d_xbuild, xb, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
+      if ((rc = build_solver_list(c, (p & 1) ? c->d_x1 : c->d_x0))) return rc;
       prof_end(c, ev);
       ++rebuilds;
       A.cand = c->d_cand;
+      A.cand_cap = c->cand_cap;
       if (p > k) rate = std::max(rate, (s.D - D) / (p - k + 1));
       D = 0.0;
       k = p;
@@ -505,7 +546,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     st->g_norm = s.gk;
     st->alpha_upper_hits = s.a_up_hits;
     st->rebuilds = rebuilds;
-    st->n_candidates = ncand;
+    st->n_candidates = A.self ? s.n_cand : 0;
     st->n_active = (long long)s.n_active;
   }
   return s.reason == 2 ? PNCG_W_MAXITER : PNCG_OK;
@@ -935,8 +976,9 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
   c->cell_user = cell;
   c->planes = P;
   c->cflags = flags;
-  // grid cell: the caller's, or the mean rest length of the surface edges
-  // (at least the candidate inflation), so each primitive touches a few cells
+  // grid cell: the caller's, or 1.5 x the mean rest length of the surface
+  // edges (at least the candidate inflation), so each primitive touches a
+  // few cells and a cell holds a few primitives
   double lsum = 0.0;
   for (int e = 0; e < c->nE; ++e) {
     const int a = c->edges[2 * e], b = c->edges[2 * e + 1];
@@ -947,7 +989,7 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
   const double lmean = c->nE > 0 ? lsum / c->nE : 0.0;
   c->lmean = lmean;
   c->skin = c->skin_user > 0.0 ? c->skin_user : default_skin(dhat, lmean);
-  c->cell = cell > 0.0 ? cell : std::max(lmean, dhat + c->skin);
+  c->cell = cell > 0.0 ? cell : std::max(1.5 * lmean, dhat + c->skin);
   c->n_excl_pt = c->n_excl_ee = 0;
   HIPCHK(c, hipSetDevice(c->device));
   if ((flags & PNCG_CONTACT_SELF) && (flags & PNCG_CONTACT_REST_EXCLUDE) && c->nF + c->nE > 0) {
@@ -1004,7 +1046,7 @@ int pncg_set_tuning(pncg_ctx* c, double skin, int32_t chunk) {
   if (!std::isfinite(skin) || skin < 0.0 || chunk < 0) return fail(c, PNCG_E_INVAL, "need skin >= 0, chunk >= 0");
   c->skin_user = skin;
   c->skin = skin > 0.0 ? skin : default_skin(c->dhat, c->lmean);
-  if (c->cell_user <= 0.0 && c->lmean > 0.0) c->cell = std::max(c->lmean, c->dhat + c->skin);
+  if (c->cell_user <= 0.0 && c->lmean > 0.0) c->cell = std::max(1.5 * c->lmean, c->dhat + c->skin);
   else if (c->cell_user <= 0.0) c->cell = c->dhat + c->skin;
   if (chunk > 0) c->chunk = chunk;
   return PNCG_OK;
@@ -1046,9 +1088,14 @@ int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, doubl
   if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_scal(c))) return rc;
-  if (st) std::memset(st, 0, sizeof(*st));
-  return c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    rc = c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)
                                     : step_impl<double>(c, x, v, h, x_out, v_out, st);
+    if (rc != kRestart) return rc;
+    if ((rc = grow_solver_buffers(c))) return rc;
+  }
+  return fail(c, PNCG_E_CAPACITY, "candidate buffers kept overflowing");
 }
 
 int pncg_step(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,

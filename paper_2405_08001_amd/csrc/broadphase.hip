@@ -467,6 +467,107 @@ __global__ void __launch_bounds__(kBlock) k_pairs_fill(Broad B, PairCtx P, int2*
   }
 }
 
+// Single-pass emission for the solver's list: every pair found is appended
+// at a position reserved with one atomic per wave (point-triangle) or per
+// block (edge-edge), in no particular order; the kind is in the pair:
+// (v, f) point-triangle, (e1, ~e2) edge-edge.  counter counts every pair
+// found, also those past cap (the caller checks it against cap).
+constexpr int kEmitBuf = 4;
+
+__device__ __forceinline__ int block_excl_scan(int v, int& total, int* sh) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  int wt;
+  const int x = wave_excl_scan(v, wt);
+  if (lane == 0) sh[w] = wt;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int i = 0; i < kBlock / kWave; ++i) {
+    if (i < w) before += sh[i];
+    total += sh[i];
+  }
+  __syncthreads();
+  return before + x;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pairs_emit(Broad B, PairCtx P, int2* out, long long cap,
+                                                      unsigned long long* counter) {
+  __shared__ SlotSpan L;
+  __shared__ int2 buf[kBlock * kEmitBuf];
+  __shared__ int ssum[kBlock / kWave];
+  __shared__ unsigned long long sbase;
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long e0 = B.start[B.tsize >> 1], e1 = B.start[B.tsize];
+  // point-triangle: one wave per surface vertex, one lane per bucket slot
+  {
+    const long long wid = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const long long nwv = ((long long)gridDim.x * kBlock) >> 6;
+    for (long long w = wid; w < B.nSV; w += nwv) {
+      const int v = B.surf[w];
+      const V3<double> p = ldx(P.x, v);
+      const int3 c = cell_of(p, P.inv);
+      const unsigned long long key = cell_key(c.x, c.y, c.z);
+      const unsigned h = hash_key(key, B.tsize, false);
+      const int s0 = B.start[h], s1 = B.start[h + 1];
+      for (int t0 = s0; t0 < s1; t0 += kWave) {
+        const int t = t0 + lane;
+        int2 pr;
+        const int hit = (t < s1 && vertex_slot_pair(B, P, v, p, key, t, pr)) ? 1 : 0;
+        int tot;
+        const int before = wave_excl_scan(hit, tot);
+        if (tot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned long long)tot);
+        base = __shfl(base, 0, kWave);
+        if (hit && (long long)(base + before) < cap) out[base + before] = pr;
+      }
+    }
+  }
+  // edge-edge: a block takes kBlock consecutive edge slots with their buckets in LDS
+  for (long long S = e0 + (long long)blockIdx.x * kBlock; S < e1; S += (long long)gridDim.x * kBlock) {
+    const long long s = S + threadIdx.x;
+    const int base = load_span(B, L, S, min(S + (long long)kBlock, e1));
+    int c = 0;
+    if (s < e1)
+      edge_slot_pairs(B, P, L, base, (int)s, [&](int2 pr) {
+        if (c < kEmitBuf) buf[threadIdx.x * kEmitBuf + c] = make_int2(pr.x, ~pr.y);
+        ++c;
+      });
+    int total;
+    const int before = block_excl_scan(c, total, ssum);
+    if (threadIdx.x == 0) sbase = total ? atomicAdd(counter, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    const unsigned long long o = sbase + before;
+    for (int i = 0; i < c && i < kEmitBuf; ++i)
+      if ((long long)(o + i) < cap) out[o + i] = buf[threadIdx.x * kEmitBuf + i];
+    if (c > kEmitBuf) {
+      // more pairs than the buffer holds: enumerate again for the rest
+      int j = 0;
+      edge_slot_pairs(B, P, L, base, (int)s, [&](int2 pr) {
+        if (j >= kEmitBuf && (long long)(o + j) < cap) out[o + j] = make_int2(pr.x, ~pr.y);
+        ++j;
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// ncand[0] = 0 (the counter), ncand[1] = -1 (the kind is in the pair)
+__global__ void k_list_reset(long long* ncand) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ncand[0] = 0;
+    ncand[1] = -1;
+  }
+}
+
+// Flags a grid or list that did not fit (the list is then incomplete).
+__global__ void k_list_check(Broad B, const long long* ncand, long long cap, int* err, long long* n_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (B.totals[0] > B.ent_cap || ncand[0] > cap) atomicOr(err, kErrCapacity);
+    *n_out = ncand[0];
+  }
+}
+
 // totals[2] = number of point-triangle pairs = offset of the first edge-edge slot
 __global__ void k_pt_total(Broad B) {
   if (threadIdx.x == 0 && blockIdx.x == 0) B.totals[2] = B.part_off[B.nSV];
@@ -517,6 +618,24 @@ void broad_fill(const Broad& B, const double4* x, double cell, double r, double 
   PairCtx P{x, 1.0 / cell, r, filter_d, filter_obj};
   const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
   hipLaunchKernelGGL(k_pairs_fill, dim3(nb), dim3(kBlock), 0, s, B, P, out, cap);
+}
+
+void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
+                       long long* ncand, int* err, long long* n_out, hipStream_t s) {
+  const double inv = 1.0 / cell;
+  const int n = B.nF + B.nE;
+  hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, s, ncand);
+  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
+  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
+  hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
+  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
+  hipLaunchKernelGGL(k_bucket_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x);
+  PairCtx P{x, inv, r, r, 0};
+  const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_pairs_emit, dim3(nb), dim3(kBlock), 0, s, B, P, out, cap, (unsigned long long*)ncand);
+  hipLaunchKernelGGL(k_list_check, dim3(1), dim3(64), 0, s, B, (const long long*)ncand, cap, err, n_out);
 }
 
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,

@@ -90,7 +90,8 @@ struct Args {
   // contact
   int self;                // point-triangle / edge-edge barriers on
   const int2* cand;        // candidate pairs: (v, f) point-triangle then (e1, e2) edge-edge
-  const long long* ncand;  // device: [0] total, [1] point-triangle count
+  const long long* ncand;  // device: [0] total, [1] point-triangle count (-1: kind in the pair)
+  long long cand_cap;      // capacity of cand (counts above it are clamped)
   const int* tris;         // [nF][3]
   const int* edges;        // [nE][2]
   Planes planes;

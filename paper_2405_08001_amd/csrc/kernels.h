@@ -71,6 +71,14 @@ void broad_build_count(const Broad& B, const double4* x, double cell, double r, 
 // (v, f); then edge-edge).
 void broad_fill(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj, int2* out,
                 long long cap, hipStream_t s);
+// The solver's list without host synchronisation: grid build and one-pass
+// pair emission (pairs within distance r, unordered, kind in the pair:
+// (v, f) point-triangle, (e1, ~e2) edge-edge; ncand[0] = pairs found,
+// ncand[1] = -1).  Sets kErrCapacity in *err if the grid entries or the
+// pairs exceeded their capacity (the list is then incomplete), and copies
+// the pair count to *n_out.
+void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
+                       long long* ncand, int* err, long long* n_out, hipStream_t s);
 // Plane candidates ((n0 x0 + n1 x1) + n2 x2) - o <= r for surface vertices.
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,
                       long long cap, hipStream_t s);

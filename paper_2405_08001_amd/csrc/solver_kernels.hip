@@ -156,15 +156,18 @@ __device__ __forceinline__ bool pair_closest(const Args<R>& A, int q, const Pos&
                                              long long npt) {
   int2 pr = A.cand[q];
   V3<double> X[4];
-  if (q < npt) {
+  // kind: by position in a sorted list (npt >= 0), or in the pair itself
+  // (npt < 0: edge-edge pairs are stored as (e1, ~e2))
+  if (npt >= 0 ? q < npt : pr.y >= 0) {
     iv[0] = pr.x;
     iv[1] = A.tris[3 * pr.y]; iv[2] = A.tris[3 * pr.y + 1]; iv[3] = A.tris[3 * pr.y + 2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) X[i] = pos(iv[i]);
     c = closest_pt(X[0], X[1], X[2], X[3]);
   } else {
+    const int e2 = pr.y >= 0 ? pr.y : ~pr.y;
     iv[0] = A.edges[2 * pr.x]; iv[1] = A.edges[2 * pr.x + 1];
-    iv[2] = A.edges[2 * pr.y]; iv[3] = A.edges[2 * pr.y + 1];
+    iv[2] = A.edges[2 * e2]; iv[3] = A.edges[2 * e2 + 1];
 #pragma unroll
     for (int i = 0; i < 4; ++i) X[i] = pos(iv[i]);
     c = closest_ee(X[0], X[1], X[2], X[3]);
@@ -210,7 +213,7 @@ __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) 
   }
   if (!fp.work) return;
   PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
-  const long long nq = A.ncand[0], npt = A.ncand[1];
+  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
   double nact = 0.0;
   const Slice sq = block_slice(nq);
   for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
@@ -493,7 +496,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   // pairs: kappa [ca (sum_i c_i p_i . t)^2 + cb |sum_i c_i p_i|^2] (eq12, eq13)
   if (A.self) {
     PosReader<R> pos{xk, pk, 0.0, 0};
-    const long long nq = A.ncand[0], npt = A.ncand[1];
+    const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
     const Slice sq = block_slice(nq);
     for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
       int iv[4];
@@ -563,7 +566,7 @@ __global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part
   __shared__ double sh[kSWaves * 2];
   const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   PosReader<R> pos{A.x0, A.p0, 0.0, 0};
-  const long long nq = A.ncand[0], npt = A.ncand[1];
+  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
   double sum = 0.0;
   for (long long q = tid; q < nq; q += stride) {
     int iv[4];
@@ -725,7 +728,7 @@ __global__ void __launch_bounds__(kSBlock) k_audit(Args<R> A, double* part) {
   __shared__ double sh[kSWaves * 2];
   const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   double dmin = HUGE_VAL, jmin = HUGE_VAL;
-  const long long nq = A.ncand[0], npt = A.ncand[1];
+  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
   for (long long q = tid; q < nq; q += stride) {
     int2 pr = A.cand[q];
     Closest c;
