@@ -331,6 +331,16 @@ int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa,
  * 512); pncg_batch_autotune picks one by timing. */
 int pncg_batch_set_block(pncg_batch* b, int32_t block);
 
+/* lds = 1: the step kernel keeps the positions and search directions of the
+ * scene it is solving in LDS (largest scene's vertex count x (24 + 3 x
+ * sizeof(real)) bytes per workgroup); lds = 0: in device memory.  The
+ * default is 1 when the largest scene fits in one workgroup's LDS;
+ * E_INVAL for 1 when it does not.  Results are the same either way. */
+int pncg_batch_set_staging(pncg_batch* b, int32_t lds);
+
+/* Current workgroup size and staging mode (each pointer nullable). */
+int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds);
+
 /* One time step of every scene with step size h > 0.  Device pointers on the
  * batch's device: x_dev, v_dev [nV][3] the state, x_out_dev, v_out_dev
  * [nV][3] the result (must not alias the inputs).  Ordered on the batch's
@@ -352,8 +362,8 @@ int pncg_batch_run(pncg_batch* b, double* x_dev, double* v_dev, double h,
 int pncg_batch_stats(pncg_batch* b, int32_t* iters, int32_t* reason,
                      int64_t* iters_total);
 
-/* Time reps steps from (x_dev, v_dev) at each workgroup size and keep the
- * fastest (written to *block_out if non-NULL).  The state is not modified;
+/* Time reps steps from (x_dev, v_dev) at each workgroup size and staging
+ * mode and keep the fastest (its size written to *block_out if non-NULL).  The state is not modified;
  * iters_total advances by the timed steps. */
 int pncg_batch_autotune(pncg_batch* b, const double* x_dev,
                         const double* v_dev, double h, int32_t reps,

@@ -33,7 +33,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_set_tuning",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
-           "pncg_batch_autotune")
+           "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -99,6 +99,8 @@ def _load():
         "pncg_batch_run": (I32, [P, P, P, D, I32]),
         "pncg_batch_stats": (I32, [P, P, P, P]),
         "pncg_batch_autotune": (I32, [P, P, P, D, I32, P]),
+        "pncg_batch_set_staging": (I32, [P, I32]),
+        "pncg_batch_get_config": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -140,7 +142,7 @@ class Context:
         self.nT = 0
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _L is not None:   # _L is None at interpreter exit
             _L.pncg_destroy(self._h)
             self._h = None
 
@@ -330,7 +332,7 @@ class Batch:
         self.precision = precision
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _L is not None:   # _L is None at interpreter exit
             _L.pncg_batch_destroy(self._h)
             self._h = None
 
@@ -350,6 +352,15 @@ class Batch:
 
     def pncg_batch_set_block(self, block):
         self._check(_L.pncg_batch_set_block(self._h, int(block)))
+
+    def pncg_batch_set_staging(self, lds):
+        self._check(_L.pncg_batch_set_staging(self._h, int(lds)))
+
+    def pncg_batch_get_config(self):
+        """(block, lds) of the step kernel."""
+        blk, lds = C.c_int32(), C.c_int32()
+        self._check(_L.pncg_batch_get_config(self._h, C.byref(blk), C.byref(lds)))
+        return blk.value, lds.value
 
     def pncg_batch_step(self, x, v, h, x_out, v_out):
         """float64 CUDA tensors (nV, 3); x_out/v_out must not alias x/v."""

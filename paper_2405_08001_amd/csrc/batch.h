@@ -24,6 +24,7 @@ struct BatchArgs {
   R4<R>* g;
   R4<R>* pg;
   R4<R>* p;
+  int vcap;                // largest scene's vertex count (LDS staging)
   double dhat, kappa, h, h2, eps;
   V3<double> grav;
   int iter_max, term;
@@ -34,12 +35,18 @@ struct BatchArgs {
   int* err;                // error bits
 };
 
-// Resident workgroups per compute unit of the step kernel at this block size.
+// LDS bytes that staging the positions and directions of a scene of vcap
+// vertices takes.
 template <typename R>
-hipError_t batch_occupancy(int block, int* per_cu);
+size_t batch_lds_bytes(int vcap);
+
+// Resident workgroups per compute unit of the step kernel at this block size
+// (lds: with the positions and directions of a scene in LDS).
+template <typename R>
+hipError_t batch_occupancy(int block, bool lds, int vcap, int* per_cu);
 
 template <typename R>
-void launch_batch_step(const BatchArgs<R>& A, int block, int grid, const double* x, const double* v, double* xo,
-                       double* vo, hipStream_t s);
+void launch_batch_step(const BatchArgs<R>& A, int block, int grid, bool lds, const double* x, const double* v,
+                       double* xo, double* vo, hipStream_t s);
 
 }  // namespace pncg

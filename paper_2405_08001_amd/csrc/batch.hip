@@ -11,11 +11,19 @@
 
 namespace pncg {
 
-template <typename R, int BS>
+// LDSX: the positions and directions of the scene being stepped live in
+// LDS (A.vcap vertices at most; dynamic shared memory of vcap * (3 doubles +
+// 3 R)), so the gathers of the element loops read LDS instead of memory;
+// otherwise they live in the per-vertex arrays x and p.
+template <typename R, int BS, bool LDSX>
 __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double* x_in, const double* v_in,
                                                    double* x_out, double* v_out) {
   constexpr int NW = BS / kWave;
   __shared__ double sh[NW * 8];
+  extern __shared__ double dyn[];
+  double* sx = dyn;                                  // [3][vcap]
+  R* sp = reinterpret_cast<R*>(dyn + 3 * A.vcap);    // [3][vcap]
+  const int vc = A.vcap;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   for (int si = blockIdx.x; si < A.nScenes; si += gridDim.x) {
     const int s = A.order[si];
@@ -24,22 +32,41 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
     const int w0 = A.wave_off[s], w1 = A.wave_off[s + 1];
     const double* pl = A.planes + 4 * s;
     const bool has_plane = pl[0] != 0.0 || pl[1] != 0.0 || pl[2] != 0.0;
+    auto X = [&](int v) -> V3<double> {
+      if (!LDSX) return ld3(A.x, v);
+      const int l = v - v0;
+      return mk3(sx[l], sx[vc + l], sx[2 * vc + l]);
+    };
+    auto setX = [&](int v, V3<double> x) {
+      if (!LDSX) { st3(A.x, v, x); return; }
+      const int l = v - v0;
+      sx[l] = x.x; sx[vc + l] = x.y; sx[2 * vc + l] = x.z;
+    };
+    auto Pd = [&](int v) -> V3<R> {
+      if (!LDSX) return ldr<R>(A.p, v);
+      const int l = v - v0;
+      return mk3(sp[l], sp[vc + l], sp[2 * vc + l]);
+    };
+    auto setP = [&](int v, V3<R> p) {
+      if (!LDSX) { str<R>(A.p, v, p); return; }
+      const int l = v - v0;
+      sp[l] = p.x; sp[vc + l] = p.y; sp[2 * vc + l] = p.z;
+    };
     // predictor: xt = x + h v + h^2 g; x_0 = x^t
     for (int v = v0 + tid; v < v1; v += BS) {
       const V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
       const V3<double> u = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
-      st3(A.xstart, v, x);
-      st3(A.x, v, x);
+      if (!LDSX) st3(A.xstart, v, x);
+      setX(v, x);
       V3<double> xt = x + A.h * u;
       xt = xt + A.h2 * A.grav;
       st3(A.xt, v, xt);
       str<R>(A.g, v, mk3(R(0), R(0), R(0)));
-      str<R>(A.p, v, mk3(R(0), R(0), R(0)));
+      setP(v, mk3(R(0), R(0), R(0)));
     }
     __syncthreads();
     int k = 0, reason = 2;
     double g0 = 0.0, dE0 = 0.0;
-    PosReader<R> pos{A.x, A.p, 0.0, 0};
     for (;;) {
       // ---- gradient, diag(H), dot products (vertex-centric sweep)
       double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -50,7 +77,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         R sv[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
         if (code >= 0) {
           const ElemRec<R> rec = A.elem[code >> 2];
-          Kin<R> kin = kinematics<R>(rec.B, pos(rec.v[0]), pos(rec.v[1]), pos(rec.v[2]), pos(rec.v[3]));
+          Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
           if (kin.J > R(0)) {
             V3<R> g, dg;
             nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg);
@@ -63,7 +90,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         const int upv = __shfl_up(myv, 1, kWave);
         if (myv < 0 || (lane > 0 && upv == myv)) continue;
         const int v = myv;
-        const V3<double> x = ld3(A.x, v), xt = ld3(A.xt, v);
+        const V3<double> x = X(v), xt = ld3(A.xt, v);
         const double m = A.mass[v];
         double gd[3] = {A.h2 * double(sv[0]) + m * (x.x - xt.x), A.h2 * double(sv[1]) + m * (x.y - xt.y),
                         A.h2 * double(sv[2]) + m * (x.z - xt.z)};
@@ -84,7 +111,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         }
         const V3<R> gR = mk3(R(gd[0]), R(gd[1]), R(gd[2]));
         const V3<R> pgR = mk3(R(gd[0] / dd[0]), R(gd[1] / dd[1]), R(gd[2] / dd[2]));
-        const V3<R> gpR = ldr<R>(A.g, v), ppR = ldr<R>(A.p, v);
+        const V3<R> gpR = ldr<R>(A.g, v), ppR = Pd(v);
         str<R>(A.g, v, gR);
         str<R>(A.pg, v, pgR);
         const double g3[3] = {double(gR.x), double(gR.y), double(gR.z)};
@@ -123,14 +150,14 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       const R rb = R(beta);
       double php = 0.0, pmv = 0.0, pmc = 0.0;
       for (int v = v0 + tid; v < v1; v += BS) {
-        const V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(A.p, v), rb);
-        str<R>(A.p, v, p);
+        const V3<R> p = direction(ldr<R>(A.pg, v), Pd(v), rb);
+        setP(v, p);
         const double px = p.x, py = p.y, pz = p.z, p2 = px * px + py * py + pz * pz;
         php += A.mass[v] * p2;
         pmv = fmax(pmv, sqrt(p2));
         pmc = fmax(pmc, fmax(fabs(px), fmax(fabs(py), fabs(pz))));
         if (has_plane && (A.vflag[v] & kSurface)) {
-          const double d = plane_dist(pl, ld3(A.x, v));
+          const double d = plane_dist(pl, X(v));
           if (d > 0.0 && d < A.dhat) {
             const double np = pl[0] * px + pl[1] * py + pl[2] * pz;
             php += A.kappa * barrier_d2b(d, A.dhat) * np * np;
@@ -142,10 +169,9 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       double el = 0.0;
       for (int e = t0 + tid; e < t1; e += BS) {
         const ElemRec<R> rec = A.elem[e];
-        Kin<R> kin = kinematics<R>(rec.B, ld3(A.x, rec.v[0]), ld3(A.x, rec.v[1]), ld3(A.x, rec.v[2]),
-                                   ld3(A.x, rec.v[3]));
+        Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
         V3<R> d[3];
-        dF_cols(rec.B, ldr<R>(A.p, rec.v[0]), ldr<R>(A.p, rec.v[1]), ldr<R>(A.p, rec.v[2]), ldr<R>(A.p, rec.v[3]), d);
+        dF_cols(rec.B, Pd(rec.v[0]), Pd(rec.v[1]), Pd(rec.v[2]), Pd(rec.v[3]), d);
         el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
       }
       double red[3] = {php + A.h2 * el, pmv, pmc};
@@ -161,9 +187,9 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       if (!isfinite(alpha)) { reason = 3; break; }
       // ---- update
       for (int v = v0 + tid; v < v1; v += BS) {
-        const V3<double> x = ld3(A.x, v);
-        const R4<R> q = A.p[v];
-        st3(A.x, v, mk3(fma(alpha, double(q.x), x.x), fma(alpha, double(q.y), x.y), fma(alpha, double(q.z), x.z)));
+        const V3<double> x = X(v);
+        const V3<R> q = Pd(v);
+        setX(v, mk3(fma(alpha, double(q.x), x.x), fma(alpha, double(q.y), x.y), fma(alpha, double(q.z), x.z)));
       }
       const double dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
       if (k == 0) dE0 = dE;
@@ -175,7 +201,8 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
     // end of step: v = (x - x^t) / h
     const double ih = 1.0 / A.h;
     for (int v = v0 + tid; v < v1; v += BS) {
-      const V3<double> x = ld3(A.x, v), xs = ld3(A.xstart, v);
+      const V3<double> x = X(v);
+      const V3<double> xs = LDSX ? mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]) : ld3(A.xstart, v);
       x_out[3 * v] = x.x; x_out[3 * v + 1] = x.y; x_out[3 * v + 2] = x.z;
       v_out[3 * v] = (x.x - xs.x) * ih; v_out[3 * v + 1] = (x.y - xs.y) * ih; v_out[3 * v + 2] = (x.z - xs.z) * ih;
     }
@@ -188,39 +215,58 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
   }
 }
 
-template <typename R>
-void launch_batch_step(const BatchArgs<R>& A, int block, int grid, const double* x, const double* v, double* xo,
-                       double* vo, hipStream_t s) {
+template <typename R, bool LDSX>
+void launch_bs(const BatchArgs<R>& A, int block, int grid, size_t shmem, const double* x, const double* v, double* xo,
+               double* vo, hipStream_t s) {
   switch (block) {
     case 256:
-      hipLaunchKernelGGL((k_batch_step<R, 256>), dim3(grid), dim3(256), 0, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 256, LDSX>), dim3(grid), dim3(256), shmem, s, A, x, v, xo, vo);
       break;
     case 512:
-      hipLaunchKernelGGL((k_batch_step<R, 512>), dim3(grid), dim3(512), 0, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 512, LDSX>), dim3(grid), dim3(512), shmem, s, A, x, v, xo, vo);
       break;
     default:
-      hipLaunchKernelGGL((k_batch_step<R, 1024>), dim3(grid), dim3(1024), 0, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 1024, LDSX>), dim3(grid), dim3(1024), shmem, s, A, x, v, xo, vo);
       break;
   }
 }
 
 template <typename R>
-hipError_t batch_occupancy(int block, int* per_cu) {
+size_t batch_lds_bytes(int vcap) {
+  return (size_t)vcap * 3 * (sizeof(double) + sizeof(R));
+}
+
+template <typename R>
+void launch_batch_step(const BatchArgs<R>& A, int block, int grid, bool lds, const double* x, const double* v,
+                       double* xo, double* vo, hipStream_t s) {
+  if (lds) launch_bs<R, true>(A, block, grid, batch_lds_bytes<R>(A.vcap), x, v, xo, vo, s);
+  else launch_bs<R, false>(A, block, grid, 0, x, v, xo, vo, s);
+}
+
+template <typename R, bool LDSX>
+hipError_t occ(int block, size_t shmem, int* per_cu) {
   switch (block) {
     case 256:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 256>, 256, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 256, LDSX>, 256, shmem);
     case 512:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 512>, 512, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 512, LDSX>, 512, shmem);
     default:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 1024>, 1024, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 1024, LDSX>, 1024, shmem);
   }
 }
 
-template hipError_t batch_occupancy<float>(int, int*);
-template hipError_t batch_occupancy<double>(int, int*);
-template void launch_batch_step<float>(const BatchArgs<float>&, int, int, const double*, const double*, double*,
+template <typename R>
+hipError_t batch_occupancy(int block, bool lds, int vcap, int* per_cu) {
+  return lds ? occ<R, true>(block, batch_lds_bytes<R>(vcap), per_cu) : occ<R, false>(block, 0, per_cu);
+}
+
+template size_t batch_lds_bytes<float>(int);
+template size_t batch_lds_bytes<double>(int);
+template hipError_t batch_occupancy<float>(int, bool, int, int*);
+template hipError_t batch_occupancy<double>(int, bool, int, int*);
+template void launch_batch_step<float>(const BatchArgs<float>&, int, int, bool, const double*, const double*, double*,
                                        double*, hipStream_t);
-template void launch_batch_step<double>(const BatchArgs<double>&, int, int, const double*, const double*, double*,
-                                        double*, hipStream_t);
+template void launch_batch_step<double>(const BatchArgs<double>&, int, int, bool, const double*, const double*,
+                                        double*, double*, hipStream_t);
 
 }  // namespace pncg

@@ -19,6 +19,11 @@ namespace {
 thread_local std::string g_batch_create_error;
 }
 
+namespace {
+constexpr int kNBlocks = 3;
+constexpr int kBlocks[kNBlocks] = {256, 512, 1024};
+}  // namespace
+
 struct pncg_batch {
   int device = 0, precision = PNCG_FP64;
   hipStream_t stream = nullptr;
@@ -42,7 +47,10 @@ struct pncg_batch {
   int iter_max = 100, term = PNCG_TERM_DELTA_E;
   double grav[3] = {0.0, 0.0, -9.8};
   unsigned flags = 0;
-  int block = 512, grid = 1, max_grid[3] = {1, 1, 1};
+  int block = 512, grid = 1, max_grid[kNBlocks] = {1, 1, 1}, max_grid_lds[kNBlocks] = {0, 0, 0};
+  int vcap = 0;             // largest scene's vertex count
+  bool lds = false;         // stage positions and directions of a scene in LDS
+  bool lds_ok = false;      // the largest scene fits in one workgroup's LDS
   // captured multi-step graph
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -50,6 +58,7 @@ struct pncg_batch {
   const void* g_v = nullptr;
   double g_h = 0.0;
   int g_steps = 0, g_block = 0;
+  bool g_lds = false;
 };
 
 namespace {
@@ -79,6 +88,7 @@ template <typename R>
 BatchArgs<R> batch_args(pncg_batch* b, double h) {
   BatchArgs<R> A{};
   A.nScenes = b->nScenes;
+  A.vcap = b->vcap;
   A.order = b->d_order;
   A.vert_off = b->d_vert_off;
   A.tet_off = b->d_tet_off;
@@ -111,14 +121,19 @@ BatchArgs<R> batch_args(pncg_batch* b, double h) {
   return A;
 }
 
-int block_index(int block) { return block == 256 ? 0 : block == 512 ? 1 : 2; }
+int block_index(int block) {
+  for (int i = 0; i < kNBlocks; ++i)
+    if (kBlocks[i] == block) return i;
+  return kNBlocks - 1;
+}
 
 void launch(pncg_batch* b, double h, const double* x, const double* v, double* xo, double* vo) {
-  const int grid = std::min(b->nScenes, b->max_grid[block_index(b->block)]);
+  const int bi = block_index(b->block);
+  const int grid = std::min(b->nScenes, b->lds ? b->max_grid_lds[bi] : b->max_grid[bi]);
   if (b->precision == PNCG_MIXED)
-    launch_batch_step<float>(batch_args<float>(b, h), b->block, grid, x, v, xo, vo, b->stream);
+    launch_batch_step<float>(batch_args<float>(b, h), b->block, grid, b->lds, x, v, xo, vo, b->stream);
   else
-    launch_batch_step<double>(batch_args<double>(b, h), b->block, grid, x, v, xo, vo, b->stream);
+    launch_batch_step<double>(batch_args<double>(b, h), b->block, grid, b->lds, x, v, xo, vo, b->stream);
 }
 
 int check_err(pncg_batch* b) {
@@ -147,15 +162,17 @@ int upload_elems(pncg_batch* b, const std::vector<int>& tets_g, const std::vecto
   return PNCG_OK;
 }
 
-int max_active(pncg_batch* b, int block, int* out) {
+// Persistent grid size: resident workgroups per CU times the CU count (0 when
+// the LDS-staged kernel cannot be resident at all).
+int max_active(pncg_batch* b, int block, bool lds, int* out) {
   int n = 0;
   hipDeviceProp_t prop;
   BCHK(b, hipGetDeviceProperties(&prop, b->device));
   if (b->precision == PNCG_MIXED)
-    BCHK(b, batch_occupancy<float>(block, &n));
+    BCHK(b, batch_occupancy<float>(block, lds, b->vcap, &n));
   else
-    BCHK(b, batch_occupancy<double>(block, &n));
-  *out = std::max(1, n) * prop.multiProcessorCount;
+    BCHK(b, batch_occupancy<double>(block, lds, b->vcap, &n));
+  *out = lds ? n * prop.multiProcessorCount : std::max(1, n) * prop.multiProcessorCount;
   return PNCG_OK;
 }
 
@@ -253,6 +270,7 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
   b->nT = nT;
   b->nWaves = (int)(inc.size() / kWave);
   b->vert_off.assign(vert_off, vert_off + nScenes + 1);
+  for (int s = 0; s < nScenes; ++s) b->vcap = std::max(b->vcap, vert_off[s + 1] - vert_off[s]);
   b->tet_off.assign(tet_off, tet_off + nScenes + 1);
   int rc = PNCG_OK;
   auto fin = [&](int code) {
@@ -303,9 +321,22 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
   if (hipMemset(b->d_iters_total, 0, sizeof(long long) * nScenes) != hipSuccess ||
       hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess)
     return fin(bfail(b, PNCG_E_HIP, "memset failed"));
-  const int blocks[3] = {256, 512, 1024};
-  for (int i = 0; i < 3; ++i)
-    if ((rc = max_active(b, blocks[i], &b->max_grid[i]))) return fin(rc);
+  for (int i = 0; i < kNBlocks; ++i)
+    if ((rc = max_active(b, kBlocks[i], false, &b->max_grid[i]))) return fin(rc);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return fin(bfail(b, PNCG_E_HIP, "device query failed"));
+    const size_t need = precision == PNCG_MIXED ? batch_lds_bytes<float>(b->vcap) : batch_lds_bytes<double>(b->vcap);
+    // static LDS of the kernel is 8 doubles per wave: at most 1 KiB
+    if (need + 1024 <= prop.sharedMemPerBlock) {
+      b->lds_ok = true;
+      for (int i = 0; i < kNBlocks; ++i) {
+        if ((rc = max_active(b, kBlocks[i], true, &b->max_grid_lds[i]))) return fin(rc);
+        if (b->max_grid_lds[i] < 1) b->lds_ok = false;
+      }
+      b->lds = b->lds_ok;
+    }
+  }
   return fin(PNCG_OK);
 }
 
@@ -346,6 +377,22 @@ int pncg_batch_set_block(pncg_batch* b, int32_t block) {
   return PNCG_OK;
 }
 
+int pncg_batch_set_staging(pncg_batch* b, int32_t lds) {
+  if (!b) return PNCG_E_INVAL;
+  if (lds != 0 && lds != 1) return bfail(b, PNCG_E_INVAL, "staging must be 0 or 1");
+  if (lds && !b->lds_ok) return bfail(b, PNCG_E_INVAL, "the largest scene does not fit in one workgroup's LDS");
+  b->lds = lds != 0;
+  drop_graph(b);
+  return PNCG_OK;
+}
+
+int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds) {
+  if (!b) return PNCG_E_INVAL;
+  if (block) *block = b->block;
+  if (lds) *lds = b->lds ? 1 : 0;
+  return PNCG_OK;
+}
+
 int pncg_batch_step(pncg_batch* b, const double* x, const double* v, double h, double* x_out, double* v_out) {
   if (!b || !x || !v || !x_out || !v_out) return bfail(b, PNCG_E_INVAL, "NULL argument");
   if (!(h > 0.0) || !std::isfinite(h)) return bfail(b, PNCG_E_INVAL, "need a finite h > 0");
@@ -360,7 +407,8 @@ int pncg_batch_run(pncg_batch* b, double* x, double* v, double h, int32_t nsteps
   if (!b || !x || !v || nsteps < 1) return bfail(b, PNCG_E_INVAL, "bad arguments");
   if (!(h > 0.0) || !std::isfinite(h)) return bfail(b, PNCG_E_INVAL, "need a finite h > 0");
   BCHK(b, hipSetDevice(b->device));
-  if (!b->gexec || b->g_x != x || b->g_v != v || b->g_h != h || b->g_steps != nsteps || b->g_block != b->block) {
+  if (!b->gexec || b->g_x != x || b->g_v != v || b->g_h != h || b->g_steps != nsteps || b->g_block != b->block ||
+      b->g_lds != b->lds) {
     drop_graph(b);
     BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const size_t n3 = 3 * (size_t)b->nV;
@@ -382,6 +430,7 @@ int pncg_batch_run(pncg_batch* b, double* x, double* v, double h, int32_t nsteps
     b->g_h = h;
     b->g_steps = nsteps;
     b->g_block = b->block;
+    b->g_lds = b->lds;
   }
   BCHK(b, hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));  // outside the graph
   BCHK(b, hipGraphLaunch(b->gexec, b->stream));
@@ -402,31 +451,36 @@ int pncg_batch_stats(pncg_batch* b, int32_t* iters, int32_t* reason, int64_t* it
 int pncg_batch_autotune(pncg_batch* b, const double* x, const double* v, double h, int32_t reps, int32_t* block_out) {
   if (!b || !x || !v || reps < 1) return bfail(b, PNCG_E_INVAL, "bad arguments");
   BCHK(b, hipSetDevice(b->device));
-  const int blocks[3] = {256, 512, 1024};
   hipEvent_t e0, e1;
   BCHK(b, hipEventCreate(&e0));
   BCHK(b, hipEventCreate(&e1));
   float best = 1e30f;
   int best_b = b->block;
+  bool best_l = b->lds;
   const int saved = b->block;
-  for (int i = 0; i < 3; ++i) {
-    b->block = blocks[i];
-    launch(b, h, x, v, b->d_xa, b->d_va);  // warm-up
-    BCHK(b, hipEventRecord(e0, b->stream));
-    for (int r = 0; r < reps; ++r) launch(b, h, x, v, b->d_xa, b->d_va);
-    BCHK(b, hipEventRecord(e1, b->stream));
-    BCHK(b, hipEventSynchronize(e1));
-    float ms = 0.0f;
-    BCHK(b, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_b = blocks[i];
+  const bool saved_l = b->lds;
+  for (int l = 0; l < (b->lds_ok ? 2 : 1); ++l)
+    for (int i = 0; i < kNBlocks; ++i) {
+      b->block = kBlocks[i];
+      b->lds = l == 1;
+      launch(b, h, x, v, b->d_xa, b->d_va);  // warm-up
+      BCHK(b, hipEventRecord(e0, b->stream));
+      for (int r = 0; r < reps; ++r) launch(b, h, x, v, b->d_xa, b->d_va);
+      BCHK(b, hipEventRecord(e1, b->stream));
+      BCHK(b, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BCHK(b, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_b = kBlocks[i];
+        best_l = b->lds;
+      }
     }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->block = best_b;
-  if (best_b != saved) drop_graph(b);
+  b->lds = best_l;
+  if (best_b != saved || best_l != saved_l) drop_graph(b);
   if (block_out) *block_out = best_b;
   return check_err(b);
 }

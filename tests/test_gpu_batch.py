@@ -169,6 +169,37 @@ def test_batch_graph_replays_equal_eager_steps():
         assert bool(torch.isfinite(x).all())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_lds_staging_same_bits(precision):
+    """Positions and directions staged in LDS or read from device memory:
+    the same arithmetic in the same order, so the same bits, at every
+    workgroup size."""
+    import torch
+    scs = _small_batch()
+    xs, vs = _states(scs, 7)
+    bt, b = _make_batch(scs, precision, 100, 1e-3, "delta_e")
+    blk, lds = bt.pncg_batch_get_config()
+    _say(f"staging precision={precision}: default block {blk} lds {lds}")
+    assert lds == 1                          # these scenes fit in LDS
+    h = scs[0].h
+    dev = torch.device("cuda:0")
+    x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
+    outs = {}
+    for block in (256, 512, 1024):
+        bt.pncg_batch_set_block(block)
+        for l in (0, 1):
+            bt.pncg_batch_set_staging(l)
+            xo, vo = torch.empty_like(x), torch.empty_like(v)
+            bt.pncg_batch_step(x, v, h, xo, vo)
+            outs[(block, l)] = (xo, vo, bt.pncg_batch_stats()[0].copy())
+        same = bool(torch.equal(outs[(block, 0)][0], outs[(block, 1)][0]) and
+                    torch.equal(outs[(block, 0)][1], outs[(block, 1)][1]))
+        _say(f"  block {block}: identical={same}")
+        assert same
+        assert np.array_equal(outs[(block, 0)][2], outs[(block, 1)][2])
+
+
 def test_batch_autotune_keeps_state_and_result():
     import torch
     import paper_2405_08001_amd as P
