@@ -223,6 +223,7 @@ def run_batched(steps, warmup):
     v = torch.tensor(b["v"], dtype=torch.float64, device=dev)
     bt.pncg_batch_run(x, v, s0.h, warmup)
     block = bt.pncg_batch_autotune(x, v, s0.h, 2)     # on the state the timed steps start from
+    cfg = bt.pncg_batch_get_config()
     _, _, tot0 = bt.pncg_batch_stats()
     bt.pncg_batch_run(x, v, s0.h, steps)      # captures the graph
     _, _, tot1 = bt.pncg_batch_stats()
@@ -240,7 +241,8 @@ def run_batched(steps, warmup):
     xz = x[:, 2].min().item()
     bt.close()
     return {"scenes": len(scs), "tets": int(T.sum()), "steps_timed": steps, "steps_warmup": warmup,
-            "block": block, "scene_steps_per_s": round(len(scs) * steps / dt, 1),
+            "block": block, "lds_staging": cfg["lds"], "max_team": cfg["max_team"], "teams": cfg["teams"],
+            "scene_steps_per_s": round(len(scs) * steps / dt, 1),
             "ms_per_batch_step": round(1e3 * dt / steps, 4),
             "mean_iters_per_scene_step": round(float(it.sum()) / (len(scs) * steps), 2),
             "iters_per_s": round(float(it.sum()) / dt, 1),

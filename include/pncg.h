@@ -338,8 +338,23 @@ int pncg_batch_set_block(pncg_batch* b, int32_t block);
  * E_INVAL for 1 when it does not.  Results are the same either way. */
 int pncg_batch_set_staging(pncg_batch* b, int32_t lds);
 
-/* Current workgroup size and staging mode (each pointer nullable). */
-int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds);
+/* Largest number of workgroups that one scene may use, in [1, 8]; > 1
+ * needs LDS staging (ignored without it).  A scene with more tets than the
+ * batch's mean per workgroup is stepped by a team of about (its tets / that
+ * mean) workgroups, which split its tet and incidence loops and meet at
+ * two barriers per iteration; the other scenes go to single workgroups,
+ * longest first to the least loaded.  A team's workgroups must all be
+ * resident at once: the step kernel's grid never exceeds the device's
+ * resident capacity, and a barrier that still waits after about 2^21 polls
+ * ends the launch with E_HIP (results invalid) instead of hanging.  Results
+ * depend on the schedule only through the order of the partial sums.
+ * Default 8 when LDS staging is on, else 1. */
+int pncg_batch_set_split(pncg_batch* b, int32_t max_team);
+
+/* Current workgroup size, staging mode, largest team and number of teams
+ * of the schedule (each pointer nullable). */
+int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds,
+                          int32_t* max_team, int32_t* teams);
 
 /* One time step of every scene with step size h > 0.  Device pointers on the
  * batch's device: x_dev, v_dev [nV][3] the state, x_out_dev, v_out_dev
@@ -362,8 +377,10 @@ int pncg_batch_run(pncg_batch* b, double* x_dev, double* v_dev, double h,
 int pncg_batch_stats(pncg_batch* b, int32_t* iters, int32_t* reason,
                      int64_t* iters_total);
 
-/* Time reps steps from (x_dev, v_dev) at each workgroup size and staging
- * mode and keep the fastest (its size written to *block_out if non-NULL).  The state is not modified;
+/* Time reps steps from (x_dev, v_dev) at each workgroup size in four
+ * modes (device memory; LDS staging; LDS staging with large scenes split
+ * over up to 2, or up to 8, workgroups) and keep the fastest (its workgroup size written
+ * to *block_out if non-NULL; the rest by pncg_batch_get_config).  The state is not modified;
  * iters_total advances by the timed steps. */
 int pncg_batch_autotune(pncg_batch* b, const double* x_dev,
                         const double* v_dev, double h, int32_t reps,

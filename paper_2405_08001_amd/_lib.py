@@ -33,7 +33,8 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_set_tuning",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
-           "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config")
+           "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
+           "pncg_batch_set_split")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -100,7 +101,8 @@ def _load():
         "pncg_batch_stats": (I32, [P, P, P, P]),
         "pncg_batch_autotune": (I32, [P, P, P, D, I32, P]),
         "pncg_batch_set_staging": (I32, [P, I32]),
-        "pncg_batch_get_config": (I32, [P, P, P]),
+        "pncg_batch_get_config": (I32, [P, P, P, P, P]),
+        "pncg_batch_set_split": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -356,11 +358,14 @@ class Batch:
     def pncg_batch_set_staging(self, lds):
         self._check(_L.pncg_batch_set_staging(self._h, int(lds)))
 
+    def pncg_batch_set_split(self, max_team):
+        self._check(_L.pncg_batch_set_split(self._h, int(max_team)))
+
     def pncg_batch_get_config(self):
-        """(block, lds) of the step kernel."""
-        blk, lds = C.c_int32(), C.c_int32()
-        self._check(_L.pncg_batch_get_config(self._h, C.byref(blk), C.byref(lds)))
-        return blk.value, lds.value
+        """dict(block, lds, max_team, teams) of the step kernel's schedule."""
+        v = [C.c_int32() for _ in range(4)]
+        self._check(_L.pncg_batch_get_config(self._h, *[C.byref(q) for q in v]))
+        return dict(zip(("block", "lds", "max_team", "teams"), [q.value for q in v]))
 
     def pncg_batch_step(self, x, v, h, x_out, v_out):
         """float64 CUDA tensors (nV, 3); x_out/v_out must not alias x/v."""

@@ -5,10 +5,22 @@
 
 namespace pncg {
 
+constexpr int kMaxTeam = 8;   // workgroups one scene may use
+
 template <typename R>
 struct BatchArgs {
   int nScenes;
-  const int* order;        // [nScenes] processing order (largest scene first)
+  // Schedule: workgroup b belongs to team blk_team[b] as rank blk_rank[b];
+  // team t has team_size[t] workgroups and steps the scenes
+  // team_scene[team_off[t] .. team_off[t+1]) in that order.
+  const int* blk_team;
+  const int* blk_rank;
+  const int* team_size;
+  const int* team_off;
+  const int* team_scene;
+  int* bar;                // [teams] barrier arrivals (zeroed before each launch)
+  double* tpart;           // [teams][2][kMaxTeam][8] reduction partials
+  int spin_limit;          // polls before a team barrier gives up
   const int* vert_off;     // [nScenes + 1] vertex offsets in the concatenation
   const int* tet_off;      // [nScenes + 1]
   const int* wave_off;     // [nScenes + 1] incidence waves of each scene
@@ -44,6 +56,9 @@ size_t batch_lds_bytes(int vcap);
 // (lds: with the positions and directions of a scene in LDS).
 template <typename R>
 hipError_t batch_occupancy(int block, bool lds, int vcap, int* per_cu);
+
+// Zero the team barrier counters (a kernel, so that it can sit in a graph).
+void launch_team_reset(int* bar, int n, hipStream_t s);
 
 template <typename R>
 void launch_batch_step(const BatchArgs<R>& A, int block, int grid, bool lds, const double* x, const double* v,

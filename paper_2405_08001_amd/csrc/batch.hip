@@ -11,10 +11,68 @@
 
 namespace pncg {
 
+// Barrier among the workgroups of one team, waited on by one thread with a
+// bounded number of polls.  The agent-scope fences publish this workgroup's
+// stores before it arrives and make the others' visible after.  A wait that
+// runs out of polls raises kErrTeam, and once that bit is set every later
+// team barrier of the launch passes at once, so the launch always ends.
+__device__ __forceinline__ void team_sync(int* bar, int target, int* err, int limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1);
+    int polls = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++polls > limit || (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTeam)) {
+        atomicOr(err, kErrTeam);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Position of a workgroup in its team and the team's barrier state.
+struct Team {
+  int G, r;          // team size, rank of this workgroup
+  int nb;            // team barriers passed so far in this launch
+  int* bar;
+  double* part;      // [2][kMaxTeam][8]
+  int* err;
+  int limit;
+  __device__ void sync() {
+    if (G > 1) team_sync(bar, G * ++nb, err, limit);
+  }
+  // Block reduction, then (G > 1) the members' results combined in rank
+  // order, so every member holds the same bits.
+  template <int N, int BS>
+  __device__ void reduce(double (&v)[N], const int (&kind)[N], double* sh) {
+    block_reduce<N, BS>(v, kind, sh);
+    if (G == 1) return;
+    double* slot = part + ((nb + 1) & 1) * (kMaxTeam * 8);
+    if (threadIdx.x == 0)
+      for (int i = 0; i < N; ++i) slot[r * 8 + i] = v[i];
+    sync();
+    for (int i = 0; i < N; ++i) {
+      double acc = slot[i];
+      for (int j = 1; j < G; ++j) acc = kind[i] ? fmax(acc, slot[j * 8 + i]) : acc + slot[j * 8 + i];
+      v[i] = acc;
+    }
+  }
+};
+
 // LDSX: the positions and directions of the scene being stepped live in
 // LDS (A.vcap vertices at most; dynamic shared memory of vcap * (3 doubles +
 // 3 R)), so the gathers of the element loops read LDS instead of memory;
-// otherwise they live in the per-vertex arrays x and p.
+// otherwise they live in the per-vertex arrays x and p.  A scene stepped by
+// a team of G > 1 workgroups (LDSX only) is split as follows: the incidence
+// waves and the tets are dealt out over the members, each member keeps a
+// full copy of the scene's x and p in its own LDS and forms the direction
+// and the update for every vertex, and the members meet twice per iteration
+// to combine their partial sums (after the gradient sweep, which also
+// publishes P g, and after the p^T H p pass).
 template <typename R, int BS, bool LDSX>
 __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double* x_in, const double* v_in,
                                                    double* x_out, double* v_out) {
@@ -25,8 +83,12 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
   R* sp = reinterpret_cast<R*>(dyn + 3 * A.vcap);    // [3][vcap]
   const int vc = A.vcap;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-  for (int si = blockIdx.x; si < A.nScenes; si += gridDim.x) {
-    const int s = A.order[si];
+  const int tm = A.blk_team[blockIdx.x];
+  Team T{A.team_size[tm], A.blk_rank[blockIdx.x], 0, A.bar + tm, A.tpart + (size_t)tm * 2 * kMaxTeam * 8, A.err,
+         A.spin_limit};
+  const int G = T.G, r = T.r;
+  for (int j = A.team_off[tm]; j < A.team_off[tm + 1]; ++j) {
+    const int s = A.team_scene[j];
     const int v0 = A.vert_off[s], v1 = A.vert_off[s + 1];
     const int t0 = A.tet_off[s], t1 = A.tet_off[s + 1];
     const int w0 = A.wave_off[s], w1 = A.wave_off[s + 1];
@@ -52,25 +114,28 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       const int l = v - v0;
       sp[l] = p.x; sp[vc + l] = p.y; sp[2 * vc + l] = p.z;
     };
-    // predictor: xt = x + h v + h^2 g; x_0 = x^t
+    // predictor: xt = x + h v + h^2 g; x_0 = x^t (the team's members share
+    // the writes of xt and g, then meet)
     for (int v = v0 + tid; v < v1; v += BS) {
       const V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
-      const V3<double> u = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
       if (!LDSX) st3(A.xstart, v, x);
       setX(v, x);
+      setP(v, mk3(R(0), R(0), R(0)));
+      if ((v - v0) / BS % G != r) continue;
+      const V3<double> u = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
       V3<double> xt = x + A.h * u;
       xt = xt + A.h2 * A.grav;
       st3(A.xt, v, xt);
       str<R>(A.g, v, mk3(R(0), R(0), R(0)));
-      setP(v, mk3(R(0), R(0), R(0)));
     }
+    T.sync();
     __syncthreads();
     int k = 0, reason = 2;
     double g0 = 0.0, dE0 = 0.0;
     for (;;) {
       // ---- gradient, diag(H), dot products (vertex-centric sweep)
       double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int w = w0 + wave; w < w1; w += NW) {
+      for (int w = w0 + r * NW + wave; w < w1; w += G * NW) {
         const int idx = w * kWave + lane;
         const int code = A.inc[idx];
         const int myv = A.inc_vert[idx];
@@ -130,7 +195,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       }
       {
         const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        block_reduce<8, BS>(dots, kind, sh);
+        T.reduce<8, BS>(dots, kind, sh);
       }
       const double gnorm = sqrt(dots[0]);
       if (k == 0) g0 = gnorm;
@@ -146,7 +211,8 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         gTp = -dots[1];
       }
       if (gTp == 0.0) { reason = 3; break; }
-      // ---- direction p = -P g + beta p (in place), inertia and plane parts of p^T H p
+      // ---- direction p = -P g + beta p (in place; every member forms all of
+      // it), inertia and plane parts of p^T H p (counted by rank 0)
       const R rb = R(beta);
       double php = 0.0, pmv = 0.0, pmc = 0.0;
       for (int v = v0 + tid; v < v1; v += BS) {
@@ -164,10 +230,11 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
           }
         }
       }
+      if (r != 0) php = 0.0;
       __syncthreads();
       // ---- element p^T H p
       double el = 0.0;
-      for (int e = t0 + tid; e < t1; e += BS) {
+      for (int e = t0 + r * BS + tid; e < t1; e += G * BS) {
         const ElemRec<R> rec = A.elem[e];
         Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
         V3<R> d[3];
@@ -177,7 +244,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       double red[3] = {php + A.h2 * el, pmv, pmc};
       {
         const int kind[3] = {0, 1, 1};
-        block_reduce<3, BS>(red, kind, sh);
+        T.reduce<3, BS>(red, kind, sh);
       }
       const double pHp = red[0];
       const double pm = (A.flags & 2u) ? red[2] : red[1];
@@ -198,21 +265,30 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       if (A.term == 0 && dE < A.eps * dE0) { reason = 0; break; }
       if (k >= A.iter_max) { reason = 2; break; }
     }
-    // end of step: v = (x - x^t) / h
+    // end of step: v = (x - x^t) / h (the members share the writes)
     const double ih = 1.0 / A.h;
-    for (int v = v0 + tid; v < v1; v += BS) {
+    for (int v = v0 + r * BS + tid; v < v1; v += G * BS) {
       const V3<double> x = X(v);
       const V3<double> xs = LDSX ? mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]) : ld3(A.xstart, v);
       x_out[3 * v] = x.x; x_out[3 * v + 1] = x.y; x_out[3 * v + 2] = x.z;
       v_out[3 * v] = (x.x - xs.x) * ih; v_out[3 * v + 1] = (x.y - xs.y) * ih; v_out[3 * v + 2] = (x.z - xs.z) * ih;
     }
-    if (tid == 0) {
+    if (tid == 0 && r == 0) {
       A.iters[s] = k;
       A.reason[s] = reason;
       A.iters_total[s] += k;
     }
     __syncthreads();
   }
+}
+
+__global__ void k_team_reset(int* bar, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) bar[i] = 0;
+}
+
+void launch_team_reset(int* bar, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_team_reset, dim3((n + 255) / 256), dim3(256), 0, s, bar, n);
 }
 
 template <typename R, bool LDSX>

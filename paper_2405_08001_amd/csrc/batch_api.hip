@@ -32,7 +32,18 @@ struct pncg_batch {
   int nScenes = 0, nV = 0, nT = 0, nWaves = 0;
   std::vector<int> vert_off, tet_off;
   std::vector<void*> allocs;
-  int *d_order = nullptr, *d_vert_off = nullptr, *d_tet_off = nullptr, *d_wave_off = nullptr;
+  int *d_vert_off = nullptr, *d_tet_off = nullptr, *d_wave_off = nullptr;
+  std::vector<int> order;   // scenes by decreasing cost
+  std::vector<double> cost; // scheduling cost of each scene: its tet count
+  // schedule (teams of workgroups, see BatchArgs)
+  int nb_cap = 0;           // largest persistent grid over the configurations
+  int *d_blk_team = nullptr, *d_blk_rank = nullptr, *d_team_size = nullptr, *d_team_off = nullptr,
+      *d_team_scene = nullptr, *d_bar = nullptr;
+  double* d_tpart = nullptr;
+  int max_team = 1;         // workgroups one scene may use (needs LDS staging when > 1)
+  int sched_grid = 0, sched_team = 0, n_teams = 0;
+  bool split = false;       // the current schedule has a team of more than one workgroup
+  int spin_limit = 1 << 21;
   void* d_elem = nullptr;
   int *d_inc = nullptr, *d_inc_vert = nullptr;
   double* d_mass = nullptr;
@@ -59,6 +70,7 @@ struct pncg_batch {
   double g_h = 0.0;
   int g_steps = 0, g_block = 0;
   bool g_lds = false;
+  int g_team = 0;
 };
 
 namespace {
@@ -89,7 +101,14 @@ BatchArgs<R> batch_args(pncg_batch* b, double h) {
   BatchArgs<R> A{};
   A.nScenes = b->nScenes;
   A.vcap = b->vcap;
-  A.order = b->d_order;
+  A.blk_team = b->d_blk_team;
+  A.blk_rank = b->d_blk_rank;
+  A.team_size = b->d_team_size;
+  A.team_off = b->d_team_off;
+  A.team_scene = b->d_team_scene;
+  A.bar = b->d_bar;
+  A.tpart = b->d_tpart;
+  A.spin_limit = b->spin_limit;
   A.vert_off = b->d_vert_off;
   A.tet_off = b->d_tet_off;
   A.wave_off = b->d_wave_off;
@@ -127,9 +146,82 @@ int block_index(int block) {
   return kNBlocks - 1;
 }
 
-void launch(pncg_batch* b, double h, const double* x, const double* v, double* xo, double* vo) {
+int grid_for(const pncg_batch* b) {
   const int bi = block_index(b->block);
-  const int grid = std::min(b->nScenes, b->lds ? b->max_grid_lds[bi] : b->max_grid[bi]);
+  return std::max(1, b->lds ? b->max_grid_lds[bi] : b->max_grid[bi]);
+}
+
+// Deal the scenes out over teams of workgroups for the current block size
+// and staging mode.  Scenes larger than the mean load per workgroup get a
+// team of about (tets / mean) workgroups (at most max_team, all with the same
+// blockIdx % 8, which the dispatcher places on one XCD); the rest go to
+// single workgroups, and every remaining scene joins the least loaded team
+// (longest first).  Uploaded on the stream, which is then synchronised; not
+// called while a graph is being captured.
+int ensure_schedule(pncg_batch* b) {
+  const int NB = grid_for(b);
+  const int maxG = b->lds ? std::min(b->max_team, kMaxTeam) : 1;
+  if (NB == b->sched_grid && maxG == b->sched_team) return PNCG_OK;
+  const std::vector<double>& cost = b->cost;
+  double total = 0.0;
+  for (double c : cost) total += c;
+  const double avg = total / NB;
+  std::vector<std::vector<int>> pool(kXcds);
+  for (int q = NB - 1; q >= 0; --q) pool[q % kXcds].push_back(q);   // back() = lowest free index
+  struct TeamB { std::vector<int> blocks, scenes; double load; };
+  std::vector<TeamB> teams;
+  size_t i = 0;
+  for (; i < b->order.size() && maxG > 1; ++i) {
+    const int s = b->order[i];
+    int G = std::min(maxG, (int)(cost[s] / avg + 0.5));
+    if (G < 2) break;
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (pool[y].size() > pool[x].size()) x = y;
+    G = std::min<int>(G, (int)pool[x].size());
+    if (G < 2) break;
+    TeamB t{{}, {s}, cost[s] / G};
+    for (int k = 0; k < G; ++k) { t.blocks.push_back(pool[x].back()); pool[x].pop_back(); }
+    teams.push_back(t);
+  }
+  for (int x = 0; x < kXcds; ++x)
+    for (int q : pool[x]) teams.push_back(TeamB{{q}, {}, 0.0});
+  for (; i < b->order.size(); ++i) {
+    const int s = b->order[i];
+    size_t best = 0;
+    for (size_t t = 1; t < teams.size(); ++t)
+      if (teams[t].load < teams[best].load) best = t;
+    teams[best].scenes.push_back(s);
+    teams[best].load += cost[s] / teams[best].blocks.size();
+  }
+  std::vector<int> blk_team(NB, 0), blk_rank(NB, 0), tsize, toff(1, 0), tscene;
+  bool split = false;
+  for (size_t t = 0; t < teams.size(); ++t) {
+    for (size_t k = 0; k < teams[t].blocks.size(); ++k) {
+      blk_team[teams[t].blocks[k]] = (int)t;
+      blk_rank[teams[t].blocks[k]] = (int)k;
+    }
+    tsize.push_back((int)teams[t].blocks.size());
+    split |= teams[t].blocks.size() > 1;
+    tscene.insert(tscene.end(), teams[t].scenes.begin(), teams[t].scenes.end());
+    toff.push_back((int)tscene.size());
+  }
+  BCHK(b, hipMemcpyAsync(b->d_blk_team, blk_team.data(), sizeof(int) * NB, hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->d_blk_rank, blk_rank.data(), sizeof(int) * NB, hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->d_team_size, tsize.data(), sizeof(int) * tsize.size(), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->d_team_off, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->d_team_scene, tscene.data(), sizeof(int) * tscene.size(), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipStreamSynchronize(b->stream));
+  b->sched_grid = NB;
+  b->sched_team = maxG;
+  b->n_teams = (int)teams.size();
+  b->split = split;
+  return PNCG_OK;
+}
+
+void launch(pncg_batch* b, double h, const double* x, const double* v, double* xo, double* vo) {
+  const int grid = b->sched_grid;
+  if (b->split) launch_team_reset(b->d_bar, b->n_teams, b->stream);
   if (b->precision == PNCG_MIXED)
     launch_batch_step<float>(batch_args<float>(b, h), b->block, grid, b->lds, x, v, xo, vo, b->stream);
   else
@@ -142,6 +234,9 @@ int check_err(pncg_batch* b) {
   BCHK(b, hipStreamSynchronize(b->stream));
   if (e & kErrInverted) return bfail(b, PNCG_E_INVERTED, "a tet has det F <= 0");
   if (e & kErrPenetration) return bfail(b, PNCG_E_PENETRATION, "a vertex is on or behind its plane");
+  if (e & kErrTeam)
+    return bfail(b, PNCG_E_HIP, "a team barrier timed out (the workgroups of a team were not all resident); "
+                                "results are invalid: call pncg_batch_set_split(b, 1)");
   return PNCG_OK;
 }
 
@@ -254,7 +349,7 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
       for (int j = 0; j < 4; ++j) pl[4 * s + j] = q[j];
     }
   }
-  // processing order: largest scene first
+  // scenes by decreasing size (scheduling order)
   std::vector<int> order(nScenes);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -270,6 +365,8 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
   b->nT = nT;
   b->nWaves = (int)(inc.size() / kWave);
   b->vert_off.assign(vert_off, vert_off + nScenes + 1);
+  b->order = order;
+  for (int s = 0; s < nScenes; ++s) b->cost.push_back(double(tet_off[s + 1] - tet_off[s]));
   for (int s = 0; s < nScenes; ++s) b->vcap = std::max(b->vcap, vert_off[s + 1] - vert_off[s]);
   b->tet_off.assign(tet_off, tet_off + nScenes + 1);
   int rc = PNCG_OK;
@@ -291,7 +388,7 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
     b->own_stream = true;
   }
   const size_t r4 = precision == PNCG_MIXED ? sizeof(float4) : sizeof(double4);
-  if ((rc = balloc(b, &b->d_order, nScenes)) || (rc = balloc(b, &b->d_vert_off, nScenes + 1)) ||
+  if ((rc = balloc(b, &b->d_vert_off, nScenes + 1)) ||
       (rc = balloc(b, &b->d_tet_off, nScenes + 1)) || (rc = balloc(b, &b->d_wave_off, nScenes + 1)) ||
       (rc = balloc(b, &b->d_inc, inc.size())) || (rc = balloc(b, &b->d_inc_vert, incv.size())) ||
       (rc = balloc(b, &b->d_mass, nV)) || (rc = balloc(b, &b->d_vflag, nV)) ||
@@ -308,7 +405,6 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
   if (rc) return fin(rc);
 #define UP(dst, src, n)                                                                          \
   if (hipMemcpy(dst, src, n, hipMemcpyHostToDevice) != hipSuccess) return fin(bfail(b, PNCG_E_HIP, "upload failed"));
-  UP(b->d_order, order.data(), sizeof(int) * nScenes);
   UP(b->d_vert_off, vert_off, sizeof(int) * (nScenes + 1));
   UP(b->d_tet_off, tet_off, sizeof(int) * (nScenes + 1));
   UP(b->d_wave_off, wave_off.data(), sizeof(int) * (nScenes + 1));
@@ -337,7 +433,14 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
       b->lds = b->lds_ok;
     }
   }
-  return fin(PNCG_OK);
+  b->max_team = b->lds ? kMaxTeam : 1;
+  for (int i = 0; i < kNBlocks; ++i) b->nb_cap = std::max({b->nb_cap, b->max_grid[i], b->max_grid_lds[i]});
+  if ((rc = balloc(b, &b->d_blk_team, b->nb_cap)) || (rc = balloc(b, &b->d_blk_rank, b->nb_cap)) ||
+      (rc = balloc(b, &b->d_team_size, b->nb_cap)) || (rc = balloc(b, &b->d_team_off, b->nb_cap + 1)) ||
+      (rc = balloc(b, &b->d_team_scene, nScenes)) || (rc = balloc(b, &b->d_bar, b->nb_cap)) ||
+      (rc = balloc(b, &b->d_tpart, (size_t)b->nb_cap * 2 * kMaxTeam * 8)))
+    return fin(rc);
+  return fin(ensure_schedule(b));
 }
 
 void pncg_batch_destroy(pncg_batch* b) {
@@ -374,7 +477,7 @@ int pncg_batch_set_block(pncg_batch* b, int32_t block) {
   if (block != 256 && block != 512 && block != 1024) return bfail(b, PNCG_E_INVAL, "block must be 256, 512 or 1024");
   b->block = block;
   drop_graph(b);
-  return PNCG_OK;
+  return ensure_schedule(b);
 }
 
 int pncg_batch_set_staging(pncg_batch* b, int32_t lds) {
@@ -383,13 +486,23 @@ int pncg_batch_set_staging(pncg_batch* b, int32_t lds) {
   if (lds && !b->lds_ok) return bfail(b, PNCG_E_INVAL, "the largest scene does not fit in one workgroup's LDS");
   b->lds = lds != 0;
   drop_graph(b);
-  return PNCG_OK;
+  return ensure_schedule(b);
 }
 
-int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds) {
+int pncg_batch_set_split(pncg_batch* b, int32_t max_team) {
+  if (!b) return PNCG_E_INVAL;
+  if (max_team < 1 || max_team > kMaxTeam) return bfail(b, PNCG_E_INVAL, "max_team must be in [1, 8]");
+  b->max_team = max_team;
+  drop_graph(b);
+  return ensure_schedule(b);
+}
+
+int pncg_batch_get_config(pncg_batch* b, int32_t* block, int32_t* lds, int32_t* max_team, int32_t* teams) {
   if (!b) return PNCG_E_INVAL;
   if (block) *block = b->block;
   if (lds) *lds = b->lds ? 1 : 0;
+  if (max_team) *max_team = b->max_team;
+  if (teams) *teams = b->n_teams;
   return PNCG_OK;
 }
 
@@ -397,6 +510,8 @@ int pncg_batch_step(pncg_batch* b, const double* x, const double* v, double h, d
   if (!b || !x || !v || !x_out || !v_out) return bfail(b, PNCG_E_INVAL, "NULL argument");
   if (!(h > 0.0) || !std::isfinite(h)) return bfail(b, PNCG_E_INVAL, "need a finite h > 0");
   BCHK(b, hipSetDevice(b->device));
+  int rc = ensure_schedule(b);
+  if (rc) return rc;
   BCHK(b, hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
   launch(b, h, x, v, x_out, v_out);
   BCHK(b, hipGetLastError());
@@ -407,8 +522,10 @@ int pncg_batch_run(pncg_batch* b, double* x, double* v, double h, int32_t nsteps
   if (!b || !x || !v || nsteps < 1) return bfail(b, PNCG_E_INVAL, "bad arguments");
   if (!(h > 0.0) || !std::isfinite(h)) return bfail(b, PNCG_E_INVAL, "need a finite h > 0");
   BCHK(b, hipSetDevice(b->device));
+  int rc = ensure_schedule(b);
+  if (rc) return rc;
   if (!b->gexec || b->g_x != x || b->g_v != v || b->g_h != h || b->g_steps != nsteps || b->g_block != b->block ||
-      b->g_lds != b->lds) {
+      b->g_lds != b->lds || b->g_team != b->max_team) {
     drop_graph(b);
     BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const size_t n3 = 3 * (size_t)b->nV;
@@ -431,6 +548,7 @@ int pncg_batch_run(pncg_batch* b, double* x, double* v, double h, int32_t nsteps
     b->g_steps = nsteps;
     b->g_block = b->block;
     b->g_lds = b->lds;
+    b->g_team = b->max_team;
   }
   BCHK(b, hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));  // outside the graph
   BCHK(b, hipGraphLaunch(b->gexec, b->stream));
@@ -455,14 +573,18 @@ int pncg_batch_autotune(pncg_batch* b, const double* x, const double* v, double 
   BCHK(b, hipEventCreate(&e0));
   BCHK(b, hipEventCreate(&e1));
   float best = 1e30f;
-  int best_b = b->block;
+  int best_b = b->block, best_t = b->max_team;
   bool best_l = b->lds;
-  const int saved = b->block;
-  const bool saved_l = b->lds;
-  for (int l = 0; l < (b->lds_ok ? 2 : 1); ++l)
+  // (staging, max team): device memory; LDS; LDS with large scenes split
+  // over up to 2 or up to 8 workgroups
+  const int modes[4][2] = {{0, 1}, {1, 1}, {1, 2}, {1, kMaxTeam}};
+  for (int m = 0; m < (b->lds_ok ? 4 : 1); ++m)
     for (int i = 0; i < kNBlocks; ++i) {
       b->block = kBlocks[i];
-      b->lds = l == 1;
+      b->lds = modes[m][0] == 1;
+      b->max_team = modes[m][1];
+      int rc = ensure_schedule(b);
+      if (rc) return rc;
       launch(b, h, x, v, b->d_xa, b->d_va);  // warm-up
       BCHK(b, hipEventRecord(e0, b->stream));
       for (int r = 0; r < reps; ++r) launch(b, h, x, v, b->d_xa, b->d_va);
@@ -474,13 +596,17 @@ int pncg_batch_autotune(pncg_batch* b, const double* x, const double* v, double 
         best = ms;
         best_b = kBlocks[i];
         best_l = b->lds;
+        best_t = b->max_team;
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->block = best_b;
   b->lds = best_l;
-  if (best_b != saved || best_l != saved_l) drop_graph(b);
+  b->max_team = best_t;
+  drop_graph(b);
+  int rc = ensure_schedule(b);
+  if (rc) return rc;
   if (block_out) *block_out = best_b;
   return check_err(b);
 }

@@ -24,6 +24,7 @@ constexpr int kErrInverted = 1;
 constexpr int kErrPenetration = 2;
 constexpr int kErrNonfinite = 4;
 constexpr int kErrCapacity = 8;
+constexpr int kErrTeam = 16;       // a team barrier of the batched kernel timed out
 
 template <typename R> struct R4T;
 template <> struct R4T<float> { using type = float4; };

@@ -171,16 +171,17 @@ def test_batch_graph_replays_equal_eager_steps():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_lds_staging_same_bits(precision):
-    """Positions and directions staged in LDS or read from device memory:
-    the same arithmetic in the same order, so the same bits, at every
-    workgroup size."""
+    """Positions and directions staged in LDS or read from device memory
+    (one workgroup per scene): the same arithmetic in the same order, so the
+    same bits, at every workgroup size."""
     import torch
     scs = _small_batch()
     xs, vs = _states(scs, 7)
     bt, b = _make_batch(scs, precision, 100, 1e-3, "delta_e")
-    blk, lds = bt.pncg_batch_get_config()
-    _say(f"staging precision={precision}: default block {blk} lds {lds}")
-    assert lds == 1                          # these scenes fit in LDS
+    cfg = bt.pncg_batch_get_config()
+    _say(f"staging precision={precision}: default {cfg}")
+    assert cfg["lds"] == 1 and cfg["max_team"] == 8       # these scenes fit in LDS
+    bt.pncg_batch_set_split(1)
     h = scs[0].h
     dev = torch.device("cuda:0")
     x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
@@ -200,6 +201,41 @@ def test_batch_lds_staging_same_bits(precision):
         assert np.array_equal(outs[(block, 0)][2], outs[(block, 1)][2])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_split_scenes_match_single_workgroup(precision):
+    """Large scenes stepped by teams of up to 8 workgroups against the same
+    scenes on one workgroup each: fixed 6 iterations, equal up to the order
+    of the partial sums; and the 8-scene batch really is split."""
+    import torch
+    scs = _small_batch()
+    xs, vs = _states(scs, 8)
+    bt, b = _make_batch(scs, precision, 6, 0.0, "delta_e")
+    h = scs[0].h
+    dev = torch.device("cuda:0")
+    x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
+    res = {}
+    for team in (1, 8):
+        bt.pncg_batch_set_split(team)
+        cfg = bt.pncg_batch_get_config()
+        xo, vo = torch.empty_like(x), torch.empty_like(v)
+        bt.pncg_batch_step(x, v, h, xo, vo)
+        it = bt.pncg_batch_stats()[0]
+        _say(f"  split {team}: {cfg}, iters {it.tolist()}")
+        assert np.all(it == 6)
+        res[team] = (cfg, xo.cpu().numpy())
+    assert res[8][0]["teams"] < res[1][0]["teams"]           # some scenes use several workgroups
+    x0 = np.concatenate(xs)
+    off = b["vert_off"]
+    for i in range(len(scs)):
+        sl = slice(off[i], off[i + 1])
+        rx = rel(res[8][1][sl], res[1][1][sl])
+        rdx = rel(res[8][1][sl] - x0[sl], res[1][1][sl] - x0[sl])
+        _say(f"  scene {i} ({scs[i].nT} tets): rel_x={rx:.2e} rel_dx={rdx:.2e}")
+        assert rx <= (1e-12 if precision == 0 else 1e-6)
+        assert rdx <= (1e-9 if precision == 0 else 1e-3)
+
+
 def test_batch_autotune_keeps_state_and_result():
     import torch
     import paper_2405_08001_amd as P
@@ -212,8 +248,9 @@ def test_batch_autotune_keeps_state_and_result():
     v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
     x0, v0 = x.clone(), v.clone()
     blk = bt.pncg_batch_autotune(x, v, h, 2)
-    _say(f"autotune picked {blk}")
-    assert blk in (256, 512, 1024)
+    cfg = bt.pncg_batch_get_config()
+    _say(f"autotune picked {blk}: {cfg}")
+    assert blk in (256, 512, 1024) and cfg["block"] == blk
     assert torch.equal(x, x0) and torch.equal(v, v0)
     with pytest.raises(P.PncgError):
         bt.pncg_batch_set_block(300)
