@@ -345,11 +345,12 @@ int pncg_batch_set_staging(pncg_batch* b, int32_t lds);
  * two barriers per iteration; the other scenes go to single workgroups,
  * longest first to the least loaded.  A team's workgroups must all be
  * resident at once: the step kernel's grid never exceeds the device's
- * resident capacity, and a barrier that still waits after about 2^21 polls
- * ends the launch with E_HIP (results invalid) instead of hanging.  Results
- * depend on the schedule only through the order of the partial sums.
- * Default 8 when LDS staging is on, else 1. */
-int pncg_batch_set_split(pncg_batch* b, int32_t max_team);
+ * resident capacity, and a barrier that still waits after max_polls polls
+ * (0: the default, 2^21, a few seconds) ends the launch with E_HIP (results
+ * invalid) instead of hanging.  Results depend on the schedule only through
+ * the order of the partial sums.  Default max_team: 8 when LDS staging is
+ * on, else 1. */
+int pncg_batch_set_split(pncg_batch* b, int32_t max_team, int32_t max_polls);
 
 /* Current workgroup size, staging mode, largest team and number of teams
  * of the schedule (each pointer nullable). */

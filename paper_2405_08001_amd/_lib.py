@@ -102,7 +102,7 @@ def _load():
         "pncg_batch_autotune": (I32, [P, P, P, D, I32, P]),
         "pncg_batch_set_staging": (I32, [P, I32]),
         "pncg_batch_get_config": (I32, [P, P, P, P, P]),
-        "pncg_batch_set_split": (I32, [P, I32]),
+        "pncg_batch_set_split": (I32, [P, I32, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -358,8 +358,8 @@ class Batch:
     def pncg_batch_set_staging(self, lds):
         self._check(_L.pncg_batch_set_staging(self._h, int(lds)))
 
-    def pncg_batch_set_split(self, max_team):
-        self._check(_L.pncg_batch_set_split(self._h, int(max_team)))
+    def pncg_batch_set_split(self, max_team, max_polls=0):
+        self._check(_L.pncg_batch_set_split(self._h, int(max_team), int(max_polls)))
 
     def pncg_batch_get_config(self):
         """dict(block, lds, max_team, teams) of the step kernel's schedule."""

@@ -1,10 +1,11 @@
 // Batched form: many independent scenes (concatenated meshes), each stepped
-// by one workgroup that runs the whole time step of Algorithm 1 (Sec. 4) on
-// its own: predictor, every PNCG iteration with its per-scene beta, alpha and
-// stop test, and the end-of-step velocity.  The grid-wide reductions of the
-// single-scene path become block reductions, so an iteration costs no kernel
-// launch; the grid is persistent (workgroups loop over scenes, largest
-// first).  Scenes have plane contact only (one optional plane each); the
+// by one workgroup, or by a team of workgroups for a large scene, that runs
+// the whole time step of Algorithm 1 (Sec. 4) inside the launch: predictor,
+// every PNCG iteration with its per-scene beta, alpha and stop test, and the
+// end-of-step velocity.  The grid-wide reductions of the single-scene path
+// become block (or team) reductions, so an iteration costs no kernel launch;
+// the grid is persistent and the host-built schedule lists each team's
+// scenes.  Scenes have plane contact only (one optional plane each); the
 // per-scene scalars follow the separate-step-size-per-object idea of Sec. 5.2.
 #include "batch.h"
 #include "sweep_common.h"

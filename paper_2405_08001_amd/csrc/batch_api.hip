@@ -20,6 +20,7 @@ thread_local std::string g_batch_create_error;
 }
 
 namespace {
+constexpr int kDefaultPolls = 1 << 21;
 constexpr int kNBlocks = 3;
 constexpr int kBlocks[kNBlocks] = {256, 512, 1024};
 }  // namespace
@@ -43,7 +44,7 @@ struct pncg_batch {
   int max_team = 1;         // workgroups one scene may use (needs LDS staging when > 1)
   int sched_grid = 0, sched_team = 0, n_teams = 0;
   bool split = false;       // the current schedule has a team of more than one workgroup
-  int spin_limit = 1 << 21;
+  int spin_limit = kDefaultPolls;  // polls before a team barrier gives up
   void* d_elem = nullptr;
   int *d_inc = nullptr, *d_inc_vert = nullptr;
   double* d_mass = nullptr;
@@ -489,10 +490,12 @@ int pncg_batch_set_staging(pncg_batch* b, int32_t lds) {
   return ensure_schedule(b);
 }
 
-int pncg_batch_set_split(pncg_batch* b, int32_t max_team) {
+int pncg_batch_set_split(pncg_batch* b, int32_t max_team, int32_t max_polls) {
   if (!b) return PNCG_E_INVAL;
   if (max_team < 1 || max_team > kMaxTeam) return bfail(b, PNCG_E_INVAL, "max_team must be in [1, 8]");
+  if (max_polls < 0) return bfail(b, PNCG_E_INVAL, "max_polls must be >= 0");
   b->max_team = max_team;
+  b->spin_limit = max_polls ? max_polls : kDefaultPolls;
   drop_graph(b);
   return ensure_schedule(b);
 }

@@ -236,6 +236,38 @@ def test_batch_split_scenes_match_single_workgroup(precision):
         assert rdx <= (1e-9 if precision == 0 else 1e-3)
 
 
+def test_batch_team_barrier_gives_up_with_an_error():
+    """A team barrier allowed a single poll (set from the host) gives up
+    instead of waiting, the launch still ends, and the step reports E_HIP;
+    with the default limit the same batch steps cleanly again."""
+    import torch
+    import paper_2405_08001_amd as P
+    scs = _small_batch()
+    xs, vs = _states(scs, 9)
+    bt, b = _make_batch(scs, 0, 6, 0.0, "delta_e")
+    h = scs[0].h
+    dev = torch.device("cuda:0")
+    x = torch.tensor(np.concatenate(xs), dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate(vs), dtype=torch.float64, device=dev)
+    xo, vo = torch.empty_like(x), torch.empty_like(v)
+    bt.pncg_batch_set_split(8, 1)
+    assert bt.pncg_batch_get_config()["teams"] < 256
+    failed = False
+    for _ in range(20):          # a single poll usually misses the other members
+        try:
+            bt.pncg_batch_step(x, v, h, xo, vo)
+        except P.PncgError as e:
+            assert e.code == P.E_HIP and "team barrier" in str(e)
+            failed = True
+            break
+    _say(f"single-poll barrier reported an error: {failed}")
+    assert failed
+    bt.pncg_batch_set_split(8, 0)
+    bt.pncg_batch_step(x, v, h, xo, vo)
+    assert np.all(bt.pncg_batch_stats()[0] == 6)
+    assert bool(torch.isfinite(xo).all())
+
+
 def test_batch_autotune_keeps_state_and_result():
     import torch
     import paper_2405_08001_amd as P
