@@ -1,7 +1,10 @@
 """Differentiable time stepping: a torch.autograd.Function over T steps of
 the library's solver whose backward pass runs the library's adjoint step
 (implicit differentiation of each converged step, pncg_adjoint_step_dev),
-recomputing the states between checkpoints taken every k steps.
+recomputing the states between checkpoints taken every k steps: k - 1
+steps per segment, since a segment's last state is the next checkpoint,
+and none for the last segment, whose states the forward pass keeps (the
+backward pass needs them first).
 
 Only marshalling and control flow live here; every step, Hessian-vector
 product, CG iteration and parameter gradient runs in the HIP library.
@@ -68,15 +71,20 @@ class _Rollout(torch.autograd.Function):
         v = v0.detach().to(torch.float64).contiguous().clone()
         xn, vn = torch.empty_like(x), torch.empty_like(v)
         ck = [(x.clone(), v.clone())]
+        tail = []          # states of the last segment, which the backward pass needs first
         sim.forward_stats = []
         for t in range(sim.steps):
             sim.forward_stats.append(sim._step(x, v, xn, vn))
             x, xn, v, vn = xn, x, vn, v
             if (t + 1) % sim.checkpoint == 0 and t + 1 < sim.steps:
                 ck.append((x.clone(), v.clone()))
+                tail = []
+            else:
+                tail.append(x.clone())
         fctx.sim = sim
         fctx.E_np = E_np
         fctx.ck = ck
+        fctx.tail = tail
         fctx.E_meta = (E.dtype, E.device)
         return x.clone(), v.clone()
 
@@ -95,15 +103,20 @@ class _Rollout(torch.autograd.Function):
         for s in reversed(range(len(ck))):
             t0 = s * k
             t1 = min(t0 + k, sim.steps)
-            # recompute x_{t0+1} .. x_{t1} from the checkpoint
-            x, v = ck[s][0].clone(), ck[s][1].clone()
-            states = []
-            xn, vn = torch.empty_like(x), torch.empty_like(v)
-            for _ in range(t0, t1):
-                sim._step(x, v, xn, vn)
-                sim.recomputed_steps += 1
-                x, xn, v, vn = xn, x, vn, v
-                states.append(x.clone())
+            if s == len(ck) - 1:
+                states = fctx.tail         # kept by the forward pass
+            else:
+                # recompute x_{t0+1} .. x_{t1-1} from the checkpoint; x_{t1}
+                # is the next checkpoint
+                x, v = ck[s][0].clone(), ck[s][1].clone()
+                states = []
+                xn, vn = torch.empty_like(x), torch.empty_like(v)
+                for _ in range(t0, t1 - 1):
+                    sim._step(x, v, xn, vn)
+                    sim.recomputed_steps += 1
+                    x, xn, v, vn = xn, x, vn, v
+                    states.append(x.clone())
+                states.append(ck[s + 1][0])
             for t in range(t1, t0, -1):
                 st = ctx.pncg_adjoint_step_dev(states[t - t0 - 1], sim.h, xbar, vbar, xb2, vb2, Ebar,
                                                cg_tol=sim.cg_tol, cg_max=sim.cg_max)

@@ -106,9 +106,14 @@ def test_checkpointing_equals_full_storage():
     v0 = np.zeros_like(sc.X)
     v0[:, 2] = -0.04
     x_tgt = sc.X + 0.001
-    g5 = _rollout_grad(_sim(sc, 7, checkpoint=5), sc.E, sc.X, v0, x_tgt)
-    g1 = _rollout_grad(_sim(sc, 7, checkpoint=1), sc.E, sc.X, v0, x_tgt)
-    _say(f"checkpoint 5 vs 1: dE {rel(g5[1], g1[1]):.2e} dx0 {rel(g5[2], g1[2]):.2e} dv0 {rel(g5[3], g1[3]):.2e}")
+    s5, s1 = _sim(sc, 7, checkpoint=5), _sim(sc, 7, checkpoint=1)
+    g5 = _rollout_grad(s5, sc.E, sc.X, v0, x_tgt)
+    g1 = _rollout_grad(s1, sc.E, sc.X, v0, x_tgt)
+    _say(f"checkpoint 5 vs 1: dE {rel(g5[1], g1[1]):.2e} dx0 {rel(g5[2], g1[2]):.2e} dv0 {rel(g5[3], g1[3]):.2e}; "
+         f"recomputed {s5.recomputed_steps} / {s1.recomputed_steps}")
+    # segments [0, 5) and [5, 7): x_1..x_4 recomputed, x_5 is a checkpoint,
+    # the last segment's states are kept by the forward pass
+    assert s5.recomputed_steps == 4 and s1.recomputed_steps == 0
     assert g5[0] == g1[0]
     for a, b in zip(g5[1:], g1[1:]):
         assert rel(a, b) <= 1e-12
