@@ -27,7 +27,10 @@
  *    pointers.  Inputs are only read during the call and never retained;
  *    host inputs are copied.  Outputs are written before the call returns
  *    (device outputs: ordered on the context's stream, which the call
- *    synchronises before returning).
+ *    synchronises before returning).  Device inputs are read on the
+ *    context's stream, which waits for no other stream: inputs written on
+ *    another stream (e.g. torch's) must be complete before the call, or the
+ *    context must be created on that stream (pncg_opts.stream).
  *  - The context owns all of its device memory and frees it in
  *    pncg_destroy.  A context must not be used from two threads at once.
  *  - Call order: pncg_create, pncg_set_mesh, pncg_set_material, then

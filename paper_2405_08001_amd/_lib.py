@@ -208,6 +208,7 @@ class Context:
             if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
                     and tuple(t.shape) == (self.nV, 3)):
                 raise ValueError("step_dev needs contiguous float64 CUDA tensors of shape (nV, 3)")
+        _ready(x)
         st = pncg_stats()
         rc = self._check(_L.pncg_step_dev(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), float(h),
                                           C.c_void_p(x_out.data_ptr()), C.c_void_p(v_out.data_ptr()), C.byref(st)))
@@ -277,6 +278,7 @@ class Context:
         n = self.nV
         if not (Ebar.is_cuda and Ebar.element_size() == 8 and Ebar.is_contiguous() and Ebar.numel() == self.nT):
             raise ValueError(f"Ebar must be a contiguous float64 CUDA tensor of {self.nT} values")
+        _ready(x1)
         st = pncg_adjoint_stats()
         rc = self._check(_L.pncg_adjoint_step_dev(
             self._h, _dev_ptr(x1, n, "x1"), float(h), _dev_ptr(xbar, n, "xbar"), _dev_ptr(vbar, n, "vbar"),
@@ -296,6 +298,14 @@ class Context:
         n = np.zeros(len(PROF_KINDS), dtype=np.int64)
         self._check(_L.pncg_get_profile(self._h, _ptr(us), _ptr(n)))
         return {k: (float(us[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
+
+
+def _ready(t):
+    """The library reads device inputs on its own stream, which does not wait
+    for torch's: finish what torch has queued on the tensor's device (a
+    clone of the state, say) before the library reads it."""
+    import torch
+    torch.cuda.current_stream(t.device).synchronize()
 
 
 def _dev_ptr(t, n, what):
@@ -370,12 +380,14 @@ class Batch:
     def pncg_batch_step(self, x, v, h, x_out, v_out):
         """float64 CUDA tensors (nV, 3); x_out/v_out must not alias x/v."""
         n = self.nV
+        _ready(x)
         self._check(_L.pncg_batch_step(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h),
                                        _dev_ptr(x_out, n, "x_out"), _dev_ptr(v_out, n, "v_out")))
 
     def pncg_batch_run(self, x, v, h, nsteps):
         """nsteps steps in place on the float64 CUDA tensors x, v (nV, 3)."""
         n = self.nV
+        _ready(x)
         self._check(_L.pncg_batch_run(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(nsteps)))
 
     def pncg_batch_stats(self):
@@ -387,6 +399,7 @@ class Batch:
 
     def pncg_batch_autotune(self, x, v, h, reps=3):
         n = self.nV
+        _ready(x)
         out = C.c_int32()
         self._check(_L.pncg_batch_autotune(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(reps),
                                            C.byref(out)))

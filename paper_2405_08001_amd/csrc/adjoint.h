@@ -32,9 +32,11 @@ struct AdjArgs {
   double4* z;
   double4* pbuf[2];       // p_k lives in pbuf[k & 1]
   double4* q;             // H p_k
+  double4* zw[2];         // fused form: {z_k, diag^-1 q_k} per vertex (2 double4) in zw[k & 1]
   const double* diag;     // [nV][3] Jacobi diagonal (prescribed rows 1)
   double* part_rz;        // [kMaxGrid][2]  r.z, r.r of the last update
   double* part_pq;        // [kMaxGrid]     p.Hp of the last Hv
+  double* part_f;         // [kMaxGrid][8]  fused form: p.q, r.z, r.r, r.w, q.z, q.w of the last launch
   CgScal* scal;           // [max_iter + 1]
   CgStatus* status;
   double tol2;            // relative residual tolerance, squared
@@ -44,10 +46,12 @@ struct AdjArgs {
 // b = xbar + vbar / h, r = b, lambda = 0, z = r / diag, partial sums.
 void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar,
                      hipStream_t s);
-// CG iteration k.  lazy: the direction is formed inside the Hv sweep (no
-// pair terms); otherwise a direction launch, the pair H p into acc, and the
-// Hv sweep (pairs need p materialised first).
-void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool lazy, hipStream_t s);
+// CG iteration k.  fused (no pair terms): one launch that finishes update
+// k-1 and forms z_k and p_k on the fly wherever the Hv sweep needs them;
+// launches 0 .. max_iter+1.
+// Otherwise a direction launch, the pair H p into acc, the Hv sweep and the
+// update launch; launches 0 .. max_iter.
+void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fused, hipStream_t s);
 // xbar_t = M lambda - vbar / h, vbar_t = h M lambda; Ebar[e] -= lambda . dG/dE_e.
 void launch_adj_out(const Args<double>& A, const AdjArgs& C, const double* vbar, const double* E, double* xbar_t,
                     double* vbar_t, double* Ebar, hipStream_t s);

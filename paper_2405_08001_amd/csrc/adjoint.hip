@@ -12,11 +12,12 @@
 // Hessian-vector product h^2 V dP(dF) b_a (Sec. 3.1), inertia M, the plane
 // barrier kappa b''(d) n n^T (exact), and the pair terms as the solver's
 // pair Hessian model (Sec. 3.2, equations eq9/eq12).  The system is solved by
-// Jacobi-preconditioned linear CG; each iteration is two launches: the Hv
-// sweep (vertex-centric, the new direction formed on the fly from z and the
-// previous direction) and the update of lambda, r, z.  Global scalars are
-// per-block partials re-reduced by the next launch in a fixed order, so every
-// block takes the same decisions.
+// Jacobi-preconditioned linear CG.  Without pair terms an iteration is one
+// launch (k_cg_fused): it finishes the previous update lazily, forms the new
+// direction on the fly and applies H; with pair terms it is a direction
+// launch, the pair H p, the Hv sweep and the update of lambda, r, z.  Global
+// scalars are per-block partials re-reduced by the next launch in a fixed
+// order, so every block takes the same decisions.
 #include "adjoint.h"
 #include "kernels.h"
 #include "sweep_common.h"
@@ -91,6 +92,8 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
     st3(C.r, v, b);
     st3(C.z, v, z);
     st3(C.lam, v, mk3(0.0, 0.0, 0.0));
+    st3(C.zw[1], 2 * v, z);                      // {z_0, w = 0} for the fused form
+    st3(C.zw[1], 2 * v + 1, mk3(0.0, 0.0, 0.0));
     rz += dot(b, z);
     rr += dot(b, b);
   }
@@ -100,6 +103,156 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
   if (threadIdx.x == 0) {
     C.part_rz[2 * blockIdx.x] = red[0];
     C.part_rz[2 * blockIdx.x + 1] = red[1];
+    double* f = C.part_f + 8 * blockIdx.x;
+    f[0] = 0.0;
+    f[1] = red[0];
+    f[2] = red[1];
+    f[3] = f[4] = f[5] = 0.0;
+  }
+}
+
+// One launch per CG iteration k (no pair terms).  With D = diag^-1, the
+// preconditioned residual z and w = D q are kept per vertex as one 64 B
+// record {z, w} (zw[k & 1]), so a corner needs two gathers ({z, w} and the
+// previous direction) like a plain Hv sweep.  From the partials of launch
+// k-1 (p.q, r.z, r.r, r.w, q.z, q.w of iteration k-1):
+//   stop if |r_{k-1}|^2 <= tol^2 |b|^2 (lambda_{k-1} is the result), or if
+//   k-1 reached the cap, or if p.q <= 0;
+//   alpha = r.z / p.q;  z_k = z_{k-1} - alpha w_{k-1};
+//   r_k.z_k = r.z - alpha (r.w + q.z) + alpha^2 q.w;
+//   beta = r_k.z_k / r.z;  p_k = z_k + beta p_{k-1},
+// z_k and p_k formed on the fly at every corner; each vertex's first lane
+// applies H and stores p_k, {z_k, D q_k} and lambda_k = lambda_{k-1} + alpha
+// p_{k-1} (lambda in place: only that lane touches it), and adds the partials
+// of launch k, with r_k = diag z_k (the residual itself is not stored).
+// k_adj_init writes {z_0, 0} into zw[1] and the partials r_0.z_0, |r_0|^2.
+__global__ void __launch_bounds__(kSBlock) k_cg_fused(Args<double> A, AdjArgs C, int k) {
+  __shared__ double sh[kSWaves * 6];
+  if (read_stopped(C.status)) return;
+  double red6[6];
+  {
+    const int kind[6] = {0, 0, 0, 0, 0, 0};
+    reduce_partials<6>(C.part_f, 8, A.grid, kind, red6, sh);
+  }
+  const double pq = red6[0], rz = red6[1], rr = red6[2], rw = red6[3], qz = red6[4], qw = red6[5];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (k == 0 && lead) C.status->bb = rr;
+  const double bb = (k == 0) ? rr : C.status->bb;
+  auto stop = [&](int reason) {
+    if (lead) {
+      C.status->iters = k > 0 ? k - 1 : 0;
+      C.status->reason = reason;
+      C.status->rr = reason == 2 ? 0.0 : rr;
+      C.status->stopped = 1;
+    }
+  };
+  if (rr <= C.tol2 * bb) { stop(0); return; }
+  if (k > 0 && k - 1 >= C.max_iter) { stop(1); return; }
+  double alpha = 0.0, beta = 0.0;
+  if (k > 0) {
+    if (!(pq > 0.0) || !isfinite(pq)) { stop(2); return; }
+    alpha = rz / pq;
+    const double rz_new = rz - alpha * (rw + qz) + alpha * alpha * qw;
+    beta = rz_new > 0.0 ? rz_new / rz : 0.0;
+    if (lead) {
+      C.scal[k - 1].alpha = alpha;
+      C.scal[k - 1].pq = pq;
+      C.scal[k].rz = rz_new;
+      C.scal[k].beta = beta;
+    }
+  } else if (lead) {
+    C.scal[0].rz = rz;
+    C.scal[0].beta = 0.0;
+  }
+  const double4* zwprev = C.zw[(k + 1) & 1];
+  double4* zwk = C.zw[k & 1];
+  const double4* pprev = C.pbuf[(k + 1) & 1];
+  double4* pk = C.pbuf[k & 1];
+  auto zget = [&](int v) -> V3<double> {
+    const V3<double> z = ld3(zwprev, 2 * v), w = ld3(zwprev, 2 * v + 1);
+    return mk3(fma(-alpha, w.x, z.x), fma(-alpha, w.y, z.y), fma(-alpha, w.z, z.z));
+  };
+  auto pnext = [&](V3<double> z, V3<double> pp) -> V3<double> {
+    if (k == 0) return z;
+    return mk3(fma(beta, pp.x, z.x), fma(beta, pp.y, z.y), fma(beta, pp.z, z.z));
+  };
+  auto pget = [&](int v, V3<double> z) -> V3<double> {
+    if (k == 0) return z;
+    return pnext(z, ld3(pprev, v));
+  };
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const Slice sl = block_slice(A.nWaves);
+  double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long w = sl.begin + wave; w < sl.end; w += kSWaves) {
+    const long long idx = w * kWave + lane;
+    const int code = A.inc[idx];
+    const int myv = A.inc_vert[idx];
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (code >= 0) {
+      const ElemRec<double> rec = A.elem[code >> 2];
+      Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
+                                           ld3(A.x0, rec.v[3]));
+      if (kin.J > 0.0) {
+        V3<double> d[3];
+        const int v0 = rec.v[0], v1 = rec.v[1], v2 = rec.v[2], v3 = rec.v[3];
+        dF_cols(rec.B, pget(v0, zget(v0)), pget(v1, zget(v1)), pget(v2, zget(v2)), pget(v3, zget(v3)), d);
+        const V3<double> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3));
+        s[0] = hp.x;
+        s[1] = hp.y;
+        s[2] = hp.z;
+      } else {
+        raise_err(A.status, kErrInverted);
+      }
+    }
+    seg_sum<double>(myv, s);
+    const int upv = __shfl_up(myv, 1, kWave);
+    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const int v = myv;
+    const V3<double> z = zget(v);
+    const V3<double> pp = k > 0 ? ld3(pprev, v) : mk3(0.0, 0.0, 0.0);
+    const V3<double> p = pnext(z, pp);
+    const double m = A.mass[v];
+    double hv[3] = {fma(A.h2, s[0], m * p.x), fma(A.h2, s[1], m * p.y), fma(A.h2, s[2], m * p.z)};
+    const uint8_t fl = A.vflag[v];
+    if (fl & kSurface) {
+      const V3<double> x = ld3(A.x0, v);
+      for (int j = 0; j < A.planes.n; ++j) {
+        const double* pl = A.planes.p[j];
+        const double d = plane_dist(pl, x);
+        if (d > 0.0 && d < A.dhat) {
+          const double c = A.kappa * barrier_d2b(d, A.dhat) * (pl[0] * p.x + pl[1] * p.y + pl[2] * p.z);
+          hv[0] += c * pl[0];
+          hv[1] += c * pl[1];
+          hv[2] += c * pl[2];
+        }
+      }
+    }
+    if (fl & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
+    const V3<double> q = mk3(hv[0], hv[1], hv[2]);
+    if (k > 0) {
+      const V3<double> l = ld3(C.lam, v);
+      st3(C.lam, v, mk3(fma(alpha, pp.x, l.x), fma(alpha, pp.y, l.y), fma(alpha, pp.z, l.z)));
+    }
+    const V3<double> dg = row3(C.diag, v);
+    const V3<double> r = mk3(dg.x * z.x, dg.y * z.y, dg.z * z.z);
+    const V3<double> wq = mk3(q.x / dg.x, q.y / dg.y, q.z / dg.z);
+    st3(pk, v, p);
+    st3(zwk, 2 * v, z);
+    st3(zwk, 2 * v + 1, wq);
+    acc6[0] += dot(p, q);
+    acc6[1] += dot(r, z);
+    acc6[2] += dot(r, r);
+    acc6[3] += dot(r, wq);
+    acc6[4] += dot(q, z);
+    acc6[5] += dot(q, wq);
+  }
+  {
+    const int kind[6] = {0, 0, 0, 0, 0, 0};
+    block_reduce<6>(acc6, kind, sh);
+  }
+  if (threadIdx.x == 0) {
+    double* f = C.part_f + 8 * blockIdx.x;
+    for (int i = 0; i < 6; ++i) f[i] = acc6[i];
   }
 }
 
@@ -127,24 +280,13 @@ __global__ void __launch_bounds__(kSBlock) k_cg_dir(Args<double> A, AdjArgs C, i
   }
 }
 
-// q = H p_k by the vertex-centric sweep; partials of p_k . q.
-template <bool LAZY>
+// q = H p_k by the vertex-centric sweep (p_k materialised by k_cg_dir, the
+// pair part already in acc); partials of p_k . q.
 __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, int k) {
   __shared__ double sh[kSWaves * 2];
   if (read_stopped(C.status)) return;
-  double beta = 0.0;
-  if (LAZY && !cg_begin(A, C, k, beta, sh)) return;
-  const double4* pprev = C.pbuf[(k + 1) & 1];
-  double4* pk = C.pbuf[k & 1];
-  auto pget = [&](int v) -> V3<double> {
-    if (!LAZY) return ld3(pk, v);
-    V3<double> p = ld3(C.z, v);
-    if (k > 0) {
-      const V3<double> pp = ld3(pprev, v);
-      p = mk3(fma(beta, pp.x, p.x), fma(beta, pp.y, p.y), fma(beta, pp.z, p.z));
-    }
-    return p;
-  };
+  const double4* pk = C.pbuf[k & 1];
+  auto pget = [&](int v) -> V3<double> { return ld3(pk, v); };
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const Slice sl = block_slice(A.nWaves);
   double pq = 0.0;
@@ -189,13 +331,12 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
         }
       }
     }
-    if (!LAZY && A.self) {
+    if (A.self) {
       hv[0] += A.acc[8 * v];
       hv[1] += A.acc[8 * v + 1];
       hv[2] += A.acc[8 * v + 2];
     }
     if (fl & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
-    if (LAZY) st3(pk, v, p);
     st3(C.q, v, mk3(hv[0], hv[1], hv[2]));
     pq += hv[0] * p.x + hv[1] * p.y + hv[2] * p.z;
   }
@@ -293,18 +434,18 @@ void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar
   hipLaunchKernelGGL(k_adj_init, dim3(A.grid), dim3(kSBlock), 0, s, A, C, xbar, vbar);
 }
 
-void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool lazy, hipStream_t s) {
-  if (lazy) {
-    hipLaunchKernelGGL(k_cg_hv<true>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
-  } else {
-    hipLaunchKernelGGL(k_cg_dir, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
-    if (A.self) {
-      Args<double> B = A;
-      B.p0 = C.pbuf[k & 1];
-      launch_pairs_hvp<double>(B, s);
-    }
-    hipLaunchKernelGGL(k_cg_hv<false>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fused, hipStream_t s) {
+  if (fused) {
+    hipLaunchKernelGGL(k_cg_fused, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+    return;
   }
+  hipLaunchKernelGGL(k_cg_dir, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+  if (A.self) {
+    Args<double> B = A;
+    B.p0 = C.pbuf[k & 1];
+    launch_pairs_hvp<double>(B, s);
+  }
+  hipLaunchKernelGGL(k_cg_hv, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
   hipLaunchKernelGGL(k_cg_update, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
 }
 

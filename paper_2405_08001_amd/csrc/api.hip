@@ -110,9 +110,10 @@ struct pncg_ctx {
   int grid = 1;
   // adjoint (allocated on first use)
   bool adj_ready = false;
-  double4 *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_pa = nullptr, *d_pb = nullptr, *d_q = nullptr;
+  double4 *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_pa = nullptr, *d_pb = nullptr, *d_q = nullptr,
+          *d_zw = nullptr;
   double *d_adiag = nullptr, *d_agrad = nullptr, *d_E = nullptr;
-  double *d_part_rz = nullptr, *d_part_pq = nullptr;
+  double *d_part_rz = nullptr, *d_part_pq = nullptr, *d_part_f = nullptr;
   double* d_aio = nullptr;         // [2][nV][3] + [nT] staging for host adjoint outputs
   CgScal* d_cgs = nullptr;
   int cgs_cap = 0;
@@ -672,7 +673,8 @@ int ensure_adjoint(pncg_ctx* c, int cg_max) {
         (rc = dmalloc(c, &c->d_adiag, 3 * nV)) || (rc = dmalloc(c, &c->d_agrad, 3 * nV)) ||
         (rc = dmalloc(c, &c->d_E, nT)) || (rc = dmalloc(c, &c->d_part_rz, 2 * (size_t)kMaxGrid)) ||
         (rc = dmalloc(c, &c->d_part_pq, (size_t)kMaxGrid)) || (rc = dmalloc(c, &c->d_aio, 6 * nV + nT)) ||
-        (rc = dmalloc(c, &c->d_cgst, 1)))
+        (rc = dmalloc(c, &c->d_cgst, 1)) || (rc = dmalloc(c, &c->d_zw, 4 * nV)) ||
+        (rc = dmalloc(c, &c->d_part_f, 8 * (size_t)kMaxGrid)))
       return rc;
     if (!c->h_cgst) HIPCHK(c, hipHostMalloc((void**)&c->h_cgst, sizeof(CgStatus), hipHostMallocDefault));
     c->adj_ready = true;
@@ -711,6 +713,9 @@ int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, co
   C.pbuf[0] = c->d_pa;
   C.pbuf[1] = c->d_pb;
   C.q = c->d_q;
+  C.zw[0] = c->d_zw;
+  C.zw[1] = c->d_zw + 2 * (size_t)c->nV;
+  C.part_f = c->d_part_f;
   C.diag = c->d_adiag;
   C.part_rz = c->d_part_rz;
   C.part_pq = c->d_part_pq;
@@ -719,15 +724,16 @@ int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, co
   C.tol2 = cg_tol * cg_tol;
   C.max_iter = cg_max;
   launch_adj_init(A, C, xbar, vbar, c->stream);
-  const bool lazy = !A.self;
+  const bool fused = !A.self;
+  const int last = fused ? cg_max + 1 : cg_max;   // the launch that reports the end at the latest
   int k = 0, chunk = 16;
   while (true) {
-    const int kend = std::min(k + chunk, cg_max + 1);
-    for (int j = k; j < kend; ++j) launch_cg_iteration(A, C, j, lazy, c->stream);
+    const int kend = std::min(k + chunk, last + 1);
+    for (int j = k; j < kend; ++j) launch_cg_iteration(A, C, j, fused, c->stream);
     HIPCHK(c, hipMemcpyAsync(c->h_cgst, c->d_cgst, sizeof(CgStatus), hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync(c))) return rc;
     if (c->h_cgst->stopped) break;
-    if (kend > cg_max) return fail(c, PNCG_E_HIP, "adjoint CG did not report its end");
+    if (kend > last) return fail(c, PNCG_E_HIP, "adjoint CG did not report its end");
     k = kend;
     chunk = std::min(chunk * 2, 256);
   }

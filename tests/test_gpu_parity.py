@@ -196,6 +196,37 @@ def test_grad_abs_rule_matches_scaled_grad_rel():
     assert np.array_equal(xa, xr)
 
 
+def test_step_dev_reads_inputs_torch_has_just_written():
+    """Device-pointer steps read their inputs on the library's stream: the
+    binding first finishes torch's queued work, so a state that torch is
+    still writing (a copy queued behind a long matrix product) is read only
+    once written.  Same bits as the host-pointer step."""
+    import torch
+    _say("step_dev after pending torch work")
+    sc, x0, v0 = _cube_drop()
+    ctx = make_ctx(sc, 0)
+    xh, vh, _ = ctx.pncg_step(x0, v0, sc.h)
+    dev = torch.device("cuda:0")
+    src_x = torch.tensor(x0, device=dev)
+    src_v = torch.tensor(v0, device=dev)
+    a = torch.randn(4096, 4096, device=dev)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        x = torch.zeros_like(src_x)
+        v = torch.zeros_like(src_v)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            a = a @ a
+            a = a / a.abs().max()
+        x.copy_(src_x)
+        v.copy_(src_v)
+        xo, vo = torch.empty_like(x), torch.empty_like(v)
+        ctx.pncg_step_dev(x, v, sc.h, xo, vo)
+        same = bool(np.array_equal(xo.cpu().numpy(), xh) and np.array_equal(vo.cpu().numpy(), vh))
+        _say(f"  rep {rep}: identical to the host step: {same}")
+        assert same
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_twisted_bar_first_step_matches_oracle(precision):
     """The 15,360-tet bar, first twist step (end faces prescribed, rotated by
