@@ -27,6 +27,17 @@ Readings where the paper is silent or garbled:
     "grad_abs": the same test against eps itself (steps that start near
     equilibrium have ||g_0|| near the gradient's rounding floor).
   * v^{t+1} = (x^{t+1} - x^t) / h.
+
+Other beta rules (the ablation of Sec. 7.1 names CD, HZ, FR and PRP beside
+DK; their formulas are in the cited papers).  Each is preconditioned by
+taking inner products that involve a gradient or y in the P metric of its
+iteration, with d = p_k the previous direction and z = P g:
+  fr   Fletcher-Reeves:   beta = g^T P g / (g_k^T P_k g_k)
+  prp  Polak-Ribiere-Polyak: beta = g^T P y / (g_k^T P_k g_k)
+  cd   Conjugate Descent: beta = -g^T P g / (d^T g_k)
+  hz   Hager-Zhang:       beta = g^T P y / (y^T d) - 2 (y^T P y / y^T d) (d^T g / y^T d)
+  dk   Dai-Kou (default): as above (the HZ form with factor 1)
+The guards and the restart are the same for every rule.
 """
 from __future__ import annotations
 
@@ -50,9 +61,37 @@ class StepStats:
     history: list = dataclasses.field(default_factory=list)
 
 
+BETA_RULES = ("dk", "fr", "prp", "cd", "hz")
+
+
+def beta_value(rule, g, P, g_prev, P_prev, p_prev):
+    """beta of iteration k > 0 by the named rule (module docstring); 0 when
+    a denominator is zero or the value is not finite."""
+    y = g - g_prev
+    if rule in ("fr", "prp"):
+        den = float(np.sum(g_prev * P_prev * g_prev))
+        num = float(np.sum(g * P * g)) if rule == "fr" else float(np.sum(g * P * y))
+        b = num / den if den != 0.0 else 0.0
+    elif rule == "cd":
+        den = float(np.sum(p_prev * g_prev))
+        b = -float(np.sum(g * P * g)) / den if den != 0.0 else 0.0
+    elif rule in ("dk", "hz"):
+        yp = float(np.sum(y * p_prev))
+        if yp == 0.0:
+            return 0.0
+        gPy = float(np.sum(g * P * y))
+        yPy = float(np.sum(y * P * y))
+        pg = float(np.sum(p_prev * g))
+        c = 1.0 if rule == "dk" else 2.0
+        b = gPy / yp - c * (yPy / yp) * (pg / yp)
+    else:
+        raise ValueError(f"unknown beta rule {rule!r}")
+    return b if np.isfinite(b) else 0.0
+
+
 def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
          alpha_norm="vertex", fixed_targets=None, track_energy=False,
-         record=False):
+         record=False, beta_rule="dk"):
     """Returns (x_new, v_new, stats)."""
     x_t = np.asarray(x_t, dtype=np.float64)
     xt = prob.predictor(x_t, v_t, h)
@@ -60,7 +99,7 @@ def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
     if len(prob.fixed):
         x[prob.fixed] = x_t[prob.fixed] if fixed_targets is None else fixed_targets
     st = StepStats()
-    g_prev = p_prev = None
+    g_prev = p_prev = P_prev = None
     dE0 = None
     g0n = None
     E_prev = prob.energy(x, xt, h) if track_energy else None
@@ -78,20 +117,7 @@ def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
             st.reason = term
             break
         P = 1.0 / D
-        if k == 0:
-            beta = 0.0
-        else:
-            y = g - g_prev
-            yp = float(np.sum(y * p_prev))
-            if yp == 0.0:
-                beta = 0.0
-            else:
-                gPy = float(np.sum(g * P * y))
-                yPy = float(np.sum(y * P * y))
-                pg = float(np.sum(p_prev * g))
-                beta = gPy / yp - (yPy / yp) * (pg / yp)
-                if not np.isfinite(beta):
-                    beta = 0.0
+        beta = 0.0 if k == 0 else beta_value(beta_rule, g, P, g_prev, P_prev, p_prev)
         p = -P * g + (beta * p_prev if k > 0 else 0.0)
         gp = float(np.sum(g * p))
         if gp >= 0.0:
@@ -134,7 +160,7 @@ def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
             dE0 = dE
             st.dE0 = dE
         st.last_dE = dE
-        g_prev, p_prev = g, p
+        g_prev, p_prev, P_prev = g, p, P
         if term == "delta_e" and dE < eps * dE0:
             st.reason = "delta_e"
             break

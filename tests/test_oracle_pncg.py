@@ -79,6 +79,78 @@ def test_dk_with_newton_step_is_jacobi_pcg_on_quadratics():
     np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b), rtol=1e-10)
 
 
+@pytest.mark.parametrize("rule", pncg.BETA_RULES)
+def test_every_beta_rule_is_jacobi_pcg_on_quadratics(rule):
+    # With an exact line search (the Newton step on a quadratic) and a fixed
+    # preconditioner, FR, PRP, CD, HZ and DK all reduce to linear PCG: the
+    # terms that tell them apart (g^T P g_k, d^T g) vanish by conjugacy.
+    rng = np.random.default_rng(1)
+    n = 24
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.diag(rng.uniform(0.5, 5, n))
+    b = rng.standard_normal(n)
+    qp = _Quadratic(A, b)
+    ref = _textbook_pcg(A, b, np.zeros(n), 10)
+    for k in (1, 2, 5, 10):
+        x, _, st = pncg.step(qp, np.zeros((n // 3, 3)), np.zeros((n // 3, 3)), 1.0,
+                             iter_max=k, eps=0.0, term="delta_e", beta_rule=rule)
+        assert st.iters == k
+        np.testing.assert_allclose(x.ravel(), ref[k - 1], rtol=1e-9, atol=1e-12)
+
+
+def test_hz_and_dk_sufficient_descent_bounds():
+    # The Hager-Zhang family beta = g^T P y / d^T y - c (y^T P y / d^T y)(d^T g / d^T y)
+    # gives d_new^T g <= -(1 - 1/(4c)) g^T P g for ANY line search (Hager and
+    # Zhang 2005, Thm 1.1, in the P metric): 7/8 for HZ (c = 2), 3/4 for DK
+    # (c = 1).  Random inexact states: both bounds hold, and DK breaks the HZ
+    # bound somewhere (so the two factors are told apart).
+    rng = np.random.default_rng(2)
+    dk_breaks_hz = 0
+    for _ in range(4000):
+        n = 6
+        g, gp, d = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+        P = rng.uniform(0.1, 3.0, n)
+        gPg = float(g @ (P * g))
+        for rule, bound in (("dk", 0.75), ("hz", 0.875)):
+            b = pncg.beta_value(rule, g, P, gp, P, d)
+            r = float((-P * g + b * d) @ g) / gPg
+            assert r <= -bound + 1e-12
+            if rule == "dk" and r > -0.875:
+                dk_breaks_hz += 1
+    assert dk_breaks_hz > 0
+
+
+def test_beta_rules_special_cases():
+    # unchanged gradient (y = 0): PRP, HZ and DK give 0, FR gives 1; CD gives
+    # -g^T P g / (d^T g_k), which is 1 when d = -P g_k (a steepest-descent
+    # previous direction)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(9)
+    P = rng.uniform(0.5, 2.0, 9)
+    d = rng.standard_normal(9)
+    assert pncg.beta_value("prp", g, P, g, P, d) == 0.0
+    assert pncg.beta_value("hz", g, P, g, P, d) == 0.0
+    assert pncg.beta_value("dk", g, P, g, P, d) == 0.0
+    assert pncg.beta_value("fr", g, P, g, P, d) == pytest.approx(1.0, rel=1e-15)
+    assert pncg.beta_value("cd", g, P, g, P, -P * g) == pytest.approx(1.0, rel=1e-15)
+    with pytest.raises(ValueError):
+        pncg.beta_value("xx", g, P, g, P, d)
+
+
+def test_beta_rules_differ_on_a_contact_step():
+    # on a real (non-quadratic) step the rules take different paths
+    sc = scenes.cube_scene()
+    P_ = problem.Problem.from_scene(sc)
+    x0 = sc.X.copy()
+    x0[:, 2] -= 0.05 - 1.2e-3
+    v0 = np.zeros_like(x0)
+    v0[:, 2] = -0.1
+    xs = {r: pncg.step(P_, x0, v0, sc.h, iter_max=6, eps=0.0, beta_rule=r)[0] for r in pncg.BETA_RULES}
+    for r in pncg.BETA_RULES:
+        if r != "dk":
+            assert not np.array_equal(xs[r], xs["dk"]), r
+
+
 def test_free_fall_converges_to_predictor():
     # no contact: the minimiser of the incremental potential is the rigidly
     # translated predictor x^t + h v + h^2 g (zero elastic energy there)
