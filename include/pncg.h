@@ -81,6 +81,22 @@ typedef struct pncg_ctx pncg_ctx;
                                         verbatim instead of its PSD projection */
 #define PNCG_ALPHA_INF_COMPONENT 2u  /* step bound with the largest |p_i|
                                         instead of the largest per-vertex |p_v|_2 */
+/* beta rule (a field of the solver flags; the ablation of Sec. 7.1 names
+ * these beside Dai-Kou).  With z = P g, d = the previous direction, y = g -
+ * g_prev and P the Jacobi preconditioner of each iteration:
+ *   DK  g^T P y / d^T y - (y^T P y / d^T y)(d^T g / d^T y)     (default)
+ *   FR  g^T P g / (g_prev^T P_prev g_prev)
+ *   PRP g^T P y / (g_prev^T P_prev g_prev)
+ *   CD  -g^T P g / (d^T g_prev)
+ *   HZ  g^T P y / d^T y - 2 (y^T P y / d^T y)(d^T g / d^T y)
+ * A zero denominator or a non-finite value gives 0; a direction that is
+ * not a descent direction restarts with -P g, for every rule. */
+#define PNCG_BETA_DK    0u
+#define PNCG_BETA_FR    (1u << 4)
+#define PNCG_BETA_PRP   (2u << 4)
+#define PNCG_BETA_CD    (3u << 4)
+#define PNCG_BETA_HZ    (4u << 4)
+#define PNCG_BETA_MASK  (7u << 4)
 
 /* contact flags */
 #define PNCG_CONTACT_SELF          1u  /* point-triangle and edge-edge pairs
@@ -155,7 +171,8 @@ int pncg_set_contact(pncg_ctx* ctx, double dhat, double kappa, double cell,
 
 /* Solver settings (Algorithm 1): iter_max >= 1, eps >= 0, term
  * PNCG_TERM_*, gravity[3] (m/s^2, f_ext = m g), flags PNCG_BARRIER_FULL /
- * PNCG_ALPHA_INF_COMPONENT.  Defaults: 100, 1e-3, DELTA_E, (0,0,-9.8), 0. */
+ * PNCG_ALPHA_INF_COMPONENT, or-ed with one PNCG_BETA_* rule.  Defaults: 100,
+ * 1e-3, DELTA_E, (0,0,-9.8), 0 (Dai-Kou). */
 int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
                     const double* gravity, uint32_t flags);
 
@@ -324,7 +341,8 @@ const char* pncg_batch_last_error(const pncg_batch* b);
 /* Parameters shared by all scenes: dhat > 0, kappa >= 0 (plane barrier),
  * iter_max >= 1, eps >= 0, term PNCG_TERM_*, gravity[3] (NULL keeps the
  * current value), flags PNCG_BARRIER_FULL / PNCG_ALPHA_INF_COMPONENT (the
- * plane Hessian is the same in both barrier modes).  Defaults: dhat 1e-3,
+ * plane Hessian is the same in both barrier modes) or-ed with a PNCG_BETA_*
+ * rule.  Defaults: dhat 1e-3,
  * kappa 1e4, 100, 1e-3, DELTA_E, (0, 0, -9.8), 0. */
 int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa,
                           int32_t iter_max, double eps, int32_t term,

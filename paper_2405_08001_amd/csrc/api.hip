@@ -1037,7 +1037,8 @@ int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, con
       (term != PNCG_TERM_DELTA_E && term != PNCG_TERM_GRAD_REL && term != PNCG_TERM_GRAD_ABS))
     return fail(c, PNCG_E_INVAL, "need iter_max >= 1, eps >= 0, term DELTA_E, GRAD_REL or GRAD_ABS");
   if (gravity && !finite_all(gravity, 3)) return fail(c, PNCG_E_NONFINITE, "non-finite gravity");
-  if (flags & ~3u) return fail(c, PNCG_E_INVAL, "unknown solver flag");
+  if ((flags & ~(3u | PNCG_BETA_MASK)) || (flags & PNCG_BETA_MASK) > PNCG_BETA_HZ)
+    return fail(c, PNCG_E_INVAL, "unknown solver flag or beta rule");
   c->iter_max = iter_max;
   c->eps = eps;
   c->term = term;

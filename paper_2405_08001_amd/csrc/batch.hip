@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
     T.sync();
     __syncthreads();
     int k = 0, reason = 2;
-    double g0 = 0.0, dE0 = 0.0;
+    double g0 = 0.0, dE0 = 0.0, gPg_prev = 0.0, gTp_prev = 0.0;
     for (;;) {
       // ---- gradient, diag(H), dot products (vertex-centric sweep)
       double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -202,15 +202,14 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
       if (k == 0) g0 = gnorm;
       if ((A.term == 1 && gnorm <= A.eps * g0) || (A.term == 2 && gnorm <= A.eps)) { reason = 1; break; }
       double beta = 0.0;
-      if (k > 0 && dots[3] != 0.0) {
-        beta = dots[2] / dots[3] - (dots[4] / dots[3]) * (dots[5] / dots[3]);
-        if (!isfinite(beta)) beta = 0.0;
-      }
+      if (k > 0) beta = beta_rule(A.flags, dots[1], dots[2], dots[3], dots[4], dots[5], gPg_prev, gTp_prev);
       double gTp = -dots[1] + beta * dots[5];
       if (!(gTp < 0.0)) {
         beta = 0.0;
         gTp = -dots[1];
       }
+      gPg_prev = dots[1];
+      gTp_prev = gTp;
       if (gTp == 0.0) { reason = 3; break; }
       // ---- direction p = -P g + beta p (in place; every member forms all of
       // it), inertia and plane parts of p^T H p (counted by rank 0)

@@ -460,7 +460,7 @@ int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa, int32_t iter
                           const double* gravity, uint32_t flags) {
   if (!b) return PNCG_E_INVAL;
   if (!(dhat > 0.0) || !(kappa >= 0.0) || iter_max < 1 || !(eps >= 0.0) || (term < 0 || term > 2) ||
-      (flags & ~3u))
+      (flags & ~(3u | PNCG_BETA_MASK)) || (flags & PNCG_BETA_MASK) > PNCG_BETA_HZ)
     return bfail(b, PNCG_E_INVAL, "bad batch parameters");
   b->dhat = dhat;
   b->kappa = kappa;

@@ -26,6 +26,32 @@ constexpr int kErrNonfinite = 4;
 constexpr int kErrCapacity = 8;
 constexpr int kErrTeam = 16;       // a team barrier of the batched kernel timed out
 
+// beta of iteration k > 0 by the rule in bits 4..6 of the solver flags, from
+// this iteration's g^T P g, g^T P y, y^T d, y^T P y, d^T g and the previous
+// iteration's g^T P g and d^T g (d the previous direction, y = g - g_prev);
+// 0 for a zero denominator or a non-finite value.
+__host__ __device__ inline double beta_rule(unsigned flags, double gPg, double gPy, double yp, double yPy,
+                                            double pg, double gPg_prev, double gTp_prev) {
+  double b = 0.0;
+  switch ((flags >> 4) & 7u) {
+    case 1:  // Fletcher-Reeves
+      b = gPg_prev != 0.0 ? gPg / gPg_prev : 0.0;
+      break;
+    case 2:  // Polak-Ribiere-Polyak
+      b = gPg_prev != 0.0 ? gPy / gPg_prev : 0.0;
+      break;
+    case 3:  // conjugate descent
+      b = gTp_prev != 0.0 ? -gPg / gTp_prev : 0.0;
+      break;
+    default: {  // Dai-Kou (0) and Hager-Zhang (4, twice the second term)
+      if (yp == 0.0) return 0.0;
+      const double c = ((flags >> 4) & 7u) == 4u ? 2.0 : 1.0;
+      b = gPy / yp - c * (yPy / yp) * (pg / yp);
+    }
+  }
+  return isfinite(b) ? b : 0.0;
+}
+
 template <typename R> struct R4T;
 template <> struct R4T<float> { using type = float4; };
 template <> struct R4T<double> { using type = double4; };
@@ -43,6 +69,7 @@ struct Planes {
 struct IterScal {
   double alpha, dE, dE0, D;
   double beta, gTp, gnorm;
+  double gPg;        // g^T P g of this iteration (denominator of the FR / PRP rules at the next)
   double n_active;
   double Dx;         // max over surface vertices of |x_k - x at the last list build|
   int stop, pause, a_up, dir_stop, restart, pad;

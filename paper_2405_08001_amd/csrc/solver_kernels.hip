@@ -424,9 +424,9 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   int dir_stop = 0, reason = 0, restart = 0;
   double beta = 0.0;
   if ((A.term == 1 && gnorm <= A.eps * g0) || (A.term == 2 && gnorm <= A.eps)) { dir_stop = 1; reason = 1; }
-  if (k > 0 && yp != 0.0) {
-    beta = gPy / yp - (yPy / yp) * (pg / yp);
-    if (!isfinite(beta)) beta = 0.0;
+  if (k > 0) {
+    const IterScal sp = A.scal[k - 1];
+    beta = beta_rule(A.flags, gPg, gPy, yp, yPy, pg, sp.gPg, sp.gTp);
   }
   double gTp = -gPg + beta * pg;
   if (!(gTp < 0.0)) {
@@ -438,6 +438,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   if (leader) {
     IterScal& o = A.scal[k];
     o.beta = beta; o.gTp = gTp; o.gnorm = gnorm; o.dir_stop = dir_stop; o.restart = restart; o.n_active = nact;
+    o.gPg = gPg;
     o.Dx = r[7];
     if (k == 0) A.status->g0 = gnorm;
     if (dir_stop) {

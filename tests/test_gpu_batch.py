@@ -40,14 +40,15 @@ def _small_batch():
     return scs
 
 
-def _make_batch(scs, precision, iter_max, eps, term):
+def _make_batch(scs, precision, iter_max, eps, term, beta="dk"):
     import paper_2405_08001_amd as P
     b = scenes.pack_batch(scs)
     bt = P.Batch(b["vert_off"], b["X"], b["tet_off"], b["tets"], b["tri_off"], b["tris"], b["E"], b["nu"],
                  b["rho"], b["planes"], precision=precision)
     s0 = scs[0]
     bt.pncg_batch_set_params(s0.dhat, s0.kappa, iter_max, eps,
-                             {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL}[term], s0.gravity, 0)
+                             {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL}[term], s0.gravity,
+                             P.BETA_RULES[beta])
     return bt, b
 
 
@@ -60,6 +61,28 @@ def _step(bt, x, v, h):
     vo = torch.empty_like(vd)
     bt.pncg_batch_step(xd, vd, h, xo, vo)
     return xo.cpu().numpy(), vo.cpu().numpy()
+
+
+@pytest.mark.parametrize("rule", ["fr", "prp", "cd", "hz"])
+def test_batch_beta_rules_match_oracle(rule):
+    """The batched kernel with the other beta rules (Sec. 7.1): 8 fixed
+    iterations per scene in float64 against the oracle with the same rule."""
+    from oracle import pncg
+    scs = _small_batch()
+    xs, vs = _states(scs, 10)
+    K = 8
+    bt, b = _make_batch(scs, 0, K, 0.0, "delta_e", beta=rule)
+    xg, _ = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
+    it = bt.pncg_batch_stats()[0]
+    off = b["vert_off"]
+    for i, s in enumerate(scs):
+        xo, _, st = pncg.step(make_problem(s), xs[i], vs[i], s.h, iter_max=K, eps=0.0, term="delta_e",
+                              beta_rule=rule)
+        sl = slice(off[i], off[i + 1])
+        rx, rdx = rel(xg[sl], xo), rel(xg[sl] - xs[i], xo - xs[i])
+        _say(f"  {rule} scene {i} ({s.nT} tets): rel_x={rx:.3e} rel_dx={rdx:.3e}")
+        assert it[i] == st.iters == K
+        assert rx <= 1e-12 and rdx <= 1e-9
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -139,6 +139,40 @@ def test_fixed_iterations_match_oracle(which, K, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("rule", ["fr", "prp", "cd", "hz"])
+@pytest.mark.parametrize("which", ["cube", "stack"])
+def test_beta_rules_match_oracle(which, rule, precision):
+    """The other beta rules of the ablation (Sec. 7.1): 12 fixed iterations
+    against the oracle with the same rule, and a rule outside the set is
+    refused."""
+    _say(f"beta rule {rule} {which} precision={precision}")
+    import paper_2405_08001_amd as P
+    from oracle import pncg
+    sc, x0, v0 = DROPS[which]()
+    K = 12
+    ctx = make_ctx(sc, precision, iter_max=K, eps=0.0, term="delta_e", beta=rule)
+    prob = make_problem(sc)
+    xo, vo, st = pncg.step(prob, x0, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", beta_rule=rule)
+    xg, vg, sg = ctx.pncg_step(x0, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - x0, xo - x0)
+    bx, bdx = (1e-12, 1e-9) if precision == 0 else (1e-6, 1e-3)
+    if precision == 1:
+        # rules without the DK correction term (CD, FR) amplify the float32
+        # rounding of the element arithmetic more: the bar follows the
+        # oracle's own spread under a 2^-24 relative perturbation of x0
+        xq = x0 * (1.0 + 2.0 ** -24)
+        xp, _, _ = pncg.step(prob, xq, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", beta_rule=rule)
+        bx = max(bx, 4.0 * rel(xp, xo))
+        bdx = max(bdx, 4.0 * rel(xp - xq, xo - x0))
+    _say(f"  iters oracle={st.iters} gpu={sg['iters']} rel_x={rx:.3e} (bar {bx:.1e}) rel_dx={rdx:.3e} (bar {bdx:.1e})")
+    assert sg["iters"] == st.iters == K
+    assert rx <= bx
+    assert rdx <= bdx
+    with pytest.raises(P.PncgError):
+        ctx.pncg_set_solver(K, 0.0, P.TERM_DELTA_E, sc.gravity, 5 << 4)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_cube_converged_step_matches_oracle(precision):
     """Tightly converged step: both sides reach the same minimiser, so the
     positions agree far below the 1e-5 bar regardless of the path."""
