@@ -182,6 +182,55 @@ def run(sc, precision, warmup, steps, profile_frames):
                 prof=prof, dmin=dmin, jmin=jmin, state=state)
 
 
+def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
+    """The beta rules of the ablation (Sec. 7.1), re-run on synthetic scenes:
+    the error of x after K iterations of one step against that step's
+    converged minimiser x* (float64 Dai-Kou to ||g|| <= 1e-9 ||g_0||),
+    relative to |x* - x^t|, for the pile (mixed, from the state after
+    warm-up) and the cube resting on its floor (float64, after 12 steps)."""
+    import torch
+    import paper_2405_08001_amd as P
+    import scenes
+    dev = torch.device("cuda:0")
+
+    def solve(sc, prec, x0, v0, iters, eps, term, flag):
+        ctx = setup_ctx(sc, prec)
+        ctx.pncg_set_solver(iters, eps, term, sc.gravity, flag)
+        x = torch.tensor(x0, device=dev)
+        v = torch.tensor(v0, device=dev)
+        xo, vo = torch.empty_like(x), torch.empty_like(v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.pncg_step_dev(x, v, sc.h, xo, vo)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
+
+    cube = scenes.cube_scene()
+    x, v = cube.x0.copy(), cube.v0.copy()
+    for _ in range(12):
+        x, v, _, _ = solve(cube, "fp64", x, v, 2000, cube.eps, P.TERM_GRAD_REL, 0)
+    cases = {"cube": (cube, "fp64", x, v), "pile": (pile, "mixed", pile_state[0], pile_state[1])}
+    out = {}
+    for name, (sc, prec, x0, v0) in cases.items():
+        xs, _, sref, _ = solve(sc, "fp64", x0, v0, 20000, 1e-9, P.TERM_GRAD_REL, 0)
+        scale = float(np.linalg.norm(xs - x0))
+        res = {"reference_iters": int(sref["iters"]),
+               "reference_grad_ratio": float(f"{sref['g_norm'] / sref['g0_norm']:.3e}"),
+               "precision": prec, "budgets": list(budgets), "rules": {}}
+        for rule, flag in P.BETA_RULES.items():
+            errs, ips = [], 0.0
+            for K in budgets:
+                xk, _, st, dt = solve(sc, prec, x0, v0, K, 0.0, P.TERM_DELTA_E, flag)
+                errs.append(float(np.linalg.norm(xk - xs)) / scale)
+                if K == budgets[-1]:
+                    ips = st["iters"] / dt
+            res["rules"][rule] = {"rel_error": [float(f"{e:.3e}") for e in errs], "iters_per_s": round(ips, 1)}
+        out[name] = res
+    return out
+
+
 def cpu_baseline(sc, state, budget_iters=1):
     """The float64 oracle, single-threaded, on one PNCG iteration from the
     same state (the rest-pose exclusion set of this scene is empty, so it is
@@ -306,6 +355,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-scene batched run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
+    ap.add_argument("--no-beta-ablation", action="store_true", help="skip the beta-rule comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -409,6 +459,11 @@ def main():
         log("adjoint: 30,000-tet bar, 30 steps ...")
         out["adjoint"] = run_adjoint()
         log(f"  {out['adjoint']['adjoint_ms_per_step']} ms/step backward")
+    if not args.no_beta_ablation:
+        log("beta rules: pile and cube ...")
+        out["beta_ablation"] = run_beta_ablation(sc, m["state"])
+        for case, r in out["beta_ablation"].items():
+            log(f"  {case}: " + ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(sc, m["state"])
