@@ -182,52 +182,95 @@ def run(sc, precision, warmup, steps, profile_frames):
                 prof=prof, dmin=dmin, jmin=jmin, state=state)
 
 
-def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
-    """The beta rules of the ablation (Sec. 7.1), re-run on synthetic scenes:
-    the error of x after K iterations of one step against that step's
-    converged minimiser x* (float64 Dai-Kou to ||g|| <= 1e-9 ||g_0||),
-    relative to |x* - x^t|, for the pile (mixed, from the state after
-    warm-up) and the cube resting on its floor (float64, after 12 steps)."""
+def _solve_once(sc, prec, x0, v0, iters, eps, term, flags=0, dhat=None):
+    """One step of scene sc from (x0, v0) with the given stopping rule (and
+    optionally another dhat): (x, v, stats, seconds)."""
     import torch
     import paper_2405_08001_amd as P
-    import scenes
     dev = torch.device("cuda:0")
+    ctx = setup_ctx(sc, prec)
+    if dhat is not None:
+        ctx.pncg_set_contact(dhat, sc.kappa, 0.0, sc.planes,
+                             (P.CONTACT_SELF if sc.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
+    ctx.pncg_set_solver(iters, eps, term, sc.gravity, flags)
+    x = torch.tensor(x0, device=dev)
+    v = torch.tensor(v0, device=dev)
+    xo, vo = torch.empty_like(x), torch.empty_like(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.pncg_step_dev(x, v, sc.h, xo, vo)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
 
-    def solve(sc, prec, x0, v0, iters, eps, term, flag):
-        ctx = setup_ctx(sc, prec)
-        ctx.pncg_set_solver(iters, eps, term, sc.gravity, flag)
-        x = torch.tensor(x0, device=dev)
-        v = torch.tensor(v0, device=dev)
-        xo, vo = torch.empty_like(x), torch.empty_like(v)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.pncg_step_dev(x, v, sc.h, xo, vo)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ctx.close()
-        return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
 
+def _reference(sc, x0, v0, dhat=None, tol=1e-7, cap=5000):
+    """x* of the step from (x0, v0): float64 Dai-Kou to ||g|| <= tol ||g_0||
+    (at most cap iterations) and how far it got."""
+    import paper_2405_08001_amd as P
+    xs, _, sref, _ = _solve_once(sc, "fp64", x0, v0, cap, tol, P.TERM_GRAD_REL, 0, dhat)
+    return xs, {"reference_iters": int(sref["iters"]),
+                "reference_grad_ratio": float(f"{sref['g_norm'] / sref['g0_norm']:.3e}")}
+
+
+def _convergence(sc, prec, x0, v0, budgets, flags, dhat, xs):
+    """Error of x after K iterations (each K in budgets) against the step's
+    minimiser xs, relative to |xs - x^t|; iterations/s at the largest K."""
+    import paper_2405_08001_amd as P
+    scale = float(np.linalg.norm(xs - x0))
+    errs, ips, act = [], 0.0, 0
+    for K in budgets:
+        xk, _, st, dt = _solve_once(sc, prec, x0, v0, K, 0.0, P.TERM_DELTA_E, flags, dhat)
+        errs.append(float(f"{float(np.linalg.norm(xk - xs)) / scale:.3e}"))
+        if K == budgets[-1]:
+            ips, act = st["iters"] / dt, st["n_active"]
+    return {"rel_error": errs, "iters_per_s": round(ips, 1), "active_pairs": int(act)}
+
+
+def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
+    """The beta rules of the ablation (Sec. 7.1), re-run on synthetic scenes:
+    the error after K iterations of one step against the step's minimiser
+    (float64 Dai-Kou to ||g|| <= 1e-7 ||g_0||, at most 5,000 iterations),
+    for the pile (mixed, from the state after warm-up) and the cube resting
+    on its floor (float64, after 12 steps)."""
+    import paper_2405_08001_amd as P
+    import scenes
     cube = scenes.cube_scene()
     x, v = cube.x0.copy(), cube.v0.copy()
     for _ in range(12):
-        x, v, _, _ = solve(cube, "fp64", x, v, 2000, cube.eps, P.TERM_GRAD_REL, 0)
+        x, v, _, _ = _solve_once(cube, "fp64", x, v, 2000, cube.eps, P.TERM_GRAD_REL)
     cases = {"cube": (cube, "fp64", x, v), "pile": (pile, "mixed", pile_state[0], pile_state[1])}
     out = {}
     for name, (sc, prec, x0, v0) in cases.items():
-        xs, _, sref, _ = solve(sc, "fp64", x0, v0, 20000, 1e-9, P.TERM_GRAD_REL, 0)
-        scale = float(np.linalg.norm(xs - x0))
-        res = {"reference_iters": int(sref["iters"]),
-               "reference_grad_ratio": float(f"{sref['g_norm'] / sref['g0_norm']:.3e}"),
-               "precision": prec, "budgets": list(budgets), "rules": {}}
+        xs, ref = _reference(sc, x0, v0)
+        res = {"precision": prec, "budgets": list(budgets), "reference_tol": 1e-7, "rules": {}}
+        res.update(ref)
         for rule, flag in P.BETA_RULES.items():
-            errs, ips = [], 0.0
-            for K in budgets:
-                xk, _, st, dt = solve(sc, prec, x0, v0, K, 0.0, P.TERM_DELTA_E, flag)
-                errs.append(float(np.linalg.norm(xk - xs)) / scale)
-                if K == budgets[-1]:
-                    ips = st["iters"] / dt
-            res["rules"][rule] = {"rel_error": [float(f"{e:.3e}") for e in errs], "iters_per_s": round(ips, 1)}
+            res["rules"][rule] = _convergence(sc, prec, x0, v0, budgets, flag, None, xs)
         out[name] = res
+    return out
+
+
+def run_dhat_strategy(pile, pile_state, fractions=(0.3, 0.5, 0.7), budgets=(10, 25, 50, 100)):
+    """The larger-dhat strategy (Sec. 5.1) on the pile, mixed, from the state
+    after warm-up: dhat at 30/50/70 % of the mean boundary edge (same-object
+    pairs closer than 1.5 dhat at rest excluded) against the configured
+    dhat; each against its own minimiser (the problem changes with dhat)."""
+    import paper_2405_08001_amd as P
+    ctx = setup_ctx(pile, "mixed")
+    lbar = ctx.pncg_mean_boundary_edge()
+    ctx.close()
+    out = {"mean_boundary_edge": lbar, "budgets": list(budgets), "reference_tol": 1e-7, "dhat": {}}
+    for label, dh in [("configured", pile.dhat)] + [(f"{f:.1f}*edge", f * lbar) for f in fractions]:
+        try:
+            xs, ref = _reference(pile, pile_state[0], pile_state[1], dh)
+            r = _convergence(pile, "mixed", pile_state[0], pile_state[1], budgets, 0, dh, xs)
+            r.update(ref)
+        except P.PncgError as e:      # e.g. a tet inverted on the way (no inversion guard, reading S4)
+            r = {"error": str(e)}
+        r["dhat"] = dh
+        out["dhat"][label] = r
     return out
 
 
@@ -356,6 +399,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-scene batched run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
     ap.add_argument("--no-beta-ablation", action="store_true", help="skip the beta-rule comparison")
+    ap.add_argument("--no-dhat-strategy", action="store_true", help="skip the larger-dhat comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -464,6 +508,10 @@ def main():
         out["beta_ablation"] = run_beta_ablation(sc, m["state"])
         for case, r in out["beta_ablation"].items():
             log(f"  {case}: " + ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
+    if not args.no_dhat_strategy:
+        log("larger-dhat strategy on the pile ...")
+        out["dhat_strategy"] = run_dhat_strategy(sc, m["state"])
+        log("  " + ", ".join(f"{k} {v.get('rel_error', v.get('error'))}" for k, v in out["dhat_strategy"]["dhat"].items()))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(sc, m["state"])

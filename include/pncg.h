@@ -188,6 +188,12 @@ int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
  * keeps a skin set here. */
 int pncg_set_tuning(pncg_ctx* ctx, double skin, int32_t chunk);
 
+/* Mean rest length of the surface edges given to pncg_set_mesh (0 if
+ * none), for the larger-dhat strategy of Sec. 5.1: dhat at 30-70 % of it,
+ * with PNCG_CONTACT_REST_EXCLUDE dropping the same-object pairs closer than
+ * 1.5 dhat at rest.  E_STATE before pncg_set_mesh. */
+int pncg_mean_boundary_edge(pncg_ctx* ctx, double* out);
+
 /* Prescribed vertices for the following steps: idx [n] (distinct),
  * target [n][3] positions they take at the start of the next step (their
  * gradient, direction and update are zero during it).  n = 0 clears. */

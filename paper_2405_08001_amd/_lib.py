@@ -32,7 +32,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
            "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
            "pncg_set_profiling", "pncg_get_profile", "pncg_adjoint_step", "pncg_adjoint_step_dev",
-           "pncg_set_tuning",
+           "pncg_set_tuning", "pncg_mean_boundary_edge",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
@@ -82,6 +82,7 @@ def _load():
         "pncg_set_solver": (I32, [P, I32, D, I32, P, U32]),
         "pncg_set_dirichlet": (I32, [P, I32, P, P]),
         "pncg_set_tuning": (I32, [P, D, I32]),
+        "pncg_mean_boundary_edge": (I32, [P, P]),
         "pncg_step": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_step_dev": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_energy": (I32, [P, P, P, D, P]),
@@ -186,6 +187,11 @@ class Context:
 
     def pncg_set_tuning(self, skin=0.0, chunk=0):
         self._check(_L.pncg_set_tuning(self._h, float(skin), int(chunk)))
+
+    def pncg_mean_boundary_edge(self):
+        out = C.c_double()
+        self._check(_L.pncg_mean_boundary_edge(self._h, C.byref(out)))
+        return out.value
 
     def pncg_set_dirichlet(self, idx, target):
         idx = _i32(idx)

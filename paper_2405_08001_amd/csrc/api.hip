@@ -1047,6 +1047,21 @@ int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, con
   return PNCG_OK;
 }
 
+int pncg_mean_boundary_edge(pncg_ctx* c, double* out) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  if (!out) return fail(c, PNCG_E_INVAL, "NULL output");
+  double lsum = 0.0;
+  for (int e = 0; e < c->nE; ++e) {
+    const int a = c->edges[2 * e], b = c->edges[2 * e + 1];
+    double l2 = 0.0;
+    for (int i = 0; i < 3; ++i) l2 += (c->X[3 * a + i] - c->X[3 * b + i]) * (c->X[3 * a + i] - c->X[3 * b + i]);
+    lsum += std::sqrt(l2);
+  }
+  *out = c->nE > 0 ? lsum / c->nE : 0.0;
+  return PNCG_OK;
+}
+
 int pncg_set_tuning(pncg_ctx* c, double skin, int32_t chunk) {
   if (!c) return PNCG_E_INVAL;
   if (c->state < 2) return fail(c, PNCG_E_STATE, "set_mesh and set_material must come first");
