@@ -138,6 +138,21 @@ def test_fixed_iterations_match_oracle(which, K, precision):
     assert rel(vg, vo) <= (1e-9 if precision == 0 else 1e-3)
 
 
+def test_mean_boundary_edge_matches_numpy():
+    """The larger-dhat strategy's reference length (Sec. 5.1): the mean rest
+    length of the surface edges."""
+    import paper_2405_08001_amd as P
+    sc = scenes.small_contact_scene()
+    ctx = P.Context(0, 0)
+    with pytest.raises(P.PncgError):
+        ctx.pncg_mean_boundary_edge()            # before set_mesh
+    ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
+    want = float(np.mean(np.linalg.norm(sc.X[sc.edges[:, 0]] - sc.X[sc.edges[:, 1]], axis=1)))
+    got = ctx.pncg_mean_boundary_edge()
+    _say(f"mean boundary edge {got:.6e} (numpy {want:.6e})")
+    assert got == pytest.approx(want, rel=1e-13)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("rule", ["fr", "prp", "cd", "hz"])
 @pytest.mark.parametrize("which", ["cube", "stack"])
