@@ -252,24 +252,45 @@ def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
     return out
 
 
-def run_dhat_strategy(pile, pile_state, fractions=(0.3, 0.5, 0.7), budgets=(10, 25, 50, 100)):
-    """The larger-dhat strategy (Sec. 5.1) on the pile, mixed, from the state
-    after warm-up: dhat at 30/50/70 % of the mean boundary edge (same-object
-    pairs closer than 1.5 dhat at rest excluded) against the configured
-    dhat; each against its own minimiser (the problem changes with dhat)."""
+def run_dhat_strategy(pile, warmup=10, fractions=(0.3, 0.5, 0.7), budgets=(10, 25, 50, 100)):
+    """The larger-dhat strategy (Sec. 5.1) on the pile, mixed: dhat at
+    30/50/70 % of the mean boundary edge (same-object pairs closer than
+    1.5 dhat at rest excluded) against the configured dhat.  Each runs its
+    own warm-up frames from the initial state with its dhat (the strategy is
+    a setting of the whole simulation), then one step is measured against
+    its own minimiser (the problem changes with dhat)."""
+    import torch
     import paper_2405_08001_amd as P
+    dev = torch.device("cuda:0")
     ctx = setup_ctx(pile, "mixed")
     lbar = ctx.pncg_mean_boundary_edge()
     ctx.close()
-    out = {"mean_boundary_edge": lbar, "budgets": list(budgets), "reference_tol": 1e-7, "dhat": {}}
+    out = {"mean_boundary_edge": lbar, "budgets": list(budgets), "reference_tol": 1e-7, "warmup_frames": warmup,
+           "dhat": {}}
     for label, dh in [("configured", pile.dhat)] + [(f"{f:.1f}*edge", f * lbar) for f in fractions]:
+        r = {"dhat": dh}
         try:
-            xs, ref = _reference(pile, pile_state[0], pile_state[1], dh)
-            r = _convergence(pile, "mixed", pile_state[0], pile_state[1], budgets, 0, dh, xs)
+            ctx = setup_ctx(pile, "mixed")
+            ctx.pncg_set_contact(dh, pile.kappa, 0.0, pile.planes,
+                                 (P.CONTACT_SELF if pile.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
+            x = torch.tensor(pile.x0, device=dev)
+            v = torch.tensor(pile.v0, device=dev)
+            x2, v2 = torch.empty_like(x), torch.empty_like(v)
+            its = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(warmup):
+                its += ctx.pncg_step_dev(x, v, pile.h, x2, v2)["iters"]
+                x, x2, v, v2 = x2, x, v2, v
+            torch.cuda.synchronize()
+            r["warmup_iters_per_s"] = round(its / (time.perf_counter() - t0), 1)
+            ctx.close()
+            x0, v0 = x.cpu().numpy(), v.cpu().numpy()
+            xs, ref = _reference(pile, x0, v0, dh)
+            r.update(_convergence(pile, "mixed", x0, v0, budgets, 0, dh, xs))
             r.update(ref)
         except P.PncgError as e:      # e.g. a tet inverted on the way (no inversion guard, reading S4)
-            r = {"error": str(e)}
-        r["dhat"] = dh
+            r["error"] = str(e)
         out["dhat"][label] = r
     return out
 
@@ -510,7 +531,7 @@ def main():
             log(f"  {case}: " + ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
     if not args.no_dhat_strategy:
         log("larger-dhat strategy on the pile ...")
-        out["dhat_strategy"] = run_dhat_strategy(sc, m["state"])
+        out["dhat_strategy"] = run_dhat_strategy(sc)
         log("  " + ", ".join(f"{k} {v.get('rel_error', v.get('error'))}" for k, v in out["dhat_strategy"]["dhat"].items()))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration ...")
