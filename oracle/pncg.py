@@ -38,6 +38,22 @@ iteration, with d = p_k the previous direction and z = P g:
   hz   Hager-Zhang:       beta = g^T P y / (y^T d) - 2 (y^T P y / y^T d) (d^T g / y^T d)
   dk   Dai-Kou (default): as above (the HZ form with factor 1)
 The guards and the restart are the same for every rule.
+
+Splitting computation (Sec. 5.2, split=True): every object (the vertices
+sharing an object id) gets its own beta, search direction and step size.
+Readings, since the details are in the missing supplemental:
+  * beta_o by the chosen rule over the object's vertices; p_v = -P g_v +
+    beta_o p_prev,v; the restart test g_o^T p_o >= 0 per object;
+  * alpha_o = min(dhat / (2 max_{v in o} ||p_v||), -g_o^T p_o / p_o^T H p_o),
+    where p_o is p on the object's vertices and zero elsewhere, so p_o^T H p_o
+    is the object's diagonal block of H (a contact pair between two objects
+    adds its term with the other object's p left out); every vertex still
+    moves at most dhat / 2, which keeps the step penetration-free;
+  * an object whose direction is zero does not move; the step stops as
+    "unbounded" only if some moving object's alpha is not finite;
+  * dE = sum_o (-alpha_o g_o^T p_o - alpha_o^2 / 2 p_o^T H p_o), with the same
+    termination rules as the unsplit step.
+With one object this is the unsplit step, operation for operation.
 """
 from __future__ import annotations
 
@@ -91,8 +107,11 @@ def beta_value(rule, g, P, g_prev, P_prev, p_prev):
 
 def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
          alpha_norm="vertex", fixed_targets=None, track_energy=False,
-         record=False, beta_rule="dk"):
+         record=False, beta_rule="dk", split=False):
     """Returns (x_new, v_new, stats)."""
+    if split:
+        return _step_split(prob, x_t, v_t, h, iter_max=iter_max, eps=eps, term=term, alpha_norm=alpha_norm,
+                           fixed_targets=fixed_targets, beta_rule=beta_rule)
     x_t = np.asarray(x_t, dtype=np.float64)
     xt = prob.predictor(x_t, v_t, h)
     x = x_t.copy()
@@ -165,6 +184,92 @@ def step(prob, x_t, v_t, h, *, iter_max=100, eps=1e-3, term="delta_e",
             st.reason = "delta_e"
             break
     if not st.reason:
+        st.reason = "iter_max"
+    st.iters = k
+    v = (x - x_t) / h
+    return x, v, st
+
+
+def _step_split(prob, x_t, v_t, h, *, iter_max, eps, term, alpha_norm, fixed_targets, beta_rule):
+    """Algorithm 1 with a beta, direction and step size per object (module
+    docstring, splitting computation)."""
+    x_t = np.asarray(x_t, dtype=np.float64)
+    xt = prob.predictor(x_t, v_t, h)
+    x = x_t.copy()
+    if len(prob.fixed):
+        x[prob.fixed] = x_t[prob.fixed] if fixed_targets is None else fixed_targets
+    objs = [prob.object_id == o for o in np.unique(prob.object_id)]
+    st = StepStats()
+    g_prev = p_prev = P_prev = None
+    dE0 = g0n = None
+    k = 0
+    while k < iter_max:
+        aset = prob.active_set(x)
+        g = prob.gradient(x, xt, h, aset)
+        D = prob.diag(x, h, aset)
+        gn = float(np.sqrt(np.sum(g * g)))
+        if g0n is None:
+            g0n = gn
+            st.g0 = gn
+        st.gk = gn
+        if (term == "grad_rel" and gn <= eps * g0n) or (term == "grad_abs" and gn <= eps):
+            st.reason = term
+            break
+        P = 1.0 / D
+        p = np.zeros_like(g)
+        gps = []
+        for m in objs:
+            beta = 0.0 if k == 0 else beta_value(beta_rule, g[m], P[m], g_prev[m], P_prev[m], p_prev[m])
+            pm = -P[m] * g[m] + (beta * p_prev[m] if k > 0 else 0.0)
+            gp = float(np.sum(g[m] * pm))
+            if gp >= 0.0:
+                pm = -P[m] * g[m]
+                gp = float(np.sum(g[m] * pm))
+            p[m] = pm
+            gps.append(gp)
+        p[~prob.free] = 0.0
+        if all(gp == 0.0 for gp in gps):
+            st.reason = "zero_gradient"
+            break
+        alphas, dE, unbounded, hits = [], 0.0, False, 0
+        for m, gp in zip(objs, gps):
+            po = np.where(m[:, None], p, 0.0)
+            if not np.any(po):
+                alphas.append(0.0)
+                continue
+            pHp = prob.pHp(x, po, h, aset)
+            a_bar = -gp / pHp if pHp > 0 else np.inf
+            if prob.has_collision_primitives:
+                pmax = float(np.max(np.linalg.norm(p[m], axis=1))) if alpha_norm == "vertex" \
+                    else float(np.max(np.abs(p[m])))
+                a_up = prob.dhat / (2.0 * pmax) if pmax > 0 else np.inf
+            else:
+                a_up = np.inf
+            alpha = min(a_up, a_bar)
+            if not np.isfinite(alpha):
+                unbounded = True
+            hits += a_up < a_bar
+            alphas.append(alpha)
+            dE += -alpha * gp - 0.5 * alpha * alpha * pHp
+        if unbounded:
+            st.reason = "unbounded"
+            break
+        st.alpha_upper_hits += hits
+        for m, alpha in zip(objs, alphas):
+            x[m] = x[m] + alpha * p[m]
+        if aset is not None:
+            st.n_active = len(aset.d)
+            st.n_plane = len(aset.pd)
+        k += 1
+        if dE0 is None:
+            dE0 = dE
+            st.dE0 = dE
+        st.last_dE = dE
+        g_prev, p_prev, P_prev = g, p, P
+        if term == "delta_e" and dE < eps * dE0:
+            st.reason = "delta_e"
+            break
+    else:
         st.reason = "iter_max"
     st.iters = k
     v = (x - x_t) / h

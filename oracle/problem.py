@@ -74,6 +74,8 @@ class Problem:
         self.barrier_mode = barrier_mode
         self.gravity = np.asarray(gravity, dtype=np.float64)
         self.surf_verts = np.unique(self.tris.reshape(-1)) if len(self.tris) else np.zeros(0, np.int64)
+        self.object_id = (np.zeros(self.nV, np.int64) if object_id is None
+                          else np.asarray(object_id, dtype=np.int64).reshape(self.nV))
         if self.self_contact and rest_exclude:
             self.excl_pt, self.excl_ee = candidates.rest_exclusion(
                 self.X, self.tris, self.edges, self.surf_verts, self.dhat, object_id)

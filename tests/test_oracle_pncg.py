@@ -243,3 +243,74 @@ def test_grad_abs_rule_is_grad_rel_scaled_by_g0():
     assert sa.iters == sr.iters and np.array_equal(xa, xr)
     x0, _, s0 = pncg.step(P, sc.X, v0, sc.h, iter_max=500, eps=2.0 * sr.g0, term="grad_abs")
     assert s0.iters == 0 and np.array_equal(x0, sc.X)
+
+
+# ------------------------------------------------ splitting computation (Sec. 5.2)
+def _two_apart_scene():
+    """Two cubes 0.2 m apart above a floor (no pair between them ever comes
+    near dhat), different stiffness, one dropping onto the floor."""
+    Xa, Ta = scenes.hex_grid(3, 3, 3, 0.01, origin=(0.0, 0.0, 5e-4))
+    Xb, Tb = scenes.hex_grid(3, 3, 3, 0.01, origin=(0.2, 0.0, 0.02))
+    X, tets, oid = scenes.merge_meshes([(Xa, Ta), (Xb, Tb)])
+    rng = np.random.default_rng(12)
+    X = X + rng.uniform(-2e-4, 2e-4, X.shape)
+    E = np.where(np.arange(len(tets)) < len(Ta), 1e5, 1e6)
+    sc = scenes.configs._scene(X, tets, E=E, nu=0.4, rho=1000.0, planes=[[0.0, 0.0, 1.0, 0.0]], dhat=1e-3,
+                               kappa=1e4, h=1.0 / 60.0, object_id=oid, self_contact=True, cell=4e-3)
+    v0 = np.zeros_like(X)
+    v0[oid == 0, 2] = -0.1
+    return sc, v0, oid
+
+
+def test_split_with_one_object_is_the_unsplit_step():
+    sc = scenes.cube_scene()
+    P_ = problem.Problem.from_scene(sc)
+    x0 = sc.X.copy()
+    x0[:, 2] -= 0.05 - 1.2e-3
+    v0 = np.zeros_like(x0)
+    v0[:, 2] = -0.1
+    for rule in ("dk", "fr"):
+        xa, _, sa = pncg.step(P_, x0, v0, sc.h, iter_max=8, eps=0.0, beta_rule=rule)
+        xb, _, sb = pncg.step(P_, x0, v0, sc.h, iter_max=8, eps=0.0, beta_rule=rule, split=True)
+        assert sa.iters == sb.iters == 8
+        assert np.array_equal(xa, xb)
+        assert sa.alpha_upper_hits == sb.alpha_upper_hits
+
+
+def test_split_on_separate_objects_equals_stepping_each_alone():
+    # no term couples the two objects, so per-object beta, p and alpha make
+    # the union's step exactly the two single-object steps (up to the order
+    # of the sums)
+    sc, v0, oid = _two_apart_scene()
+    P_ = problem.Problem.from_scene(sc)
+    xs, _, st = pncg.step(P_, sc.X, v0, sc.h, iter_max=10, eps=0.0, split=True)
+    assert st.iters == 10
+    xu, _, _ = pncg.step(P_, sc.X, v0, sc.h, iter_max=10, eps=0.0)
+    for o in (0, 1):
+        m = oid == o
+        vmap = -np.ones(len(oid), np.int64)
+        vmap[m] = np.arange(m.sum())
+        tm = np.all(m[sc.tets], axis=1)
+        sub = scenes.configs._scene(sc.X[m], vmap[sc.tets[tm]], E=sc.E[tm], nu=0.4, rho=1000.0,
+                                    planes=sc.planes, dhat=sc.dhat, kappa=sc.kappa, h=sc.h,
+                                    self_contact=True, cell=4e-3)
+        xo, _, so = pncg.step(problem.Problem.from_scene(sub), sub.X, v0[m], sc.h, iter_max=10, eps=0.0)
+        assert so.iters == 10
+        np.testing.assert_allclose(xs[m], xo, rtol=0, atol=1e-13)
+    # while the unsplit step (one alpha for both) moves the free-falling cube
+    # differently from its own single-object step
+    assert not np.allclose(xu[oid == 1], xs[oid == 1], rtol=0, atol=1e-12)
+
+
+def test_split_keeps_every_vertex_within_half_dhat_per_iteration():
+    sc = scenes.small_contact_scene()
+    P_ = problem.Problem.from_scene(sc)
+    v0 = np.zeros_like(sc.X)
+    v0[sc.object_id == 1, 2] = -0.05
+    x_prev = sc.X.copy()
+    for k in range(1, 7):
+        x, _, st = pncg.step(P_, sc.X, v0, sc.h, iter_max=k, eps=0.0, split=True)
+        assert st.iters == k
+        assert np.max(np.linalg.norm(x - x_prev, axis=1)) <= 0.5 * sc.dhat * (1 + 1e-12)
+        x_prev = x
+
