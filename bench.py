@@ -205,11 +205,12 @@ def _solve_once(sc, prec, x0, v0, iters, eps, term, flags=0, dhat=None):
     return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
 
 
-def _reference(sc, x0, v0, dhat=None, tol=1e-7, cap=5000):
-    """x* of the step from (x0, v0): float64 Dai-Kou to ||g|| <= tol ||g_0||
-    (at most cap iterations) and how far it got."""
+def _reference(sc, x0, v0, dhat=None, tol=1e-7, cap=5000, flags=0):
+    """x* of the step from (x0, v0): float64 Dai-Kou (split by object if the
+    flags say so) to ||g|| <= tol ||g_0|| (at most cap iterations) and how far
+    it got."""
     import paper_2405_08001_amd as P
-    xs, _, sref, _ = _solve_once(sc, "fp64", x0, v0, cap, tol, P.TERM_GRAD_REL, 0, dhat)
+    xs, _, sref, _ = _solve_once(sc, "fp64", x0, v0, cap, tol, P.TERM_GRAD_REL, flags, dhat)
     return xs, {"reference_iters": int(sref["iters"]),
                 "reference_grad_ratio": float(f"{sref['g_norm'] / sref['g0_norm']:.3e}")}
 
@@ -249,6 +250,42 @@ def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
         for rule, flag in P.BETA_RULES.items():
             res["rules"][rule] = _convergence(sc, prec, x0, v0, budgets, flag, None, xs)
         out[name] = res
+    return out
+
+
+def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
+    """Splitting computation (Sec. 5.2) on the pile (24 objects), mixed, from
+    the state after warm-up: the error after K iterations against the step's
+    minimiser (the same energy either way), split and unsplit, and the
+    iteration rate of each over 10 frames as configured.  The minimiser is
+    taken from the split float64 solve, which gets much closer to it."""
+    import torch
+    import paper_2405_08001_amd as P
+    dev = torch.device("cuda:0")
+    xs, ref = _reference(pile, pile_state[0], pile_state[1], flags=P.SPLIT_OBJECTS)
+    out = {"budgets": list(budgets), "objects": int(len(np.unique(pile.object_id))), "reference_tol": 1e-7}
+    out.update(ref)
+    for name, flag in (("unsplit", 0), ("split", P.SPLIT_OBJECTS)):
+        r = _convergence(pile, "mixed", pile_state[0], pile_state[1], budgets, flag, None, xs)
+        ctx = setup_ctx(pile, "mixed")
+        ctx.pncg_set_solver(pile.iter_max, pile.eps, P.TERM_DELTA_E, pile.gravity, flag)
+        x = torch.tensor(pile_state[0], device=dev)
+        v = torch.tensor(pile_state[1], device=dev)
+        x2, v2 = torch.empty_like(x), torch.empty_like(v)
+        its = reb = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            st = ctx.pncg_step_dev(x, v, pile.h, x2, v2)
+            its += st["iters"]
+            reb += st["rebuilds"]
+            x, x2, v, v2 = x2, x, v2, v
+        torch.cuda.synchronize()
+        r["frames_iters_per_s"] = round(its / (time.perf_counter() - t0), 1)
+        r["frames_iters_per_frame"] = round(its / 10, 2)
+        r["frames_rebuilds_per_frame"] = round(reb / 10, 2)
+        ctx.close()
+        out[name] = r
     return out
 
 
@@ -421,6 +458,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
     ap.add_argument("--no-beta-ablation", action="store_true", help="skip the beta-rule comparison")
     ap.add_argument("--no-dhat-strategy", action="store_true", help="skip the larger-dhat comparison")
+    ap.add_argument("--no-split", action="store_true", help="skip the per-object splitting comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -529,6 +567,10 @@ def main():
         out["beta_ablation"] = run_beta_ablation(sc, m["state"])
         for case, r in out["beta_ablation"].items():
             log(f"  {case}: " + ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
+    if not args.no_split:
+        log("splitting computation on the pile ...")
+        out["split"] = run_split(sc, m["state"])
+        log(f"  unsplit {out['split']['unsplit']['rel_error']} split {out['split']['split']['rel_error']}")
     if not args.no_dhat_strategy:
         log("larger-dhat strategy on the pile ...")
         out["dhat_strategy"] = run_dhat_strategy(sc)

@@ -97,6 +97,15 @@ typedef struct pncg_ctx pncg_ctx;
 #define PNCG_BETA_CD    (3u << 4)
 #define PNCG_BETA_HZ    (4u << 4)
 #define PNCG_BETA_MASK  (7u << 4)
+/* Splitting computation (Sec. 5.2): every object (the object_id given to
+ * pncg_set_mesh) gets its own beta, search direction and step size
+ * alpha_o = min(dhat / (2 max_{v in o} |p_v|), -g_o^T p_o / p_o^T H p_o), where
+ * p_o^T H p_o is the object's diagonal block of H (a pair between two
+ * objects adds its term to each with the other side's direction left out);
+ * dE is the sum over objects.  Needs object ids non-decreasing over the
+ * vertices and the tets grouped by object (E_INVAL from pncg_set_solver
+ * otherwise).  With one object the step is the unsplit one. */
+#define PNCG_SPLIT_OBJECTS (1u << 8)
 
 /* contact flags */
 #define PNCG_CONTACT_SELF          1u  /* point-triangle and edge-edge pairs

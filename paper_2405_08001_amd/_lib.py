@@ -23,6 +23,7 @@ TERM_DELTA_E, TERM_GRAD_REL, TERM_GRAD_ABS = 0, 1, 2
 BARRIER_FULL, ALPHA_INF_COMPONENT = 1, 2
 BETA_DK, BETA_FR, BETA_PRP, BETA_CD, BETA_HZ = 0, 1 << 4, 2 << 4, 3 << 4, 4 << 4
 BETA_RULES = {"dk": BETA_DK, "fr": BETA_FR, "prp": BETA_PRP, "cd": BETA_CD, "hz": BETA_HZ}
+SPLIT_OBJECTS = 1 << 8
 CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
 

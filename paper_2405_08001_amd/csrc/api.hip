@@ -10,6 +10,7 @@
 // chunks (to stop, or to rebuild the candidate list when the accumulated
 // displacement bound exceeds half the skin).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -87,6 +88,12 @@ struct pncg_ctx {
   long long* d_ncand = nullptr;
   IterScal* d_scal = nullptr;
   int scal_cap = 0;
+  // splitting computation: objects as contiguous vertex / tet ranges
+  int nObj = 0, oscal_cap = 0;
+  bool split_ready = false;
+  int *d_vobj = nullptr, *d_voff = nullptr, *d_toff = nullptr;
+  ObjScal* d_oscal = nullptr;
+  double *d_vdots = nullptr, *d_tphp = nullptr, *d_vphp = nullptr, *d_opair = nullptr;
   StepStatus* d_status = nullptr;
   StepStatus* h_status = nullptr;  // pinned
   long long* h_n = nullptr;        // pinned [2]
@@ -247,6 +254,16 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.part_dir = c->d_part_dir;
   A.part_narrow = c->d_part_narrow;
   A.grid = c->grid;
+  A.split = (c->sflags & PNCG_SPLIT_OBJECTS) ? 1 : 0;
+  A.nObj = c->nObj;
+  A.vobj = c->d_vobj;
+  A.voff = c->d_voff;
+  A.toff = c->d_toff;
+  A.oscal = c->d_oscal;
+  A.vdots = c->d_vdots;
+  A.tphp = c->d_tphp;
+  A.vphp = c->d_vphp;
+  A.opair = c->d_opair;
   return A;
 }
 
@@ -780,6 +797,22 @@ int grid_for(const pncg_ctx* c) {
 }  // namespace
 
 // =================================================================== C ABI
+// Objects of the split step must be contiguous vertex ranges (non-decreasing
+// ids) whose tets are contiguous too; the reason if not, else NULL.
+static const char* split_layout_error(const pncg_ctx* c) {
+  for (int v = 1; v < c->nV; ++v)
+    if (c->oid[v] < c->oid[v - 1]) return "splitting needs object ids non-decreasing over the vertices";
+  int prev = INT_MIN;
+  for (int e = 0; e < c->nT; ++e) {
+    const int o = c->oid[c->tets[4 * e]];
+    for (int a = 1; a < 4; ++a)
+      if (c->oid[c->tets[4 * e + a]] != o) return "splitting: a tet spans two objects";
+    if (o < prev) return "splitting needs the tets grouped by object in object order";
+    prev = o;
+  }
+  return nullptr;
+}
+
 extern "C" {
 
 int pncg_create(pncg_ctx** out, const pncg_opts* o) {
@@ -916,6 +949,9 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
     return rc;
   c->scal_cap = 0;
   c->d_scal = nullptr;
+  c->split_ready = false;
+  c->oscal_cap = 0;
+  c->d_oscal = nullptr;
   c->d_ent_key = nullptr; c->d_ent_item = nullptr; c->d_bkt_key = nullptr; c->d_bkt_item = nullptr;
   c->d_bkt_lo = nullptr; c->d_bkt_hi = nullptr; c->d_bkt_ids = nullptr;
   c->d_count = nullptr; c->d_start = nullptr; c->d_part_cnt = nullptr; c->d_part_off = nullptr;
@@ -1037,8 +1073,12 @@ int pncg_set_solver(pncg_ctx* c, int32_t iter_max, double eps, int32_t term, con
       (term != PNCG_TERM_DELTA_E && term != PNCG_TERM_GRAD_REL && term != PNCG_TERM_GRAD_ABS))
     return fail(c, PNCG_E_INVAL, "need iter_max >= 1, eps >= 0, term DELTA_E, GRAD_REL or GRAD_ABS");
   if (gravity && !finite_all(gravity, 3)) return fail(c, PNCG_E_NONFINITE, "non-finite gravity");
-  if ((flags & ~(3u | PNCG_BETA_MASK)) || (flags & PNCG_BETA_MASK) > PNCG_BETA_HZ)
+  if ((flags & ~(3u | PNCG_BETA_MASK | PNCG_SPLIT_OBJECTS)) || (flags & PNCG_BETA_MASK) > PNCG_BETA_HZ)
     return fail(c, PNCG_E_INVAL, "unknown solver flag or beta rule");
+  if (flags & PNCG_SPLIT_OBJECTS) {
+    const char* why = split_layout_error(c);
+    if (why) return fail(c, PNCG_E_INVAL, why);
+  }
   c->iter_max = iter_max;
   c->eps = eps;
   c->term = term;
@@ -1091,6 +1131,47 @@ int pncg_set_dirichlet(pncg_ctx* c, int32_t n, const int32_t* idx, const double*
   return upload_flags_targets(c);
 }
 
+// Object ranges and per-object buffers of the split step (allocated on the
+// first split step after set_mesh; the per-iteration scalars grow with
+// iter_max).
+static int ensure_split(pncg_ctx* c) {
+  if (!(c->sflags & PNCG_SPLIT_OBJECTS)) return PNCG_OK;
+  int rc;
+  if (!c->split_ready) {
+    const char* why = split_layout_error(c);
+    if (why) return fail(c, PNCG_E_INVAL, why);
+    std::vector<int> vobj(c->nV), voff(1, 0), toff(1, 0);
+    int n = 0;
+    for (int v = 0; v < c->nV; ++v) {
+      if (v > 0 && c->oid[v] != c->oid[v - 1]) { voff.push_back(v); ++n; }
+      vobj[v] = n;
+    }
+    voff.push_back(c->nV);
+    c->nObj = n + 1;
+    for (int o = 0, e = 0; o < c->nObj; ++o) {
+      while (e < c->nT && vobj[c->tets[4 * e]] == o) ++e;
+      toff.push_back(e);
+    }
+    if ((rc = dmalloc(c, &c->d_vobj, c->nV)) || (rc = dmalloc(c, &c->d_voff, c->nObj + 1)) ||
+        (rc = dmalloc(c, &c->d_toff, c->nObj + 1)) || (rc = dmalloc(c, &c->d_vdots, 6 * (size_t)c->nV)) ||
+        (rc = dmalloc(c, &c->d_tphp, (size_t)c->nT)) || (rc = dmalloc(c, &c->d_vphp, 3 * (size_t)c->nV)) ||
+        (rc = dmalloc(c, &c->d_opair, 2 * (size_t)c->nObj)))
+      return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_vobj, vobj.data(), sizeof(int) * c->nV, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_voff, voff.data(), sizeof(int) * voff.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_toff, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice, c->stream));
+    c->split_ready = true;
+  }
+  if (c->oscal_cap < c->iter_max + 2) {
+    if (c->d_oscal) dfree(c, c->d_oscal);
+    c->d_oscal = nullptr;
+    if ((rc = dmalloc(c, &c->d_oscal, (size_t)(c->iter_max + 2) * c->nObj))) return rc;
+    c->oscal_cap = c->iter_max + 2;
+    HIPCHK(c, hipMemsetAsync(c->d_oscal, 0, sizeof(ObjScal) * (size_t)c->oscal_cap * c->nObj, c->stream));
+  }
+  return sync(c);
+}
+
 static int ensure_scal(pncg_ctx* c) {
   if (c->scal_cap >= c->iter_max + 2) return PNCG_OK;
   if (c->d_scal) dfree(c, c->d_scal);
@@ -1109,7 +1190,7 @@ int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, doubl
   if (!x || !v || !x_out || !v_out) return fail(c, PNCG_E_INVAL, "NULL state pointer");
   if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
   HIPCHK(c, hipSetDevice(c->device));
-  if ((rc = ensure_scal(c))) return rc;
+  if ((rc = ensure_scal(c)) || (rc = ensure_split(c))) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (st) std::memset(st, 0, sizeof(*st));
     rc = c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)

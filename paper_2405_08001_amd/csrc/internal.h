@@ -75,6 +75,16 @@ struct IterScal {
   int stop, pause, a_up, dir_stop, restart, pad;
 };
 
+// Per-object scalars of iteration k when the step is split by object
+// (Sec. 5.2): [iteration][object].  beta, gTp, gPg, gg by the object's
+// gradient reduction; alpha, pHp, pmv, dE, a_up, moving by its direction
+// reduction.
+struct ObjScal {
+  double beta, gTp, gPg, gg;
+  double alpha, pHp, pmv, dE;
+  int a_up, moving, pad0, pad1;
+};
+
 // Step status, written when the step ends or pauses (one writer at a time).
 struct StepStatus {
   int stopped;      // the step has ended
@@ -135,6 +145,16 @@ struct Args {
   double* part_dir;        // [kMaxGrid][4]
   double* part_narrow;     // [kMaxGrid]
   int grid;
+  // splitting computation (Sec. 5.2): objects are contiguous vertex and tet ranges
+  int split, nObj;
+  const int* vobj;         // [nV] object of each vertex
+  const int* voff;         // [nObj + 1] vertex ranges
+  const int* toff;         // [nObj + 1] tet ranges
+  ObjScal* oscal;          // [iter_max + 2][nObj]
+  double* vdots;           // [nV][6] per-vertex beta dot products
+  double* tphp;            // [nT] h^2 p^T H_e p of each tet
+  double* vphp;            // [nV][3] inertia + plane p^T H p, |p_v|_2, max_i |p_v,i|
+  double* opair;           // [2][nObj] pair p^T H p per object (float64 atomics)
 };
 
 }  // namespace pncg

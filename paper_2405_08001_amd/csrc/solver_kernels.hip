@@ -45,6 +45,8 @@ __global__ void __launch_bounds__(kSBlock) k_predict(Args<R> A, const double* x_
     s->stopped = 0; s->final_k = 0; s->iters = 0; s->reason = 2; s->paused_at = -1; s->err = 0;
     s->a_up_hits = 0; s->g0 = 0; s->gk = 0; s->dE0 = 0; s->last_dE = 0; s->n_active = 0;
   }
+  if (A.split && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < 2 * A.nObj; i += kSBlock) A.opair[i] = 0.0;
   for (int v = blockIdx.x * kSBlock + threadIdx.x; v < A.nV; v += gridDim.x * kSBlock) {
     V3<double> x = mk3(x_in[3 * v], x_in[3 * v + 1], x_in[3 * v + 2]);
     V3<double> vel = mk3(v_in[3 * v], v_in[3 * v + 1], v_in[3 * v + 2]);
@@ -74,7 +76,10 @@ struct FirstPro {
   int work;          // evaluate the iteration's terms at x_k
 };
 
-template <typename R>
+// SPLIT: one step size per object (Sec. 5.2), taken from the per-object
+// scalars of iteration k - 1; dE is their sum and the displacement bound
+// grows by the largest alpha_o max_{v in o} |p_v|.
+template <typename R, bool SPLIT>
 __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh) {
   FirstPro fp{0.0, 0, 1};
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -96,18 +101,37 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
     fp.work = 0;
     return fp;
   }
-  const int kind[3] = {0, 1, 1};
-  double r[3];
-  reduce_partials<3>(A.part_dir, 4, A.grid, kind, r, sh);
-  const double pHp = r[0], pmv = r[1], pmc = r[2];
-  const double gTp = prev.gTp;
-  const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
-  const double pm = (A.flags & 2u) ? pmc : pmv;
-  const double aup = (A.has_prims && pm > 0.0) ? A.dhat / (2.0 * pm) : HUGE_VAL;
-  const double alpha = fmin(aup, abar);
+  double alpha = 0.0, dE = 0.0, dmove = 0.0;
+  int hits = 0;
+  bool unbounded = false;
+  if (!SPLIT) {
+    const int kind[3] = {0, 1, 1};
+    double r[3];
+    reduce_partials<3>(A.part_dir, 4, A.grid, kind, r, sh);
+    const double pHp = r[0], pmv = r[1], pmc = r[2];
+    const double gTp = prev.gTp;
+    const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
+    const double pm = (A.flags & 2u) ? pmc : pmv;
+    const double aup = (A.has_prims && pm > 0.0) ? A.dhat / (2.0 * pm) : HUGE_VAL;
+    alpha = fmin(aup, abar);
+    hits = aup < abar ? 1 : 0;
+    unbounded = !isfinite(alpha);
+    dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
+    dmove = alpha * pmv;
+  } else {
+    const ObjScal* os = A.oscal + (size_t)(k - 1) * A.nObj;
+    for (int o = 0; o < A.nObj; ++o) {
+      const ObjScal q = os[o];
+      if (!q.moving) continue;
+      if (!isfinite(q.alpha)) unbounded = true;
+      dE += q.dE;
+      hits += q.a_up;
+      dmove = fmax(dmove, q.alpha * q.pmv);
+    }
+  }
   IterScal s{};
-  s.a_up = prev.a_up + (aup < abar ? 1 : 0);
-  if (!isfinite(alpha)) {
+  s.a_up = prev.a_up + hits;
+  if (unbounded) {
     if (leader) {
       s.alpha = 0; s.dE = 0; s.dE0 = prev.dE0; s.D = prev.D; s.stop = 1; s.pause = 0;
       A.scal[k].alpha = s.alpha; A.scal[k].dE = 0; A.scal[k].dE0 = s.dE0; A.scal[k].D = s.D;
@@ -120,11 +144,10 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
     fp.work = 0;
     return fp;
   }
-  const double dE = -alpha * gTp - 0.5 * alpha * alpha * pHp;
   const double dE0 = (k == 1) ? dE : prev.dE0;
   // displacement of any surface vertex since the list build: exact at x_{k-1}
   // (measured by the gradient sweep) plus at most alpha |p|_max this update
-  const double D = (A.self ? prev.Dx : prev.D) + alpha * pmv;
+  const double D = (A.self ? prev.Dx : prev.D) + dmove;
   int stop = 0, reason = 0;
   if (A.term == 0 && dE < A.eps * dE0) { stop = 1; reason = 0; }
   else if (mode == kModeFinish) { stop = 1; reason = 2; }
@@ -146,6 +169,35 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
   fp.materialize = 1;
   fp.work = (stop || pause) ? 0 : 1;
   return fp;
+}
+
+// Reader of the positions of iteration k in the first launch (lazy when the
+// launch also applies the update) and the update itself.
+template <typename R, bool SPLIT>
+struct FirstPos {
+  using type = PosReader<R>;
+};
+template <typename R>
+struct FirstPos<R, true> {
+  using type = PosReaderSplit<R>;
+};
+
+template <typename R, bool SPLIT>
+__device__ __forceinline__ typename FirstPos<R, SPLIT>::type first_pos(const Args<R>& A, int k, const FirstPro& fp,
+                                                                       const double4* xsrc, const R4<R>* pk) {
+  if constexpr (SPLIT)
+    return PosReaderSplit<R>{xsrc, pk, A.oscal + (size_t)(k > 0 ? k - 1 : 0) * A.nObj, A.vobj, fp.materialize};
+  else
+    return PosReader<R>{xsrc, pk, fp.alpha, fp.materialize};
+}
+
+// x_k = x_{k-1} + alpha p_k on this block's vertex slice.
+template <typename R, bool SPLIT>
+__device__ __forceinline__ void apply_update(const Args<R>& A, int k, const FirstPro& fp, double4* xcur,
+                                             const double4* xprev, const R4<R>* pk) {
+  const auto pos = first_pos<R, SPLIT>(A, k, fp, xprev, pk);
+  const Slice sv = block_slice(A.nV);
+  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) st3(xcur, v, pos(v));
 }
 
 // ----------------------------------------------------------- narrow phase
@@ -196,23 +248,16 @@ __device__ __forceinline__ void pair_hess_coefs(const Args<R>& A, double d, doub
 // First launch of an iteration with self contact: apply the pending update,
 // then barrier gradient + diagonal of every active pair into acc (eq8,
 // eq10, eq11).
-template <typename R>
+template <typename R, bool SPLIT>
 __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) {
   __shared__ double sh[kSWaves * 8];
-  FirstPro fp = first_prologue(A, k, mode, sh);
+  FirstPro fp = first_prologue<R, SPLIT>(A, k, mode, sh);
   double4* xcur = xbuf(A, k);
   const double4* xprev = xbuf(A, k - 1);
   const R4<R>* pk = pbuf(A, k);
-  if (fp.materialize) {
-    const Slice sv = block_slice(A.nV);
-    for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
-      V3<double> x = ld3(xprev, v);
-      R4<R> q = pk[v];
-      st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
-    }
-  }
+  if (fp.materialize) apply_update<R, SPLIT>(A, k, fp, xcur, xprev, pk);
   if (!fp.work) return;
-  PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
+  const auto pos = first_pos<R, SPLIT>(A, k, fp, fp.materialize ? xprev : xcur, pk);
   const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
   double nact = 0.0;
   const Slice sq = block_slice(nq);
@@ -304,12 +349,14 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // Mode kGradFirst: first launch of the iteration (no self contact): applies
 // the pending update lazily.  kGradDirect: x_k already materialised.
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
-template <typename R, int MODE>
+// SPLIT: the beta dot products go per vertex to vdots (reduced per object
+// by k_objred_grad) instead of into the block partials.
+template <typename R, int MODE, bool SPLIT = false>
 __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   __shared__ double sh[kSWaves * 8];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
-    fp = first_prologue(A, k, mode, sh);
+    fp = first_prologue<R, SPLIT>(A, k, mode, sh);
   } else if (MODE == kGradDirect) {
     const IterScal s = A.scal[k];
     if (s.stop || s.pause) return;
@@ -321,16 +368,11 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
   const R4<R>* pk = pbuf(A, k);
   if (MODE == kGradFirst && fp.materialize && !fp.work) {
     // stop test passed: only apply the last update
-    const Slice sv = block_slice(A.nV);
-    for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
-      V3<double> x = ld3(xprev, v);
-      R4<R> q = pk[v];
-      st3(xcur, v, mk3(fma(fp.alpha, double(q.x), x.x), fma(fp.alpha, double(q.y), x.y), fma(fp.alpha, double(q.z), x.z)));
-    }
+    apply_update<R, SPLIT>(A, k, fp, xcur, xprev, pk);
     return;
   }
   if (!fp.work) return;
-  PosReader<R> pos{fp.materialize ? xprev : xcur, pk, fp.alpha, fp.materialize};
+  const auto pos = first_pos<R, SPLIT>(A, k, fp, fp.materialize ? xprev : xcur, pk);
   double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int w = (int)swv.begin + (threadIdx.x >> 6); w < swv.end; w += kSWaves) {
     const int idx = w * kWave + lane;
@@ -378,16 +420,33 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
     const double pg3[3] = {double(pgR.x), double(pgR.y), double(pgR.z)};
     const double gp3[3] = {double(gpR.x), double(gpR.y), double(gpR.z)};
     const double pp3[3] = {double(ppR.x), double(ppR.y), double(ppR.z)};
+    if constexpr (SPLIT) {
+      double vd[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const double P = 1.0 / dd[j];
-      const double y = g3[j] - gp3[j];
-      dots[0] += g3[j] * g3[j];
-      dots[1] += g3[j] * pg3[j];
-      dots[2] += g3[j] * P * y;
-      dots[3] += y * pp3[j];
-      dots[4] += y * P * y;
-      dots[5] += pp3[j] * g3[j];
+      for (int j = 0; j < 3; ++j) {
+        const double P = 1.0 / dd[j];
+        const double y = g3[j] - gp3[j];
+        vd[0] += g3[j] * g3[j];
+        vd[1] += g3[j] * pg3[j];
+        vd[2] += g3[j] * P * y;
+        vd[3] += y * pp3[j];
+        vd[4] += y * P * y;
+        vd[5] += pp3[j] * g3[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) A.vdots[6 * (size_t)v + i] = vd[i];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double P = 1.0 / dd[j];
+        const double y = g3[j] - gp3[j];
+        dots[0] += g3[j] * g3[j];
+        dots[1] += g3[j] * pg3[j];
+        dots[2] += g3[j] * P * y;
+        dots[3] += y * pp3[j];
+        dots[4] += y * P * y;
+        dots[5] += pp3[j] * g3[j];
+      }
     }
   }
   if (MODE == kGradQuery) return;
@@ -400,7 +459,9 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
 }
 
 // ------------------------------------------------------ direction + pHp
-template <typename R>
+// SPLIT: beta per object (from k_objred_grad), and the p^T H p terms go
+// per tet, per vertex and per object (pairs) for k_objred_dir.
+template <typename R, bool SPLIT = false>
 __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   __shared__ double sh[kSWaves * 8];
   const IterScal s = A.scal[k];
@@ -418,23 +479,38 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
     reduce_partials<1>(A.part_narrow, 1, A.grid, kind, q, sh);
     nact += q[0];
   }
-  const double gg = r[0], gPg = r[1], gPy = r[2], yp = r[3], yPy = r[4], pg = r[5];
+  const ObjScal* os = A.oscal + (size_t)k * A.nObj;
+  double gg = r[0], gPg = r[1];
+  int dir_stop = 0, reason = 0, restart = 0;
+  double beta = 0.0, gTp = 0.0;
+  bool any_dir = false;
+  if constexpr (SPLIT) {
+    gg = 0.0; gPg = 0.0;
+    for (int o = 0; o < A.nObj; ++o) {
+      gg += os[o].gg;
+      gPg += os[o].gPg;
+      gTp += os[o].gTp;
+      any_dir |= os[o].gTp != 0.0;
+    }
+  }
   const double gnorm = sqrt(gg);
   const double g0 = k == 0 ? gnorm : A.status->g0;
-  int dir_stop = 0, reason = 0, restart = 0;
-  double beta = 0.0;
   if ((A.term == 1 && gnorm <= A.eps * g0) || (A.term == 2 && gnorm <= A.eps)) { dir_stop = 1; reason = 1; }
-  if (k > 0) {
-    const IterScal sp = A.scal[k - 1];
-    beta = beta_rule(A.flags, gPg, gPy, yp, yPy, pg, sp.gPg, sp.gTp);
+  if constexpr (!SPLIT) {
+    const double gPy = r[2], yp = r[3], yPy = r[4], pg = r[5];
+    if (k > 0) {
+      const IterScal sp = A.scal[k - 1];
+      beta = beta_rule(A.flags, gPg, gPy, yp, yPy, pg, sp.gPg, sp.gTp);
+    }
+    gTp = -gPg + beta * pg;
+    if (!(gTp < 0.0)) {
+      restart = 1;
+      beta = 0.0;
+      gTp = -gPg;
+    }
+    any_dir = gTp != 0.0;
   }
-  double gTp = -gPg + beta * pg;
-  if (!(gTp < 0.0)) {
-    restart = 1;
-    beta = 0.0;
-    gTp = -gPg;
-  }
-  if (!dir_stop && gTp == 0.0) { dir_stop = 1; reason = 3; }
+  if (!dir_stop && !any_dir) { dir_stop = 1; reason = 3; }
   if (leader) {
     IterScal& o = A.scal[k];
     o.beta = beta; o.gTp = gTp; o.gnorm = gnorm; o.dir_stop = dir_stop; o.restart = restart; o.n_active = nact;
@@ -448,7 +524,10 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
     }
   }
   if (dir_stop) return;
-  const R rb = R(beta);
+  auto beta_of = [&](int v) -> R {
+    if constexpr (SPLIT) return R(os[A.vobj[v]].beta);
+    else return R(beta);
+  };
   const double4* xk = xbuf(A, k);
   const R4<R>* pk = pbuf(A, k);
   R4<R>* pn = pbuf(A, k + 1);
@@ -458,6 +537,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   const Slice st = block_slice(A.nT);
   for (int e = (int)st.begin + threadIdx.x; e < st.end; e += kSBlock) {
     const ElemRec<R> rec = A.elem[e];
+    const R rb = beta_of(rec.v[0]);      // a tet lies in one object
     V3<R> P[4];
     V3<double> X[4];
 #pragma unroll
@@ -469,19 +549,18 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
     Kin<R> kin = kinematics<R>(rec.B, X[0], X[1], X[2], X[3]);
     V3<R> d[3];
     dF_cols(rec.B, P[0], P[1], P[2], P[3], d);
-    el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+    if constexpr (SPLIT) A.tphp[e] = A.h2 * double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+    else el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
   }
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
   const Slice sv = block_slice(A.nV);
   for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
-    V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), rb);
+    V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), beta_of(v));
     str<R>(pn, v, p);
     const double px = p.x, py = p.y, pz = p.z;
     const double p2 = px * px + py * py + pz * pz;
-    acc_pHp += A.mass[v] * p2;
-    pmv = fmax(pmv, sqrt(p2));
-    pmc = fmax(pmc, fmax(fabs(px), fmax(fabs(py), fabs(pz))));
+    double vp = A.mass[v] * p2;
     if ((A.vflag[v] & kSurface) && A.planes.n > 0) {
       const V3<double> x = ld3(xk, v);
       for (int j = 0; j < A.planes.n; ++j) {
@@ -489,12 +568,23 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
         const double d = plane_dist(pl, x);
         if (d > 0.0 && d < A.dhat) {
           const double np = pl[0] * px + pl[1] * py + pl[2] * pz;
-          acc_pHp += A.kappa * barrier_d2b(d, A.dhat) * np * np;
+          vp += A.kappa * barrier_d2b(d, A.dhat) * np * np;
         }
       }
     }
+    const double pabs = sqrt(p2), pcomp = fmax(fabs(px), fmax(fabs(py), fabs(pz)));
+    if constexpr (SPLIT) {
+      A.vphp[3 * (size_t)v] = vp;
+      A.vphp[3 * (size_t)v + 1] = pabs;
+      A.vphp[3 * (size_t)v + 2] = pcomp;
+    } else {
+      acc_pHp += vp;
+      pmv = fmax(pmv, pabs);
+      pmc = fmax(pmc, pcomp);
+    }
   }
-  // pairs: kappa [ca (sum_i c_i p_i . t)^2 + cb |sum_i c_i p_i|^2] (eq12, eq13)
+  // pairs: kappa [ca (sum_i c_i p_i . t)^2 + cb |sum_i c_i p_i|^2] (eq12, eq13);
+  // split: each object's side of the pair with the other side's p left out
   if (A.self) {
     PosReader<R> pos{xk, pk, 0.0, 0};
     const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
@@ -505,16 +595,41 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
       if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
       double ca, cb;
       pair_hess_coefs(A, c.d, ca, cb);
-      V3<double> sp = mk3(0.0, 0.0, 0.0);
+      if constexpr (SPLIT) {
+        const int oa = A.vobj[iv[0]];
+        int ob = -1;
+        V3<double> sa = mk3(0.0, 0.0, 0.0), sb = mk3(0.0, 0.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        V3<R> p = direction(ldr<R>(A.pg, iv[i]), ldr<R>(pk, iv[i]), rb);
-        sp = sp + c.c[i] * cast3<double>(p);
+        for (int i = 0; i < 4; ++i) {
+          const int oi = A.vobj[iv[i]];
+          const V3<double> cp = c.c[i] * cast3<double>(direction(ldr<R>(A.pg, iv[i]), ldr<R>(pk, iv[i]), beta_of(iv[i])));
+          if (oi == oa) {
+            sa = sa + cp;
+          } else {
+            sb = sb + cp;
+            ob = oi;
+          }
+        }
+        double* op = A.opair + (size_t)(k & 1) * A.nObj;
+        const double ta = dot(sa, c.t);
+        atomicAdd(op + oa, ca * ta * ta + cb * dot(sa, sa));
+        if (ob >= 0) {
+          const double tb = dot(sb, c.t);
+          atomicAdd(op + ob, ca * tb * tb + cb * dot(sb, sb));
+        }
+      } else {
+        V3<double> sp = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          V3<R> p = direction(ldr<R>(A.pg, iv[i]), ldr<R>(pk, iv[i]), beta_of(iv[i]));
+          sp = sp + c.c[i] * cast3<double>(p);
+        }
+        const double st = dot(sp, c.t);
+        acc_pHp += ca * st * st + cb * dot(sp, sp);
       }
-      const double st = dot(sp, c.t);
-      acc_pHp += ca * st * st + cb * dot(sp, sp);
     }
   }
+  if constexpr (SPLIT) return;
   double v[3] = {acc_pHp, pmv, pmc};
   const int kind[3] = {0, 1, 1};
   block_reduce<3>(v, kind, sh);
@@ -523,6 +638,71 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
     A.part_dir[blockIdx.x * 4 + 1] = v[1];
     A.part_dir[blockIdx.x * 4 + 2] = v[2];
   }
+}
+
+// ------------------------------------------------- split: object reductions
+// One block per object: the object's beta dot products (from vdots) give
+// its beta by the solver's rule, the restart test and g_o^T p_o (Sec. 5.2).
+template <typename R>
+__global__ void __launch_bounds__(kSBlock) k_objred_grad(Args<R> A, int k) {
+  __shared__ double sh[kSWaves * 6];
+  const IterScal s = A.scal[k];
+  if (s.stop || s.pause) return;
+  const int o = blockIdx.x;
+  double d[6] = {0, 0, 0, 0, 0, 0};
+  for (int v = A.voff[o] + threadIdx.x; v < A.voff[o + 1]; v += kSBlock)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d[i] += A.vdots[6 * (size_t)v + i];
+  const int kind[6] = {0, 0, 0, 0, 0, 0};
+  block_reduce<6>(d, kind, sh);
+  if (threadIdx.x != 0) return;
+  const double gg = d[0], gPg = d[1], gPy = d[2], yp = d[3], yPy = d[4], pg = d[5];
+  double beta = 0.0;
+  if (k > 0) {
+    const ObjScal q = A.oscal[(size_t)(k - 1) * A.nObj + o];
+    beta = beta_rule(A.flags, gPg, gPy, yp, yPy, pg, q.gPg, q.gTp);
+  }
+  double gTp = -gPg + beta * pg;
+  if (!(gTp < 0.0)) {
+    beta = 0.0;
+    gTp = -gPg;
+  }
+  ObjScal& w = A.oscal[(size_t)k * A.nObj + o];
+  w.beta = beta; w.gTp = gTp; w.gPg = gPg; w.gg = gg;
+}
+
+// One block per object: its p^T H p (tets, vertices, pairs) and max |p_v|
+// give its step size alpha_o = min(dhat / (2 max |p_v|), -g_o^T p_o / p_o^T H p_o)
+// (equations upper, alpha) and its share of dE; an object whose direction is
+// zero does not move.
+template <typename R>
+__global__ void __launch_bounds__(kSBlock) k_objred_dir(Args<R> A, int k) {
+  __shared__ double sh[kSWaves * 4];
+  const IterScal s = A.scal[k];
+  if (s.stop || s.pause || s.dir_stop) return;
+  const int o = blockIdx.x;
+  double r[4] = {0, 0, 0, 0};
+  for (int e = A.toff[o] + threadIdx.x; e < A.toff[o + 1]; e += kSBlock) r[0] += A.tphp[e];
+  for (int v = A.voff[o] + threadIdx.x; v < A.voff[o + 1]; v += kSBlock) {
+    r[1] += A.vphp[3 * (size_t)v];
+    r[2] = fmax(r[2], A.vphp[3 * (size_t)v + 1]);
+    r[3] = fmax(r[3], A.vphp[3 * (size_t)v + 2]);
+  }
+  const int kind[4] = {0, 0, 1, 1};
+  block_reduce<4>(r, kind, sh);
+  if (threadIdx.x != 0) return;
+  double* op = A.opair + (size_t)(k & 1) * A.nObj + o;
+  const double pHp = r[0] + r[1] + *op;
+  *op = 0.0;   // ready for iteration k + 2
+  ObjScal& w = A.oscal[(size_t)k * A.nObj + o];
+  const double gTp = w.gTp, pmv = r[2], pm = (A.flags & 2u) ? r[3] : r[2];
+  const int moving = pmv > 0.0 ? 1 : 0;
+  const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
+  const double aup = (A.has_prims && pm > 0.0) ? A.dhat / (2.0 * pm) : HUGE_VAL;
+  const double alpha = moving ? fmin(aup, abar) : 0.0;
+  w.alpha = alpha; w.pHp = pHp; w.pmv = pmv; w.moving = moving;
+  w.a_up = (moving && aup < abar) ? 1 : 0;
+  w.dE = moving ? -alpha * gTp - 0.5 * alpha * alpha * pHp : 0.0;
 }
 
 // --------------------------------------------------------------- finalize
@@ -767,22 +947,43 @@ template <typename R>
 void launch_predict(const Args<R>& A, const double* x, const double* v, double3 grav, hipStream_t s) {
   hipLaunchKernelGGL(k_predict<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, x, v, grav);
 }
+// With splitting the gradient part of an iteration ends with the per-object
+// beta reduction and the direction part with the per-object alpha reduction.
 template <typename R>
 void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
-  if (A.self)
-    hipLaunchKernelGGL(k_narrow<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
-  else
+  if (A.self) {
+    if (A.split)
+      hipLaunchKernelGGL((k_narrow<R, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
+    else
+      hipLaunchKernelGGL((k_narrow<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
+  } else if (A.split) {
+    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode,
+                       (double*)nullptr, (double*)nullptr);
+    hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
+  } else {
     hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode, (double*)nullptr,
                        (double*)nullptr);
+  }
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
-  hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0, (double*)nullptr,
-                     (double*)nullptr);
+  if (A.split) {
+    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0,
+                       (double*)nullptr, (double*)nullptr);
+    hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
+  } else {
+    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0, (double*)nullptr,
+                       (double*)nullptr);
+  }
 }
 template <typename R>
 void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_dir<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, k);
+  if (A.split) {
+    hipLaunchKernelGGL((k_dir<R, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k);
+    hipLaunchKernelGGL(k_objred_dir<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
+  } else {
+    hipLaunchKernelGGL((k_dir<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k);
+  }
 }
 template <typename R>
 void launch_finalize(const Args<R>& A, double* x_out, double* v_out, hipStream_t s) {

@@ -112,6 +112,25 @@ __device__ __forceinline__ void raise_err(StepStatus* st, int bit) { atomicOr(&s
 
 // x of iteration k, either materialised in x[k & 1] or, inside the launch
 // that applies the update, lazily as x_{k-1} + alpha p_k.
+// Same with one step size per object (the split step): x_{k-1} + alpha_o p_k.
+template <typename R>
+struct PosReaderSplit {
+  const double4* xsrc;
+  const R4<R>* p;
+  const ObjScal* os;     // the previous iteration's per-object scalars
+  const int* vobj;
+  int lazy;
+  __device__ __forceinline__ V3<double> operator()(int v) const {
+    V3<double> x = ld3(xsrc, v);
+    if (lazy) {
+      const double alpha = os[vobj[v]].alpha;
+      R4<R> q = p[v];
+      x = mk3(fma(alpha, double(q.x), x.x), fma(alpha, double(q.y), x.y), fma(alpha, double(q.z), x.z));
+    }
+    return x;
+  }
+};
+
 template <typename R>
 struct PosReader {
   const double4* xsrc;   // x_{k-1} (lazy) or x_k (direct)

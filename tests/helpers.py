@@ -4,7 +4,7 @@ import numpy as np
 
 
 def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_max=None, eps=None, term=None,
-             rest_exclude=True, chunk=0, cell=None, beta="dk"):
+             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False):
     import paper_2405_08001_amd as P
     ctx = P.Context(0, precision, chunk=chunk)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
@@ -14,7 +14,7 @@ def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_ma
     term = {"delta_e": P.TERM_DELTA_E, "grad_rel": P.TERM_GRAD_REL,
             "grad_abs": P.TERM_GRAD_ABS}[sc.term if term is None else term]
     sflags = (P.BARRIER_FULL if barrier_full else 0) | (P.ALPHA_INF_COMPONENT if alpha_component else 0) | \
-        P.BETA_RULES[beta]
+        P.BETA_RULES[beta] | (P.SPLIT_OBJECTS if split else 0)
     ctx.pncg_set_solver(sc.iter_max if iter_max is None else iter_max, sc.eps if eps is None else eps, term,
                         sc.gravity, sflags)
     if len(sc.fixed):

@@ -138,6 +138,63 @@ def test_fixed_iterations_match_oracle(which, K, precision):
     assert rel(vg, vo) <= (1e-9 if precision == 0 else 1e-3)
 
 
+def _two_apart():
+    Xa, Ta = scenes.hex_grid(3, 3, 3, 0.01, origin=(0.0, 0.0, 5e-4))
+    Xb, Tb = scenes.hex_grid(3, 3, 3, 0.01, origin=(0.2, 0.0, 0.02))
+    X, tets, oid = scenes.merge_meshes([(Xa, Ta), (Xb, Tb)])
+    X = X + np.random.default_rng(12).uniform(-2e-4, 2e-4, X.shape)
+    E = np.where(np.arange(len(tets)) < len(Ta), 1e5, 1e6)
+    sc = scenes.configs._scene(X, tets, E=E, nu=0.4, rho=1000.0, planes=[[0.0, 0.0, 1.0, 0.0]], dhat=1e-3,
+                               kappa=1e4, h=1.0 / 60.0, object_id=oid, self_contact=True, cell=4e-3)
+    v0 = np.zeros_like(X)
+    v0[oid == 0, 2] = -0.1
+    return sc, sc.X.copy(), v0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("which", ["stack", "apart", "cube"])
+def test_split_step_matches_oracle(which, precision):
+    """Splitting computation (Sec. 5.2): a beta, direction and step size per
+    object.  10 fixed iterations against the oracle's split step: the stacked
+    cubes (pairs between the two objects), two cubes apart (independent
+    objects) and one cube (one object: the unsplit step)."""
+    from oracle import pncg
+    _say(f"split step {which} precision={precision}")
+    sc, x0, v0 = {"stack": _stack_drop, "apart": _two_apart, "cube": _cube_drop}[which]()
+    K = 10
+    prob = make_problem(sc)
+    xo, _, st = pncg.step(prob, x0, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", split=True)
+    ctx = make_ctx(sc, precision, iter_max=K, eps=0.0, term="delta_e", split=True)
+    xg, _, sg = ctx.pncg_step(x0, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - x0, xo - x0)
+    bx, bdx = (1e-12, 1e-9) if precision == 0 else (1e-6, 1e-3)
+    if precision == 1:
+        xq = x0 * (1.0 + 2.0 ** -24)
+        xp, _, _ = pncg.step(prob, xq, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", split=True)
+        bx = max(bx, 4.0 * rel(xp, xo))
+        bdx = max(bdx, 4.0 * rel(xp - xq, xo - x0))
+    _say(f"  iters oracle={st.iters} gpu={sg['iters']} hits {st.alpha_upper_hits}/{sg['alpha_upper_hits']} "
+         f"rel_x={rx:.3e} (bar {bx:.1e}) rel_dx={rdx:.3e} (bar {bdx:.1e})")
+    assert sg["iters"] == st.iters == K
+    assert sg["alpha_upper_hits"] == st.alpha_upper_hits
+    assert rx <= bx and rdx <= bdx
+    if which == "cube":        # one object: the unsplit step to rounding
+        xu, _, _ = make_ctx(sc, precision, iter_max=K, eps=0.0, term="delta_e").pncg_step(x0, v0, sc.h)
+        assert rel(xg - x0, xu - x0) <= (1e-9 if precision == 0 else 1e-4)
+
+
+def test_split_needs_contiguous_objects():
+    import paper_2405_08001_amd as P
+    sc, _, _ = _stack_drop()
+    ctx = P.Context(0, 0)
+    oid = sc.object_id[::-1].copy()           # decreasing ids: not contiguous ranges in order
+    ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, oid)
+    ctx.pncg_set_material(sc.E, sc.nu, sc.rho)
+    with pytest.raises(P.PncgError):
+        ctx.pncg_set_solver(10, 0.0, P.TERM_DELTA_E, sc.gravity, P.SPLIT_OBJECTS)
+    ctx.pncg_set_solver(10, 0.0, P.TERM_DELTA_E, sc.gravity, 0)
+
+
 def test_mean_boundary_edge_matches_numpy():
     """The larger-dhat strategy's reference length (Sec. 5.1): the mean rest
     length of the surface edges."""
