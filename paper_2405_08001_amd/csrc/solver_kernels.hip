@@ -76,6 +76,34 @@ struct FirstPro {
   int work;          // evaluate the iteration's terms at x_k
 };
 
+// Sums (kind 0) or maxima (kind 1) of N per-object values over all objects,
+// by the block's first wave (lane l takes objects l, l + 64, ...) in a fixed
+// order, then handed to every thread through LDS.  Called by all threads.
+template <int N, typename F>
+__device__ __forceinline__ void over_objects(int nObj, const int (&kind)[N], F&& get, double (&out)[N],
+                                             double* sh) {
+  if (threadIdx.x < kWave) {
+    double acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0.0;
+    for (int o = threadIdx.x; o < nObj; o += kWave) {
+      double val[N];
+      get(o, val);
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] = kind[i] ? fmax(acc[i], val[i]) : acc[i] + val[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      acc[i] = kind[i] ? wave_max(acc[i]) : wave_sum(acc[i]);
+      if (threadIdx.x == 0) sh[i] = acc[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = sh[i];
+  __syncthreads();
+}
+
 // SPLIT: one step size per object (Sec. 5.2), taken from the per-object
 // scalars of iteration k - 1; dE is their sum and the displacement bound
 // grows by the largest alpha_o max_{v in o} |p_v|.
@@ -120,14 +148,19 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
     dmove = alpha * pmv;
   } else {
     const ObjScal* os = A.oscal + (size_t)(k - 1) * A.nObj;
-    for (int o = 0; o < A.nObj; ++o) {
+    const int kind[4] = {0, 0, 1, 1};
+    double r[4];
+    over_objects<4>(A.nObj, kind, [&](int o, double (&val)[4]) {
       const ObjScal q = os[o];
-      if (!q.moving) continue;
-      if (!isfinite(q.alpha)) unbounded = true;
-      dE += q.dE;
-      hits += q.a_up;
-      dmove = fmax(dmove, q.alpha * q.pmv);
-    }
+      val[0] = q.moving ? q.dE : 0.0;
+      val[1] = q.moving ? double(q.a_up) : 0.0;
+      val[2] = q.moving ? q.alpha * q.pmv : 0.0;
+      val[3] = (q.moving && !isfinite(q.alpha)) ? 1.0 : 0.0;
+    }, r, sh);
+    dE = r[0];
+    hits = int(r[1]);
+    dmove = r[2];
+    unbounded = r[3] > 0.0;
   }
   IterScal s{};
   s.a_up = prev.a_up + hits;
@@ -485,13 +518,17 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   double beta = 0.0, gTp = 0.0;
   bool any_dir = false;
   if constexpr (SPLIT) {
-    gg = 0.0; gPg = 0.0;
-    for (int o = 0; o < A.nObj; ++o) {
-      gg += os[o].gg;
-      gPg += os[o].gPg;
-      gTp += os[o].gTp;
-      any_dir |= os[o].gTp != 0.0;
-    }
+    const int kind[4] = {0, 0, 0, 1};
+    double q[4];
+    over_objects<4>(A.nObj, kind, [&](int o, double (&val)[4]) {
+      const ObjScal w = os[o];
+      val[0] = w.gg;
+      val[1] = w.gPg;
+      val[2] = w.gTp;
+      val[3] = w.gTp != 0.0 ? 1.0 : 0.0;
+    }, q, sh);
+    gg = q[0]; gPg = q[1]; gTp = q[2];
+    any_dir = q[3] > 0.0;
   }
   const double gnorm = sqrt(gg);
   const double g0 = k == 0 ? gnorm : A.status->g0;
@@ -650,7 +687,20 @@ __global__ void __launch_bounds__(kSBlock) k_objred_grad(Args<R> A, int k) {
   if (s.stop || s.pause) return;
   const int o = blockIdx.x;
   double d[6] = {0, 0, 0, 0, 0, 0};
-  for (int v = A.voff[o] + threadIdx.x; v < A.voff[o + 1]; v += kSBlock)
+  const int v0 = A.voff[o], v1 = A.voff[o + 1];
+  int v = v0 + threadIdx.x;
+  for (; v + 3 * kSBlock < v1; v += 4 * kSBlock) {   // four independent loads in flight
+    double t[4][6];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) t[u][i] = A.vdots[6 * (size_t)(v + u * kSBlock) + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) d[i] += t[u][i];
+  }
+  for (; v < v1; v += kSBlock)
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] += A.vdots[6 * (size_t)v + i];
   const int kind[6] = {0, 0, 0, 0, 0, 0};
@@ -682,8 +732,24 @@ __global__ void __launch_bounds__(kSBlock) k_objred_dir(Args<R> A, int k) {
   if (s.stop || s.pause || s.dir_stop) return;
   const int o = blockIdx.x;
   double r[4] = {0, 0, 0, 0};
-  for (int e = A.toff[o] + threadIdx.x; e < A.toff[o + 1]; e += kSBlock) r[0] += A.tphp[e];
-  for (int v = A.voff[o] + threadIdx.x; v < A.voff[o + 1]; v += kSBlock) {
+  const int t0 = A.toff[o], t1 = A.toff[o + 1];
+  int e = t0 + threadIdx.x;
+  for (; e + 3 * kSBlock < t1; e += 4 * kSBlock) {   // four independent loads in flight
+    const double a0 = A.tphp[e], a1 = A.tphp[e + kSBlock], a2 = A.tphp[e + 2 * kSBlock], a3 = A.tphp[e + 3 * kSBlock];
+    r[0] += a0; r[0] += a1; r[0] += a2; r[0] += a3;
+  }
+  for (; e < t1; e += kSBlock) r[0] += A.tphp[e];
+  const int v0 = A.voff[o], v1 = A.voff[o + 1];
+  int v = v0 + threadIdx.x;
+  for (; v + kSBlock < v1; v += 2 * kSBlock) {
+    const double* a = A.vphp + 3 * (size_t)v;
+    const double* b = A.vphp + 3 * (size_t)(v + kSBlock);
+    const double a0 = a[0], a1 = a[1], a2 = a[2], b0 = b[0], b1 = b[1], b2 = b[2];
+    r[1] += a0; r[1] += b0;
+    r[2] = fmax(r[2], fmax(a1, b1));
+    r[3] = fmax(r[3], fmax(a2, b2));
+  }
+  for (; v < v1; v += kSBlock) {
     r[1] += A.vphp[3 * (size_t)v];
     r[2] = fmax(r[2], A.vphp[3 * (size_t)v + 1]);
     r[3] = fmax(r[3], A.vphp[3 * (size_t)v + 2]);
