@@ -30,6 +30,15 @@
 
 namespace pncg {
 
+// threads per block of the vertex-centric sweep: it is latency bound and
+// gains from more resident waves per compute unit than the 256-thread blocks
+// of the other kernels give (the grid, and so the number of partials, stays
+// the same).  The direction kernel measured slower at 512.
+#ifndef PNCG_GRAD_BLOCK
+#define PNCG_GRAD_BLOCK 512
+#endif
+constexpr int kGradBlock = PNCG_GRAD_BLOCK;
+
 template <typename R>
 __device__ __forceinline__ double4* xbuf(const Args<R>& A, int k) { return (k & 1) ? A.x1 : A.x0; }
 template <typename R>
@@ -107,7 +116,7 @@ __device__ __forceinline__ void over_objects(int nObj, const int (&kind)[N], F&&
 // SPLIT: one step size per object (Sec. 5.2), taken from the per-object
 // scalars of iteration k - 1; dE is their sum and the displacement bound
 // grows by the largest alpha_o max_{v in o} |p_v|.
-template <typename R, bool SPLIT>
+template <typename R, bool SPLIT, int BS = kSBlock>
 __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh) {
   FirstPro fp{0.0, 0, 1};
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -135,7 +144,7 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
   if (!SPLIT) {
     const int kind[3] = {0, 1, 1};
     double r[3];
-    reduce_partials<3>(A.part_dir, 4, A.grid, kind, r, sh);
+    reduce_partials<3, BS>(A.part_dir, 4, A.grid, kind, r, sh);
     const double pHp = r[0], pmv = r[1], pmc = r[2];
     const double gTp = prev.gTp;
     const double abar = pHp > 0.0 ? -gTp / pHp : HUGE_VAL;
@@ -225,12 +234,12 @@ __device__ __forceinline__ typename FirstPos<R, SPLIT>::type first_pos(const Arg
 }
 
 // x_k = x_{k-1} + alpha p_k on this block's vertex slice.
-template <typename R, bool SPLIT>
+template <typename R, bool SPLIT, int BS = kSBlock>
 __device__ __forceinline__ void apply_update(const Args<R>& A, int k, const FirstPro& fp, double4* xcur,
                                              const double4* xprev, const R4<R>* pk) {
   const auto pos = first_pos<R, SPLIT>(A, k, fp, xprev, pk);
   const Slice sv = block_slice(A.nV);
-  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) st3(xcur, v, pos(v));
+  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += BS) st3(xcur, v, pos(v));
 }
 
 // ----------------------------------------------------------- narrow phase
@@ -384,12 +393,13 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
-template <typename R, int MODE, bool SPLIT = false>
-__global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
-  __shared__ double sh[kSWaves * 8];
+template <typename R, int MODE, bool SPLIT = false, int BS = kGradBlock>
+__global__ void __launch_bounds__(BS, 4) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
+  constexpr int NW = BS / kWave;
+  __shared__ double sh[NW * 8];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
-    fp = first_prologue<R, SPLIT>(A, k, mode, sh);
+    fp = first_prologue<R, SPLIT, BS>(A, k, mode, sh);
   } else if (MODE == kGradDirect) {
     const IterScal s = A.scal[k];
     if (s.stop || s.pause) return;
@@ -401,13 +411,13 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
   const R4<R>* pk = pbuf(A, k);
   if (MODE == kGradFirst && fp.materialize && !fp.work) {
     // stop test passed: only apply the last update
-    apply_update<R, SPLIT>(A, k, fp, xcur, xprev, pk);
+    apply_update<R, SPLIT, BS>(A, k, fp, xcur, xprev, pk);
     return;
   }
   if (!fp.work) return;
   const auto pos = first_pos<R, SPLIT>(A, k, fp, fp.materialize ? xprev : xcur, pk);
   double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int w = (int)swv.begin + (threadIdx.x >> 6); w < swv.end; w += kSWaves) {
+  for (int w = (int)swv.begin + (threadIdx.x >> 6); w < swv.end; w += NW) {
     const int idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
@@ -484,7 +494,7 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
   }
   if (MODE == kGradQuery) return;
   const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 1};
-  block_reduce<8>(dots, kind, sh);
+  block_reduce<8, BS>(dots, kind, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) A.part_grad[blockIdx.x * 8 + i] = dots[i];
@@ -494,22 +504,22 @@ __global__ void __launch_bounds__(kSBlock) k_grad(Args<R> A, int k, int mode, do
 // ------------------------------------------------------ direction + pHp
 // SPLIT: beta per object (from k_objred_grad), and the p^T H p terms go
 // per tet, per vertex and per object (pairs) for k_objred_dir.
-template <typename R, bool SPLIT = false>
-__global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
-  __shared__ double sh[kSWaves * 8];
+template <typename R, bool SPLIT = false, int BS = kSBlock>
+__global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
+  __shared__ double sh[BS / kWave * 8];
   const IterScal s = A.scal[k];
   if (s.stop || s.pause) return;
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   double r[8];
   {
     const int kind[8] = {0, 0, 0, 0, 0, 0, 0, 1};
-    reduce_partials<8>(A.part_grad, 8, A.grid, kind, r, sh);
+    reduce_partials<8, BS>(A.part_grad, 8, A.grid, kind, r, sh);
   }
   double nact = r[6];
   if (A.self) {
     const int kind[1] = {0};
     double q[1];
-    reduce_partials<1>(A.part_narrow, 1, A.grid, kind, q, sh);
+    reduce_partials<1, BS>(A.part_narrow, 1, A.grid, kind, q, sh);
     nact += q[0];
   }
   const ObjScal* os = A.oscal + (size_t)k * A.nObj;
@@ -572,7 +582,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   // tets: element p^T H p with p recomputed at the four corners
   double el = 0.0;
   const Slice st = block_slice(A.nT);
-  for (int e = (int)st.begin + threadIdx.x; e < st.end; e += kSBlock) {
+  for (int e = (int)st.begin + threadIdx.x; e < st.end; e += BS) {
     const ElemRec<R> rec = A.elem[e];
     const R rb = beta_of(rec.v[0]);      // a tet lies in one object
     V3<R> P[4];
@@ -592,7 +602,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
   const Slice sv = block_slice(A.nV);
-  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += kSBlock) {
+  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += BS) {
     V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), beta_of(v));
     str<R>(pn, v, p);
     const double px = p.x, py = p.y, pz = p.z;
@@ -626,7 +636,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
     PosReader<R> pos{xk, pk, 0.0, 0};
     const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
     const Slice sq = block_slice(nq);
-    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
+    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += BS) {
       int iv[4];
       Closest c;
       if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
@@ -669,7 +679,7 @@ __global__ void __launch_bounds__(kSBlock) k_dir(Args<R> A, int k) {
   if constexpr (SPLIT) return;
   double v[3] = {acc_pHp, pmv, pmc};
   const int kind[3] = {0, 1, 1};
-  block_reduce<3>(v, kind, sh);
+  block_reduce<3, BS>(v, kind, sh);
   if (threadIdx.x == 0) {
     A.part_dir[blockIdx.x * 4 + 0] = v[0];
     A.part_dir[blockIdx.x * 4 + 1] = v[1];
@@ -1023,22 +1033,22 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_narrow<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
   } else if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode,
+    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, mode,
                        (double*)nullptr, (double*)nullptr);
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode, (double*)nullptr,
+    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, mode, (double*)nullptr,
                        (double*)nullptr);
   }
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0,
+    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, 0,
                        (double*)nullptr, (double*)nullptr);
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, 0, (double*)nullptr,
+    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, 0, (double*)nullptr,
                        (double*)nullptr);
   }
 }
@@ -1062,7 +1072,7 @@ void launch_load_query(const Args<R>& A, const double* x, const double* xt, cons
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kSBlock), 0, s, A, 0, 0, g, d);
+  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kGradBlock), 0, s, A, 0, 0, g, d);
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {

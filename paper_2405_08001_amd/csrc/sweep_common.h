@@ -43,19 +43,19 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kind)[N
 }
 
 // Re-reduce the per-block partials [n][stride] of the previous launch.
-template <int N>
+template <int N, int BS = kSBlock>
 __device__ __forceinline__ void reduce_partials(const double* part, int stride, int n, const int (&kind)[N],
                                                 double (&out)[N], double* sh) {
 #pragma unroll
   for (int i = 0; i < N; ++i) out[i] = kind[i] ? 0.0 : 0.0;
-  for (int j = threadIdx.x; j < n; j += kSBlock) {
+  for (int j = threadIdx.x; j < n; j += BS) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       double v = part[j * stride + i];
       out[i] = kind[i] ? fmax(out[i], v) : out[i] + v;
     }
   }
-  block_reduce<N>(out, kind, sh);
+  block_reduce<N, BS>(out, kind, sh);
 }
 
 // ------------------------------------------------------- work partitioning
