@@ -26,6 +26,10 @@ namespace pncg {
 
 namespace {
 
+// threads per block of the fused CG iteration (512 measured slower: the
+// register cap it needs makes the sweep spill)
+constexpr int kCgBlock = 256;
+
 __device__ __forceinline__ int read_stopped(const CgStatus* st) {
   __shared__ int s_stop;
   if (threadIdx.x == 0) s_stop = *reinterpret_cast<const volatile int*>(&st->stopped);
@@ -126,13 +130,14 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
 // p_{k-1} (lambda in place: only that lane touches it), and adds the partials
 // of launch k, with r_k = diag z_k (the residual itself is not stored).
 // k_adj_init writes {z_0, 0} into zw[1] and the partials r_0.z_0, |r_0|^2.
-__global__ void __launch_bounds__(kSBlock) k_cg_fused(Args<double> A, AdjArgs C, int k) {
-  __shared__ double sh[kSWaves * 6];
+__global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C, int k) {
+  constexpr int NW = kCgBlock / kWave;
+  __shared__ double sh[NW * 6];
   if (read_stopped(C.status)) return;
   double red6[6];
   {
     const int kind[6] = {0, 0, 0, 0, 0, 0};
-    reduce_partials<6>(C.part_f, 8, A.grid, kind, red6, sh);
+    reduce_partials<6, kCgBlock>(C.part_f, 8, A.grid, kind, red6, sh);
   }
   const double pq = red6[0], rz = red6[1], rr = red6[2], rw = red6[3], qz = red6[4], qw = red6[5];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -183,7 +188,7 @@ __global__ void __launch_bounds__(kSBlock) k_cg_fused(Args<double> A, AdjArgs C,
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const Slice sl = block_slice(A.nWaves);
   double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (long long w = sl.begin + wave; w < sl.end; w += kSWaves) {
+  for (long long w = sl.begin + wave; w < sl.end; w += NW) {
     const long long idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
@@ -248,7 +253,7 @@ __global__ void __launch_bounds__(kSBlock) k_cg_fused(Args<double> A, AdjArgs C,
   }
   {
     const int kind[6] = {0, 0, 0, 0, 0, 0};
-    block_reduce<6>(acc6, kind, sh);
+    block_reduce<6, kCgBlock>(acc6, kind, sh);
   }
   if (threadIdx.x == 0) {
     double* f = C.part_f + 8 * blockIdx.x;
@@ -436,7 +441,7 @@ void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar
 
 void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fused, hipStream_t s) {
   if (fused) {
-    hipLaunchKernelGGL(k_cg_fused, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+    hipLaunchKernelGGL(k_cg_fused, dim3(A.grid), dim3(kCgBlock), 0, s, A, C, k);
     return;
   }
   hipLaunchKernelGGL(k_cg_dir, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
