@@ -30,14 +30,20 @@
 
 namespace pncg {
 
-// threads per block of the vertex-centric sweep: it is latency bound and
+// Threads per block of the vertex-centric sweep: it is latency bound and
 // gains from more resident waves per compute unit than the 256-thread blocks
 // of the other kernels give (the grid, and so the number of partials, stays
-// the same).  The direction kernel measured slower at 512.
-#ifndef PNCG_GRAD_BLOCK
-#define PNCG_GRAD_BLOCK 512
-#endif
-constexpr int kGradBlock = PNCG_GRAD_BLOCK;
+// the same).  Measured on the 110k-tet pile: float 384 (19.1 us; 512 needs a
+// register cap that spills), double 512 with four waves per SIMD (21.8 us;
+// 384 took 32 us).  The direction kernel measured slower at 512.
+template <typename R>
+struct GradBlock {
+  static constexpr int value = 384, min_waves = 1;
+};
+template <>
+struct GradBlock<double> {
+  static constexpr int value = 512, min_waves = 4;
+};
 
 template <typename R>
 __device__ __forceinline__ double4* xbuf(const Args<R>& A, int k) { return (k & 1) ? A.x1 : A.x0; }
@@ -393,8 +399,8 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
-template <typename R, int MODE, bool SPLIT = false, int BS = kGradBlock>
-__global__ void __launch_bounds__(BS, 4) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
+template <typename R, int MODE, bool SPLIT = false, int BS = GradBlock<R>::value>
+__global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
   __shared__ double sh[NW * 8];
   FirstPro fp{0.0, 0, 1};
@@ -1033,22 +1039,22 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_narrow<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
   } else if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, mode,
+    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, mode,
                        (double*)nullptr, (double*)nullptr);
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, mode, (double*)nullptr,
+    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
                        (double*)nullptr);
   }
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, 0,
+    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, 0,
                        (double*)nullptr, (double*)nullptr);
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(kGradBlock), 0, s, A, k, 0, (double*)nullptr,
+    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
                        (double*)nullptr);
   }
 }
@@ -1072,7 +1078,7 @@ void launch_load_query(const Args<R>& A, const double* x, const double* xt, cons
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(kGradBlock), 0, s, A, 0, 0, g, d);
+  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d);
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
