@@ -553,6 +553,17 @@ def main():
         fips = f["iters"] / f["seconds"]
         out["fp64"] = {"iters_per_s": round(fips, 1), "ms_per_frame": round(1e3 * f["seconds"] / f["frames"], 4),
                        "us_per_iter": round(1e6 / fips, 3)}
+        t8, v8, a8, q8 = BYTES["iter"]["fp64"]
+        b8 = t8 * sc.nT + v8 * sc.nV + a8 * f["mean_active"] + q8 * f["mean_cand"]
+        out["fp64"]["iter_roofline"] = {"bytes_per_iter": int(b8), "achieved_GBps": round(b8 * fips / 1e9, 1),
+                                        "frac": round(b8 * fips / HBM_PEAK, 4)}
+        fprof = {k: v for k, v in f["prof"].items() if v[1] > 0}
+        if "grad" in fprof:
+            gus = fprof["grad"][0] / fprof["grad"][1]
+            kt, kv, kq = KERNEL_BYTES["grad"]["fp64"]
+            gb = kt * sc.nT + kv * sc.nV + kq * f["mean_cand"]
+            out["fp64"]["grad_roofline"] = {"achieved": round(gb / (gus * 1e-6) / 1e9, 1), "avg_launch_us": round(gus, 3),
+                                            "bytes_per_launch": int(gb), "frac": round(gb / (gus * 1e-6) / HBM_PEAK, 4)}
         out["mixed_vs_fp64_speedup"] = round(ips / fips, 3)
     if not args.no_batched:
         log("batched: 256 scenes ...")
