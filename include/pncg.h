@@ -203,6 +203,13 @@ int pncg_set_tuning(pncg_ctx* ctx, double skin, int32_t chunk);
  * 1.5 dhat at rest.  E_STATE before pncg_set_mesh. */
 int pncg_mean_boundary_edge(pncg_ctx* ctx, double* out);
 
+/* on = 1: each pncg_adjoint_step* call starts its CG from the lambda of the
+ * previous call on this context (consecutive steps of a backward pass have
+ * close lambdas), with r = b - H lambda; the stop rule stays relative to
+ * |b|.  Without self contact only (otherwise ignored); the first call after
+ * pncg_set_mesh starts from 0.  Default 0. */
+int pncg_set_adjoint_warm_start(pncg_ctx* ctx, int32_t on);
+
 /* Prescribed vertices for the following steps: idx [n] (distinct),
  * target [n][3] positions they take at the start of the next step (their
  * gradient, direction and update are zero during it).  n = 0 clears. */

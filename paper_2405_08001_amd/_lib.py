@@ -33,7 +33,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
            "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
            "pncg_set_profiling", "pncg_get_profile", "pncg_adjoint_step", "pncg_adjoint_step_dev",
-           "pncg_set_tuning", "pncg_mean_boundary_edge",
+           "pncg_set_tuning", "pncg_mean_boundary_edge", "pncg_set_adjoint_warm_start",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
@@ -84,6 +84,7 @@ def _load():
         "pncg_set_dirichlet": (I32, [P, I32, P, P]),
         "pncg_set_tuning": (I32, [P, D, I32]),
         "pncg_mean_boundary_edge": (I32, [P, P]),
+        "pncg_set_adjoint_warm_start": (I32, [P, I32]),
         "pncg_step": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_step_dev": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_energy": (I32, [P, P, P, D, P]),
@@ -188,6 +189,9 @@ class Context:
 
     def pncg_set_tuning(self, skin=0.0, chunk=0):
         self._check(_L.pncg_set_tuning(self._h, float(skin), int(chunk)))
+
+    def pncg_set_adjoint_warm_start(self, on):
+        self._check(_L.pncg_set_adjoint_warm_start(self._h, 1 if on else 0))
 
     def pncg_mean_boundary_edge(self):
         out = C.c_double()

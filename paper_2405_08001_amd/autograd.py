@@ -36,9 +36,10 @@ class Simulation:
     checkpoint  keep the state every ``checkpoint`` steps; the backward pass
                 recomputes the steps in between
     cg_tol, cg_max   adjoint CG stopping rule (relative residual, cap)
+    warm_start  start each step's adjoint CG from the previous step's lambda
     """
 
-    def __init__(self, ctx, nu, rho, h, steps, checkpoint=5, cg_tol=1e-10, cg_max=20000):
+    def __init__(self, ctx, nu, rho, h, steps, checkpoint=5, cg_tol=1e-10, cg_max=20000, warm_start=True):
         if ctx.precision != _lib.FP64:
             raise ValueError("differentiation needs a float64 context")
         if steps < 1 or checkpoint < 1:
@@ -51,6 +52,7 @@ class Simulation:
         self.checkpoint = int(checkpoint)
         self.cg_tol = float(cg_tol)
         self.cg_max = int(cg_max)
+        self.warm_start = bool(warm_start)
         self.forward_stats = []
         self.adjoint_stats = []
         self.recomputed_steps = 0
@@ -93,6 +95,7 @@ class _Rollout(torch.autograd.Function):
         sim, ck = fctx.sim, fctx.ck
         ctx = sim.ctx
         sim._set_E(fctx.E_np)
+        ctx.pncg_set_adjoint_warm_start(sim.warm_start)
         x_ref = ck[0][0]
         xbar = torch.zeros_like(x_ref) if gx is None else gx.detach().to(torch.float64).contiguous().clone()
         vbar = torch.zeros_like(x_ref) if gv is None else gv.detach().to(torch.float64).contiguous().clone()

@@ -43,8 +43,11 @@ struct AdjArgs {
   int max_iter;
 };
 
-// b = xbar + vbar / h, r = b, lambda = 0, z = r / diag, partial sums.
-void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar,
+// b = xbar + vbar / h, r = b, lambda = 0, z = r / diag, partial sums; warm
+// (no pair terms): start from the lambda already in C.lam, r = b - H lambda.
+// The caller clears status->stopped before a warm start (the Hv sweep
+// checks it).
+void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar, bool warm,
                      hipStream_t s);
 // CG iteration k.  fused (no pair terms): one launch that finishes update
 // k-1 and forms z_k and p_k on the fly wherever the Hv sweep needs them;

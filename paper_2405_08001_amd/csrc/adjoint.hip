@@ -73,9 +73,12 @@ __device__ __forceinline__ bool cg_begin(const Args<double>& A, const AdjArgs& C
 
 }  // namespace
 
+// warm: lambda holds a starting guess and q = H lambda (k_cg_hv on it), so
+// r = b - q; otherwise lambda = 0 and r = b.  The stop rule's reference
+// |b|^2 goes to slot 6 of the fused partials.
 __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C, const double* xbar,
-                                                      const double* vbar) {
-  __shared__ double sh[kSWaves * 2];
+                                                      const double* vbar, int warm) {
+  __shared__ double sh[kSWaves * 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     C.status->stopped = 0;
     C.status->iters = 0;
@@ -84,26 +87,33 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
     C.status->rr = 0.0;
   }
   const double ih = 1.0 / A.h;
-  double rz = 0.0, rr = 0.0;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
   const Slice sl = block_slice(A.nV);
   for (long long i = sl.begin + threadIdx.x; i < sl.end; i += kSBlock) {
     const int v = (int)i;
     const bool fixed = A.vflag[v] & kFixed;
     V3<double> b = mk3(0.0, 0.0, 0.0);
     if (!fixed) b = row3(xbar, v) + ih * row3(vbar, v);
+    bb += dot(b, b);
+    V3<double> r = b;
+    if (warm) {
+      const V3<double> q = ld3(C.q, v);
+      r = mk3(b.x - q.x, b.y - q.y, b.z - q.z);
+    } else {
+      st3(C.lam, v, mk3(0.0, 0.0, 0.0));
+    }
     const V3<double> d = row3(C.diag, v);
-    const V3<double> z = mk3(b.x / d.x, b.y / d.y, b.z / d.z);
-    st3(C.r, v, b);
+    const V3<double> z = mk3(r.x / d.x, r.y / d.y, r.z / d.z);
+    st3(C.r, v, r);
     st3(C.z, v, z);
-    st3(C.lam, v, mk3(0.0, 0.0, 0.0));
     st3(C.zw[1], 2 * v, z);                      // {z_0, w = 0} for the fused form
     st3(C.zw[1], 2 * v + 1, mk3(0.0, 0.0, 0.0));
-    rz += dot(b, z);
-    rr += dot(b, b);
+    rz += dot(r, z);
+    rr += dot(r, r);
   }
-  double red[2] = {rz, rr};
-  const int kind[2] = {0, 0};
-  block_reduce<2>(red, kind, sh);
+  double red[3] = {rz, rr, bb};
+  const int kind[3] = {0, 0, 0};
+  block_reduce<3>(red, kind, sh);
   if (threadIdx.x == 0) {
     C.part_rz[2 * blockIdx.x] = red[0];
     C.part_rz[2 * blockIdx.x + 1] = red[1];
@@ -112,6 +122,7 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
     f[1] = red[0];
     f[2] = red[1];
     f[3] = f[4] = f[5] = 0.0;
+    f[6] = red[2];
   }
 }
 
@@ -132,17 +143,18 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
 // k_adj_init writes {z_0, 0} into zw[1] and the partials r_0.z_0, |r_0|^2.
 __global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C, int k) {
   constexpr int NW = kCgBlock / kWave;
-  __shared__ double sh[NW * 6];
+  __shared__ double sh[NW * 7];
   if (read_stopped(C.status)) return;
-  double red6[6];
+  double red6[7];
   {
-    const int kind[6] = {0, 0, 0, 0, 0, 0};
-    reduce_partials<6, kCgBlock>(C.part_f, 8, A.grid, kind, red6, sh);
+    const int kind[7] = {0, 0, 0, 0, 0, 0, 0};
+    reduce_partials<7, kCgBlock>(C.part_f, 8, A.grid, kind, red6, sh);
   }
   const double pq = red6[0], rz = red6[1], rr = red6[2], rw = red6[3], qz = red6[4], qw = red6[5];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  if (k == 0 && lead) C.status->bb = rr;
-  const double bb = (k == 0) ? rr : C.status->bb;
+  // the stop rule's reference: |b|^2 from k_adj_init (slot 6)
+  if (k == 0 && lead) C.status->bb = red6[6];
+  const double bb = (k == 0) ? red6[6] : C.status->bb;
   auto stop = [&](int reason) {
     if (lead) {
       C.status->iters = k > 0 ? k - 1 : 0;
@@ -258,6 +270,7 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C
   if (threadIdx.x == 0) {
     double* f = C.part_f + 8 * blockIdx.x;
     for (int i = 0; i < 6; ++i) f[i] = acc6[i];
+    f[6] = 0.0;
   }
 }
 
@@ -434,9 +447,15 @@ __global__ void __launch_bounds__(kSBlock) k_adj_out(Args<double> A, AdjArgs C, 
   }
 }
 
-void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar,
+void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar, const double* vbar, bool warm,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_init, dim3(A.grid), dim3(kSBlock), 0, s, A, C, xbar, vbar);
+  if (warm) {
+    // q = H lambda with the Hv sweep reading lambda as its direction
+    AdjArgs W = C;
+    W.pbuf[0] = C.lam;
+    hipLaunchKernelGGL(k_cg_hv, dim3(A.grid), dim3(kSBlock), 0, s, A, W, 0);
+  }
+  hipLaunchKernelGGL(k_adj_init, dim3(A.grid), dim3(kSBlock), 0, s, A, C, xbar, vbar, warm ? 1 : 0);
 }
 
 void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fused, hipStream_t s) {

@@ -117,6 +117,8 @@ struct pncg_ctx {
   int grid = 1;
   // adjoint (allocated on first use)
   bool adj_ready = false;
+  bool adj_warm = false;       // start each adjoint CG from the previous call's lambda
+  bool adj_lam_valid = false;  // d_lam holds a solution of this mesh
   double4 *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_pa = nullptr, *d_pb = nullptr, *d_q = nullptr,
           *d_zw = nullptr;
   double *d_adiag = nullptr, *d_agrad = nullptr, *d_E = nullptr;
@@ -740,8 +742,10 @@ int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, co
   C.status = c->d_cgst;
   C.tol2 = cg_tol * cg_tol;
   C.max_iter = cg_max;
-  launch_adj_init(A, C, xbar, vbar, c->stream);
   const bool fused = !A.self;
+  const bool warm = fused && c->adj_warm && c->adj_lam_valid;
+  if (warm) HIPCHK(c, hipMemsetAsync(&c->d_cgst->stopped, 0, sizeof(int), c->stream));
+  launch_adj_init(A, C, xbar, vbar, warm, c->stream);
   const int last = fused ? cg_max + 1 : cg_max;   // the launch that reports the end at the latest
   int k = 0, chunk = 16;
   while (true) {
@@ -760,7 +764,11 @@ int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, co
     st->reason = cs.reason;
     st->rel_residual = cs.bb > 0.0 ? std::sqrt(cs.rr / cs.bb) : 0.0;
   }
-  if (cs.reason == 2) return fail(c, PNCG_E_INDEFINITE, "p^T H p <= 0 or not finite in the adjoint CG");
+  if (cs.reason == 2) {
+    c->adj_lam_valid = false;
+    return fail(c, PNCG_E_INDEFINITE, "p^T H p <= 0 or not finite in the adjoint CG");
+  }
+  c->adj_lam_valid = true;
   launch_adj_out(A, C, vbar, c->d_E, xbar_t, vbar_t, Ebar, c->stream);
   if ((rc = read_status(c))) return rc;
   if ((rc = check_status_err(c, *c->h_status))) return rc;
@@ -926,6 +934,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
   c->adj_ready = false; c->d_cgs = nullptr; c->cgs_cap = 0; c->E_uploaded = false;
+  c->adj_lam_valid = false;
   c->d_excl_pt = c->d_excl_ee = nullptr; c->n_excl_pt = c->n_excl_ee = 0;
   const size_t r4 = (c->precision == PNCG_MIXED) ? sizeof(float4) : sizeof(double4);
   const int gmax = kMaxGrid;
@@ -1099,6 +1108,13 @@ int pncg_mean_boundary_edge(pncg_ctx* c, double* out) {
     lsum += std::sqrt(l2);
   }
   *out = c->nE > 0 ? lsum / c->nE : 0.0;
+  return PNCG_OK;
+}
+
+int pncg_set_adjoint_warm_start(pncg_ctx* c, int32_t on) {
+  if (!c) return PNCG_E_INVAL;
+  if (on != 0 && on != 1) return fail(c, PNCG_E_INVAL, "on must be 0 or 1");
+  c->adj_warm = on != 0;
   return PNCG_OK;
 }
 

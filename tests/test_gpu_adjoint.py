@@ -76,6 +76,34 @@ def test_adjoint_step_matches_oracle():
     assert rel(Eg2, 2 * Eo) <= 1e-9
 
 
+def test_adjoint_warm_start_same_solution_fewer_iterations():
+    """Starting the CG from the previous call's lambda (a nearby right-hand
+    side, as consecutive steps of a backward pass give): the same solution
+    as the oracle's direct solve, in fewer CG iterations than from zero."""
+    from oracle import adjoint
+    sc = _bar(8, 3, 3)
+    P = make_problem(sc)
+    v0 = np.zeros_like(sc.X)
+    v0[:, 2] = -0.04
+    x1, _ = adjoint.newton_solve(P, sc.X, v0, sc.h, tol=1e-12)
+    rng = np.random.default_rng(9)
+    xbar = rng.standard_normal(x1.shape)
+    vbar = rng.standard_normal(x1.shape)
+    xbar2 = xbar + 0.01 * rng.standard_normal(x1.shape)
+    xo, vo, Eo, _ = adjoint.step_adjoint(P, x1, sc.h, xbar2, vbar)
+    ctx = make_ctx(sc, 0)
+    ctx.pncg_adjoint_step(x1, sc.h, xbar, vbar, cg_tol=1e-13, cg_max=20000)
+    _, _, _, cold = ctx.pncg_adjoint_step(x1, sc.h, xbar2, vbar, cg_tol=1e-13, cg_max=20000)
+    ctx.pncg_set_adjoint_warm_start(1)
+    ctx.pncg_adjoint_step(x1, sc.h, xbar, vbar, cg_tol=1e-13, cg_max=20000)
+    xg, vg, Eg, warm = ctx.pncg_adjoint_step(x1, sc.h, xbar2, vbar, cg_tol=1e-13, cg_max=20000)
+    _say(f"warm start: cg {warm['cg_iters']} (cold {cold['cg_iters']}) res {warm['rel_residual']:.1e} "
+         f"rel xbar {rel(xg, xo):.2e} Ebar {rel(Eg, Eo):.2e}")
+    assert warm["reason"] == 0
+    assert warm["cg_iters"] < cold["cg_iters"]
+    assert rel(xg, xo) <= 1e-9 and rel(vg, vo) <= 1e-9 and rel(Eg, Eo) <= 1e-9
+
+
 def test_trajectory_gradient_matches_oracle():
     """4 steps of the small bar falling onto the floor: dL/dE through the GPU
     forward (PNCG, absolute gradient rule) and adjoint versus the oracle's Newton
