@@ -84,7 +84,7 @@ def param_gradient_matrix(prob, x, h):
     F = elastic.deformation_gradient(x, prob.tets, prob.Bmat)
     dmu = 1.0 / (2.0 * (1.0 + prob.nu))
     dlam = prob.nu / ((1.0 + prob.nu) * (1.0 - 2.0 * prob.nu))
-    ge = h * h * elastic.element_param_gradient(F, prob.b, prob.vol, dmu, dlam)   # (T,4,3)
+    ge = h * h * elastic.element_param_gradient(F, prob.b, prob.vol, dmu, dlam, prob.model)   # (T,4,3)
     T = prob.tets.shape[0]
     rows = (3 * prob.tets[:, :, None] + np.arange(3)[None, None, :]).ravel()
     cols = np.repeat(np.arange(T), 12)

@@ -1,16 +1,34 @@
-"""Neo-Hookean hyperelasticity on linear tetrahedra (Sec. 3.1).
+"""Hyperelasticity on linear tetrahedra (Sec. 3.1, and the materials of
+Table 1).
 
-The energy density is written with the invariants I2 = tr(F^T F) and
-I3 = det F (Sec. 3.1); Neo-Hookean:
-    Psi = mu/2 (I2 - 3) - mu log I3 + lam/2 (log I3)^2.
-Its Hessian with respect to F is assembled exactly as the paper's chain rule
+The energy density is written with the invariants I1 = tr S (polar
+decomposition F = R S), I2 = tr(F^T F) and I3 = det F (Sec. 3.1).  Models
+(`model` argument):
+    "nh"   Neo-Hookean (Sec. 3.1):
+           Psi = mu/2 (I2 - 3) - mu log I3 + lam/2 (log I3)^2
+    "snh"  stable Neo-Hookean (Smith et al. 2018, in the invariant form of
+           Kim and Eberle's course that Sec. 3.1 cites):
+           Psi = mu/2 (I2 - 3) - mu (I3 - 1) + lam'/2 (I3 - 1)^2,
+           lam' = lam + mu so that its small-strain limit is linear
+           elasticity with the same (mu, lam)
+    "arap" as-rigid-as-possible: Psi = mu |F - R|^2 = mu (I2 - 2 I1 + 3)
+    "fcr"  fixed corotated (Stomakhin et al. 2012):
+           Psi = mu |F - R|^2 + lam/2 (I3 - 1)^2
+R and S are those of the rotation-variant polar decomposition (R a proper
+rotation; an inverted F gives S a negative eigenvalue), so I1 is defined for
+every F.
+The Hessian with respect to F is assembled exactly as the paper's chain rule
 states it (Sec. 3.1):
     d2Psi/dF2 = sum_i (Psi_ii g_i g_i^T + Psi_i H_i),
-with g2 = 2 vec F, H2 = 2 I9, g3 = vec[f1 x f2, f2 x f0, f0 x f1] and H3 the
-block cross-product matrix, and mapped to the 12 vertex coordinates through
-vec(dF/dx) (9 x 12).  diag(H) and p^T H p are then taken from that explicit
-matrix (the "two matrix-matrix products" route the paper compares against),
-so this file contains none of the compact per-term formulas.
+with g1 = vec R, H1 = sum_i lambda_i q_i q_i^T (the twist eigenpairs of
+Kim and Eberle's course: q_i = vec(U T_i V^T) / sqrt 2 with T_i the unit
+skew matrices, lambda_i = 2 / (s_j + s_k) over the two singular values that
+T_i couples), g2 = 2 vec F, H2 = 2 I9, g3 = vec[f1 x f2, f2 x f0, f0 x f1]
+and H3 the block cross-product matrix, and mapped to the 12 vertex
+coordinates through vec(dF/dx) (9 x 12).  diag(H) and p^T H p are then taken
+from that explicit matrix (the "two matrix-matrix products" route the paper
+compares against), so this file contains none of the compact per-term
+formulas.  No model's Hessian is projected to be positive semi-definite.
 
 Discretisation readings: constant-strain tets, F = D_s D_m^{-1}; the element
 energy is V_e Psi(F_e) with V_e the rest volume; lumped mass m_v = sum over
@@ -20,8 +38,14 @@ mu = E / (2 (1 + nu)), lam = E nu / ((1 + nu)(1 - 2 nu)).
 import numpy as np
 
 
+MODELS = ("nh", "snh", "arap", "fcr")
+
+
 class InvertedElement(ValueError):
-    """A tet with det F <= 0 (log I3 undefined), or a degenerate rest tet."""
+    """A tet with det F <= 0 under the Neo-Hookean model (log I3 undefined),
+    a tet whose I1 Hessian is undefined (two singular values of the
+    rotation-variant decomposition summing to <= 0), or a degenerate rest
+    tet."""
 
 
 def lame(E, nu):
@@ -77,27 +101,84 @@ def invariants(F):
     return I2, I3
 
 
-def psi(F, mu, lam):
-    """Neo-Hookean energy density (Sec. 3.1)."""
+def _check_model(model):
+    if model not in MODELS:
+        raise ValueError(f"unknown material model {model!r}")
+
+
+def polar_rv(F):
+    """Rotation-variant SVD F = U diag(s) V^T with det U = det V = +1: the
+    sign of det F is carried by the last (smallest) singular value.  Returns
+    (U, s, V); R = U V^T, S = V diag(s) V^T, I1 = s0 + s1 + s2."""
+    U, s, Vt = np.linalg.svd(F)
+    U = U.copy()
+    s = s.copy()
+    V = np.transpose(Vt, (0, 2, 1)).copy()
+    fu = np.linalg.det(U) < 0
+    U[fu, :, 2] *= -1.0
+    s[fu, 2] *= -1.0
+    fv = np.linalg.det(V) < 0
+    V[fv, :, 2] *= -1.0
+    s[fv, 2] *= -1.0
+    return U, s, V
+
+
+def psi(F, mu, lam, model="nh"):
+    """Energy density of `model` (Sec. 3.1, Table 1)."""
+    _check_model(model)
     I2, I3 = invariants(F)
-    if np.any(I3 <= 0):
+    if model == "nh":
+        if np.any(I3 <= 0):
+            raise InvertedElement("det F <= 0")
+        L = np.log(I3)
+        return 0.5 * mu * (I2 - 3.0) - mu * L + 0.5 * lam * L * L
+    if model == "snh":
+        lamp = lam + mu
+        return 0.5 * mu * (I2 - 3.0) - mu * (I3 - 1.0) + 0.5 * lamp * (I3 - 1.0) ** 2
+    _, s, _ = polar_rv(F)
+    I1 = s.sum(axis=1)
+    out = mu * (I2 - 2.0 * I1 + 3.0)
+    if model == "fcr":
+        out = out + 0.5 * lam * (I3 - 1.0) ** 2
+    return out
+
+
+def _psi_derivs(I3, mu, lam, model="nh"):
+    """Psi_1, Psi_2, Psi_3, Psi_33 of `model` (no density here has a
+    Psi_11, Psi_22 or mixed term)."""
+    if model == "nh":
+        L = np.log(I3)
+        return 0.0 * I3, 0.5 * mu + 0.0 * I3, -mu / I3 + lam * L / I3, mu / I3 ** 2 + lam * (1.0 - L) / I3 ** 2
+    if model == "snh":
+        lamp = lam + mu
+        return 0.0 * I3, 0.5 * mu + 0.0 * I3, lamp * (I3 - 1.0) - mu, lamp + 0.0 * I3
+    psi1 = -2.0 * mu + 0.0 * I3
+    psi2 = mu + 0.0 * I3
+    if model == "arap":
+        return psi1, psi2, 0.0 * I3, 0.0 * I3
+    return psi1, psi2, lam * (I3 - 1.0), lam + 0.0 * I3
+
+
+def _uses_I1(model):
+    return model in ("arap", "fcr")
+
+
+def _checked_I3(F, model):
+    _, I3 = invariants(F)
+    if model == "nh" and np.any(I3 <= 0):
         raise InvertedElement("det F <= 0")
-    L = np.log(I3)
-    return 0.5 * mu * (I2 - 3.0) - mu * L + 0.5 * lam * L * L
-
-
-def _psi_derivs(I3, mu, lam):
-    """Psi_2, Psi_3, Psi_33 of the Neo-Hookean density (Psi_22 = Psi_23 = 0)."""
-    L = np.log(I3)
-    psi2 = 0.5 * mu
-    psi3 = -mu / I3 + lam * L / I3
-    psi33 = mu / I3 ** 2 + lam * (1.0 - L) / I3 ** 2
-    return psi2, psi3, psi33
+    return I3
 
 
 def vec(M):
     """Column-wise flattening of (T,3,3) into (T,9): [col0; col1; col2]."""
     return np.transpose(M, (0, 2, 1)).reshape(M.shape[0], 9)
+
+
+def vec_inv(v):
+    """Inverse of vec for one (9,) vector: the 3x3 matrix with columns
+    v[0:3], v[3:6], v[6:9]."""
+    return np.asarray(v, dtype=np.float64).reshape(3, 3).T
 
 
 def _cross_matrix(f):
@@ -122,28 +203,56 @@ def invariant_grads(F):
     return g2, g3, H3
 
 
-def dPsi_dF(F, mu, lam):
-    """vec(dPsi/dF) = Psi_2 g2 + Psi_3 g3  (T,9)."""
-    _, I3 = invariants(F)
-    if np.any(I3 <= 0):
-        raise InvertedElement("det F <= 0")
-    psi2, psi3, _ = _psi_derivs(I3, mu, lam)
-    psi2 = np.broadcast_to(psi2, I3.shape)
+# unit skew matrices of the twist modes and the singular-value pair each
+# couples: T couples (i, j) with T[i, j] = -1, T[j, i] = +1
+_TWIST = [((0, 1), np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])),
+          ((1, 2), np.array([[0.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]])),
+          ((0, 2), np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 0.0], [-1.0, 0.0, 0.0]]))]
+
+
+def I1_grad_hess(F):
+    """g1 = vec R (T,9) and H1 = sum_i lambda_i q_i q_i^T (T,9,9) from the
+    rotation-variant SVD; raises InvertedElement where a lambda_i is
+    undefined (s_j + s_k <= 0)."""
+    U, s, V = polar_rv(F)
+    Vt = np.transpose(V, (0, 2, 1))
+    g1 = vec(U @ Vt)
+    H1 = np.zeros((F.shape[0], 9, 9))
+    for (i, j), T in _TWIST:
+        den = s[:, i] + s[:, j]
+        if np.any(den <= 0):
+            raise InvertedElement("singular values summing to <= 0: I1 Hessian undefined")
+        q = vec(U @ T[None] @ Vt) / np.sqrt(2.0)
+        H1 += (2.0 / den)[:, None, None] * np.einsum("ti,tj->tij", q, q)
+    return g1, H1
+
+
+def dPsi_dF(F, mu, lam, model="nh"):
+    """vec(dPsi/dF) = Psi_1 g1 + Psi_2 g2 + Psi_3 g3  (T,9)."""
+    _check_model(model)
+    I3 = _checked_I3(F, model)
+    psi1, psi2, psi3, _ = _psi_derivs(I3, mu, lam, model)
     g2, g3, _ = invariant_grads(F)
-    return psi2[:, None] * g2 + psi3[:, None] * g3
+    out = psi2[:, None] * g2 + psi3[:, None] * g3
+    if _uses_I1(model):
+        g1, _ = I1_grad_hess(F)
+        out = out + psi1[:, None] * g1
+    return out
 
 
-def d2Psi_dF2(F, mu, lam):
-    """9x9 Hessian: Psi_2 H2 + Psi_33 g3 g3^T + Psi_3 H3 (Psi_22 = 0)."""
-    _, I3 = invariants(F)
-    if np.any(I3 <= 0):
-        raise InvertedElement("det F <= 0")
-    psi2, psi3, psi33 = _psi_derivs(I3, mu, lam)
+def d2Psi_dF2(F, mu, lam, model="nh"):
+    """9x9 Hessian: Psi_1 H1 + Psi_2 H2 + Psi_33 g3 g3^T + Psi_3 H3."""
+    _check_model(model)
+    I3 = _checked_I3(F, model)
+    psi1, psi2, psi3, psi33 = _psi_derivs(I3, mu, lam, model)
     _, g3, H3 = invariant_grads(F)
     H2 = 2.0 * np.eye(9)[None]
-    psi2 = np.broadcast_to(psi2, I3.shape)
-    return (psi2[:, None, None] * H2 + psi33[:, None, None] * np.einsum("ti,tj->tij", g3, g3)
-            + psi3[:, None, None] * H3)
+    out = (psi2[:, None, None] * H2 + psi33[:, None, None] * np.einsum("ti,tj->tij", g3, g3)
+           + psi3[:, None, None] * H3)
+    if _uses_I1(model):
+        _, H1 = I1_grad_hess(F)
+        out = out + psi1[:, None, None] * H1
+    return out
 
 
 def dF_dx(b):
@@ -157,31 +266,27 @@ def dF_dx(b):
     return A
 
 
-def element_energy(F, vol, mu, lam):
-    return vol * psi(F, mu, lam)
+def element_energy(F, vol, mu, lam, model="nh"):
+    return vol * psi(F, mu, lam, model)
 
 
-def element_gradient(F, b, vol, mu, lam):
+def element_gradient(F, b, vol, mu, lam, model="nh"):
     """(T,4,3): V_e * vec(dF/dx)^T vec(dPsi/dF)."""
     A = dF_dx(b)
-    g = np.einsum("tmn,tm->tn", A, dPsi_dF(F, mu, lam))
+    g = np.einsum("tmn,tm->tn", A, dPsi_dF(F, mu, lam, model))
     return (vol[:, None] * g).reshape(-1, 4, 3)
 
 
-def element_hessian(F, b, vol, mu, lam):
+def element_hessian(F, b, vol, mu, lam, model="nh"):
     """(T,12,12): V_e * vec(dF/dx)^T d2Psi/dF2 vec(dF/dx)  (Sec. 3.1)."""
     A = dF_dx(b)
-    K = d2Psi_dF2(F, mu, lam)
+    K = d2Psi_dF2(F, mu, lam, model)
     return vol[:, None, None] * (np.transpose(A, (0, 2, 1)) @ (K @ A))
 
 
-def element_param_gradient(F, b, vol, dmu, dlam):
-    """d(element gradient)/d(parameter) for mu = dmu * s, lam = dlam * s
-    (the gradient is linear in (mu, lam)); shape (T,4,3)."""
-    _, I3 = invariants(F)
-    L = np.log(I3)
-    g2, g3, _ = invariant_grads(F)
-    # dPsi/dF = (mu/2) g2 + ((lam L - mu)/I3) g3, differentiated in s
-    dvecP = 0.5 * dmu[:, None] * g2 + ((dlam * L - dmu) / I3)[:, None] * g3
-    A = dF_dx(b)
-    return (vol[:, None] * np.einsum("tmn,tm->tn", A, dvecP)).reshape(-1, 4, 3)
+def element_param_gradient(F, b, vol, dmu, dlam, model="nh"):
+    """d(element gradient)/d(parameter) for mu = dmu * s, lam = dlam * s,
+    shape (T,4,3).  Every density here has a stress that is linear in
+    (mu, lam) jointly, so this is the element gradient evaluated with
+    (mu, lam) = (dmu, dlam)."""
+    return element_gradient(F, b, vol, np.broadcast_to(dmu, vol.shape), np.broadcast_to(dlam, vol.shape), model)

@@ -53,7 +53,7 @@ class Problem:
 
     def __init__(self, X, tets, tris, edges, E, nu, rho, planes, dhat, kappa,
                  self_contact=False, fixed=None, barrier_mode="psd",
-                 rest_exclude=True, gravity=(0.0, 0.0, -9.8), object_id=None):
+                 rest_exclude=True, gravity=(0.0, 0.0, -9.8), object_id=None, model="nh"):
         self.X = np.asarray(X, dtype=np.float64)
         self.tets = np.asarray(tets, dtype=np.int64)
         self.tris = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
@@ -63,6 +63,7 @@ class Problem:
         self.b = elastic.shape_vectors(self.Bmat)
         self.rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), self.vol.shape).copy()
         self.set_material(E, nu)
+        self.set_model(model)
         self.mass = elastic.lumped_mass(self.vol, self.rho, self.tets, self.nV)
         self.planes = np.asarray(planes, dtype=np.float64).reshape(-1, 4)
         self.dhat = float(dhat)
@@ -94,6 +95,12 @@ class Problem:
         self.E = np.broadcast_to(np.asarray(E, dtype=np.float64), self.vol.shape).copy()
         self.nu = np.broadcast_to(np.asarray(nu, dtype=np.float64), self.vol.shape).copy()
         self.mu, self.lam = elastic.lame(self.E, self.nu)
+
+    def set_model(self, model):
+        """Elastic density: one of elastic.MODELS (Sec. 3.1, Table 1)."""
+        if model not in elastic.MODELS:
+            raise ValueError(f"unknown material model {model!r}")
+        self.model = model
 
     @property
     def has_collision_primitives(self):
@@ -147,7 +154,7 @@ class Problem:
     # --------------------------------------------------------------- pieces
     def _F(self, x):
         F = elastic.deformation_gradient(x, self.tets, self.Bmat)
-        if np.any(np.linalg.det(F) <= 0):
+        if self.model == "nh" and np.any(np.linalg.det(F) <= 0):
             raise elastic.InvertedElement("inverted element")
         return F
 
@@ -167,14 +174,14 @@ class Problem:
         aset = self.active_set(x) if aset is None else aset
         dx = x - xt
         Ein = 0.5 * np.sum(self.mass[:, None] * dx * dx)
-        Eel = h * h * np.sum(elastic.element_energy(self._F(x), self.vol, self.mu, self.lam))
+        Eel = h * h * np.sum(elastic.element_energy(self._F(x), self.vol, self.mu, self.lam, self.model))
         Eb = self.kappa * (np.sum(barrier.b(aset.d, self.dhat)) + np.sum(barrier.b(aset.pd, self.dhat)))
         return Ein + Eel + Eb
 
     def gradient(self, x, xt, h, aset=None, project=True):
         aset = self.active_set(x) if aset is None else aset
         g = self.mass[:, None] * (x - xt)
-        ge = elastic.element_gradient(self._F(x), self.b, self.vol, self.mu, self.lam)
+        ge = elastic.element_gradient(self._F(x), self.b, self.vol, self.mu, self.lam, self.model)
         g += h * h * self._scatter(ge, self.tets)
         if len(aset.d):
             coef = self.kappa * barrier.db(aset.d, self.dhat) / aset.d
@@ -205,7 +212,7 @@ class Problem:
         return self.kappa * H
 
     def element_hessians(self, x, h):
-        return h * h * elastic.element_hessian(self._F(x), self.b, self.vol, self.mu, self.lam)
+        return h * h * elastic.element_hessian(self._F(x), self.b, self.vol, self.mu, self.lam, self.model)
 
     def diag(self, x, h, aset=None, mode=None):
         """diag(H) (V,3); prescribed rows are 1."""
