@@ -107,6 +107,12 @@ typedef struct pncg_ctx pncg_ctx;
  * otherwise).  With one object the step is the unsplit one. */
 #define PNCG_SPLIT_OBJECTS (1u << 8)
 
+/* material models (pncg_set_model, pncg_batch_set_model) */
+#define PNCG_MODEL_NH   0
+#define PNCG_MODEL_SNH  1
+#define PNCG_MODEL_ARAP 2
+#define PNCG_MODEL_FCR  3
+
 /* contact flags */
 #define PNCG_CONTACT_SELF          1u  /* point-triangle and edge-edge pairs
                                           (all objects, including self) */
@@ -170,6 +176,26 @@ int pncg_set_mesh(pncg_ctx* ctx, int32_t nV, const double* X, int32_t nT,
  * lam = E nu/((1+nu)(1-2nu)); lumped mass m_v = sum rho V_e / 4. */
 int pncg_set_material(pncg_ctx* ctx, const double* E, const double* nu,
                       const double* rho);
+
+/* Elastic density (Sec. 3.1 invariants I1 = tr S of F = R S, I2 = tr F^T F,
+ * I3 = det F; the materials of Table 1), with (mu, lam) from
+ * pncg_set_material:
+ *   PNCG_MODEL_NH   Neo-Hookean, mu/2 (I2 - 3) - mu log I3
+ *                   + lam/2 log^2 I3 (the default)
+ *   PNCG_MODEL_SNH  stable Neo-Hookean, mu/2 (I2 - 3) - mu (I3 - 1)
+ *                   + lam'/2 (I3 - 1)^2 with lam' = lam + mu (its
+ *                   small-strain limit is linear elasticity with mu, lam)
+ *   PNCG_MODEL_ARAP as-rigid-as-possible, mu |F - R|^2
+ *   PNCG_MODEL_FCR  fixed corotated, mu |F - R|^2 + lam/2 (I3 - 1)^2
+ * R is the rotation of the rotation-variant polar decomposition, so SNH,
+ * ARAP and FCR are defined for inverted tets; steps report E_INVERTED only
+ * for det F <= 0 under NH, and under ARAP/FCR where two singular values of
+ * the rotation-variant decomposition sum to <= 0 (the I1 Hessian is
+ * undefined there).  Hessians are exact (not projected).  May be called
+ * at any time after pncg_create; the choice persists across pncg_set_mesh
+ * and applies to steps, queries and the adjoint.  E_INVAL for an unknown
+ * model. */
+int pncg_set_model(pncg_ctx* ctx, int32_t model);
 
 /* Barrier parameters (Sec. 3, equation barrier): dhat > 0, kappa >= 0;
  * cell = spatial-hash cell size (> 0) or 0 for a size derived from the
@@ -373,6 +399,13 @@ int pncg_batch_set_params(pncg_batch* b, double dhat, double kappa,
 /* Threads per workgroup of the step kernel: 256, 512 or 1024 (default
  * 512); pncg_batch_autotune picks one by timing. */
 int pncg_batch_set_block(pncg_batch* b, int32_t block);
+
+/* Elastic density of every scene (PNCG_MODEL_*, as pncg_set_model); the
+ * default is PNCG_MODEL_NH.  Resizes the persistent grid for that model's
+ * kernel (LDS staging is switched off if that kernel cannot hold the
+ * largest scene) and drops a captured multi-step graph.  E_INVAL for an
+ * unknown model. */
+int pncg_batch_set_model(pncg_batch* b, int32_t model);
 
 /* lds = 1: the step kernel keeps the positions and search directions of the
  * scene it is solving in LDS (largest scene's vertex count x (24 + 3 x

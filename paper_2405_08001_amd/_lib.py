@@ -24,6 +24,8 @@ BARRIER_FULL, ALPHA_INF_COMPONENT = 1, 2
 BETA_DK, BETA_FR, BETA_PRP, BETA_CD, BETA_HZ = 0, 1 << 4, 2 << 4, 3 << 4, 4 << 4
 BETA_RULES = {"dk": BETA_DK, "fr": BETA_FR, "prp": BETA_PRP, "cd": BETA_CD, "hz": BETA_HZ}
 SPLIT_OBJECTS = 1 << 8
+MODEL_NH, MODEL_SNH, MODEL_ARAP, MODEL_FCR = 0, 1, 2, 3
+MODELS = {"nh": MODEL_NH, "snh": MODEL_SNH, "arap": MODEL_ARAP, "fcr": MODEL_FCR}
 CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
 
@@ -37,7 +39,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
-           "pncg_batch_set_split")
+           "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -83,6 +85,8 @@ def _load():
         "pncg_set_solver": (I32, [P, I32, D, I32, P, U32]),
         "pncg_set_dirichlet": (I32, [P, I32, P, P]),
         "pncg_set_tuning": (I32, [P, D, I32]),
+        "pncg_set_model": (I32, [P, I32]),
+        "pncg_batch_set_model": (I32, [P, I32]),
         "pncg_mean_boundary_edge": (I32, [P, P]),
         "pncg_set_adjoint_warm_start": (I32, [P, I32]),
         "pncg_step": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
@@ -177,6 +181,10 @@ class Context:
         n = max(self.nT, np.size(E))
         E, nu, rho = (_f64(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))) for a in (E, nu, rho))
         self._check(_L.pncg_set_material(self._h, _ptr(E), _ptr(nu), _ptr(rho)))
+
+    def pncg_set_model(self, model):
+        """model: a MODEL_* value or one of the names in MODELS."""
+        self._check(_L.pncg_set_model(self._h, int(MODELS.get(model, model) if isinstance(model, str) else model)))
 
     def pncg_set_contact(self, dhat, kappa, cell=0.0, planes=None, flags=0):
         pl = _f64(np.zeros((0, 4)) if planes is None else np.asarray(planes, dtype=np.float64).reshape(-1, 4))
@@ -377,6 +385,10 @@ class Batch:
 
     def pncg_batch_set_block(self, block):
         self._check(_L.pncg_batch_set_block(self._h, int(block)))
+
+    def pncg_batch_set_model(self, model):
+        """model: a MODEL_* value or one of the names in MODELS."""
+        self._check(_L.pncg_batch_set_model(self._h, int(MODELS.get(model, model) if isinstance(model, str) else model)))
 
     def pncg_batch_set_staging(self, lds):
         self._check(_L.pncg_batch_set_staging(self._h, int(lds)))

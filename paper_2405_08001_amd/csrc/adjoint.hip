@@ -141,6 +141,7 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
 // p_{k-1} (lambda in place: only that lane touches it), and adds the partials
 // of launch k, with r_k = diag z_k (the residual itself is not stored).
 // k_adj_init writes {z_0, 0} into zw[1] and the partials r_0.z_0, |r_0|^2.
+template <int M>
 __global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C, int k) {
   constexpr int NW = kCgBlock / kWave;
   __shared__ double sh[NW * 7];
@@ -209,11 +210,11 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C
       const ElemRec<double> rec = A.elem[code >> 2];
       Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
                                            ld3(A.x0, rec.v[3]));
-      if (kin.J > 0.0) {
-        V3<double> d[3];
-        const int v0 = rec.v[0], v1 = rec.v[1], v2 = rec.v[2], v3 = rec.v[3];
-        dF_cols(rec.B, pget(v0, zget(v0)), pget(v1, zget(v1)), pget(v2, zget(v2)), pget(v3, zget(v3)), d);
-        const V3<double> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3));
+      V3<double> d[3];
+      const int v0 = rec.v[0], v1 = rec.v[1], v2 = rec.v[2], v3 = rec.v[3];
+      dF_cols(rec.B, pget(v0, zget(v0)), pget(v1, zget(v1)), pget(v2, zget(v2)), pget(v3, zget(v3)), d);
+      V3<double> hp;
+      if (el_Hp<double, M>(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3), hp)) {
         s[0] = hp.x;
         s[1] = hp.y;
         s[2] = hp.z;
@@ -300,6 +301,7 @@ __global__ void __launch_bounds__(kSBlock) k_cg_dir(Args<double> A, AdjArgs C, i
 
 // q = H p_k by the vertex-centric sweep (p_k materialised by k_cg_dir, the
 // pair part already in acc); partials of p_k . q.
+template <int M>
 __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, int k) {
   __shared__ double sh[kSWaves * 2];
   if (read_stopped(C.status)) return;
@@ -317,10 +319,10 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
       const ElemRec<double> rec = A.elem[code >> 2];
       Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
                                            ld3(A.x0, rec.v[3]));
-      if (kin.J > 0.0) {
-        V3<double> d[3];
-        dF_cols(rec.B, pget(rec.v[0]), pget(rec.v[1]), pget(rec.v[2]), pget(rec.v[3]), d);
-        const V3<double> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3));
+      V3<double> d[3];
+      dF_cols(rec.B, pget(rec.v[0]), pget(rec.v[1]), pget(rec.v[2]), pget(rec.v[3]), d);
+      V3<double> hp;
+      if (el_Hp<double, M>(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3), hp)) {
         s[0] = hp.x;
         s[1] = hp.y;
         s[2] = hp.z;
@@ -412,6 +414,7 @@ __global__ void __launch_bounds__(kSBlock) k_cg_update(Args<double> A, AdjArgs C
 }
 
 // Adjoints of x^t, v^t and the per-tet moduli (accumulated into Ebar).
+template <int M>
 __global__ void __launch_bounds__(kSBlock) k_adj_out(Args<double> A, AdjArgs C, const double* vbar, const double* E,
                                                      double* xbar_t, double* vbar_t, double* Ebar) {
   const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
@@ -431,17 +434,19 @@ __global__ void __launch_bounds__(kSBlock) k_adj_out(Args<double> A, AdjArgs C, 
     const ElemRec<double> rec = A.elem[e];
     Kin<double> kin = kinematics<double>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]),
                                          ld3(A.x0, rec.v[3]));
-    if (!(kin.J > 0.0)) {
-      raise_err(A.status, kErrInverted);
-      continue;
-    }
     // mu and lam are linear in E: d(V mu)/dE = V mu / E, likewise for lam
     const double iE = 1.0 / E[e];
     double s = 0.0;
+    bool ok = true;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const V3<double> dg = nh_dgdE(kin, rec.vmu * iE, rec.vlam * iE, shape_vec(rec.B, a));
-      s += dot(ld3(C.lam, rec.v[a]), dg);
+      V3<double> dg;
+      ok = ok && el_dgdE<double, M>(kin, rec.vmu * iE, rec.vlam * iE, shape_vec(rec.B, a), dg);
+      if (ok) s += dot(ld3(C.lam, rec.v[a]), dg);
+    }
+    if (!ok) {
+      raise_err(A.status, kErrInverted);
+      continue;
     }
     Ebar[e] -= A.h2 * s;
   }
@@ -453,14 +458,14 @@ void launch_adj_init(const Args<double>& A, const AdjArgs& C, const double* xbar
     // q = H lambda with the Hv sweep reading lambda as its direction
     AdjArgs W = C;
     W.pbuf[0] = C.lam;
-    hipLaunchKernelGGL(k_cg_hv, dim3(A.grid), dim3(kSBlock), 0, s, A, W, 0);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL(k_cg_hv<M_>, dim3(A.grid), dim3(kSBlock), 0, s, A, W, 0));
   }
   hipLaunchKernelGGL(k_adj_init, dim3(A.grid), dim3(kSBlock), 0, s, A, C, xbar, vbar, warm ? 1 : 0);
 }
 
 void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fused, hipStream_t s) {
   if (fused) {
-    hipLaunchKernelGGL(k_cg_fused, dim3(A.grid), dim3(kCgBlock), 0, s, A, C, k);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL(k_cg_fused<M_>, dim3(A.grid), dim3(kCgBlock), 0, s, A, C, k));
     return;
   }
   hipLaunchKernelGGL(k_cg_dir, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
@@ -469,13 +474,14 @@ void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fu
     B.p0 = C.pbuf[k & 1];
     launch_pairs_hvp<double>(B, s);
   }
-  hipLaunchKernelGGL(k_cg_hv, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
+  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL(k_cg_hv<M_>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k));
   hipLaunchKernelGGL(k_cg_update, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
 }
 
 void launch_adj_out(const Args<double>& A, const AdjArgs& C, const double* vbar, const double* E, double* xbar_t,
                     double* vbar_t, double* Ebar, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_out, dim3(A.grid), dim3(kSBlock), 0, s, A, C, vbar, E, xbar_t, vbar_t, Ebar);
+  PNCG_BY_MODEL(A.model,
+                hipLaunchKernelGGL(k_adj_out<M_>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, vbar, E, xbar_t, vbar_t, Ebar));
 }
 
 }  // namespace pncg

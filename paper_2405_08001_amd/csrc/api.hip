@@ -56,6 +56,7 @@ struct pncg_ctx {
   std::vector<uint8_t> vflag;
   std::vector<int> inc, inc_vert;
   int nWaves = 0;
+  int model = PNCG_MODEL_NH;   // elastic density (PNCG_MODEL_*)
 
   // contact / solver parameters
   double dhat = 1e-3, kappa = 0.0, cell_user = 0.0, cell = 0.0, skin = 0.0, skin_user = 0.0, lmean = 0.0;
@@ -258,6 +259,7 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.grid = c->grid;
   A.split = (c->sflags & PNCG_SPLIT_OBJECTS) ? 1 : 0;
   A.nObj = c->nObj;
+  A.model = kernel_model(c->model);
   A.vobj = c->d_vobj;
   A.voff = c->d_voff;
   A.toff = c->d_toff;
@@ -425,7 +427,7 @@ __global__ void k_rows_to_x4(const double* a, double4* x, int n) {
 
 int check_status_err(pncg_ctx* c, const StepStatus& st) {
   if (st.err & kErrNonfinite) return fail(c, PNCG_E_NONFINITE, "non-finite value in positions or velocities");
-  if (st.err & kErrInverted) return fail(c, PNCG_E_INVERTED, "a tet has det F <= 0");
+  if (st.err & kErrInverted) return fail(c, PNCG_E_INVERTED, inverted_message(c->model));
   if (st.err & kErrPenetration) return fail(c, PNCG_E_PENETRATION, "a contact distance is <= 0");
   return PNCG_OK;
 }
@@ -659,7 +661,7 @@ int upload_elements(pncg_ctx* c) {
     const double mu = c->E[e] / (2.0 * (1.0 + c->nu[e]));
     const double lam = c->E[e] * c->nu[e] / ((1.0 + c->nu[e]) * (1.0 - 2.0 * c->nu[e]));
     r.vmu = R(c->vol[e] * mu);
-    r.vlam = R(c->vol[e] * lam);
+    r.vlam = R(c->vol[e] * record_lam(c->model, mu, lam));
   }
   if (!c->d_elem) {
     int rc = dmalloc(c, reinterpret_cast<ElemRec<R>**>(&c->d_elem), (size_t)c->nT);
@@ -1116,6 +1118,16 @@ int pncg_set_adjoint_warm_start(pncg_ctx* c, int32_t on) {
   if (on != 0 && on != 1) return fail(c, PNCG_E_INVAL, "on must be 0 or 1");
   c->adj_warm = on != 0;
   return PNCG_OK;
+}
+
+int pncg_set_model(pncg_ctx* c, int32_t model) {
+  if (!c) return PNCG_E_INVAL;
+  if (model < PNCG_MODEL_NH || model > PNCG_MODEL_FCR) return fail(c, PNCG_E_INVAL, "unknown material model");
+  c->model = model;
+  c->adj_lam_valid = false;
+  if (c->state < 2) return PNCG_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  return (c->precision == PNCG_MIXED) ? upload_elements<float>(c) : upload_elements<double>(c);
 }
 
 int pncg_set_tuning(pncg_ctx* c, double skin, int32_t chunk) {

@@ -41,6 +41,7 @@ struct BatchArgs {
   V3<double> grav;
   int iter_max, term;
   unsigned flags;
+  int model;               // device_math.h Model (kernel template argument)
   int* iters;              // [nScenes] iterations of the last step
   int* reason;             // [nScenes]
   long long* iters_total;  // [nScenes] accumulated over steps
@@ -53,9 +54,10 @@ template <typename R>
 size_t batch_lds_bytes(int vcap);
 
 // Resident workgroups per compute unit of the step kernel at this block size
-// (lds: with the positions and directions of a scene in LDS).
+// (lds: with the positions and directions of a scene in LDS) for the kernel
+// model `model` (device_math.h Model).
 template <typename R>
-hipError_t batch_occupancy(int block, bool lds, int vcap, int* per_cu);
+hipError_t batch_occupancy(int block, bool lds, int vcap, int model, int* per_cu);
 
 // Zero the team barrier counters (a kernel, so that it can sit in a graph).
 void launch_team_reset(int* bar, int n, hipStream_t s);

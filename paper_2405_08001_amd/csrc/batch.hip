@@ -74,7 +74,7 @@ struct Team {
 // and the update for every vertex, and the members meet twice per iteration
 // to combine their partial sums (after the gradient sweep, which also
 // publishes P g, and after the p^T H p pass).
-template <typename R, int BS, bool LDSX>
+template <typename R, int BS, bool LDSX, int M>
 __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double* x_in, const double* v_in,
                                                    double* x_out, double* v_out) {
   constexpr int NW = BS / kWave;
@@ -144,9 +144,8 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         if (code >= 0) {
           const ElemRec<R> rec = A.elem[code >> 2];
           Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
-          if (kin.J > R(0)) {
-            V3<R> g, dg;
-            nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg);
+          V3<R> g, dg;
+          if (el_grad_diag<R, M>(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg)) {
             sv[0] = g.x; sv[1] = g.y; sv[2] = g.z; sv[3] = dg.x; sv[4] = dg.y; sv[5] = dg.z;
           } else {
             atomicOr(A.err, kErrInverted);
@@ -239,7 +238,9 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
         V3<R> d[3];
         dF_cols(rec.B, Pd(rec.v[0]), Pd(rec.v[1]), Pd(rec.v[2]), Pd(rec.v[3]), d);
-        el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+        R ph = R(0);
+        if (!el_pHp<R, M>(kin, rec.vmu, rec.vlam, d, ph)) atomicOr(A.err, kErrInverted);
+        el += double(ph);
       }
       double red[3] = {php + A.h2 * el, pmv, pmc};
       {
@@ -291,18 +292,18 @@ void launch_team_reset(int* bar, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_team_reset, dim3((n + 255) / 256), dim3(256), 0, s, bar, n);
 }
 
-template <typename R, bool LDSX>
-void launch_bs(const BatchArgs<R>& A, int block, int grid, size_t shmem, const double* x, const double* v, double* xo,
-               double* vo, hipStream_t s) {
+template <typename R, bool LDSX, int M>
+void launch_bsm(const BatchArgs<R>& A, int block, int grid, size_t shmem, const double* x, const double* v,
+                double* xo, double* vo, hipStream_t s) {
   switch (block) {
     case 256:
-      hipLaunchKernelGGL((k_batch_step<R, 256, LDSX>), dim3(grid), dim3(256), shmem, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 256, LDSX, M>), dim3(grid), dim3(256), shmem, s, A, x, v, xo, vo);
       break;
     case 512:
-      hipLaunchKernelGGL((k_batch_step<R, 512, LDSX>), dim3(grid), dim3(512), shmem, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 512, LDSX, M>), dim3(grid), dim3(512), shmem, s, A, x, v, xo, vo);
       break;
     default:
-      hipLaunchKernelGGL((k_batch_step<R, 1024, LDSX>), dim3(grid), dim3(1024), shmem, s, A, x, v, xo, vo);
+      hipLaunchKernelGGL((k_batch_step<R, 1024, LDSX, M>), dim3(grid), dim3(1024), shmem, s, A, x, v, xo, vo);
       break;
   }
 }
@@ -315,31 +316,38 @@ size_t batch_lds_bytes(int vcap) {
 template <typename R>
 void launch_batch_step(const BatchArgs<R>& A, int block, int grid, bool lds, const double* x, const double* v,
                        double* xo, double* vo, hipStream_t s) {
-  if (lds) launch_bs<R, true>(A, block, grid, batch_lds_bytes<R>(A.vcap), x, v, xo, vo, s);
-  else launch_bs<R, false>(A, block, grid, 0, x, v, xo, vo, s);
+  if (lds)
+    PNCG_BY_MODEL(A.model, (launch_bsm<R, true, M_>(A, block, grid, batch_lds_bytes<R>(A.vcap), x, v, xo, vo, s)));
+  else
+    PNCG_BY_MODEL(A.model, (launch_bsm<R, false, M_>(A, block, grid, 0, x, v, xo, vo, s)));
 }
 
-template <typename R, bool LDSX>
+template <typename R, bool LDSX, int M>
 hipError_t occ(int block, size_t shmem, int* per_cu) {
   switch (block) {
     case 256:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 256, LDSX>, 256, shmem);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 256, LDSX, M>, 256, shmem);
     case 512:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 512, LDSX>, 512, shmem);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 512, LDSX, M>, 512, shmem);
     default:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 1024, LDSX>, 1024, shmem);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_step<R, 1024, LDSX, M>, 1024, shmem);
   }
 }
 
 template <typename R>
-hipError_t batch_occupancy(int block, bool lds, int vcap, int* per_cu) {
-  return lds ? occ<R, true>(block, batch_lds_bytes<R>(vcap), per_cu) : occ<R, false>(block, 0, per_cu);
+hipError_t batch_occupancy(int block, bool lds, int vcap, int model, int* per_cu) {
+  hipError_t e = hipSuccess;
+  if (lds)
+    PNCG_BY_MODEL(model, (e = occ<R, true, M_>(block, batch_lds_bytes<R>(vcap), per_cu)));
+  else
+    PNCG_BY_MODEL(model, (e = occ<R, false, M_>(block, 0, per_cu)));
+  return e;
 }
 
 template size_t batch_lds_bytes<float>(int);
 template size_t batch_lds_bytes<double>(int);
-template hipError_t batch_occupancy<float>(int, bool, int, int*);
-template hipError_t batch_occupancy<double>(int, bool, int, int*);
+template hipError_t batch_occupancy<float>(int, bool, int, int, int*);
+template hipError_t batch_occupancy<double>(int, bool, int, int, int*);
 template void launch_batch_step<float>(const BatchArgs<float>&, int, int, bool, const double*, const double*, double*,
                                        double*, hipStream_t);
 template void launch_batch_step<double>(const BatchArgs<double>&, int, int, bool, const double*, const double*,

@@ -46,6 +46,9 @@ struct pncg_batch {
   bool split = false;       // the current schedule has a team of more than one workgroup
   int spin_limit = kDefaultPolls;  // polls before a team barrier gives up
   void* d_elem = nullptr;
+  std::vector<char> elem_host;        // host copy of the element records
+  std::vector<double> vol_mu, vol_lam;  // V mu and V lam per tet
+  int model = PNCG_MODEL_NH;
   int *d_inc = nullptr, *d_inc_vert = nullptr;
   double* d_mass = nullptr;
   uint8_t* d_vflag = nullptr;
@@ -134,6 +137,7 @@ BatchArgs<R> batch_args(pncg_batch* b, double h) {
   A.iter_max = b->iter_max;
   A.term = b->term;
   A.flags = b->flags;
+  A.model = kernel_model(b->model);
   A.iters = b->d_iters;
   A.reason = b->d_reason;
   A.iters_total = b->d_iters_total;
@@ -233,7 +237,7 @@ int check_err(pncg_batch* b) {
   int e = 0;
   BCHK(b, hipMemcpyAsync(&e, b->d_err, sizeof(int), hipMemcpyDeviceToHost, b->stream));
   BCHK(b, hipStreamSynchronize(b->stream));
-  if (e & kErrInverted) return bfail(b, PNCG_E_INVERTED, "a tet has det F <= 0");
+  if (e & kErrInverted) return bfail(b, PNCG_E_INVERTED, inverted_message(b->model));
   if (e & kErrPenetration) return bfail(b, PNCG_E_PENETRATION, "a vertex is on or behind its plane");
   if (e & kErrTeam)
     return bfail(b, PNCG_E_HIP, "a team barrier timed out (the workgroups of a team were not all resident); "
@@ -245,30 +249,67 @@ template <typename R>
 int upload_elems(pncg_batch* b, const std::vector<int>& tets_g, const std::vector<double>& Bm,
                  const std::vector<double>& vol, const double* E, const double* nu) {
   std::vector<ElemRec<R>> rec(b->nT);
+  b->vol_mu.resize(b->nT);
+  b->vol_lam.resize(b->nT);
   for (int e = 0; e < b->nT; ++e) {
     for (int a = 0; a < 4; ++a) rec[e].v[a] = tets_g[4 * e + a];
     for (int j = 0; j < 9; ++j) rec[e].B[j] = R(Bm[9 * (size_t)e + j]);
     const double mu = E[e] / (2.0 * (1.0 + nu[e])), lam = E[e] * nu[e] / ((1.0 + nu[e]) * (1.0 - 2.0 * nu[e]));
+    b->vol_mu[e] = vol[e] * mu;
+    b->vol_lam[e] = vol[e] * lam;
     rec[e].vmu = R(vol[e] * mu);
-    rec[e].vlam = R(vol[e] * lam);
+    rec[e].vlam = R(vol[e] * record_lam(b->model, mu, lam));
   }
   int rc = balloc(b, reinterpret_cast<ElemRec<R>**>(&b->d_elem), (size_t)b->nT);
   if (rc) return rc;
+  const char* bytes = reinterpret_cast<const char*>(rec.data());
+  b->elem_host.assign(bytes, bytes + sizeof(ElemRec<R>) * (size_t)b->nT);
   BCHK(b, hipMemcpy(b->d_elem, rec.data(), sizeof(ElemRec<R>) * (size_t)b->nT, hipMemcpyHostToDevice));
+  return PNCG_OK;
+}
+
+// Rewrite the records' lam for the current model and upload them.
+template <typename R>
+int repack_elems(pncg_batch* b) {
+  ElemRec<R>* rec = reinterpret_cast<ElemRec<R>*>(b->elem_host.data());
+  for (int e = 0; e < b->nT; ++e) rec[e].vlam = R(record_lam(b->model, b->vol_mu[e], b->vol_lam[e]));
+  BCHK(b, hipMemcpy(b->d_elem, rec, sizeof(ElemRec<R>) * (size_t)b->nT, hipMemcpyHostToDevice));
   return PNCG_OK;
 }
 
 // Persistent grid size: resident workgroups per CU times the CU count (0 when
 // the LDS-staged kernel cannot be resident at all).
-int max_active(pncg_batch* b, int block, bool lds, int* out) {
+int max_active(pncg_batch* b, int block, bool lds, int kmodel, int* out) {
   int n = 0;
   hipDeviceProp_t prop;
   BCHK(b, hipGetDeviceProperties(&prop, b->device));
   if (b->precision == PNCG_MIXED)
-    BCHK(b, batch_occupancy<float>(block, lds, b->vcap, &n));
+    BCHK(b, batch_occupancy<float>(block, lds, b->vcap, kmodel, &n));
   else
-    BCHK(b, batch_occupancy<double>(block, lds, b->vcap, &n));
+    BCHK(b, batch_occupancy<double>(block, lds, b->vcap, kmodel, &n));
   *out = lds ? n * prop.multiProcessorCount : std::max(1, n) * prop.multiProcessorCount;
+  return PNCG_OK;
+}
+
+// Persistent grid sizes of every block size, with and without LDS staging,
+// for kernel model kmodel; lds_ok: the staged kernel is resident at all.
+int size_grids(pncg_batch* b, int kmodel, int* grid, int* grid_lds, bool* lds_ok) {
+  int rc;
+  for (int i = 0; i < kNBlocks; ++i)
+    if ((rc = max_active(b, kBlocks[i], false, kmodel, &grid[i]))) return rc;
+  *lds_ok = false;
+  for (int i = 0; i < kNBlocks; ++i) grid_lds[i] = 0;
+  hipDeviceProp_t prop;
+  BCHK(b, hipGetDeviceProperties(&prop, b->device));
+  const size_t need = b->precision == PNCG_MIXED ? batch_lds_bytes<float>(b->vcap) : batch_lds_bytes<double>(b->vcap);
+  // static LDS of the kernel is 8 doubles per wave: at most 1 KiB
+  if (need + 1024 <= prop.sharedMemPerBlock) {
+    *lds_ok = true;
+    for (int i = 0; i < kNBlocks; ++i) {
+      if ((rc = max_active(b, kBlocks[i], true, kmodel, &grid_lds[i]))) return rc;
+      if (grid_lds[i] < 1) *lds_ok = false;
+    }
+  }
   return PNCG_OK;
 }
 
@@ -418,24 +459,16 @@ int pncg_batch_create(pncg_batch** out, const pncg_opts* o, int32_t nScenes, con
   if (hipMemset(b->d_iters_total, 0, sizeof(long long) * nScenes) != hipSuccess ||
       hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess)
     return fin(bfail(b, PNCG_E_HIP, "memset failed"));
-  for (int i = 0; i < kNBlocks; ++i)
-    if ((rc = max_active(b, kBlocks[i], false, &b->max_grid[i]))) return fin(rc);
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return fin(bfail(b, PNCG_E_HIP, "device query failed"));
-    const size_t need = precision == PNCG_MIXED ? batch_lds_bytes<float>(b->vcap) : batch_lds_bytes<double>(b->vcap);
-    // static LDS of the kernel is 8 doubles per wave: at most 1 KiB
-    if (need + 1024 <= prop.sharedMemPerBlock) {
-      b->lds_ok = true;
-      for (int i = 0; i < kNBlocks; ++i) {
-        if ((rc = max_active(b, kBlocks[i], true, &b->max_grid_lds[i]))) return fin(rc);
-        if (b->max_grid_lds[i] < 1) b->lds_ok = false;
-      }
-      b->lds = b->lds_ok;
-    }
+  // the schedule buffers hold the largest grid of any model
+  for (int km = 0; km < 3; ++km) {
+    int g[kNBlocks], gl[kNBlocks];
+    bool ok;
+    if ((rc = size_grids(b, km, g, gl, &ok))) return fin(rc);
+    for (int i = 0; i < kNBlocks; ++i) b->nb_cap = std::max({b->nb_cap, g[i], gl[i]});
   }
+  if ((rc = size_grids(b, kernel_model(b->model), b->max_grid, b->max_grid_lds, &b->lds_ok))) return fin(rc);
+  b->lds = b->lds_ok;
   b->max_team = b->lds ? kMaxTeam : 1;
-  for (int i = 0; i < kNBlocks; ++i) b->nb_cap = std::max({b->nb_cap, b->max_grid[i], b->max_grid_lds[i]});
   if ((rc = balloc(b, &b->d_blk_team, b->nb_cap)) || (rc = balloc(b, &b->d_blk_rank, b->nb_cap)) ||
       (rc = balloc(b, &b->d_team_size, b->nb_cap)) || (rc = balloc(b, &b->d_team_off, b->nb_cap + 1)) ||
       (rc = balloc(b, &b->d_team_scene, nScenes)) || (rc = balloc(b, &b->d_bar, b->nb_cap)) ||
@@ -478,6 +511,24 @@ int pncg_batch_set_block(pncg_batch* b, int32_t block) {
   if (block != 256 && block != 512 && block != 1024) return bfail(b, PNCG_E_INVAL, "block must be 256, 512 or 1024");
   b->block = block;
   drop_graph(b);
+  return ensure_schedule(b);
+}
+
+int pncg_batch_set_model(pncg_batch* b, int32_t model) {
+  if (!b) return PNCG_E_INVAL;
+  if (model < PNCG_MODEL_NH || model > PNCG_MODEL_FCR) return bfail(b, PNCG_E_INVAL, "unknown material model");
+  BCHK(b, hipSetDevice(b->device));
+  if (b->stream) BCHK(b, hipStreamSynchronize(b->stream));
+  b->model = model;
+  int rc = b->precision == PNCG_MIXED ? repack_elems<float>(b) : repack_elems<double>(b);
+  if (rc) return rc;
+  if ((rc = size_grids(b, kernel_model(model), b->max_grid, b->max_grid_lds, &b->lds_ok))) return rc;
+  if (!b->lds_ok) {
+    b->lds = false;
+    b->max_team = 1;
+  }
+  drop_graph(b);
+  b->sched_grid = 0;
   return ensure_schedule(b);
 }
 

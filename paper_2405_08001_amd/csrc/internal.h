@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "device_math.h"
+#include "../../include/pncg.h"
 
 namespace pncg {
 
@@ -147,6 +148,7 @@ struct Args {
   int grid;
   // splitting computation (Sec. 5.2): objects are contiguous vertex and tet ranges
   int split, nObj;
+  int model;               // Model of device_math.h (kernel template argument)
   const int* vobj;         // [nV] object of each vertex
   const int* voff;         // [nObj + 1] vertex ranges
   const int* toff;         // [nObj + 1] tet ranges
@@ -156,5 +158,35 @@ struct Args {
   double* vphp;            // [nV][3] inertia + plane p^T H p, |p_v|_2, max_i |p_v,i|
   double* opair;           // [2][nObj] pair p^T H p per object (float64 atomics)
 };
+
+// Runs CALL with the constexpr M_ set to the model the arguments carry.
+#define PNCG_BY_MODEL(model, CALL)                                  \
+  do {                                                              \
+    if ((model) == kModelSNH) {                                     \
+      constexpr int M_ = kModelSNH;                                 \
+      CALL;                                                         \
+    } else if ((model) == kModelCorot) {                            \
+      constexpr int M_ = kModelCorot;                               \
+      CALL;                                                         \
+    } else {                                                        \
+      constexpr int M_ = kModelNH;                                  \
+      CALL;                                                         \
+    }                                                               \
+  } while (0)
+
+// Kernel model (device_math.h Model) of a PNCG_MODEL_* value: ARAP runs
+// the fixed-corotated kernels with lam = 0.
+inline int kernel_model(int model) {
+  return model == PNCG_MODEL_SNH ? 1 : (model == PNCG_MODEL_ARAP || model == PNCG_MODEL_FCR) ? 2 : 0;
+}
+// The lam the element record holds: lam' = lam + mu for the stable
+// Neo-Hookean density, 0 for ARAP, lam otherwise.
+inline double record_lam(int model, double mu, double lam) {
+  return model == PNCG_MODEL_SNH ? lam + mu : model == PNCG_MODEL_ARAP ? 0.0 : lam;
+}
+inline const char* inverted_message(int model) {
+  return model == PNCG_MODEL_NH ? "a tet has det F <= 0"
+                                : "a tet's I1 Hessian is undefined (two singular values summing to <= 0)";
+}
 
 }  // namespace pncg

@@ -341,21 +341,19 @@ __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) 
 // ---------------------------------------------------- vertex-centric sweep
 enum GradMode { kGradFirst = 0, kGradDirect = 1, kGradQuery = 2 };
 
-// Element gradient and diagonal of one (tet, corner) lane; false if the lane
-// holds no tet.  Without the h^2 factor.
-template <typename R, typename Pos>
+// Element gradient and diagonal of one (tet, corner) lane under model M;
+// false if the lane holds no tet.  Without the h^2 factor.
+template <typename R, int M, typename Pos>
 __device__ __forceinline__ bool lane_elem(const Args<R>& A, int code, const Pos& pos, V3<R>& g, V3<R>& dg) {
   if (code < 0) return false;
   const int e = code >> 2, a = code & 3;
   const ElemRec<R> rec = A.elem[e];
   Kin<R> kin = kinematics<R>(rec.B, pos(rec.v[0]), pos(rec.v[1]), pos(rec.v[2]), pos(rec.v[3]));
-  if (!(kin.J > R(0))) {
+  if (!el_grad_diag<R, M>(kin, rec.vmu, rec.vlam, shape_vec(rec.B, a), g, dg)) {
     raise_err(A.status, kErrInverted);
     g = mk3(R(0), R(0), R(0));
     dg = g;
-    return true;
   }
-  nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, a), g, dg);
   return true;
 }
 
@@ -399,7 +397,7 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
-template <typename R, int MODE, bool SPLIT = false, int BS = GradBlock<R>::value>
+template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, int BS = GradBlock<R>::value>
 __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
   __shared__ double sh[NW * 8];
@@ -429,7 +427,7 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
     const int myv = A.inc_vert[idx];
     V3<R> g, dg;
     R s[6];
-    if (lane_elem(A, code, pos, g, dg)) {
+    if (lane_elem<R, M>(A, code, pos, g, dg)) {
       s[0] = g.x; s[1] = g.y; s[2] = g.z; s[3] = dg.x; s[4] = dg.y; s[5] = dg.z;
     } else {
 #pragma unroll
@@ -510,7 +508,7 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
 // ------------------------------------------------------ direction + pHp
 // SPLIT: beta per object (from k_objred_grad), and the p^T H p terms go
 // per tet, per vertex and per object (pairs) for k_objred_dir.
-template <typename R, bool SPLIT = false, int BS = kSBlock>
+template <typename R, bool SPLIT = false, int M = kModelNH, int BS = kSBlock>
 __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   __shared__ double sh[BS / kWave * 8];
   const IterScal s = A.scal[k];
@@ -602,8 +600,10 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
     Kin<R> kin = kinematics<R>(rec.B, X[0], X[1], X[2], X[3]);
     V3<R> d[3];
     dF_cols(rec.B, P[0], P[1], P[2], P[3], d);
-    if constexpr (SPLIT) A.tphp[e] = A.h2 * double(nh_pHp(kin, rec.vmu, rec.vlam, d));
-    else el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));
+    R ph = R(0);
+    if (!el_pHp<R, M>(kin, rec.vmu, rec.vlam, d, ph)) raise_err(A.status, kErrInverted);
+    if constexpr (SPLIT) A.tphp[e] = A.h2 * double(ph);
+    else el += double(ph);
   }
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part
 }
 
 // Energy of elements, inertia and planes at x0 (partials per block).
-template <typename R>
+template <typename R, int M>
 __global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
   __shared__ double sh[kSWaves * 2];
   const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
@@ -885,8 +885,9 @@ __global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
   for (int e = tid; e < A.nT; e += stride) {
     const ElemRec<R> rec = A.elem[e];
     Kin<R> kin = kinematics<R>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]), ld3(A.x0, rec.v[3]));
-    if (!(kin.J > R(0))) { raise_err(A.status, kErrInverted); continue; }
-    el += double(nh_energy(kin, rec.vmu, rec.vlam));
+    R ee;
+    if (!el_energy<R, M>(kin, rec.vmu, rec.vlam, ee)) { raise_err(A.status, kErrInverted); continue; }
+    el += double(ee);
   }
   for (int v = tid; v < A.nV; v += stride) {
     V3<double> x = ld3(A.x0, v), xt = ld3(A.xt, v);
@@ -910,7 +911,7 @@ __global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
 
 // H p by the vertex-centric sweep (p in p0, prescribed rows zero) and the
 // per-block partials of p^T H p.  Pair contributions must already be in acc.
-template <typename R>
+template <typename R, int M>
 __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
   __shared__ double sh[kSWaves * 2];
   const int lane = threadIdx.x & (kWave - 1);
@@ -926,10 +927,10 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
       const int e = code >> 2, a = code & 3;
       const ElemRec<R> rec = A.elem[e];
       Kin<R> kin = kinematics<R>(rec.B, ld3(A.x0, rec.v[0]), ld3(A.x0, rec.v[1]), ld3(A.x0, rec.v[2]), ld3(A.x0, rec.v[3]));
-      if (kin.J > R(0)) {
-        V3<R> d[3];
-        dF_cols(rec.B, ldr<R>(A.p0, rec.v[0]), ldr<R>(A.p0, rec.v[1]), ldr<R>(A.p0, rec.v[2]), ldr<R>(A.p0, rec.v[3]), d);
-        V3<R> hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, a));
+      V3<R> d[3];
+      dF_cols(rec.B, ldr<R>(A.p0, rec.v[0]), ldr<R>(A.p0, rec.v[1]), ldr<R>(A.p0, rec.v[2]), ldr<R>(A.p0, rec.v[3]), d);
+      V3<R> hp;
+      if (el_Hp<R, M>(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, a), hp)) {
         s[0] = hp.x; s[1] = hp.y; s[2] = hp.z;
       } else {
         raise_err(A.status, kErrInverted);
@@ -1025,6 +1026,7 @@ __global__ void __launch_bounds__(kSBlock) k_audit(Args<R> A, double* part) {
 }
 
 // ============================================================== launchers
+
 template <typename R>
 void launch_predict(const Args<R>& A, const double* x, const double* v, double3 grav, hipStream_t s) {
   hipLaunchKernelGGL(k_predict<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, x, v, grav);
@@ -1039,32 +1041,36 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_narrow<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
   } else if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst, true>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, mode,
-                       (double*)nullptr, (double*)nullptr);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, true, M_>), dim3(A.grid),
+                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              (double*)nullptr));
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradFirst>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
-                       (double*)nullptr);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, false, M_>), dim3(A.grid),
+                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              (double*)nullptr));
   }
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect, true>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, 0,
-                       (double*)nullptr, (double*)nullptr);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, true, M_>), dim3(A.grid),
+                                              dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
+                                              (double*)nullptr));
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_grad<R, kGradDirect>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
-                       (double*)nullptr);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, false, M_>), dim3(A.grid),
+                                              dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
+                                              (double*)nullptr));
   }
 }
 template <typename R>
 void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    hipLaunchKernelGGL((k_dir<R, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, true, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, k));
     hipLaunchKernelGGL(k_objred_dir<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    hipLaunchKernelGGL((k_dir<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k);
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, false, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, k));
   }
 }
 template <typename R>
@@ -1078,11 +1084,12 @@ void launch_load_query(const Args<R>& A, const double* x, const double* xt, cons
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL((k_grad<R, kGradQuery>), dim3(A.grid), dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d);
+  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradQuery, false, M_>), dim3(A.grid),
+                                            dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d));
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_dir);
+  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_energy<R, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_dir));
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 1>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid,
                      A.self ? A.part_narrow : (const double*)nullptr, A.grid, out);
@@ -1090,7 +1097,7 @@ void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
 template <typename R>
 void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  hipLaunchKernelGGL(k_hvp<R>, dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir);
+  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_hvp<R, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir));
   // pair p^T H p is already inside H p at the vertices, so only k_hvp's partials are summed
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
 }

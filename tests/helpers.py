@@ -4,9 +4,11 @@ import numpy as np
 
 
 def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_max=None, eps=None, term=None,
-             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False):
+             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False, model="nh"):
     import paper_2405_08001_amd as P
     ctx = P.Context(0, precision, chunk=chunk)
+    if model != "nh":
+        ctx.pncg_set_model(model)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
     ctx.pncg_set_material(sc.E, sc.nu, sc.rho)
     flags = (P.CONTACT_SELF if sc.self_contact else 0) | (P.CONTACT_REST_EXCLUDE if rest_exclude else 0)
@@ -22,10 +24,10 @@ def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_ma
     return ctx
 
 
-def make_problem(sc, barrier_full=False, rest_exclude=True):
+def make_problem(sc, barrier_full=False, rest_exclude=True, model="nh"):
     from oracle import problem
     return problem.Problem.from_scene(sc, barrier_mode="full" if barrier_full else "psd",
-                                      rest_exclude=rest_exclude)
+                                      rest_exclude=rest_exclude, model=model)
 
 
 def rel(a, b):
