@@ -134,9 +134,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup_ctx(sc, precision):
+def setup_ctx(sc, precision, model="nh"):
     import paper_2405_08001_amd as P
     ctx = P.Context(0, P.MIXED if precision == "mixed" else P.FP64)
+    if model != "nh":
+        ctx.pncg_set_model(model)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
     ctx.pncg_set_material(sc.E, sc.nu, sc.rho)
     ctx.pncg_set_contact(sc.dhat, sc.kappa, sc.cell, sc.planes,
@@ -145,9 +147,9 @@ def setup_ctx(sc, precision):
     return ctx
 
 
-def run(sc, precision, warmup, steps, profile_frames):
+def run(sc, precision, warmup, steps, profile_frames, model="nh"):
     import torch
-    ctx = setup_ctx(sc, precision)
+    ctx = setup_ctx(sc, precision, model)
     dev = torch.device("cuda:0")
     x = torch.tensor(sc.x0, dtype=torch.float64, device=dev)
     v = torch.tensor(sc.v0, dtype=torch.float64, device=dev)
@@ -289,6 +291,30 @@ def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
         r["frames_rebuilds_per_frame"] = round(reb / 10, 2)
         ctx.close()
         out[name] = r
+    return out
+
+
+def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr")):
+    """The pile as configured under each other material model (mixed form):
+    iteration rate, frame time, iterations per frame, and the sweep's
+    roofline (its algorithmic bytes do not depend on the model)."""
+    out = {"frames_warmup": warmup, "frames_timed": steps}
+    kt, kv, kq = KERNEL_BYTES["grad"]["mixed"]
+    for model in models:
+        try:
+            r = run(sc, "mixed", warmup, steps, profile_frames, model=model)
+        except Exception as e:  # a model whose trajectory leaves its domain
+            out[model] = {"error": str(e)}
+            continue
+        ips = r["iters"] / r["seconds"]
+        prof = {k: v for k, v in r["prof"].items() if v[1] > 0}
+        gus = prof["grad"][0] / prof["grad"][1]
+        gb = kt * sc.nT + kv * sc.nV + kq * r["mean_cand"]
+        out[model] = {"iters_per_s": round(ips, 1), "ms_per_frame": round(1e3 * r["seconds"] / r["frames"], 4),
+                      "iters_per_frame": round(r["iters"] / r["frames"], 2),
+                      "grad_us": round(gus, 3), "dir_us": round(prof["dir"][0] / prof["dir"][1], 3),
+                      "grad_frac": round(gb / (gus * 1e-6) / HBM_PEAK, 4),
+                      "min_distance_after": r["dmin"], "min_detF_after": r["jmin"]}
     return out
 
 
@@ -462,6 +488,7 @@ def main():
     ap.add_argument("--no-beta-ablation", action="store_true", help="skip the beta-rule comparison")
     ap.add_argument("--no-dhat-strategy", action="store_true", help="skip the larger-dhat comparison")
     ap.add_argument("--no-split", action="store_true", help="skip the per-object splitting comparison")
+    ap.add_argument("--no-materials", action="store_true", help="skip the pile under the other material models")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -576,6 +603,11 @@ def main():
         log("adjoint: 30,000-tet bar, 30 steps ...")
         out["adjoint"] = run_adjoint()
         log(f"  {out['adjoint']['adjoint_ms_per_step']} ms/step backward")
+    if not args.no_materials:
+        log("pile under the SNH, ARAP and FCR models ...")
+        out["materials"] = run_materials(sc)
+        log("  " + ", ".join(f"{k} {v.get('iters_per_s', v.get('error'))}" for k, v in out["materials"].items()
+                             if isinstance(v, dict)))
     if not args.no_beta_ablation:
         log("beta rules: pile and cube ...")
         out["beta_ablation"] = run_beta_ablation(sc, m["state"])

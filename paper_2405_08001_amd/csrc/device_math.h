@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <limits>
 
 namespace pncg {
 
@@ -319,12 +320,26 @@ struct Polar {
   R ik[3];            // 1 / kappa_i
 };
 
+// Reciprocal, square root and reciprocal square root inside the polar
+// decomposition: the hardware's approximate (1 ulp) instructions in float,
+// whose result is accurate to float rounding either way; IEEE operations in
+// double.
+__device__ __forceinline__ float pol_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double pol_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float pol_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double pol_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float pol_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double pol_rsq(double x) { return 1.0 / sqrt(x); }
+
 template <typename R>
-__host__ __device__ __forceinline__ void jacobi_rot(R& app, R& aqq, R& apq, R& arp, R& arq, V3<R>& vp, V3<R>& vq) {
-  if (apq == R(0)) return;
-  const R th = (aqq - app) / (R(2) * apq);
-  const R t = std::copysign(R(1), th) / (std::fabs(th) + std::sqrt(std::fma(th, th, R(1))));
-  const R c = R(1) / std::sqrt(std::fma(t, t, R(1)));
+__device__ __forceinline__ void jacobi_rot(R& app, R& aqq, R& apq, R& arp, R& arq, V3<R>& vp, V3<R>& vq) {
+  // skip zero and subnormal off-diagonals: the float reciprocal flushes a
+  // subnormal input to zero, and (aqq - app) * inf is NaN when aqq == app
+  if (!(std::fabs(apq) >= std::numeric_limits<R>::min())) return;
+  const R th = (aqq - app) * pol_rcp(R(2) * apq);
+  // |th| large: th^2 overflows, the reciprocal gives t = 0 (no rotation)
+  const R t = std::copysign(pol_rcp(std::fabs(th) + pol_sqrt(std::fma(th, th, R(1)))), th);
+  const R c = pol_rsq(std::fma(t, t, R(1)));
   const R sn = t * c;
   app -= t * apq;
   aqq += t * apq;
@@ -340,17 +355,17 @@ __host__ __device__ __forceinline__ void jacobi_rot(R& app, R& aqq, R& apq, R& a
 // Jacobi sweeps: enough for rounding-level off-diagonals from any start.
 template <typename R>
 struct PolarSweeps {
-  static constexpr int value = 5;
+  static constexpr int value = 4;
 };
 template <>
 struct PolarSweeps<double> {
-  static constexpr int value = 6;
+  static constexpr int value = 5;
 };
 
 // False where a kappa_i is not positive (the I1 Hessian is undefined there)
 // or the decomposition is not finite (F of rank < 2).
 template <typename R>
-__host__ __device__ __forceinline__ bool polar_rv(const V3<R> f[3], Polar<R>& P) {
+__device__ __forceinline__ bool polar_rv(const V3<R> f[3], Polar<R>& P) {
   R a00 = dot(f[0], f[0]), a11 = dot(f[1], f[1]), a22 = dot(f[2], f[2]);
   R a01 = dot(f[0], f[1]), a02 = dot(f[0], f[2]), a12 = dot(f[1], f[2]);
   V3<R> v0 = mk3(R(1), R(0), R(0)), v1 = mk3(R(0), R(1), R(0)), v2 = mk3(R(0), R(0), R(1));
@@ -367,9 +382,9 @@ __host__ __device__ __forceinline__ bool polar_rv(const V3<R> f[3], Polar<R>& P)
   const V3<R> Fv0 = v0.x * f[0] + v0.y * f[1] + v0.z * f[2];
   const V3<R> Fv1 = v1.x * f[0] + v1.y * f[1] + v1.z * f[2];
   const V3<R> Fv2 = v2.x * f[0] + v2.y * f[1] + v2.z * f[2];
-  const V3<R> u0 = (R(1) / std::sqrt(dot(Fv0, Fv0))) * Fv0;
+  const V3<R> u0 = pol_rsq(dot(Fv0, Fv0)) * Fv0;
   const V3<R> w1 = Fv1 - dot(u0, Fv1) * u0;
-  const V3<R> u1 = (R(1) / std::sqrt(dot(w1, w1))) * w1;
+  const V3<R> u1 = pol_rsq(dot(w1, w1)) * w1;
   const V3<R> u2 = cross(u0, u1);
   P.u[0] = u0; P.u[1] = u1; P.u[2] = u2;
   P.v[0] = v0; P.v[1] = v1; P.v[2] = v2;
@@ -377,9 +392,9 @@ __host__ __device__ __forceinline__ bool polar_rv(const V3<R> f[3], Polar<R>& P)
   P.s[1] = dot(u1, Fv1);
   P.s[2] = dot(u2, Fv2);
   const R k0 = P.s[1] + P.s[2], k1 = P.s[0] + P.s[2], k2 = P.s[0] + P.s[1];
-  P.ik[0] = R(1) / k0;
-  P.ik[1] = R(1) / k1;
-  P.ik[2] = R(1) / k2;
+  P.ik[0] = pol_rcp(k0);
+  P.ik[1] = pol_rcp(k1);
+  P.ik[2] = pol_rcp(k2);
   return k0 > R(0) && k1 > R(0) && k2 > R(0) && P.ik[0] < R(INFINITY) && P.ik[1] < R(INFINITY) &&
          P.ik[2] < R(INFINITY);
 }
