@@ -54,7 +54,9 @@ KERNEL_BYTES = {
 
 
 # kernels of the mixed single-scene path, by the name rocprofv3 records
-KERNEL_NAMES = {"grad": "k_grad<float", "dir": "k_dir<float", "narrow": "k_narrow<float"}
+# the Neo-Hookean, unsplit instantiations the pile runs (template arguments:
+# real type, sweep mode, split, model, ...)
+KERNEL_NAMES = {"grad": "k_grad<float, 1, false, 0,", "dir": "k_dir<float, false, 0,", "narrow": "k_narrow<float, false>"}
 CALIB_BYTES = 256 << 20          # the calibration copy reads and writes this many bytes
 SOLVER_SOURCES = ("solver_kernels.hip", "sweep_common.h", "device_math.h", "internal.h")
 
