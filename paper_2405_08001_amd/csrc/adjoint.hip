@@ -322,7 +322,15 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
       V3<double> d[3];
       dF_cols(rec.B, pget(rec.v[0]), pget(rec.v[1]), pget(rec.v[2]), pget(rec.v[3]), d);
       V3<double> hp;
-      if (el_Hp<double, M>(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3), hp)) {
+      bool ok;
+      if constexpr (M == kModelNH) {
+        // spelled out for Neo-Hookean: the generic helper costs registers here
+        ok = kin.J > 0.0;
+        if (ok) hp = nh_Hp(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3));
+      } else {
+        ok = el_Hp<double, M>(kin, rec.vmu, rec.vlam, d, shape_vec(rec.B, code & 3), hp);
+      }
+      if (ok) {
         s[0] = hp.x;
         s[1] = hp.y;
         s[2] = hp.z;

@@ -145,7 +145,16 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
           const ElemRec<R> rec = A.elem[code >> 2];
           Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
           V3<R> g, dg;
-          if (el_grad_diag<R, M>(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg)) {
+          bool ok;
+          if constexpr (M == kModelNH) {
+            // the Neo-Hookean form spelled out: the generic helper's checks
+            // cost this register-bound kernel registers and spills
+            ok = kin.J > R(0);
+            if (ok) nh_grad_diag(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg);
+          } else {
+            ok = el_grad_diag<R, M>(kin, rec.vmu, rec.vlam, shape_vec(rec.B, code & 3), g, dg);
+          }
+          if (ok) {
             sv[0] = g.x; sv[1] = g.y; sv[2] = g.z; sv[3] = dg.x; sv[4] = dg.y; sv[5] = dg.z;
           } else {
             atomicOr(A.err, kErrInverted);
@@ -238,9 +247,13 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
         Kin<R> kin = kinematics<R>(rec.B, X(rec.v[0]), X(rec.v[1]), X(rec.v[2]), X(rec.v[3]));
         V3<R> d[3];
         dF_cols(rec.B, Pd(rec.v[0]), Pd(rec.v[1]), Pd(rec.v[2]), Pd(rec.v[3]), d);
-        R ph = R(0);
-        if (!el_pHp<R, M>(kin, rec.vmu, rec.vlam, d, ph)) atomicOr(A.err, kErrInverted);
-        el += double(ph);
+        if constexpr (M == kModelNH) {
+          el += double(nh_pHp(kin, rec.vmu, rec.vlam, d));   // inversion is caught by the sweep
+        } else {
+          R ph = R(0);
+          if (!el_pHp<R, M>(kin, rec.vmu, rec.vlam, d, ph)) atomicOr(A.err, kErrInverted);
+          el += double(ph);
+        }
       }
       double red[3] = {php + A.h2 * el, pmv, pmc};
       {
