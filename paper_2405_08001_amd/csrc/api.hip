@@ -96,7 +96,8 @@ struct pncg_ctx {
   ObjScal* d_oscal = nullptr;
   double *d_vdots = nullptr, *d_tphp = nullptr, *d_vphp = nullptr, *d_opair = nullptr;
   StepStatus* d_status = nullptr;
-  StepStatus* h_status = nullptr;  // pinned
+  StepStatus* h_status = nullptr;  // pinned [2]: the step loop reads one while the other is in flight
+  hipEvent_t st_ev[2] = {nullptr, nullptr};  // recorded after each status copy
   long long* h_n = nullptr;        // pinned [2]
   double* d_part_grad = nullptr;
   double* d_part_dir = nullptr;
@@ -201,7 +202,8 @@ int ensure_device(pncg_ctx* c) {
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->own_stream = true;
   }
-  HIPCHK(c, hipHostMalloc((void**)&c->h_status, sizeof(StepStatus), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->h_status, 2 * sizeof(StepStatus), hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i) HIPCHK(c, hipEventCreateWithFlags(&c->st_ev[i], hipEventDisableTiming));
   HIPCHK(c, hipHostMalloc((void**)&c->h_n, 4 * sizeof(long long), hipHostMallocDefault));
   c->dev_ready = true;
   return PNCG_OK;
@@ -465,6 +467,20 @@ void prof_collect(pncg_ctx* c) {
   c->ev_used = 0;
 }
 
+// Copy the step status into pinned slot `slot` behind the work enqueued so
+// far, and mark it with that slot's event.
+int enqueue_status(pncg_ctx* c, int slot) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status + slot, c->d_status, sizeof(StepStatus), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(c->st_ev[slot], c->stream));
+  return PNCG_OK;
+}
+// Wait for slot's copy (and everything enqueued before it).
+int wait_status(pncg_ctx* c, int slot) {
+  HIPCHK(c, hipEventSynchronize(c->st_ev[slot]));
+  if (c->profiling) prof_collect(c);
+  return PNCG_OK;
+}
+
 int read_status(pncg_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(StepStatus), hipMemcpyDeviceToHost, c->stream));
   int rc = sync(c);
@@ -494,64 +510,96 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     A.cand = c->d_cand;
     A.cand_cap = c->cand_cap;
   }
-  int k = 0;
-  int mode = 0;  // kModeNormal
   // With self contact the chunk length is chosen so that the displacement
   // bound is expected to stay inside half the skin (observed growth per
   // iteration, starting from the worst case dhat / 2); the device pauses the
   // chunk if the prediction fails.
   double D = 0.0, rate = 0.5 * c->dhat;
-  while (true) {
+  auto chunk_len = [&](double Dpred) {
     int m = c->chunk;
     if (A.self) {
-      const double room = 0.5 * c->skin - D;
+      const double room = 0.5 * c->skin - Dpred;
       const double want = room / std::max(rate, 1e-300);
       m = (int)std::min<double>(std::max<double>(std::floor(want), 1.0), (double)c->chunk);
     }
-    const int kend = std::min(k + m, c->iter_max + 1);
-    const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
-    for (int j = k; j < kend; ++j) {
+    return m;
+  };
+  // Enqueue iterations [k0, k0 + m) (the last launch of the cap finishes the
+  // step); returns the end of the chunk.
+  const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
+  auto launch_chunk = [&](int k0, int m, int mode0) {
+    const int kend = std::min(k0 + m, c->iter_max + 1);
+    for (int j = k0; j < kend; ++j) {
+      int e = prof_begin(c, kind_first);
       if (j == c->iter_max) {
-        ev = prof_begin(c, kind_first);
         launch_iteration_first<R>(A, j, 1 /*finish*/, c->stream);
-        prof_end(c, ev);
+        prof_end(c, e);
         break;
       }
-      ev = prof_begin(c, kind_first);
-      launch_iteration_first<R>(A, j, (j == k) ? mode : 0, c->stream);
-      prof_end(c, ev);
+      launch_iteration_first<R>(A, j, (j == k0) ? mode0 : 0, c->stream);
+      prof_end(c, e);
       if (A.self) {
-        ev = prof_begin(c, PNCG_PROF_GRAD);
+        e = prof_begin(c, PNCG_PROF_GRAD);
         launch_iteration_grad<R>(A, j, c->stream);
-        prof_end(c, ev);
+        prof_end(c, e);
       }
-      ev = prof_begin(c, PNCG_PROF_DIR);
+      e = prof_begin(c, PNCG_PROF_DIR);
       launch_iteration_dir<R>(A, j, c->stream);
-      prof_end(c, ev);
+      prof_end(c, e);
     }
-    mode = 0;
-    if ((rc = read_status(c))) return rc;
-    const StepStatus s = *c->h_status;
-    if (s.err & kErrCapacity) return kRestart;
-    if ((rc = check_status_err(c, s))) return rc;
+    return kend;
+  };
+  // One chunk stays in flight while the status of the one before it is read,
+  // so the device does not idle across the host's round trip.  Launches after
+  // a stop or a pause do nothing (each iteration's first kernel sees its
+  // predecessor's flag), and a resume rewrites the paused iteration's
+  // scalars, so a chunk sent ahead is harmless.  With profiling on, chunks go
+  // one at a time so that every recorded event pair has completed when the
+  // totals are collected.
+  const bool ahead = !c->profiling;
+  auto bail = [&](int code) {
+    (void)hipStreamSynchronize(c->stream);
+    return code;
+  };
+  int k = 0, cur = 0;
+  int kend = launch_chunk(0, chunk_len(0.0), 0 /*kModeNormal*/);
+  if ((rc = enqueue_status(c, cur))) return rc;
+  while (true) {
+    int kn = -1;
+    if (ahead && kend <= c->iter_max) {
+      kn = launch_chunk(kend, chunk_len(D + rate * (kend - k)), 0);
+      if ((rc = enqueue_status(c, cur ^ 1))) return bail(rc);
+    }
+    if ((rc = wait_status(c, cur))) return bail(rc);
+    const StepStatus s = c->h_status[cur];
+    if (s.err & kErrCapacity) return bail(kRestart);
+    if ((rc = check_status_err(c, s))) return bail(rc);
     if (s.stopped) break;
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
-      ev = prof_begin(c, PNCG_PROF_REBUILD);
-      if ((rc = build_solver_list(c, (p & 1) ? c->d_x1 : c->d_x0))) return rc;
-      prof_end(c, ev);
+      int e = prof_begin(c, PNCG_PROF_REBUILD);
+      if ((rc = build_solver_list(c, (p & 1) ? c->d_x1 : c->d_x0))) return bail(rc);
+      prof_end(c, e);
       ++rebuilds;
       A.cand = c->d_cand;
       A.cand_cap = c->cand_cap;
       if (p > k) rate = std::max(rate, (s.D - D) / (p - k + 1));
       D = 0.0;
       k = p;
-      mode = 2;  // kModeResume
+      kend = launch_chunk(k, chunk_len(D), 2 /*kModeResume*/);
+      if ((rc = enqueue_status(c, cur))) return bail(rc);
       continue;
     }
     if (kend > k) rate = std::max(0.0, (s.D - D) / (kend - k));
     D = s.D;
     k = kend;
+    if (kn >= 0) {
+      kend = kn;
+      cur ^= 1;
+    } else {
+      kend = launch_chunk(k, chunk_len(D), 0);
+      if ((rc = enqueue_status(c, cur))) return bail(rc);
+    }
   }
   ev = prof_begin(c, PNCG_PROF_PREDICT);
   launch_finalize<R>(A, x_out, v_out, c->stream);
@@ -868,6 +916,8 @@ void pncg_destroy(pncg_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->st_ev)
+      if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
