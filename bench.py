@@ -138,7 +138,9 @@ def log(msg):
 
 def setup_ctx(sc, precision, model="nh"):
     import paper_2405_08001_amd as P
-    ctx = P.Context(0, P.MIXED if precision == "mixed" else P.FP64)
+    # the library runs on torch's current stream (see main), so its inputs
+    # need no host-side wait
+    ctx = P.Context(0, P.MIXED if precision == "mixed" else P.FP64, stream=_torch_stream())
     if model != "nh":
         ctx.pncg_set_model(model)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
@@ -147,6 +149,14 @@ def setup_ctx(sc, precision, model="nh"):
                          (P.CONTACT_SELF if sc.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
     ctx.pncg_set_solver(sc.iter_max, sc.eps, P.TERM_DELTA_E, sc.gravity, 0)
     return ctx
+
+
+def _torch_stream():
+    """Handle of torch's current stream, or None for its default stream (the
+    library then uses a stream of its own)."""
+    import torch
+    h = torch.cuda.current_stream().cuda_stream
+    return h or None
 
 
 def run(sc, precision, warmup, steps, profile_frames, model="nh"):
@@ -512,6 +522,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    # one stream (default priority) for torch and the library's contexts:
+    # device inputs are then ordered without a host-side wait per step
+    torch.cuda.set_stream(torch.cuda.Stream())
     if args.calibrate_copy:
         calibration_copy()
     import scenes

@@ -143,6 +143,7 @@ class Context:
 
     def __init__(self, device=0, precision=FP64, stream=None, chunk=0):
         opts = pncg_opts(device, precision, stream, 0, chunk)
+        self._stream = int(stream or 0)
         h = C.c_void_p()
         rc = _L.pncg_create(C.byref(h), C.byref(opts))
         if rc < 0:
@@ -229,7 +230,7 @@ class Context:
             if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
                     and tuple(t.shape) == (self.nV, 3)):
                 raise ValueError("step_dev needs contiguous float64 CUDA tensors of shape (nV, 3)")
-        _ready(x)
+        _ready(x, self._stream)
         st = pncg_stats()
         rc = self._check(_L.pncg_step_dev(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), float(h),
                                           C.c_void_p(x_out.data_ptr()), C.c_void_p(v_out.data_ptr()), C.byref(st)))
@@ -299,7 +300,7 @@ class Context:
         n = self.nV
         if not (Ebar.is_cuda and Ebar.element_size() == 8 and Ebar.is_contiguous() and Ebar.numel() == self.nT):
             raise ValueError(f"Ebar must be a contiguous float64 CUDA tensor of {self.nT} values")
-        _ready(x1)
+        _ready(x1, self._stream)
         st = pncg_adjoint_stats()
         rc = self._check(_L.pncg_adjoint_step_dev(
             self._h, _dev_ptr(x1, n, "x1"), float(h), _dev_ptr(xbar, n, "xbar"), _dev_ptr(vbar, n, "vbar"),
@@ -321,12 +322,17 @@ class Context:
         return {k: (float(us[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
 
 
-def _ready(t):
+def _ready(t, stream=0):
     """The library reads device inputs on its own stream, which does not wait
     for torch's: finish what torch has queued on the tensor's device (a
-    clone of the state, say) before the library reads it."""
+    clone of the state, say) before the library reads it.  Nothing to wait
+    for when the library runs on torch's current stream (``stream``, the
+    handle given at creation)."""
     import torch
-    torch.cuda.current_stream(t.device).synchronize()
+    cur = torch.cuda.current_stream(t.device)
+    if stream and cur.cuda_stream == stream:
+        return
+    cur.synchronize()
 
 
 def _dev_ptr(t, n, what):
@@ -355,6 +361,7 @@ class Batch:
             raise ValueError("E, nu, rho need one value per tet")
         pl = None if planes is None else _f64(planes).reshape(S, 4)
         opts = pncg_opts(device, precision, stream, 0, 0)
+        self._stream = int(stream or 0)
         h = C.c_void_p()
         rc = _L.pncg_batch_create(C.byref(h), C.byref(opts), S, _ptr(vert_off), _ptr(X), _ptr(tet_off), _ptr(tets),
                                   _ptr(tri_off), _ptr(tris), _ptr(E), _ptr(nu), _ptr(rho), _ptr(pl))
@@ -405,14 +412,14 @@ class Batch:
     def pncg_batch_step(self, x, v, h, x_out, v_out):
         """float64 CUDA tensors (nV, 3); x_out/v_out must not alias x/v."""
         n = self.nV
-        _ready(x)
+        _ready(x, self._stream)
         self._check(_L.pncg_batch_step(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h),
                                        _dev_ptr(x_out, n, "x_out"), _dev_ptr(v_out, n, "v_out")))
 
     def pncg_batch_run(self, x, v, h, nsteps):
         """nsteps steps in place on the float64 CUDA tensors x, v (nV, 3)."""
         n = self.nV
-        _ready(x)
+        _ready(x, self._stream)
         self._check(_L.pncg_batch_run(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(nsteps)))
 
     def pncg_batch_stats(self):
@@ -424,7 +431,7 @@ class Batch:
 
     def pncg_batch_autotune(self, x, v, h, reps=3):
         n = self.nV
-        _ready(x)
+        _ready(x, self._stream)
         out = C.c_int32()
         self._check(_L.pncg_batch_autotune(self._h, _dev_ptr(x, n, "x"), _dev_ptr(v, n, "v"), float(h), int(reps),
                                            C.byref(out)))

@@ -102,7 +102,7 @@ struct pncg_ctx {
   double* d_part_grad = nullptr;
   double* d_part_dir = nullptr;
   double* d_part_narrow = nullptr;
-  double* d_io = nullptr;          // [3][nV][3] staging for host inputs/outputs
+  double* d_io = nullptr;          // [4][nV][3] staging for host inputs/outputs
   double* d_scalar = nullptr;      // [8]
   // broad phase
   int tsize = 0;
@@ -527,8 +527,23 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   // Enqueue iterations [k0, k0 + m) (the last launch of the cap finishes the
   // step); returns the end of the chunk.
   const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
+  // A chunk that reaches the cap ends the step whatever happens before it
+  // (unless a pause comes first), so the output kernel goes right behind it;
+  // it reads the final iteration from the device status, and a later one
+  // supersedes it if the step resumes.  Not when an output overlaps an
+  // input: a capacity rerun of the step reads the inputs again.
+  const size_t n3 = 3 * (size_t)c->nV;
+  auto overlap = [n3](const double* a, const double* b) {
+    const uintptr_t ua = reinterpret_cast<uintptr_t>(a), ub = reinterpret_cast<uintptr_t>(b);
+    const uintptr_t len = n3 * sizeof(double);
+    return ua < ub + len && ub < ua + len;
+  };
+  const bool early_final = !overlap(x_out, x_dev) && !overlap(x_out, v_dev) && !overlap(v_out, x_dev) &&
+                           !overlap(v_out, v_dev);
+  bool last_is_final = false;
   auto launch_chunk = [&](int k0, int m, int mode0) {
     const int kend = std::min(k0 + m, c->iter_max + 1);
+    last_is_final = false;
     for (int j = k0; j < kend; ++j) {
       int e = prof_begin(c, kind_first);
       if (j == c->iter_max) {
@@ -546,6 +561,12 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
       e = prof_begin(c, PNCG_PROF_DIR);
       launch_iteration_dir<R>(A, j, c->stream);
       prof_end(c, e);
+    }
+    if (early_final && kend == c->iter_max + 1) {
+      const int e = prof_begin(c, PNCG_PROF_PREDICT);
+      launch_finalize<R>(A, x_out, v_out, c->stream);
+      prof_end(c, e);
+      last_is_final = true;
     }
     return kend;
   };
@@ -578,6 +599,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if (s.paused_at >= 0) {
       const int p = s.paused_at;
       int e = prof_begin(c, PNCG_PROF_REBUILD);
+      last_is_final = false;
       if ((rc = build_solver_list(c, (p & 1) ? c->d_x1 : c->d_x0))) return bail(rc);
       prof_end(c, e);
       ++rebuilds;
@@ -601,9 +623,11 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
       if ((rc = enqueue_status(c, cur))) return bail(rc);
     }
   }
-  ev = prof_begin(c, PNCG_PROF_PREDICT);
-  launch_finalize<R>(A, x_out, v_out, c->stream);
-  prof_end(c, ev);
+  if (!last_is_final) {
+    ev = prof_begin(c, PNCG_PROF_PREDICT);
+    launch_finalize<R>(A, x_out, v_out, c->stream);
+    prof_end(c, ev);
+  }
   if ((rc = read_status(c))) return rc;
   const StepStatus s = *c->h_status;
   if ((rc = check_status_err(c, s))) return rc;
@@ -1002,7 +1026,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
       (rc = dmalloc(c, &c->d_oid, nV)) || (rc = dmalloc(c, &c->d_ncand, 4)) ||
       (rc = dmalloc(c, &c->d_status, 1)) || (rc = dmalloc(c, &c->d_part_grad, 8 * (size_t)gmax)) ||
       (rc = dmalloc(c, &c->d_part_dir, 4 * (size_t)gmax)) || (rc = dmalloc(c, &c->d_part_narrow, gmax)) ||
-      (rc = dmalloc(c, &c->d_io, 9 * (size_t)nV)) || (rc = dmalloc(c, &c->d_scalar, 8)) ||
+      (rc = dmalloc(c, &c->d_io, 12 * (size_t)nV)) || (rc = dmalloc(c, &c->d_scalar, 8)) ||
       (rc = dmalloc(c, &c->d_item_lo, (size_t)nF + nE)) || (rc = dmalloc(c, &c->d_item_hi, (size_t)nF + nE)) ||
       (rc = dmalloc(c, &c->d_item_cnt, (size_t)nF + nE + surf.size())) ||
       (rc = dmalloc(c, &c->d_item_off, (size_t)nF + nE + surf.size() + 1)) ||
@@ -1290,7 +1314,7 @@ int pncg_step(pncg_ctx* c, const double* x, const double* v, double h, double* x
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = upload_rows(c, x, c->d_io, c->nV)) || (rc = upload_rows(c, v, c->d_io + n3, c->nV))) return rc;
   double* xo = c->d_io + 2 * n3;
-  double* vo = c->d_io + n3;  // v is consumed by the predictor before finalize writes here
+  double* vo = c->d_io + 3 * n3;
   rc = pncg_step_dev(c, c->d_io, c->d_io + n3, h, xo, vo, st);
   if (rc < 0) return rc;
   HIPCHK(c, hipMemcpyAsync(x_out, xo, sizeof(double) * n3, hipMemcpyDeviceToHost, c->stream));
