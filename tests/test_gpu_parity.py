@@ -302,6 +302,41 @@ def test_grad_abs_rule_matches_scaled_grad_rel():
     assert np.array_equal(xa, xr)
 
 
+@pytest.mark.parametrize("K", [1, 12])
+def test_in_place_step_after_capacity_rerun(K):
+    """Outputs may alias the inputs.  On the stacked cubes (4 mm cells) a
+    fresh context's first solver-list build needs more spatial-grid entries
+    than the initial 8 (nF + nE) + nSV + 4096, so the step is run again from
+    its inputs with a larger grid; the in-place step, the out-of-place step
+    and the host-pointer step agree."""
+    import torch
+    _say(f"in-place step with a capacity rerun K={K}")
+    sc, x0, v0 = _stack_drop()
+    dev = torch.device("cuda:0")
+    outs = []
+    for how in ("apart", "in_place", "host"):
+        ctx = make_ctx(sc, 0, iter_max=K, eps=0.0, term="delta_e")
+        if how == "host":
+            xh, vh, st = ctx.pncg_step(x0, v0, sc.h)
+            outs.append((xh, vh, st))
+            continue
+        x = torch.tensor(x0, device=dev)
+        v = torch.tensor(v0, device=dev)
+        if how == "apart":
+            xo, vo = torch.empty_like(x), torch.empty_like(v)
+        else:
+            xo, vo = x, v
+        st = ctx.pncg_step_dev(x, v, sc.h, xo, vo)
+        outs.append((xo.cpu().numpy(), vo.cpu().numpy(), st))
+    (xa, va, sa), (xi, vi, si), (xh, vh, sh) = outs
+    _say(f"  rebuilds {sa['rebuilds']}/{si['rebuilds']}/{sh['rebuilds']} "
+         f"rel dx in place {rel(xi - x0, xa - x0):.2e} host {rel(xh - x0, xa - x0):.2e}")
+    assert sa["iters"] == si["iters"] == sh["iters"] == K
+    # pair forces are summed with float64 atomics: equal up to their order
+    for xb, vb in ((xi, vi), (xh, vh)):
+        assert rel(xb - x0, xa - x0) <= 1e-12 and rel(vb, va) <= 1e-12
+
+
 def test_step_dev_reads_inputs_torch_has_just_written():
     """Device-pointer steps read their inputs on the library's stream: the
     binding first finishes torch's queued work, so a state that torch is
