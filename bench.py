@@ -306,10 +306,11 @@ def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
     return out
 
 
-def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr")):
+def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr"), batched=True):
     """The pile as configured under each other material model (mixed form):
     iteration rate, frame time, iterations per frame, and the sweep's
-    roofline (its algorithmic bytes do not depend on the model)."""
+    roofline (its algorithmic bytes do not depend on the model); and the
+    256-scene batch under each model (10 graph-captured steps)."""
     out = {"frames_warmup": warmup, "frames_timed": steps}
     kt, kv, kq = KERNEL_BYTES["grad"]["mixed"]
     for model in models:
@@ -327,6 +328,10 @@ def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "ara
                       "grad_us": round(gus, 3), "dir_us": round(prof["dir"][0] / prof["dir"][1], 3),
                       "grad_frac": round(gb / (gus * 1e-6) / HBM_PEAK, 4),
                       "min_distance_after": r["dmin"], "min_detF_after": r["jmin"]}
+        if batched:
+            bb = run_batched(10, 10, model=model)
+            out[model]["batched"] = {k: bb[k] for k in ("scene_steps_per_s", "ms_per_batch_step",
+                                                         "mean_iters_per_scene_step", "block", "max_team")}
     return out
 
 
@@ -397,7 +402,7 @@ def cpu_baseline(sc, state, budget_iters=1):
                        f"(float64 NumPy oracle, 1 thread, {dt:.1f} s)")
 
 
-def run_batched(steps, warmup):
+def run_batched(steps, warmup, model="nh"):
     """The 256-scene batch, mixed precision: W eager steps (the scenes fall
     onto their planes), then K steps as one captured graph."""
     import torch
@@ -407,6 +412,8 @@ def run_batched(steps, warmup):
     b = scenes.pack_batch(scs)
     bt = P.Batch(b["vert_off"], b["X"], b["tet_off"], b["tets"], b["tri_off"], b["tris"], b["E"], b["nu"], b["rho"],
                  b["planes"], precision=P.MIXED)
+    if model != "nh":
+        bt.pncg_batch_set_model(model)
     s0 = scs[0]
     bt.pncg_batch_set_params(s0.dhat, s0.kappa, s0.iter_max, s0.eps, P.TERM_DELTA_E, s0.gravity, 0)
     dev = torch.device("cuda:0")
@@ -500,7 +507,7 @@ def main():
     ap.add_argument("--no-beta-ablation", action="store_true", help="skip the beta-rule comparison")
     ap.add_argument("--no-dhat-strategy", action="store_true", help="skip the larger-dhat comparison")
     ap.add_argument("--no-split", action="store_true", help="skip the per-object splitting comparison")
-    ap.add_argument("--no-materials", action="store_true", help="skip the pile under the other material models")
+    ap.add_argument("--no-materials", action="store_true", help="skip the pile and batch under the other material models")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
