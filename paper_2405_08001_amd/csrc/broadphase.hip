@@ -304,12 +304,14 @@ __device__ __forceinline__ bool vertex_slot_pair(const Broad& B, const PairCtx& 
   const V3<double> lo = v4(B.bkt_lo[t]), hi = v4(B.bkt_hi[t]);
   if (!(lo.x <= p.x && p.x <= hi.x && lo.y <= p.y && p.y <= hi.y && lo.z <= p.z && p.z <= hi.z)) return false;
   const int f = B.bkt_item[t] - B.nSV;
-  const unsigned long long pk = ((unsigned long long)(unsigned)v << 32) | (unsigned)f;
-  if (B.n_excl_pt && in_sorted(B.excl_pt, B.n_excl_pt, pk)) return false;
+  // the distance filter first: it rejects most pairs in one step, while the
+  // exclusion lookup is a chain of dependent loads (the filters commute)
   if (P.filter_d >= 0.0) {
     if (P.filter_obj && B.oid[v] != B.oid[idB.x]) return false;
     if (!(closest_pt(p, ldx(P.x, idB.x), ldx(P.x, idB.y), ldx(P.x, idB.z)).d < P.filter_d)) return false;
   }
+  const unsigned long long pk = ((unsigned long long)(unsigned)v << 32) | (unsigned)f;
+  if (B.n_excl_pt && in_sorted(B.excl_pt, B.n_excl_pt, pk)) return false;
   out = make_int2(v, f);
   return true;
 }
@@ -379,12 +381,13 @@ __device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, con
     const int3 cc = cell_of(corner, P.inv);
     if (cell_key(cc.x, cc.y, cc.z) != key) continue;
     const int e1 = ia - ebase, e2 = ib - ebase;
-    const unsigned long long pk = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
-    if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, pk)) continue;
+    // distance filter before the exclusion lookup (see vertex_slot_pair)
     if (P.filter_d >= 0.0) {
       if (P.filter_obj && B.oid[idA.x] != B.oid[idB.x]) continue;
       if (!(closest_ee(ldx(P.x, idA.x), ldx(P.x, idA.y), ldx(P.x, idB.x), ldx(P.x, idB.y)).d < P.filter_d)) continue;
     }
+    const unsigned long long pk = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
+    if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, pk)) continue;
     emit(make_int2(e1, e2));
   }
 }
