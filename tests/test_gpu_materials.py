@@ -311,3 +311,30 @@ def test_unknown_model_is_rejected():
     with pytest.raises(L.PncgError) as ei:
         ctx.pncg_set_model(7)
     assert ei.value.code == L.E_INVAL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("model", ["snh", "fcr"])
+def test_material_split_step_matches_oracle(model, precision):
+    """The per-object step (splitting computation) under a model: 10 fixed
+    iterations on the stacked cubes against the oracle's split step."""
+    from oracle import pncg
+    _say(f"material split step {model} precision={precision}")
+    sc, x0, v0 = _stack_drop()
+    K = 10
+    prob = make_problem(sc, model=model)
+    xo, _, st = pncg.step(prob, x0, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", split=True)
+    ctx = make_ctx(sc, precision, iter_max=K, eps=0.0, term="delta_e", split=True, model=model)
+    xg, _, sg = ctx.pncg_step(x0, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - x0, xo - x0)
+    bx, bdx = (1e-12, 1e-9) if precision == 0 else (1e-6, 1e-3)
+    if precision == 1:
+        u = np.random.default_rng(17).uniform(-1.0, 1.0, x0.shape)
+        xq = x0 * (1.0 + 2.0 ** -24 * u)
+        xp, _, _ = pncg.step(prob, xq, v0, sc.h, iter_max=K, eps=0.0, term="delta_e", split=True)
+        bx = max(bx, 20.0 * rel(xp, xo))
+        bdx = max(bdx, 20.0 * rel(xp - xq, xo - x0))
+    _say(f"  iters oracle={st.iters} gpu={sg['iters']} rel_x={rx:.3e} (bar {bx:.1e}) rel_dx={rdx:.3e} (bar {bdx:.1e})")
+    assert sg["iters"] == st.iters == K
+    assert sg["alpha_upper_hits"] == st.alpha_upper_hits
+    assert rx <= bx and rdx <= bdx
