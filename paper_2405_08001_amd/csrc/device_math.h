@@ -373,6 +373,10 @@ __device__ __forceinline__ bool polar_rv(const V3<R> f[3], Polar<R>& P) {
     jacobi_rot(a00, a11, a01, a02, a12, v0, v1);
     jacobi_rot(a00, a22, a02, a01, a12, v0, v2);
     jacobi_rot(a11, a22, a12, a01, a02, v1, v2);
+    // stop once the off-diagonal is at rounding level in every active lane
+    // of the wave (a wave-wide vote keeps the loop uniform)
+    const R off = std::fabs(a01) + std::fabs(a02) + std::fabs(a12);
+    if (__all(off <= std::numeric_limits<R>::epsilon() * (a00 + a11 + a22))) break;
   }
   // order by decreasing eigenvalue
   if (a00 < a11) { R t = a00; a00 = a11; a11 = t; V3<R> w = v0; v0 = v1; v1 = w; }
