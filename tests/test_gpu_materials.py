@@ -259,7 +259,7 @@ def test_material_batch_matches_single_scene_path(model, precision):
         assert rdx <= (1e-9 if precision == 0 else 1e-3)
 
 
-@pytest.mark.parametrize("model", ["snh", "fcr"])
+@pytest.mark.parametrize("model", ["snh", "arap", "fcr"])
 def test_material_adjoint_step_matches_oracle(model):
     """lambda and the parameter adjoint under a model: device CG against the
     oracle's sparse direct solve at the oracle's converged x^{t+1}."""
@@ -338,3 +338,35 @@ def test_material_split_step_matches_oracle(model, precision):
     assert sg["iters"] == st.iters == K
     assert sg["alpha_upper_hits"] == st.alpha_upper_hits
     assert rx <= bx and rdx <= bdx
+
+
+@pytest.mark.parametrize("model", ["snh", "fcr"])
+def test_material_trajectory_gradient_matches_oracle(model):
+    """The differentiable rollout under a model (the moduli are re-uploaded
+    on every pass): 4 steps of the small bar onto the floor, dL/dE against
+    the oracle's Newton trajectory and direct-solve adjoint recursion."""
+    import torch
+    import paper_2405_08001_amd as L
+    from oracle import adjoint, problem
+    sc = scenes.diff_bar_scene(seed=4, nx=4, ny=2, nz=2, dx=0.01, lift=0.0012)
+    v0 = np.zeros_like(sc.X)
+    v0[:, 2] = -0.04
+    steps = 4
+    rng = np.random.default_rng(5)
+    E_tgt = 1e5 * np.exp(0.5 * rng.standard_normal(sc.nT))
+    P2 = problem.Problem.from_scene(sc, model=model)
+    P2.set_material(E_tgt, sc.nu)
+    x_tgt = adjoint.trajectory(P2, sc.X, v0, sc.h, steps)[0][-1]
+    P = make_problem(sc, model=model)
+    Lo, Eo, _ = adjoint.loss_and_gradient(P, sc.X, v0, sc.h, steps, x_tgt)
+    ctx = make_ctx(sc, 0, model=model)
+    sim = L.Simulation(ctx, sc.nu, sc.rho, sc.h, steps, checkpoint=2, cg_tol=1e-12, cg_max=20000)
+    dev = torch.device("cuda:0")
+    Et = torch.tensor(sc.E, dtype=torch.float64, requires_grad=True)
+    xT, _ = L.simulate(Et, torch.tensor(sc.X, device=dev), torch.tensor(v0, device=dev), sim)
+    loss = ((xT - torch.tensor(x_tgt, device=dev)) ** 2).sum()
+    loss.backward()
+    Lg, Eg = float(loss.detach()), Et.grad.numpy()
+    _say(f"trajectory {model}: L {Lg:.6e}/{Lo:.6e} rel dL/dE {rel(Eg, Eo):.2e}")
+    assert abs(Lg - Lo) <= 1e-8 * Lo
+    assert rel(Eg, Eo) <= 1e-5
