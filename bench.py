@@ -196,6 +196,23 @@ def run(sc, precision, warmup, steps, profile_frames, model="nh"):
                 prof=prof, dmin=dmin, jmin=jmin, state=state)
 
 
+def run_host_io(sc, state, frames=20):
+    """The pile through pncg_step with host arrays (mixed form, from the state
+    after warm-up): x and v go to the device and x', v' come back every
+    step, so the rate includes the PCIe transfers."""
+    ctx = setup_ctx(sc, "mixed")
+    x, v = state[0].copy(), state[1].copy()
+    its = 0
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        x, v, st = ctx.pncg_step(x, v, sc.h)
+        its += st["iters"]
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"frames": frames, "iters_per_s": round(its / dt, 1), "ms_per_frame": round(1e3 * dt / frames, 4),
+            "bytes_per_frame_over_pcie": 4 * 3 * 8 * sc.nV}
+
+
 def _solve_once(sc, prec, x0, v0, iters, eps, term, flags=0, dhat=None):
     """One step of scene sc from (x0, v0) with the given stopping rule (and
     optionally another dhat): (x, v, stats, seconds)."""
@@ -617,6 +634,9 @@ def main():
             out["fp64"]["grad_roofline"] = {"achieved": round(gb / (gus * 1e-6) / 1e9, 1), "avg_launch_us": round(gus, 3),
                                             "bytes_per_launch": int(gb), "frac": round(gb / (gus * 1e-6) / HBM_PEAK, 4)}
         out["mixed_vs_fp64_speedup"] = round(ips / fips, 3)
+    log("pile through host arrays (PCIe-inclusive) ...")
+    out["host_io"] = run_host_io(sc, m["state"])
+    log(f"  {out['host_io']['iters_per_s']} it/s, {out['host_io']['ms_per_frame']} ms/frame")
     if not args.no_batched:
         log("batched: 256 scenes ...")
         out["batched"] = run_batched(args.batched_steps, args.batched_warmup)
