@@ -323,11 +323,13 @@ def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
     return out
 
 
-def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr"), batched=True):
+def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr"), batched=True,
+                  adjoint_model="fcr"):
     """The pile as configured under each other material model (mixed form):
     iteration rate, frame time, iterations per frame, and the sweep's
-    roofline (its algorithmic bytes do not depend on the model); and the
-    256-scene batch under each model (10 graph-captured steps)."""
+    roofline (its algorithmic bytes do not depend on the model); the
+    256-scene batch under each model (10 graph-captured steps); and the
+    differentiable 30,000-tet rollout under one corotated model."""
     out = {"frames_warmup": warmup, "frames_timed": steps}
     kt, kv, kq = KERNEL_BYTES["grad"]["mixed"]
     for model in models:
@@ -349,6 +351,10 @@ def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "ara
             bb = run_batched(10, 10, model=model)
             out[model]["batched"] = {k: bb[k] for k in ("scene_steps_per_s", "ms_per_batch_step",
                                                          "mean_iters_per_scene_step", "block", "max_team")}
+    if adjoint_model:
+        a = run_adjoint(model=adjoint_model)
+        out[adjoint_model]["adjoint"] = {k: a[k] for k in ("adjoint_ms_per_step", "forward_ms_per_step",
+                                                            "mean_forward_iters", "mean_cg_iters", "max_cg_iters")}
     return out
 
 
@@ -467,7 +473,7 @@ def run_batched(steps, warmup, model="nh"):
             "min_z_after": xz, "dtype": "f32+f64"}
 
 
-def run_adjoint(steps=30, checkpoint=5):
+def run_adjoint(steps=30, checkpoint=5, model="nh"):
     """Loss ||x_T - x_target||^2 of the 30,000-tet bar over 30 steps; the
     target is the forward result under a second seeded modulus field."""
     import torch
@@ -475,7 +481,7 @@ def run_adjoint(steps=30, checkpoint=5):
     import scenes
     sc = scenes.diff_bar_scene(seed=4)
     tgt = scenes.diff_bar_scene(seed=5)
-    ctx = setup_ctx(sc, "fp64")
+    ctx = setup_ctx(sc, "fp64", model)
     ctx.pncg_set_solver(sc.iter_max, sc.eps, P.TERM_GRAD_ABS, sc.gravity, 0)
     sim = P.Simulation(ctx, sc.nu, sc.rho, sc.h, steps, checkpoint=checkpoint, cg_tol=1e-10, cg_max=20000)
     dev = torch.device("cuda:0")
