@@ -238,11 +238,14 @@ __global__ void __launch_bounds__(kBlock) k_bucket_fill(Broad B, const double4* 
       lo = B.item_lo[f];
       hi = B.item_hi[f];
     } else {
+      // an edge record holds its two end points (its box is their
+      // component-wise min and max), so the exact distance of a pair reads
+      // the staged records instead of gathering positions
       const int e = it - ebase;
       ids.x = B.edges[2 * e];
       ids.y = B.edges[2 * e + 1];
-      lo = B.item_lo[B.nF + e];
-      hi = B.item_hi[B.nF + e];
+      lo = x[ids.x];
+      hi = x[ids.y];
     }
     B.bkt_key[slot] = k;
     B.bkt_item[slot] = it;
@@ -364,7 +367,8 @@ __device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, con
   const unsigned long long key = R.key(s);
   const unsigned h = hash_key(key, B.tsize, true);
   const int s0 = B.start[h], s1 = B.start[h + 1];
-  const V3<double> loA = R.lo(s), hiA = R.hi(s);
+  const V3<double> a0 = R.lo(s), a1 = R.hi(s);   // end points
+  const V3<double> loA = vmin3(a0, a1), hiA = vmax3(a0, a1);
   const int4 idA = R.ids(s);
   const double r = P.r, q = 0.5 * P.r + kEdgeMargin;
   for (int t = s0; t < s1; ++t) {
@@ -372,7 +376,8 @@ __device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, con
     if (ib <= ia || R.key(t) != key) continue;
     const int4 idB = R.ids(t);
     if (idA.x == idB.x || idA.x == idB.y || idA.y == idB.x || idA.y == idB.y) continue;
-    const V3<double> lo = R.lo(t), hi = R.hi(t);
+    const V3<double> b0 = R.lo(t), b1 = R.hi(t);
+    const V3<double> lo = vmin3(b0, b1), hi = vmax3(b0, b1);
     // exact test with e1 = this (smaller) edge
     if (!((loA.x - r) <= hi.x && (loA.y - r) <= hi.y && (loA.z - r) <= hi.z)) continue;
     if (!(lo.x <= (hiA.x + r) && lo.y <= (hiA.y + r) && lo.z <= (hiA.z + r))) continue;
@@ -384,7 +389,7 @@ __device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, con
     // distance filter before the exclusion lookup (see vertex_slot_pair)
     if (P.filter_d >= 0.0) {
       if (P.filter_obj && B.oid[idA.x] != B.oid[idB.x]) continue;
-      if (!(closest_ee(ldx(P.x, idA.x), ldx(P.x, idA.y), ldx(P.x, idB.x), ldx(P.x, idB.y)).d < P.filter_d)) continue;
+      if (!(closest_ee(a0, a1, b0, b1).d < P.filter_d)) continue;
     }
     const unsigned long long pk = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
     if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, pk)) continue;

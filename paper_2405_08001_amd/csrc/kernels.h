@@ -46,7 +46,7 @@ struct Broad {
   int* ent_item;                 // [ent_cap]
   unsigned long long* bkt_key;   // [ent_cap] records grouped by bucket
   int* bkt_item;                 // [ent_cap]
-  double4* bkt_lo;               // [ent_cap] vertex: position; triangle: inflated box; edge: box
+  double4* bkt_lo;               // [ent_cap] vertex: position; triangle: inflated box (lo, hi); edge: its two end points (box = their min, max)
   double4* bkt_hi;               // [ent_cap]
   int4* bkt_ids;                 // [ent_cap] vertex ids of the item (-1 unused)
   int tsize;             // power of two
