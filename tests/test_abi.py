@@ -165,3 +165,37 @@ def test_batch_without_gpu_fails_loudly():
     with pytest.raises(P.PncgError) as e:
         P.Batch(**_batch_args())
     assert e.value.code == P.E_HIP
+
+
+def _header_constants():
+    """PNCG_* integer constants of the header, evaluated (plain integers,
+    `u` suffixes and shifts only)."""
+    out = {}
+    for name, expr in re.findall(r"^#define\s+PNCG_([A-Z0-9_]+)\s+([^/\n]+)", open(HEADER).read(), flags=re.M):
+        expr = re.sub(r"(\d+)u\b", r"\1", expr.strip())
+        if re.fullmatch(r"[\d\s()<\-+]+", expr):
+            out[name] = eval(expr)     # noqa: S307 - digits, parentheses and shifts only
+    return out
+
+
+def test_binding_constants_match_the_header():
+    import paper_2405_08001_amd._lib as L
+    consts = _header_constants()
+    checked = 0
+    for name, value in consts.items():
+        if name == "PROF_KINDS":
+            # the binding holds the kind names in index order
+            assert len(L.PROF_KINDS) == value
+            assert all(consts["PROF_" + k.upper()] == i for i, k in enumerate(L.PROF_KINDS))
+            continue
+        if hasattr(L, name):
+            assert getattr(L, name) == value, name
+            checked += 1
+    for name in ("MODEL_NH", "MODEL_SNH", "MODEL_ARAP", "MODEL_FCR", "BETA_HZ", "SPLIT_OBJECTS", "E_INVERTED",
+                 "TERM_GRAD_ABS", "CONTACT_REST_EXCLUDE", "MIXED"):
+        assert name in consts and hasattr(L, name), name
+    assert checked >= 30
+    assert L.MODELS == {"nh": consts["MODEL_NH"], "snh": consts["MODEL_SNH"], "arap": consts["MODEL_ARAP"],
+                        "fcr": consts["MODEL_FCR"]}
+    assert L.BETA_RULES == {"dk": consts["BETA_DK"], "fr": consts["BETA_FR"], "prp": consts["BETA_PRP"],
+                            "cd": consts["BETA_CD"], "hz": consts["BETA_HZ"]}
