@@ -311,6 +311,14 @@ def test_unknown_model_is_rejected():
     with pytest.raises(L.PncgError) as ei:
         ctx.pncg_set_model(7)
     assert ei.value.code == L.E_INVAL
+    scs = scenes.batched_scenes(seed=5, n_scenes=2, t_lo=30, t_hi=200)
+    b = scenes.pack_batch(scs)
+    bt = L.Batch(b["vert_off"], b["X"], b["tet_off"], b["tets"], b["tri_off"], b["tris"], b["E"], b["nu"],
+                 b["rho"], b["planes"], precision=L.MIXED)
+    with pytest.raises(L.PncgError) as ei:
+        bt.pncg_batch_set_model(-1)
+    assert ei.value.code == L.E_INVAL
+    bt.pncg_batch_set_model("arap")          # a known model is accepted
 
 
 @pytest.mark.parametrize("precision", [0, 1])
