@@ -185,7 +185,7 @@ class Context:
 
     def pncg_set_model(self, model):
         """model: a MODEL_* value or one of the names in MODELS."""
-        self._check(_L.pncg_set_model(self._h, int(MODELS.get(model, model) if isinstance(model, str) else model)))
+        self._check(_L.pncg_set_model(self._h, _model_code(model)))
 
     def pncg_set_contact(self, dhat, kappa, cell=0.0, planes=None, flags=0):
         pl = _f64(np.zeros((0, 4)) if planes is None else np.asarray(planes, dtype=np.float64).reshape(-1, 4))
@@ -322,6 +322,16 @@ class Context:
         return {k: (float(us[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
 
 
+def _model_code(model):
+    """A MODEL_* value from a name in MODELS or an integer (which the library
+    validates)."""
+    if isinstance(model, str):
+        if model not in MODELS:
+            raise ValueError(f"unknown material model {model!r}; one of {sorted(MODELS)}")
+        return MODELS[model]
+    return int(model)
+
+
 def _ready(t, stream=0):
     """The library reads device inputs on its own stream, which does not wait
     for torch's: finish what torch has queued on the tensor's device (a
@@ -395,7 +405,7 @@ class Batch:
 
     def pncg_batch_set_model(self, model):
         """model: a MODEL_* value or one of the names in MODELS."""
-        self._check(_L.pncg_batch_set_model(self._h, int(MODELS.get(model, model) if isinstance(model, str) else model)))
+        self._check(_L.pncg_batch_set_model(self._h, _model_code(model)))
 
     def pncg_batch_set_staging(self, lds):
         self._check(_L.pncg_batch_set_staging(self._h, int(lds)))
