@@ -255,6 +255,16 @@ int pncg_step_dev(pncg_ctx* ctx, const double* x_dev, const double* v_dev,
                   double h, double* x_out_dev, double* v_out_dev,
                   pncg_stats* st);
 
+/* nsteps >= 1 time steps in place on the device state x_dev, v_dev [nV][3]
+ * (each exactly as pncg_step_dev with the outputs written over the
+ * inputs), without returning to the caller in between: a simulation loop
+ * with no per-step host round trip.  steps (nullable) receives one
+ * pncg_stats per step, [nsteps].  Returns the first error (the state then
+ * holds the last completed step), else PNCG_W_MAXITER if any step hit the
+ * iteration cap, else PNCG_OK.  E_INVAL for nsteps < 1 or a NULL state. */
+int pncg_run_dev(pncg_ctx* ctx, double* x_dev, double* v_dev, double h,
+                 int32_t nsteps, pncg_stats* steps);
+
 /* Queries at a given x with the active set computed at x (Algorithm 1,
  * ComputeConstraintSet), in the context's precision.  xt is the predictor.
  *   pncg_energy:   E(x) of equation E

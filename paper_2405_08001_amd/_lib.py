@@ -39,7 +39,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
-           "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model")
+           "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model", "pncg_run_dev")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -91,6 +91,7 @@ def _load():
         "pncg_set_adjoint_warm_start": (I32, [P, I32]),
         "pncg_step": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_step_dev": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
+        "pncg_run_dev": (I32, [P, P, P, D, I32, P]),
         "pncg_energy": (I32, [P, P, P, D, P]),
         "pncg_gradient": (I32, [P, P, P, D, P, P]),
         "pncg_hvp": (I32, [P, P, P, D, P, P]),
@@ -237,6 +238,22 @@ class Context:
         d = st.as_dict()
         d["status"] = rc
         return d
+
+    def pncg_run_dev(self, x, v, h, nsteps):
+        """nsteps steps in place on the float64 CUDA tensors x, v (nV, 3);
+        returns the per-step statistics (list of dicts) and the status."""
+        for t in (x, v):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+                    and tuple(t.shape) == (self.nV, 3)):
+                raise ValueError("run_dev needs contiguous float64 CUDA tensors of shape (nV, 3)")
+        n = int(nsteps)
+        if n < 1:
+            raise ValueError("nsteps must be >= 1")
+        _ready(x, self._stream)
+        sts = (pncg_stats * n)()
+        rc = self._check(_L.pncg_run_dev(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), float(h), n,
+                                         sts))
+        return [s.as_dict() for s in sts], rc
 
     # ------------------------------------------------------------ queries
     def pncg_energy(self, x, xt, h):

@@ -1303,6 +1303,21 @@ int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, doubl
   return fail(c, PNCG_E_CAPACITY, "candidate buffers kept overflowing");
 }
 
+int pncg_run_dev(pncg_ctx* c, double* x, double* v, double h, int32_t nsteps, pncg_stats* steps) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !v) return fail(c, PNCG_E_INVAL, "NULL state pointer");
+  if (nsteps < 1) return fail(c, PNCG_E_INVAL, "need nsteps >= 1");
+  int out = PNCG_OK;
+  for (int i = 0; i < nsteps; ++i) {
+    // in place: the predictor reads (x, v) before the step writes them
+    rc = pncg_step_dev(c, x, v, h, x, v, steps ? steps + i : nullptr);
+    if (rc < 0) return rc;
+    out = std::max(out, rc);
+  }
+  return out;
+}
+
 int pncg_step(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
               pncg_stats* st) {
   int rc = ready(c);

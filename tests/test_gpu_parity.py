@@ -337,6 +337,48 @@ def test_in_place_step_after_capacity_rerun(K):
         assert rel(xb - x0, xa - x0) <= 1e-12 and rel(vb, va) <= 1e-12
 
 
+def _run_pair(sc, x0, v0, precision, n, **kw):
+    """(state, stats) after n steps by pncg_run_dev (in place) and by n
+    separate pncg_step_dev calls, each on a fresh context."""
+    import torch
+    dev = torch.device("cuda:0")
+    ca = make_ctx(sc, precision, **kw)
+    x, v = torch.tensor(x0, device=dev), torch.tensor(v0, device=dev)
+    sts, rc = ca.pncg_run_dev(x, v, sc.h, n)
+    cb = make_ctx(sc, precision, **kw)
+    xb, vb = torch.tensor(x0, device=dev), torch.tensor(v0, device=dev)
+    ref = []
+    for _ in range(n):
+        xo, vo = torch.empty_like(xb), torch.empty_like(vb)
+        ref.append(cb.pncg_step_dev(xb, vb, sc.h, xo, vo))
+        xb, vb = xo, vo
+    return (x.cpu().numpy(), v.cpu().numpy(), sts, rc), (xb.cpu().numpy(), vb.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_run_dev_equals_repeated_steps(precision):
+    """pncg_run_dev: n steps in place with no return in between give the
+    states and per-step statistics of n separate steps.  The cube on its
+    floor has no pair atomics, so the bits agree; the stacked cubes (self
+    contact, list rebuilds) run 12 fixed iterations per step and agree to
+    the order of their float64 atomic sums."""
+    _say(f"run_dev vs repeated steps precision={precision}")
+    sc, x0, v0 = _cube_drop()
+    (xa, va, sts, rc), (xr, vr, ref) = _run_pair(sc, x0, v0, precision, 4)
+    _say(f"  cube iters {[s['iters'] for s in sts]} / {[s['iters'] for s in ref]}")
+    assert rc == max(s["status"] for s in ref)
+    assert np.array_equal(xa, xr) and np.array_equal(va, vr)
+    for s, r in zip(sts, ref):
+        assert s["iters"] == r["iters"] and s["reason"] == r["reason"] and s["g_norm"] == r["g_norm"]
+    sc, x0, v0 = _stack_drop()
+    (xa, va, sts, rc), (xr, vr, ref) = _run_pair(sc, x0, v0, precision, 5, iter_max=12, eps=0.0, term="delta_e")
+    _say(f"  stack iters {[s['iters'] for s in sts]} rebuilds {[s['rebuilds'] for s in sts]} "
+         f"rel dx {rel(xa - x0, xr - x0):.2e}")
+    assert [s["iters"] for s in sts] == [r["iters"] for r in ref] == [12] * 5
+    assert rel(xa - x0, xr - x0) <= (1e-9 if precision == 0 else 1e-5)
+    assert rel(va, vr) <= (1e-9 if precision == 0 else 1e-5)
+
+
 def test_step_dev_reads_inputs_torch_has_just_written():
     """Device-pointer steps read their inputs on the library's stream: the
     binding first finishes torch's queued work, so a state that torch is
