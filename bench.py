@@ -160,40 +160,48 @@ def _torch_stream():
 
 
 def run(sc, precision, warmup, steps, profile_frames, model="nh"):
+    """W warm-up frames, then K timed frames in one pncg_run_dev call (the
+    state stays on the device and no host round trip separates the steps);
+    then K frames by separate pncg_step_dev calls from Python, for
+    comparison, and the profiled frames."""
     import torch
     ctx = setup_ctx(sc, precision, model)
     dev = torch.device("cuda:0")
     x = torch.tensor(sc.x0, dtype=torch.float64, device=dev)
     v = torch.tensor(sc.v0, dtype=torch.float64, device=dev)
-    x2 = torch.empty_like(x)
-    v2 = torch.empty_like(v)
-    for _ in range(warmup):
-        ctx.pncg_step_dev(x, v, sc.h, x2, v2)
-        x, x2, v, v2 = x2, x, v2, v
+    if warmup > 0:
+        ctx.pncg_run_dev(x, v, sc.h, warmup)
     state = (x.cpu().numpy().copy(), v.cpu().numpy().copy())
-    iters = 0
-    act = cand = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts, _ = ctx.pncg_run_dev(x, v, sc.h, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(st["iters"] for st in sts)
+    act = sum(st["n_active"] for st in sts)
+    cand = sum(st["n_candidates"] for st in sts)
+    # the same number of frames through one Python call per step
+    x2, v2 = torch.empty_like(x), torch.empty_like(v)
+    it_pc = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         st = ctx.pncg_step_dev(x, v, sc.h, x2, v2)
         x, x2, v, v2 = x2, x, v2, v
-        iters += st["iters"]
-        act += st["n_active"]
-        cand += st["n_candidates"]
+        it_pc += st["iters"]
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt_pc = time.perf_counter() - t0
     # profiled pass (events around every launch) on further frames
     ctx.pncg_set_profiling(True)
-    for _ in range(profile_frames):
-        ctx.pncg_step_dev(x, v, sc.h, x2, v2)
-        x, x2, v, v2 = x2, x, v2, v
+    if profile_frames > 0:
+        ctx.pncg_run_dev(x, v, sc.h, profile_frames)
     prof = ctx.pncg_get_profile()
     ctx.pncg_set_profiling(False)
     dmin, jmin = ctx.pncg_min_distance(x.cpu().numpy())
     ctx.close()
     return dict(seconds=dt, iters=iters, frames=steps, mean_active=act / steps, mean_cand=cand / steps,
-                prof=prof, dmin=dmin, jmin=jmin, state=state)
+                prof=prof, dmin=dmin, jmin=jmin, state=state,
+                per_call={"iters_per_s": round(it_pc / dt_pc, 1), "ms_per_frame": round(1e3 * dt_pc / steps, 4)})
 
 
 def run_host_io(sc, state, frames=20):
@@ -610,6 +618,7 @@ def main():
                    "mean_active_pairs": round(m["mean_active"], 1),
                    "mean_candidates": round(m["mean_cand"], 1)},
         "ms_per_frame": round(ms_frame, 4),
+        "per_call": m["per_call"],
         "us_per_iter": round(1e6 / ips, 3),
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved * 1e9 / HBM_PEAK, 4),
