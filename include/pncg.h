@@ -124,11 +124,29 @@ typedef struct pncg_ctx pncg_ctx;
 #define PNCG_KIND_EE 1   /* (surface edge e1, surface edge e2), e1 < e2 */
 #define PNCG_KIND_PG 2   /* (surface vertex, plane) */
 
+/* How the per-vertex sums of the contact-pair terms are formed (the scatter-add
+ * of a pair's gradient, diagonal and H p terms into its four vertices,
+ * Sec. 3.2 equations eq8-eq11 and Sec. 4.2).  pncg_opts.scatter:
+ *   PNCG_SCATTER_AUTO       the library's choice: SEGMENTED
+ *   PNCG_SCATTER_ATOMIC     float64 atomic adds per pair corner; the order of
+ *                           the additions, and so the last bits of any result
+ *                           with active pairs, may differ from run to run
+ *   PNCG_SCATTER_SEGMENTED  every (pair, corner) writes its own slot and each
+ *                           vertex adds its slots in a fixed order (the
+ *                           candidate list is put in lexicographic order at
+ *                           every build): steps and queries are
+ *                           bit-reproducible.  The per-object pair curvature
+ *                           of the split step (PNCG_SPLIT_OBJECTS) is still
+ *                           summed with atomics. */
+#define PNCG_SCATTER_AUTO      0
+#define PNCG_SCATTER_ATOMIC    1
+#define PNCG_SCATTER_SEGMENTED 2
+
 typedef struct {
   int32_t device;      /* HIP device ordinal */
   int32_t precision;   /* PNCG_FP64 or PNCG_MIXED */
   void*   stream;      /* hipStream_t to run on; NULL = a stream the context creates */
-  int32_t block;       /* threads per block for element kernels; 0 = default (256) */
+  int32_t scatter;     /* PNCG_SCATTER_*; 0 = AUTO */
   int32_t chunk;       /* iterations launched between host status reads; 0 = default */
 } pncg_opts;
 
@@ -210,6 +228,26 @@ int pncg_set_contact(pncg_ctx* ctx, double dhat, double kappa, double cell,
  * 1e-3, DELTA_E, (0,0,-9.8), 0 (Dai-Kou). */
 int pncg_set_solver(pncg_ctx* ctx, int32_t iter_max, double eps, int32_t term,
                     const double* gravity, uint32_t flags);
+
+/* Test hook for the constraint set (Algorithm 1, ComputeConstraintSet):
+ * replace the spatial-hash candidates of one kind by an explicit list for the
+ * following steps and energy / gradient / H p / adjoint queries.  The narrow
+ * phase still keeps only the pairs with 0 < d < dhat (Sec. 3, equation
+ * barrier), so a list that holds every pair within dhat gives the same
+ * results as the hash.
+ *   kind PNCG_KIND_PT: pairs [n][2] = (v, f), v a vertex and f a triangle of
+ *                      pncg_set_mesh, v not a corner of f
+ *   kind PNCG_KIND_EE: pairs [n][2] = (e1, e2), two edges of pncg_set_mesh
+ *                      without a shared vertex, e1 != e2
+ * While any override is installed the hash is not used for those calls: the
+ * candidates are the installed lists, and a kind never installed has none.
+ * Installing a kind again replaces its list; n < 0 removes every override
+ * (pairs may then be NULL).  The list is copied.  Only has an effect with
+ * PNCG_CONTACT_SELF.  pncg_candidates and pncg_min_distance keep using the
+ * hash.  Errors: E_INVAL (unknown kind, index out of range, a pair sharing a
+ * vertex, a repeated pair), E_STATE before pncg_set_mesh, which clears every
+ * override. */
+int pncg_set_candidates_override(pncg_ctx* ctx, int32_t kind, int64_t n, const int32_t* pairs);
 
 /* Performance settings (results do not depend on them beyond rounding
  * order).  skin > 0: the solver keeps the pairs within dhat + skin at the

@@ -77,6 +77,7 @@ class Problem:
         self.surf_verts = np.unique(self.tris.reshape(-1)) if len(self.tris) else np.zeros(0, np.int64)
         self.object_id = (np.zeros(self.nV, np.int64) if object_id is None
                           else np.asarray(object_id, dtype=np.int64).reshape(self.nV))
+        self._override = None
         if self.self_contact and rest_exclude:
             self.excl_pt, self.excl_ee = candidates.rest_exclusion(
                 self.X, self.tris, self.edges, self.surf_verts, self.dhat, object_id)
@@ -116,11 +117,26 @@ class Problem:
         pg = candidates.pg_candidates(x, self.surf_verts, self.planes, r)
         return pt, ee, pg
 
+    def set_candidates_override(self, pt=None, ee=None):
+        """Explicit point-triangle (v, f) and edge-edge (e1, e2) candidate
+        lists for active_set in place of the AABB lists (the library's test
+        hook for ComputeConstraintSet, Algorithm 1); a list left None is empty
+        while the other is given, and both None restore the AABB lists.  The
+        distance test 0 < d < dhat still selects the active pairs."""
+        if pt is None and ee is None:
+            self._override = None
+            return
+        pt = np.zeros((0, 2), np.int64) if pt is None else np.asarray(pt, dtype=np.int64).reshape(-1, 2)
+        ee = np.zeros((0, 2), np.int64) if ee is None else np.sort(np.asarray(ee, dtype=np.int64).reshape(-1, 2), axis=1)
+        self._override = (pt, ee)
+
     def active_set(self, x):
         """ComputeConstraintSet (Algorithm 1): candidates, closest points, and
         the pairs with 0 < d < dhat."""
         x = np.asarray(x, dtype=np.float64)
         pt, ee, pg = self.candidate_lists(x)
+        if self._override is not None and self.self_contact:
+            pt, ee = self._override
         kinds, idxs, cs, ts, ds = [], [], [], [], []
         if len(pt):
             f = self.tris[pt[:, 1]]

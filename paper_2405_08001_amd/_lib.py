@@ -28,6 +28,7 @@ MODEL_NH, MODEL_SNH, MODEL_ARAP, MODEL_FCR = 0, 1, 2, 3
 MODELS = {"nh": MODEL_NH, "snh": MODEL_SNH, "arap": MODEL_ARAP, "fcr": MODEL_FCR}
 CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SEGMENTED = 0, 1, 2
 
 CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
               -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY", -9: "E_INDEFINITE"}
@@ -39,7 +40,8 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
-           "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model", "pncg_run_dev")
+           "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model", "pncg_run_dev",
+           "pncg_set_candidates_override")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -51,7 +53,7 @@ class PncgError(RuntimeError):
 
 class pncg_opts(C.Structure):
     _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("stream", C.c_void_p),
-                ("block", C.c_int32), ("chunk", C.c_int32)]
+                ("scatter", C.c_int32), ("chunk", C.c_int32)]
 
 
 class pncg_stats(C.Structure):
@@ -85,6 +87,7 @@ def _load():
         "pncg_set_solver": (I32, [P, I32, D, I32, P, U32]),
         "pncg_set_dirichlet": (I32, [P, I32, P, P]),
         "pncg_set_tuning": (I32, [P, D, I32]),
+        "pncg_set_candidates_override": (I32, [P, I32, C.c_int64, P]),
         "pncg_set_model": (I32, [P, I32]),
         "pncg_batch_set_model": (I32, [P, I32]),
         "pncg_mean_boundary_edge": (I32, [P, P]),
@@ -142,8 +145,8 @@ def _ptr(a):
 class Context:
     """One libpncg context (a device, a precision, a mesh)."""
 
-    def __init__(self, device=0, precision=FP64, stream=None, chunk=0):
-        opts = pncg_opts(device, precision, stream, 0, chunk)
+    def __init__(self, device=0, precision=FP64, stream=None, chunk=0, scatter=SCATTER_AUTO):
+        opts = pncg_opts(device, precision, stream, scatter, chunk)
         self._stream = int(stream or 0)
         h = C.c_void_p()
         rc = _L.pncg_create(C.byref(h), C.byref(opts))
@@ -196,6 +199,15 @@ class Context:
     def pncg_set_solver(self, iter_max=100, eps=1e-3, term=TERM_DELTA_E, gravity=(0.0, 0.0, -9.8), flags=0):
         g = _f64(gravity)
         self._check(_L.pncg_set_solver(self._h, int(iter_max), float(eps), int(term), _ptr(g), int(flags)))
+
+    def pncg_set_candidates_override(self, kind, pairs):
+        """Install an explicit (n, 2) pair list of KIND_PT or KIND_EE in place of
+        the hash candidates; pairs=None removes every override."""
+        if pairs is None:
+            self._check(_L.pncg_set_candidates_override(self._h, int(kind), -1, None))
+            return
+        pr = _i32(np.asarray(pairs).reshape(-1, 2))
+        self._check(_L.pncg_set_candidates_override(self._h, int(kind), pr.shape[0], _ptr(pr)))
 
     def pncg_set_tuning(self, skin=0.0, chunk=0):
         self._check(_L.pncg_set_tuning(self._h, float(skin), int(chunk)))
@@ -465,5 +477,5 @@ class Batch:
         return out.value
 
 
-def pncg_create(device=0, precision=FP64, stream=None, chunk=0):
-    return Context(device, precision, stream, chunk)
+def pncg_create(device=0, precision=FP64, stream=None, chunk=0, scatter=SCATTER_AUTO):
+    return Context(device, precision, stream, chunk, scatter)

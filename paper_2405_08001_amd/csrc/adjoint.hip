@@ -301,9 +301,10 @@ __global__ void __launch_bounds__(kSBlock) k_cg_dir(Args<double> A, AdjArgs C, i
 
 // q = H p_k by the vertex-centric sweep (p_k materialised by k_cg_dir, the
 // pair part already in acc); partials of p_k . q.
-template <int M>
+template <int M, bool SEG = false>
 __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, int k) {
   __shared__ double sh[kSWaves * 2];
+  __shared__ double gsh[SEG ? kSWaves * 3 * kWave : 1];
   if (read_stopped(C.status)) return;
   const double4* pk = C.pbuf[k & 1];
   auto pget = [&](int v) -> V3<double> { return ld3(pk, v); };
@@ -340,7 +341,10 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
     }
     seg_sum<double>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
-    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    double prs[3];
+    if constexpr (SEG) pair_gather<3>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + wave * 3 * kWave);
+    if (!vlane) continue;
     const int v = myv;
     const V3<double> p = pget(v);
     const double m = A.mass[v];
@@ -360,9 +364,15 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
       }
     }
     if (A.self) {
-      hv[0] += A.acc[8 * v];
-      hv[1] += A.acc[8 * v + 1];
-      hv[2] += A.acc[8 * v + 2];
+      if constexpr (SEG) {
+        hv[0] += prs[0];
+        hv[1] += prs[1];
+        hv[2] += prs[2];
+      } else {
+        hv[0] += A.acc[8 * v];
+        hv[1] += A.acc[8 * v + 1];
+        hv[2] += A.acc[8 * v + 2];
+      }
     }
     if (fl & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
     st3(C.q, v, mk3(hv[0], hv[1], hv[2]));
@@ -482,7 +492,8 @@ void launch_cg_iteration(const Args<double>& A, const AdjArgs& C, int k, bool fu
     B.p0 = C.pbuf[k & 1];
     launch_pairs_hvp<double>(B, s);
   }
-  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL(k_cg_hv<M_>, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k));
+  PNCG_BY_SCATTER(A.self && A.seg,
+                  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_cg_hv<M_, S_>), dim3(A.grid), dim3(kSBlock), 0, s, A, C, k)));
   hipLaunchKernelGGL(k_cg_update, dim3(A.grid), dim3(kSBlock), 0, s, A, C, k);
 }
 

@@ -42,7 +42,7 @@ struct pncg_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool dev_ready = false;
-  int block = kBlock;
+  int scatter = PNCG_SCATTER_SEGMENTED;   // resolved PNCG_SCATTER_* of the options
   int chunk = 16;
   std::string err;
   int state = 0;  // 0 created, 1 mesh, 2 material
@@ -86,6 +86,19 @@ struct pncg_ctx {
   int n_excl_pt = 0, n_excl_ee = 0;
   int2* d_cand = nullptr;
   long long cand_cap = 0;
+  // segmented scatter: the unsorted list, its canonical order's index and
+  // the per-(pair, corner) slots (all sized by cand_cap)
+  int2* d_cand_raw = nullptr;
+  int *d_bcnt = nullptr, *d_boff = nullptr, *d_vcnt = nullptr, *d_coff = nullptr, *d_cent = nullptr,
+      *d_pl_tmp = nullptr;
+  uint8_t* d_cact = nullptr;
+  double* d_cslot = nullptr;
+  // explicit candidate lists (pncg_set_candidates_override), kind in the pair
+  bool ovr_set[2] = {false, false};
+  std::vector<int2> ovr[2];
+  int2* d_ovr = nullptr;
+  long long n_ovr = 0;
+  bool ovr_uploaded = false;
   long long* d_ncand = nullptr;
   IterScal* d_scal = nullptr;
   int scal_cap = 0;
@@ -236,6 +249,11 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.p0 = reinterpret_cast<R4<R>*>(c->d_p0);
   A.p1 = reinterpret_cast<R4<R>*>(c->d_p1);
   A.acc = c->d_acc;
+  A.seg = c->scatter == PNCG_SCATTER_SEGMENTED ? 1 : 0;
+  A.coff = c->d_coff;
+  A.cent = c->d_cent;
+  A.cact = c->d_cact;
+  A.cslot = c->d_cslot;
   A.self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0 ? 1 : 0;
   A.cand = c->d_cand;
   A.ncand = c->d_ncand;
@@ -271,6 +289,22 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.vphp = c->d_vphp;
   A.opair = c->d_opair;
   return A;
+}
+
+// Point the list-dependent arguments at the current candidate list and its
+// segmented-scatter arrays (a list build may reallocate them); E_STATE if
+// the segmented arrays are missing where a kernel would use them.
+template <typename R>
+int list_args(pncg_ctx* c, Args<R>& A) {
+  A.cand = c->d_cand;
+  A.cand_cap = c->cand_cap;
+  A.coff = c->d_coff;
+  A.cent = c->d_cent;
+  A.cact = c->d_cact;
+  A.cslot = c->d_cslot;
+  if (A.self && A.seg && (!A.cand || !A.coff || !A.cent || !A.cact || !A.cslot))
+    return fail(c, PNCG_E_STATE, "internal: the candidate list or its pair index is not allocated");
+  return PNCG_OK;
 }
 
 Broad make_broad(pncg_ctx* c) {
@@ -310,6 +344,80 @@ Broad make_broad(pncg_ctx* c) {
   return B;
 }
 
+PairIndex make_pairindex(pncg_ctx* c) {
+  PairIndex P{};
+  P.nV = c->nV;
+  P.nE = c->nE;
+  P.tris = c->d_tris;
+  P.edges = c->d_edges;
+  P.bcnt = c->d_bcnt;
+  P.boff = c->d_boff;
+  P.vcnt = c->d_vcnt;
+  P.coff = c->d_coff;
+  P.cent = c->d_cent;
+  P.scan_tmp = c->d_pl_tmp;
+  P.grid = c->grid;
+  return P;
+}
+
+// Capacity of the candidate list and of the arrays sized by it (the sort
+// buffer, corner entries, activity flags and slots of the segmented
+// scatter); contents are not kept.
+int ensure_cand_cap(pncg_ctx* c, long long cap) {
+  if (cap <= c->cand_cap) return PNCG_OK;
+  for (void* p : {(void*)c->d_cand, (void*)c->d_cand_raw, (void*)c->d_cent, (void*)c->d_cact, (void*)c->d_cslot})
+    dfree(c, p);
+  c->d_cand = c->d_cand_raw = nullptr;
+  c->d_cent = nullptr;
+  c->d_cact = nullptr;
+  c->d_cslot = nullptr;
+  c->cand_cap = 0;
+  int rc;
+  if ((rc = dmalloc(c, &c->d_cand, (size_t)cap))) return rc;
+  if (c->scatter == PNCG_SCATTER_SEGMENTED &&
+      ((rc = dmalloc(c, &c->d_cand_raw, (size_t)cap)) || (rc = dmalloc(c, &c->d_cent, 4 * (size_t)cap)) ||
+       (rc = dmalloc(c, &c->d_cact, (size_t)cap)) || (rc = dmalloc(c, &c->d_cslot, 24 * (size_t)cap))))
+    return rc;
+  c->cand_cap = cap;
+  return PNCG_OK;
+}
+
+bool self_contact(const pncg_ctx* c) { return (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0; }
+
+// The override lists (pncg_set_candidates_override) as one device list.
+int upload_override(pncg_ctx* c) {
+  if (c->ovr_uploaded) return PNCG_OK;
+  std::vector<int2> all(c->ovr[0]);
+  for (const int2& e : c->ovr[1]) all.push_back(make_int2(e.x, ~e.y));
+  dfree(c, c->d_ovr);
+  c->d_ovr = nullptr;
+  int rc;
+  if ((rc = dmalloc(c, &c->d_ovr, all.size()))) return rc;
+  if (!all.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_ovr, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, c->stream));
+  c->n_ovr = (long long)all.size();
+  c->ovr_uploaded = true;
+  return PNCG_OK;
+}
+
+// With the segmented scatter, put the list in d_cand_raw into canonical
+// order in d_cand and index its corners.
+void finish_list(pncg_ctx* c) {
+  if (c->scatter != PNCG_SCATTER_SEGMENTED) return;
+  pairs_canonical(make_pairindex(c), c->d_cand_raw, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
+}
+
+// The override as the current candidate list (kind in the pair).
+int install_override(pncg_ctx* c) {
+  int rc;
+  if ((rc = upload_override(c))) return rc;
+  if ((rc = ensure_cand_cap(c, std::max<long long>(c->n_ovr, 1024)))) return rc;
+  const bool seg = c->scatter == PNCG_SCATTER_SEGMENTED;
+  pairs_install(c->d_ovr, c->n_ovr, seg ? c->d_cand_raw : c->d_cand, c->d_ncand, &c->d_status->n_cand, c->stream);
+  finish_list(c);
+  return PNCG_OK;
+}
+
 // (Re)allocate the cell-entry arrays for `ent` entries and the hash table and
 // work arrays that depend on it.
 int alloc_grid(pncg_ctx* c, long long ent) {
@@ -346,7 +454,7 @@ __global__ void k_copy_counts(const long long* totals, long long* ncand) {
 // (to size the pair list); the grid is rebuilt larger if its entry capacity
 // was too small.
 int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, int filter_obj, long long* n_total,
-                     long long* n_pt) {
+                     long long* n_pt, bool canonical = false) {
   int rc;
   long long n = 0;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -361,15 +469,12 @@ int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, i
   n = c->h_n[1];
   const long long npt = c->h_n[2];
   hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, c->stream, (const long long*)c->d_totals, c->d_ncand);
-  if (n > c->cand_cap) {
-    long long cap = std::max<long long>(n + n / 2, 1024);
-    int2* nc = nullptr;
-    if ((rc = dmalloc(c, &nc, (size_t)cap))) return rc;
-    dfree(c, c->d_cand);
-    c->d_cand = nc;
-    c->cand_cap = cap;
-  }
-  broad_fill(make_broad(c), x, c->cell, r, filter_d, filter_obj, c->d_cand, c->cand_cap, c->stream);
+  if ((n > c->cand_cap || c->cand_cap == 0) && (rc = ensure_cand_cap(c, std::max<long long>(n + n / 2, 1024))))
+    return rc;
+  const bool seg = canonical && c->scatter == PNCG_SCATTER_SEGMENTED;
+  broad_fill(make_broad(c), x, c->cell, r, filter_d, filter_obj, seg ? c->d_cand_raw : c->d_cand, c->cand_cap,
+             c->stream);
+  if (canonical) finish_list(c);
   if (n_total) *n_total = n;
   if (n_pt) *n_pt = npt;
   return PNCG_OK;
@@ -383,17 +488,16 @@ constexpr int kRestart = 1000;   // internal: a capacity was exceeded, run the s
 // the step status, which the step loop turns into a rerun with larger
 // buffers.  Also records the build positions.
 int build_solver_list(pncg_ctx* c, const double4* x) {
-  const long long want = std::max<long long>(4096, 2LL * c->nSV);
-  if (c->cand_cap < want) {
-    int2* nc = nullptr;
-    int rc = dmalloc(c, &nc, (size_t)want);
-    if (rc) return rc;
-    dfree(c, c->d_cand);
-    c->d_cand = nc;
-    c->cand_cap = want;
+  int rc;
+  if (c->ovr_set[0] || c->ovr_set[1]) {
+    if ((rc = install_override(c))) return rc;
+  } else {
+    if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;
+    const bool seg = c->scatter == PNCG_SCATTER_SEGMENTED;
+    broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, seg ? c->d_cand_raw : c->d_cand, c->cand_cap,
+                      c->d_ncand, &c->d_status->err, &c->d_status->n_cand, c->stream);
+    finish_list(c);
   }
-  broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, c->d_cand, c->cand_cap, c->d_ncand,
-                    &c->d_status->err, &c->d_status->n_cand, c->stream);
   HIPCHK(c, hipMemcpyAsync(c->d_xbuild, x, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
   return PNCG_OK;
 }
@@ -406,14 +510,7 @@ int grow_solver_buffers(pncg_ctx* c) {
   int rc = sync(c);
   if (rc) return rc;
   if (cnt[0] > c->ent_cap && (rc = alloc_grid(c, cnt[0] + cnt[0] / 2))) return rc;
-  if (cnt[1] > c->cand_cap) {
-    const long long cap = cnt[1] + cnt[1] / 2 + 1024;
-    int2* nc = nullptr;
-    if ((rc = dmalloc(c, &nc, (size_t)cap))) return rc;
-    dfree(c, c->d_cand);
-    c->d_cand = nc;
-    c->cand_cap = cap;
-  }
+  if (cnt[1] > c->cand_cap && (rc = ensure_cand_cap(c, cnt[1] + cnt[1] / 2 + 1024))) return rc;
   return PNCG_OK;
 }
 
@@ -507,8 +604,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     if ((rc = build_solver_list(c, c->d_x0))) return rc;
     prof_end(c, ev);
     ++rebuilds;
-    A.cand = c->d_cand;
-    A.cand_cap = c->cand_cap;
+    if ((rc = list_args(c, A))) return rc;
   }
   // With self contact the chunk length is chosen so that the displacement
   // bound is expected to stay inside half the skin (observed growth per
@@ -603,8 +699,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
       if ((rc = build_solver_list(c, (p & 1) ? c->d_x1 : c->d_x0))) return bail(rc);
       prof_end(c, e);
       ++rebuilds;
-      A.cand = c->d_cand;
-      A.cand_cap = c->cand_cap;
+      if ((rc = list_args(c, A))) return bail(rc);
       if (p > k) rate = std::max(rate, (s.D - D) / (p - k + 1));
       D = 0.0;
       k = p;
@@ -654,8 +749,9 @@ int ready(pncg_ctx* c) {
 
 // Ensure the candidate buffer reflects r at device positions in d_x0.
 int query_candidates(pncg_ctx* c, double r) {
-  if (!((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0)) return PNCG_OK;
-  return build_candidates(c, c->d_x0, r, r, 0, nullptr, nullptr);
+  if (!self_contact(c)) return PNCG_OK;
+  if (c->ovr_set[0] || c->ovr_set[1]) return install_override(c);
+  return build_candidates(c, c->d_x0, r, r, 0, nullptr, nullptr, true);
 }
 
 int stage_positions(pncg_ctx* c, const double* x) {
@@ -691,6 +787,7 @@ int energy_impl(pncg_ctx* c, const double* x, const double* xt, double h, double
   int rc = load_query<R>(c, x, xt, nullptr);
   if (rc) return rc;
   Args<R> A = make_args<R>(c, h);
+  if ((rc = list_args(c, A))) return rc;
   launch_query_energy<R>(A, c->d_scalar, c->stream);
   HIPCHK(c, hipMemcpyAsync(out, c->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return finish_query(c);
@@ -701,6 +798,7 @@ int gradient_impl(pncg_ctx* c, const double* x, const double* xt, double h, doub
   int rc = load_query<R>(c, x, xt, nullptr);
   if (rc) return rc;
   Args<R> A = make_args<R>(c, h);
+  if ((rc = list_args(c, A))) return rc;
   const size_t n3 = 3 * (size_t)c->nV;
   double* dg = c->d_io;          // x staging is no longer needed
   double* dd = c->d_io + 2 * n3;
@@ -715,6 +813,7 @@ int hvp_impl(pncg_ctx* c, const double* x, const double* p, double h, double* hp
   int rc = load_query<R>(c, x, nullptr, p);
   if (rc) return rc;
   Args<R> A = make_args<R>(c, h);
+  if ((rc = list_args(c, A))) return rc;
   const size_t n3 = 3 * (size_t)c->nV;
   double* dh = c->d_io + n3;
   launch_query_hvp<R>(A, hp ? dh : nullptr, c->d_scalar, c->stream);
@@ -793,7 +892,7 @@ int adjoint_impl(pncg_ctx* c, const double* x1, double h, const double* xbar, co
   Args<double> A = make_args<double>(c, h);
   launch_load_query<double>(A, x1, nullptr, nullptr, c->stream);
   if ((rc = query_candidates(c, c->dhat))) return rc;
-  A.cand = c->d_cand;
+  if ((rc = list_args(c, A))) return rc;
   // Jacobi diagonal of H at x^{t+1} (the gradient written alongside is
   // unused; the predictor is taken as x^{t+1} so that it stays finite)
   A.xt = c->d_x0;
@@ -914,16 +1013,17 @@ int pncg_create(pncg_ctx** out, const pncg_opts* o) {
       g_create_error = "precision must be PNCG_FP64 or PNCG_MIXED";
       return PNCG_E_INVAL;
     }
-    if (o->device < 0 || o->block < 0 || o->chunk < 0) {
+    if (o->device < 0 || o->chunk < 0) {
       delete c;
-      g_create_error = "negative device, block or chunk";
+      g_create_error = "negative device or chunk";
       return PNCG_E_INVAL;
     }
-    if (o->block != 0 && o->block != kBlock) {
+    if (o->scatter < PNCG_SCATTER_AUTO || o->scatter > PNCG_SCATTER_SEGMENTED) {
       delete c;
-      g_create_error = "block must be 0 or 256";
+      g_create_error = "scatter must be PNCG_SCATTER_AUTO, _ATOMIC or _SEGMENTED";
       return PNCG_E_INVAL;
     }
+    c->scatter = o->scatter == PNCG_SCATTER_ATOMIC ? PNCG_SCATTER_ATOMIC : PNCG_SCATTER_SEGMENTED;
     c->device = o->device;
     c->precision = o->precision;
     c->stream = reinterpret_cast<hipStream_t>(o->stream);
@@ -1009,6 +1109,9 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
+  c->d_cand_raw = nullptr; c->d_cent = nullptr; c->d_cact = nullptr; c->d_cslot = nullptr;
+  c->d_ovr = nullptr; c->n_ovr = 0; c->ovr_uploaded = false;
+  c->ovr_set[0] = c->ovr_set[1] = false; c->ovr[0].clear(); c->ovr[1].clear();
   c->adj_ready = false; c->d_cgs = nullptr; c->cgs_cap = 0; c->E_uploaded = false;
   c->adj_lam_valid = false;
   c->d_excl_pt = c->d_excl_ee = nullptr; c->n_excl_pt = c->n_excl_ee = 0;
@@ -1030,7 +1133,10 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
       (rc = dmalloc(c, &c->d_item_lo, (size_t)nF + nE)) || (rc = dmalloc(c, &c->d_item_hi, (size_t)nF + nE)) ||
       (rc = dmalloc(c, &c->d_item_cnt, (size_t)nF + nE + surf.size())) ||
       (rc = dmalloc(c, &c->d_item_off, (size_t)nF + nE + surf.size() + 1)) ||
-      (rc = dmalloc(c, &c->d_totals, 4)))
+      (rc = dmalloc(c, &c->d_totals, 4)) ||
+      (rc = dmalloc(c, &c->d_bcnt, 2 * ((size_t)nV + nE))) || (rc = dmalloc(c, &c->d_boff, (size_t)nV + nE + 1)) ||
+      (rc = dmalloc(c, &c->d_vcnt, 2 * (size_t)nV)) || (rc = dmalloc(c, &c->d_coff, (size_t)nV + 1)) ||
+      (rc = dmalloc(c, &c->d_pl_tmp, ((size_t)nV + nE) / kTileScan + 16)))
     return rc;
   c->scal_cap = 0;
   c->d_scal = nullptr;
@@ -1236,6 +1342,49 @@ int pncg_set_dirichlet(pncg_ctx* c, int32_t n, const int32_t* idx, const double*
 // Object ranges and per-object buffers of the split step (allocated on the
 // first split step after set_mesh; the per-iteration scalars grow with
 // iter_max).
+int pncg_set_candidates_override(pncg_ctx* c, int32_t kind, int64_t n, const int32_t* pairs) {
+  if (!c) return PNCG_E_INVAL;
+  if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  if (n < 0) {
+    c->ovr_set[0] = c->ovr_set[1] = false;
+    c->ovr[0].clear();
+    c->ovr[1].clear();
+    c->ovr_uploaded = false;
+    return PNCG_OK;
+  }
+  if (kind != PNCG_KIND_PT && kind != PNCG_KIND_EE) return fail(c, PNCG_E_INVAL, "kind must be PNCG_KIND_PT or _EE");
+  if (n > 0 && !pairs) return fail(c, PNCG_E_INVAL, "NULL pairs");
+  if (n > (int64_t)INT_MAX / 8) return fail(c, PNCG_E_INVAL, "too many pairs");
+  std::vector<int2> lst((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    int a = pairs[2 * i], b = pairs[2 * i + 1];
+    if (kind == PNCG_KIND_PT) {
+      if (a < 0 || a >= c->nV || b < 0 || b >= c->nF)
+        return fail(c, PNCG_E_INVAL, "point-triangle pair " + std::to_string(i) + " out of range");
+      const int* t = c->tris.data() + 3 * (size_t)b;
+      if (a == t[0] || a == t[1] || a == t[2])
+        return fail(c, PNCG_E_INVAL, "point-triangle pair " + std::to_string(i) + " shares a vertex");
+    } else {
+      if (a < 0 || a >= c->nE || b < 0 || b >= c->nE || a == b)
+        return fail(c, PNCG_E_INVAL, "edge-edge pair " + std::to_string(i) + " out of range or repeated edge");
+      if (a > b) std::swap(a, b);
+      const int* e1 = c->edges.data() + 2 * (size_t)a;
+      const int* e2 = c->edges.data() + 2 * (size_t)b;
+      if (e1[0] == e2[0] || e1[0] == e2[1] || e1[1] == e2[0] || e1[1] == e2[1])
+        return fail(c, PNCG_E_INVAL, "edge-edge pair " + std::to_string(i) + " shares a vertex");
+    }
+    lst[(size_t)i] = make_int2(a, b);
+  }
+  std::vector<int2> srt(lst);
+  std::sort(srt.begin(), srt.end(), [](const int2& p, const int2& q) { return p.x < q.x || (p.x == q.x && p.y < q.y); });
+  for (size_t i = 1; i < srt.size(); ++i)
+    if (srt[i].x == srt[i - 1].x && srt[i].y == srt[i - 1].y) return fail(c, PNCG_E_INVAL, "repeated pair");
+  c->ovr[kind] = lst;
+  c->ovr_set[kind] = true;
+  c->ovr_uploaded = false;
+  return PNCG_OK;
+}
+
 static int ensure_split(pncg_ctx* c) {
   if (!(c->sflags & PNCG_SPLIT_OBJECTS)) return PNCG_OK;
   int rc;
@@ -1376,13 +1525,7 @@ int pncg_candidates(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, 
   std::vector<int2> out;
   if (kind == PNCG_KIND_PG) {
     const long long capd = (long long)c->nSV * std::max(c->planes.n, 1);
-    if (capd > c->cand_cap) {
-      int2* nc = nullptr;
-      if ((rc = dmalloc(c, &nc, (size_t)std::max<long long>(capd, 1024)))) return rc;
-      dfree(c, c->d_cand);
-      c->d_cand = nc;
-      c->cand_cap = std::max<long long>(capd, 1024);
-    }
+    if (capd > c->cand_cap && (rc = ensure_cand_cap(c, std::max<long long>(capd, 1024)))) return rc;
     Broad B = make_broad(c);
     plane_candidates(B, c->d_x0, c->planes, c->dhat, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
     HIPCHK(c, hipMemcpyAsync(c->h_n, c->d_ncand, sizeof(long long), hipMemcpyDeviceToHost, c->stream));

@@ -601,7 +601,154 @@ __global__ void __launch_bounds__(kBlock) k_plane_cand(Broad B, const double4* x
   }
 }
 
+// --------------------------------------------- canonical order of a list
+// kind (0 point-triangle, 1 edge-edge) and the two indices of pair q
+__device__ __forceinline__ void pl_decode(int2 pr, long long q, long long npt, int& kind, int& a, int& b) {
+  if (npt >= 0) {
+    kind = q < npt ? 0 : 1;
+    a = pr.x;
+    b = pr.y;
+  } else if (pr.y >= 0) {
+    kind = 0;
+    a = pr.x;
+    b = pr.y;
+  } else {
+    kind = 1;
+    a = pr.x;
+    b = ~pr.y;
+  }
+}
+// the four vertices in the order the narrow phase uses them
+__device__ __forceinline__ void pl_corners(const PairIndex& P, int kind, int a, int b, int (&v)[4]) {
+  if (kind == 0) {
+    v[0] = a;
+    v[1] = P.tris[3 * b];
+    v[2] = P.tris[3 * b + 1];
+    v[3] = P.tris[3 * b + 2];
+  } else {
+    v[0] = P.edges[2 * a];
+    v[1] = P.edges[2 * a + 1];
+    v[2] = P.edges[2 * b];
+    v[3] = P.edges[2 * b + 1];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pl_zero(PairIndex P) {
+  const int nb = 2 * (P.nV + P.nE), nv = 2 * P.nV;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) P.bcnt[i] = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nv; i += gridDim.x * kBlock) P.vcnt[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pl_count(PairIndex P, const int2* in, const long long* ncand,
+                                                     long long cap) {
+  const long long n = min(ncand[0], cap), npt = ncand[1];
+  for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+    int kind, a, b;
+    pl_decode(in[q], q, npt, kind, a, b);
+    atomicAdd(&P.bcnt[kind ? P.nV + a : a], 1);
+    int v[4];
+    pl_corners(P, kind, a, b, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) atomicAdd(&P.vcnt[v[i]], 1);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pl_scatter(PairIndex P, const int2* in, int2* out,
+                                                       const long long* ncand, long long cap) {
+  const long long n = min(ncand[0], cap), npt = ncand[1];
+  const int nb = P.nV + P.nE;
+  for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+    int kind, a, b;
+    pl_decode(in[q], q, npt, kind, a, b);
+    const int bk = kind ? P.nV + a : a;
+    const int pos = P.boff[bk] + atomicAdd(&P.bcnt[nb + bk], 1);
+    out[pos] = make_int2(a, kind ? ~b : b);
+  }
+}
+
+// one thread per first index: insertion sort of its pairs by the second index
+__global__ void __launch_bounds__(kBlock) k_pl_sort(PairIndex P, int2* out) {
+  const int nb = P.nV + P.nE;
+  for (int bk = blockIdx.x * kBlock + threadIdx.x; bk < nb; bk += gridDim.x * kBlock) {
+    const int s0 = P.boff[bk], s1 = P.boff[bk + 1];
+    const bool ee = bk >= P.nV;
+    for (int i = s0 + 1; i < s1; ++i) {
+      const int2 x = out[i];
+      const int kx = ee ? ~x.y : x.y;
+      int j = i - 1;
+      while (j >= s0) {
+        const int2 y = out[j];
+        if ((ee ? ~y.y : y.y) <= kx) break;
+        out[j + 1] = y;
+        --j;
+      }
+      out[j + 1] = x;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pl_corners(PairIndex P, const int2* out, long long* ncand,
+                                                       long long cap) {
+  const long long n = min(ncand[0], cap);
+  for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+    int kind, a, b;
+    pl_decode(out[q], q, -1, kind, a, b);
+    int v[4];
+    pl_corners(P, kind, a, b, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int pos = P.coff[v[i]] + atomicAdd(&P.vcnt[P.nV + v[i]], 1);
+      P.cent[pos] = (int)(4 * q + i);
+    }
+  }
+}
+
+// one thread per vertex: insertion sort of its slot ids, then mark the list
+// as kind-in-pair
+__global__ void __launch_bounds__(kBlock) k_pl_csort(PairIndex P, long long* ncand) {
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < P.nV; v += gridDim.x * kBlock) {
+    const int s0 = P.coff[v], s1 = P.coff[v + 1];
+    for (int i = s0 + 1; i < s1; ++i) {
+      const int x = P.cent[i];
+      int j = i - 1;
+      while (j >= s0 && P.cent[j] > x) {
+        P.cent[j + 1] = P.cent[j];
+        --j;
+      }
+      P.cent[j + 1] = x;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ncand[1] = -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pl_install(const int2* src, long long n, int2* out, long long* ncand,
+                                                       long long* n_out) {
+  for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) out[q] = src[q];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ncand[0] = n;
+    ncand[1] = -1;
+    *n_out = n;
+  }
+}
+
 }  // namespace
+
+void pairs_canonical(const PairIndex& P, const int2* in, int2* out, long long* ncand, long long cap, hipStream_t s) {
+  const int nb = P.nV + P.nE;
+  hipLaunchKernelGGL(k_pl_zero, dim3(P.grid), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_pl_count, dim3(P.grid), dim3(kBlock), 0, s, P, in, (const long long*)ncand, cap);
+  scan_exclusive<int>(P.bcnt, nb, P.boff, P.boff + nb, P.scan_tmp, s);
+  scan_exclusive<int>(P.vcnt, P.nV, P.coff, P.coff + P.nV, P.scan_tmp, s);
+  hipLaunchKernelGGL(k_pl_scatter, dim3(P.grid), dim3(kBlock), 0, s, P, in, out, (const long long*)ncand, cap);
+  hipLaunchKernelGGL(k_pl_sort, dim3(P.grid), dim3(kBlock), 0, s, P, out);
+  hipLaunchKernelGGL(k_pl_corners, dim3(P.grid), dim3(kBlock), 0, s, P, (const int2*)out, ncand, cap);
+  hipLaunchKernelGGL(k_pl_csort, dim3(P.grid), dim3(kBlock), 0, s, P, ncand);
+}
+
+void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s) {
+  const int g = (int)std::min<long long>(std::max<long long>((n + kBlock - 1) / kBlock, 1), 1024);
+  hipLaunchKernelGGL(k_pl_install, dim3(g), dim3(kBlock), 0, s, src, n, out, ncand, n_out);
+}
 
 void broad_build_count(const Broad& B, const double4* x, double cell, double r, double filter_d, int filter_obj,
                        hipStream_t s) {

@@ -125,7 +125,14 @@ struct Args {
   R4<R>* pg;               // P g
   R4<R>* p0;               // direction buffers (p_k lives in p[k & 1])
   R4<R>* p1;
-  double* acc;             // [nV][8] contact accumulators: g xyz, diag xyz
+  double* acc;             // [nV][8] contact accumulators: g xyz, diag xyz (atomic scatter)
+  // segmented scatter: every (pair, corner) writes a slot, each vertex adds
+  // its slots in the order of its corner entries
+  int seg;                 // 1: segmented, 0: atomic
+  const int* coff;         // [nV + 1] corner entries of each vertex
+  const int* cent;         // [4 cap] slot ids 4 q + corner, per vertex in pair-key order
+  uint8_t* cact;           // [cap] the pair was active at the last narrow phase
+  double* cslot;           // [4 cap][6] gradient xyz, diag xyz (or H p xyz) of each corner
   // contact
   int self;                // point-triangle / edge-edge barriers on
   const int2* cand;        // candidate pairs: (v, f) point-triangle then (e1, e2) edge-edge
@@ -172,6 +179,19 @@ struct Args {
       constexpr int M_ = kModelNH;                                  \
       CALL;                                                         \
     }                                                               \
+  } while (0)
+
+// Runs CALL with the constexpr S_ set to whether the pair terms use the
+// segmented slots.
+#define PNCG_BY_SCATTER(seg, CALL) \
+  do {                             \
+    if (seg) {                     \
+      constexpr bool S_ = true;    \
+      CALL;                        \
+    } else {                       \
+      constexpr bool S_ = false;   \
+      CALL;                        \
+    }                              \
   } while (0)
 
 // Kernel model (device_math.h Model) of a PNCG_MODEL_* value: ARAP runs

@@ -79,6 +79,29 @@ void broad_fill(const Broad& B, const double4* x, double cell, double r, double 
 // the pair count to *n_out.
 void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
                        long long* ncand, int* err, long long* n_out, hipStream_t s);
+// Canonical order of a candidate list and the per-vertex index of its
+// (pair, corner) slots, for the segmented scatter of the pair terms.
+struct PairIndex {
+  int nV, nE;
+  const int* tris;       // [nF][3]
+  const int* edges;      // [nE][2]
+  int* bcnt;             // [2 (nV + nE)] pairs per first index (v, or nV + e1), then fill counters
+  int* boff;             // [nV + nE + 1] their offsets
+  int* vcnt;             // [2 nV] corners per vertex, then fill counters
+  int* coff;             // [nV + 1] their offsets
+  int* cent;             // [4 cap] slot ids (4 q + corner) grouped by vertex, ascending per vertex
+  int* scan_tmp;         // scan partials, (nV + nE) / 4096 + 2 ints
+  int grid;
+};
+// Sort in[0, min(ncand[0], cap)) lexicographically into out: point-triangle
+// (v, f) first, then edge-edge (e1, ~e2) (the kind is taken by position when
+// ncand[1] >= 0, else from the sign of the second index); set ncand[1] = -1
+// (kind in the pair) and build coff / cent for out.  No host
+// synchronisation; deterministic.
+void pairs_canonical(const PairIndex& P, const int2* in, int2* out, long long* ncand, long long cap, hipStream_t s);
+// Copy n pairs (kind in the pair) into out, set ncand = {n, -1} and *n_out = n.
+void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s);
+
 // Plane candidates ((n0 x0 + n1 x1) + n2 x2) - o <= r for surface vertices.
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,
                       long long cap, hipStream_t s);

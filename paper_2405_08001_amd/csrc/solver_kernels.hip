@@ -293,6 +293,25 @@ __device__ __forceinline__ void pair_hess_coefs(const Args<R>& A, double d, doub
   }
 }
 
+// Barrier gradient and diagonal of one active pair (eq8, eq10, eq11) into
+// its corners' slots (segmented scatter) or accumulators (atomic scatter).
+template <typename R>
+__device__ __forceinline__ void pair_grad_diag_out(const Args<R>& A, long long q, const int (&iv)[4],
+                                                   const Closest& c) {
+  const double d = c.d;
+  const double cg = A.kappa * barrier_db(d, A.dhat) / d;
+  double ca, cb;
+  pair_hess_coefs(A, d, ca, cb);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double ci = c.c[i];
+    const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
+    const double dj = cb * ci * ci;
+    const double val[6] = {cg * tx, cg * ty, cg * tz, ca * tx * tx + dj, ca * ty * ty + dj, ca * tz * tz + dj};
+    pair_corner_out<6>(A.seg, A.cslot, A.acc, 4 * q + i, iv[i], val);
+  }
+}
+
 // First launch of an iteration with self contact: apply the pending update,
 // then barrier gradient + diagonal of every active pair into acc (eq8,
 // eq10, eq11).
@@ -312,25 +331,11 @@ __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) 
   for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
     int iv[4];
     Closest c;
-    if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+    const bool act = pair_closest(A, (int)q, pos, iv, c, npt);
+    if (A.seg) A.cact[q] = act ? 1 : 0;
+    if (!act) continue;
     nact += 1.0;
-    const double d = c.d;
-    const double cg = A.kappa * barrier_db(d, A.dhat) / d;
-    double ca, cb;
-    pair_hess_coefs(A, d, ca, cb);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double ci = c.c[i];
-      double* a = A.acc + 8 * iv[i];
-      const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
-      atomicAdd(a + 0, cg * tx);
-      atomicAdd(a + 1, cg * ty);
-      atomicAdd(a + 2, cg * tz);
-      const double dj = cb * ci * ci;
-      atomicAdd(a + 3, ca * tx * tx + dj);
-      atomicAdd(a + 4, ca * ty * ty + dj);
-      atomicAdd(a + 5, ca * tz * tz + dj);
-    }
+    pair_grad_diag_out(A, q, iv, c);
   }
   double v[1] = {nact};
   const int kind[1] = {0};
@@ -358,10 +363,11 @@ __device__ __forceinline__ bool lane_elem(const Args<R>& A, int code, const Pos&
 }
 
 // Vertex terms at x_v: inertia m (x - xt), plane barriers (surface
-// vertices), contact accumulators; returns g and diag in float64.
+// vertices), contact-pair sums (`pairs`: the segmented sums of the vertex's
+// slots, or NULL for the atomic accumulators); returns g and diag in float64.
 template <typename R>
 __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double> x, double (&gd)[3], double (&dd)[3],
-                                             double& nplane, bool zero_acc) {
+                                             double& nplane, bool zero_acc, const double* pairs = nullptr) {
   const double m = A.mass[v];
   V3<double> xt = ld3(A.xt, v);
   gd[0] += m * (x.x - xt.x); gd[1] += m * (x.y - xt.y); gd[2] += m * (x.z - xt.z);
@@ -381,12 +387,17 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
     }
   }
   if (A.self) {
-    double* a = A.acc + 8 * v;
+    if (pairs) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) { gd[j] += a[j]; dd[j] += a[3 + j]; }
-    if (zero_acc) {
+      for (int j = 0; j < 3; ++j) { gd[j] += pairs[j]; dd[j] += pairs[3 + j]; }
+    } else {
+      double* a = A.acc + 8 * v;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) a[j] = 0.0;
+      for (int j = 0; j < 3; ++j) { gd[j] += a[j]; dd[j] += a[3 + j]; }
+      if (zero_acc) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a[j] = 0.0;
+      }
     }
   }
 }
@@ -397,10 +408,13 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
-template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, int BS = GradBlock<R>::value>
+// SEG: the contact-pair terms come from the segmented slots (pair_gather)
+// instead of the atomic accumulators.
+template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, bool SEG = false, int BS = GradBlock<R>::value>
 __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
   __shared__ double sh[NW * 8];
+  __shared__ double gsh[SEG ? NW * 6 * kWave : 1];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
     fp = first_prologue<R, SPLIT, BS>(A, k, mode, sh);
@@ -435,14 +449,17 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
     }
     seg_sum<R>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
-    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    double prs[6];
+    if constexpr (SEG) pair_gather<6>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + (threadIdx.x >> 6) * 6 * kWave);
+    if (!vlane) continue;
     // this lane is the vertex's first lane
     const int v = myv;
     const V3<double> x = pos(v);
     if (MODE == kGradFirst && fp.materialize) st3(xcur, v, x);
     double gd[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
     double dd[3] = {A.h2 * double(s[3]), A.h2 * double(s[4]), A.h2 * double(s[5])};
-    vertex_terms(A, v, x, gd, dd, dots[6], MODE != kGradQuery);
+    vertex_terms(A, v, x, gd, dd, dots[6], MODE != kGradQuery, SEG ? prs : nullptr);
     if (MODE == kGradDirect && A.self && (A.vflag[v] & kSurface)) {
       const V3<double> xb = ld3(A.xbuild, v);
       const double ex = x.x - xb.x, ey = x.y - xb.y, ez = x.z - xb.z;
@@ -834,26 +851,19 @@ __global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part
   for (long long q = tid; q < nq; q += stride) {
     int iv[4];
     Closest c;
-    if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+    const bool act = pair_closest(A, (int)q, pos, iv, c, npt);
+    if (WHAT != 1 && A.seg) A.cact[q] = act ? 1 : 0;
+    if (!act) continue;
     const double d = c.d;
     if (WHAT == 1) {
       sum += A.kappa * barrier_b(d, A.dhat);
       continue;
     }
-    double ca, cb;
-    pair_hess_coefs(A, d, ca, cb);
     if (WHAT == 0) {
-      const double cg = A.kappa * barrier_db(d, A.dhat) / d;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double ci = c.c[i];
-        double* a = A.acc + 8 * iv[i];
-        const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
-        atomicAdd(a + 0, cg * tx); atomicAdd(a + 1, cg * ty); atomicAdd(a + 2, cg * tz);
-        const double dj = cb * ci * ci;
-        atomicAdd(a + 3, ca * tx * tx + dj); atomicAdd(a + 4, ca * ty * ty + dj); atomicAdd(a + 5, ca * tz * tz + dj);
-      }
+      pair_grad_diag_out(A, q, iv, c);
     } else {
+      double ca, cb;
+      pair_hess_coefs(A, d, ca, cb);
       V3<double> sp = mk3(0.0, 0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) sp = sp + c.c[i] * cast3<double>(ldr<R>(A.p0, iv[i]));
@@ -863,10 +873,9 @@ __global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const double ci = c.c[i];
-        double* a = A.acc + 8 * iv[i];
-        atomicAdd(a + 0, ci * (ca * st * c.t.x + cb * sp.x));
-        atomicAdd(a + 1, ci * (ca * st * c.t.y + cb * sp.y));
-        atomicAdd(a + 2, ci * (ca * st * c.t.z + cb * sp.z));
+        const double val[3] = {ci * (ca * st * c.t.x + cb * sp.x), ci * (ca * st * c.t.y + cb * sp.y),
+                               ci * (ca * st * c.t.z + cb * sp.z)};
+        pair_corner_out<3>(A.seg, A.cslot, A.acc, 4 * q + i, iv[i], val);
       }
     }
   }
@@ -911,9 +920,10 @@ __global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
 
 // H p by the vertex-centric sweep (p in p0, prescribed rows zero) and the
 // per-block partials of p^T H p.  Pair contributions must already be in acc.
-template <typename R, int M>
+template <typename R, int M, bool SEG = false>
 __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
   __shared__ double sh[kSWaves * 2];
+  __shared__ double gsh[SEG ? kSWaves * 3 * kWave : 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = (blockIdx.x * kSBlock + threadIdx.x) >> 6;
   const int nw = (gridDim.x * kSBlock) >> 6;
@@ -938,7 +948,10 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
     }
     seg_sum<R>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
-    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    double prs[3];
+    if constexpr (SEG) pair_gather<3>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + (threadIdx.x >> 6) * 3 * kWave);
+    if (!vlane) continue;
     const int v = myv;
     V3<R> pr = ldr<R>(A.p0, v);
     const double p3[3] = {double(pr.x), double(pr.y), double(pr.z)};
@@ -957,7 +970,11 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
       }
     }
     if (A.self) {
-      for (int j = 0; j < 3; ++j) hv[j] += A.acc[8 * v + j];
+      if constexpr (SEG) {
+        for (int j = 0; j < 3; ++j) hv[j] += prs[j];
+      } else {
+        for (int j = 0; j < 3; ++j) hv[j] += A.acc[8 * v + j];
+      }
     }
     if (A.vflag[v] & kFixed) hv[0] = hv[1] = hv[2] = 0.0;
     php += hv[0] * p3[0] + hv[1] * p3[1] + hv[2] * p3[2];
@@ -1053,15 +1070,16 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
 }
 template <typename R>
 void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
+  const bool seg = A.self && A.seg;
   if (A.split) {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, true, M_>), dim3(A.grid),
+    PNCG_BY_SCATTER(seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, true, M_, S_>), dim3(A.grid),
                                               dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
-                                              (double*)nullptr));
+                                              (double*)nullptr)));
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, false, M_>), dim3(A.grid),
+    PNCG_BY_SCATTER(seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, false, M_, S_>), dim3(A.grid),
                                               dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
-                                              (double*)nullptr));
+                                              (double*)nullptr)));
   }
 }
 template <typename R>
@@ -1084,8 +1102,8 @@ void launch_load_query(const Args<R>& A, const double* x, const double* xt, cons
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradQuery, false, M_>), dim3(A.grid),
-                                            dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d));
+  PNCG_BY_SCATTER(A.self && A.seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradQuery, false, M_, S_>), dim3(A.grid),
+                                            dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d)));
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
@@ -1097,7 +1115,7 @@ void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
 template <typename R>
 void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) {
   if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
-  PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_hvp<R, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir));
+  PNCG_BY_SCATTER(A.self && A.seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_hvp<R, M_, S_>), dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir)));
   // pair p^T H p is already inside H p at the vertices, so only k_hvp's partials are summed
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
 }

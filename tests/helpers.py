@@ -4,9 +4,9 @@ import numpy as np
 
 
 def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_max=None, eps=None, term=None,
-             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False, model="nh"):
+             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False, model="nh", scatter=0):
     import paper_2405_08001_amd as P
-    ctx = P.Context(0, precision, chunk=chunk)
+    ctx = P.Context(0, precision, chunk=chunk, scatter=scatter)
     if model != "nh":
         ctx.pncg_set_model(model)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)
@@ -35,3 +35,12 @@ def rel(a, b):
     b = np.asarray(b, dtype=np.float64)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def elem(a, b):
+    """Element-by-element deviation: max_i |a_i - b_i| / max_i |b_i|, so that
+    every element satisfies |a_i - b_i| <= elem(a, b) * max|b|."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0)) if b.size else 0.0

@@ -56,6 +56,27 @@ def test_create_rejects_bad_precision():
     assert e.value.code == P.E_INVAL
 
 
+def test_create_rejects_bad_scatter_mode():
+    import paper_2405_08001_amd as P
+    for bad in (-1, 3):
+        with pytest.raises(P.PncgError) as e:
+            P.Context(0, P.FP64, scatter=bad)
+        assert e.value.code == P.E_INVAL
+    for ok in (P.SCATTER_AUTO, P.SCATTER_ATOMIC, P.SCATTER_SEGMENTED):
+        P.Context(0, P.MIXED, scatter=ok).close()
+
+
+def test_candidates_override_needs_a_mesh():
+    import paper_2405_08001_amd as P
+    c = _ctx()
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_candidates_override(P.KIND_PT, np.array([[0, 0]]))
+    assert e.value.code == P.E_STATE
+    with pytest.raises(P.PncgError) as e:
+        c.pncg_set_candidates_override(P.KIND_PT, None)
+    assert e.value.code == P.E_STATE
+
+
 def test_call_order_is_enforced():
     import paper_2405_08001_amd as P
     c = _ctx()

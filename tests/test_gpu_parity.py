@@ -332,9 +332,9 @@ def test_in_place_step_after_capacity_rerun(K):
     _say(f"  rebuilds {sa['rebuilds']}/{si['rebuilds']}/{sh['rebuilds']} "
          f"rel dx in place {rel(xi - x0, xa - x0):.2e} host {rel(xh - x0, xa - x0):.2e}")
     assert sa["iters"] == si["iters"] == sh["iters"] == K
-    # pair forces are summed with float64 atomics: equal up to their order
+    # the segmented pair scatter is deterministic: equal bits
     for xb, vb in ((xi, vi), (xh, vh)):
-        assert rel(xb - x0, xa - x0) <= 1e-12 and rel(vb, va) <= 1e-12
+        assert np.array_equal(xb, xa) and np.array_equal(vb, va)
 
 
 def _run_pair(sc, x0, v0, precision, n, **kw):
@@ -358,10 +358,9 @@ def _run_pair(sc, x0, v0, precision, n, **kw):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_run_dev_equals_repeated_steps(precision):
     """pncg_run_dev: n steps in place with no return in between give the
-    states and per-step statistics of n separate steps.  The cube on its
-    floor has no pair atomics, so the bits agree; the stacked cubes (self
-    contact, list rebuilds) run 12 fixed iterations per step and agree to
-    the order of their float64 atomic sums."""
+    states and per-step statistics of n separate steps, bit for bit: the cube
+    on its floor, and the stacked cubes (self contact, list rebuilds, 12 fixed
+    iterations per step) under the default segmented pair scatter."""
     _say(f"run_dev vs repeated steps precision={precision}")
     sc, x0, v0 = _cube_drop()
     (xa, va, sts, rc), (xr, vr, ref) = _run_pair(sc, x0, v0, precision, 4)
@@ -375,8 +374,9 @@ def test_run_dev_equals_repeated_steps(precision):
     _say(f"  stack iters {[s['iters'] for s in sts]} rebuilds {[s['rebuilds'] for s in sts]} "
          f"rel dx {rel(xa - x0, xr - x0):.2e}")
     assert [s["iters"] for s in sts] == [r["iters"] for r in ref] == [12] * 5
-    assert rel(xa - x0, xr - x0) <= (1e-9 if precision == 0 else 1e-5)
-    assert rel(va, vr) <= (1e-9 if precision == 0 else 1e-5)
+    assert np.array_equal(xa, xr) and np.array_equal(va, vr)
+    for s, r in zip(sts, ref):
+        assert s["iters"] == r["iters"] and s["n_active"] == r["n_active"] and s["g_norm"] == r["g_norm"]
 
 
 def test_step_dev_reads_inputs_torch_has_just_written():

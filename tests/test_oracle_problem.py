@@ -123,3 +123,27 @@ def test_rigid_motion_has_zero_elastic_gradient():
     g = P.gradient(x, x, sc.h)             # x = xt: inertia term vanishes too
     assert np.abs(g).max() < 1e-12
     assert abs(P.energy(x, x, sc.h)) < 1e-14
+
+
+def test_candidates_override_with_the_full_lists_changes_nothing():
+    # an explicit list holding every pair within dhat (the brute-force AABB
+    # lists) gives the same active set; a subset drops exactly its complement
+    sc, P, x, xt = _contact_state()
+    a = P.active_set(x)
+    from oracle import candidates
+    pt = candidates.pt_brute(x, P.tris, P.surf_verts, P.dhat, P.excl_pt)
+    ee = candidates.ee_brute(x, P.edges, P.dhat, P.excl_ee)
+    P.set_candidates_override(pt, ee[:, ::-1])      # edge order inside a pair does not matter
+    b = P.active_set(x)
+    order_a = np.lexsort(a.idx.T[::-1])
+    order_b = np.lexsort(b.idx.T[::-1])
+    np.testing.assert_array_equal(a.idx[order_a], b.idx[order_b])
+    np.testing.assert_array_equal(a.d[order_a], b.d[order_b])
+    g_full = P.gradient(x, xt, 1.0 / 60, b)
+    P.set_candidates_override(pt, None)              # point-triangle pairs only
+    c = P.active_set(x)
+    assert np.all(c.kind == 0) and np.sum(c.kind == 0) == np.sum(a.kind == 0)
+    assert not np.allclose(P.gradient(x, xt, 1.0 / 60, c), g_full)
+    P.set_candidates_override(None, None)
+    d = P.active_set(x)
+    np.testing.assert_array_equal(np.sort(d.d), np.sort(a.d))
