@@ -293,6 +293,27 @@ int pncg_step_dev(pncg_ctx* ctx, const double* x_dev, const double* v_dev,
                   double h, double* x_out_dev, double* v_out_dev,
                   pncg_stats* st);
 
+/* Allocation-free variant of pncg_step_dev, for callers that cannot
+ * allocate device memory during a call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, results
+ * and errors as pncg_step_dev, and the same kernels.  The step's reduction
+ * scratch (its status record, the per-block partial sums of the
+ * per-iteration kernels and one scalar record per iteration) lives in a
+ * static device array of 1 MiB that the library holds on every device it
+ * runs on until the process ends; the per-vertex state and the candidate
+ * buffers are the context's, sized by pncg_set_mesh, pncg_set_contact and
+ * earlier steps.  Every call on one device shares that device's array, so
+ * calls that overlap on one device (from two host threads, or on two
+ * streams) race and must not be made.  Errors, besides pncg_step_dev's:
+ * E_INVAL for iter_max above PNCG_NOALLOC_ITER_MAX or a split step
+ * (PNCG_SPLIT_OBJECTS); E_STATE with profiling on; E_CAPACITY when the
+ * candidate list or the spatial grid would have to grow (outputs are then
+ * unspecified, a state passed in place is left unchanged, and one
+ * pncg_step_dev call grows the buffers). */
+#define PNCG_NOALLOC_ITER_MAX 9566
+int pncg_step_dev_noalloc(pncg_ctx* ctx, const double* x_dev, const double* v_dev, double h,
+                          double* x_out_dev, double* v_out_dev, pncg_stats* st);
+
 /* nsteps >= 1 time steps in place on the device state x_dev, v_dev [nV][3]
  * (each exactly as pncg_step_dev with the outputs written over the
  * inputs), without returning to the caller in between: a simulation loop

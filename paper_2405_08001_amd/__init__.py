@@ -16,7 +16,7 @@ _BINDING_NAMES = {
     "BARRIER_FULL", "ALPHA_INF_COMPONENT", "BETA_DK", "BETA_FR", "BETA_PRP", "BETA_CD", "BETA_HZ", "BETA_RULES", "SPLIT_OBJECTS", "MODEL_NH", "MODEL_SNH", "MODEL_ARAP", "MODEL_FCR", "MODELS", "CONTACT_SELF", "CONTACT_REST_EXCLUDE", "KIND_PT", "KIND_EE",
     "KIND_PG", "W_MAXITER", "E_INVAL", "E_STATE", "E_INVERTED", "E_NONFINITE", "E_PENETRATION", "E_HIP",
     "E_CAPACITY", "E_INDEFINITE", "EXPORTS", "LIB_PATH", "PROF_KINDS", "SCATTER_AUTO", "SCATTER_ATOMIC",
-    "SCATTER_SEGMENTED",
+    "SCATTER_SEGMENTED", "NOALLOC_ITER_MAX", "E_CAPACITY",
 }
 
 

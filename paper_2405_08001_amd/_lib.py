@@ -29,6 +29,7 @@ MODELS = {"nh": MODEL_NH, "snh": MODEL_SNH, "arap": MODEL_ARAP, "fcr": MODEL_FCR
 CONTACT_SELF, CONTACT_REST_EXCLUDE = 1, 2
 KIND_PT, KIND_EE, KIND_PG = 0, 1, 2
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SEGMENTED = 0, 1, 2
+NOALLOC_ITER_MAX = 9566
 
 CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
               -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY", -9: "E_INDEFINITE"}
@@ -41,7 +42,7 @@ EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "p
            "pncg_batch_set_block", "pncg_batch_step", "pncg_batch_run", "pncg_batch_stats",
            "pncg_batch_autotune", "pncg_batch_set_staging", "pncg_batch_get_config",
            "pncg_batch_set_split", "pncg_set_model", "pncg_batch_set_model", "pncg_run_dev",
-           "pncg_set_candidates_override")
+           "pncg_set_candidates_override", "pncg_step_dev_noalloc")
 PROF_KINDS = ("narrow", "grad", "dir", "rebuild", "predict")
 
 
@@ -88,6 +89,7 @@ def _load():
         "pncg_set_dirichlet": (I32, [P, I32, P, P]),
         "pncg_set_tuning": (I32, [P, D, I32]),
         "pncg_set_candidates_override": (I32, [P, I32, C.c_int64, P]),
+        "pncg_step_dev_noalloc": (I32, [P, P, P, D, P, P, C.POINTER(pncg_stats)]),
         "pncg_set_model": (I32, [P, I32]),
         "pncg_batch_set_model": (I32, [P, I32]),
         "pncg_mean_boundary_edge": (I32, [P, P]),
@@ -247,6 +249,22 @@ class Context:
         st = pncg_stats()
         rc = self._check(_L.pncg_step_dev(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), float(h),
                                           C.c_void_p(x_out.data_ptr()), C.c_void_p(v_out.data_ptr()), C.byref(st)))
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def pncg_step_dev_noalloc(self, x, v, h, x_out, v_out):
+        """pncg_step_dev through the allocation-free entry point (the step's
+        reduction scratch in the library's static device array)."""
+        for t in (x, v, x_out, v_out):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+                    and tuple(t.shape) == (self.nV, 3)):
+                raise ValueError("step_dev_noalloc needs contiguous float64 CUDA tensors of shape (nV, 3)")
+        _ready(x, self._stream)
+        st = pncg_stats()
+        rc = self._check(_L.pncg_step_dev_noalloc(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()),
+                                                  float(h), C.c_void_p(x_out.data_ptr()),
+                                                  C.c_void_p(v_out.data_ptr()), C.byref(st)))
         d = st.as_dict()
         d["status"] = rc
         return d

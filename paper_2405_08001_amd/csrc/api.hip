@@ -11,6 +11,7 @@
 // displacement bound exceeds half the skin).
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +30,41 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Reduction scratch of the allocation-free step (pncg_step_dev_noalloc): the
+// step status, the per-block partials of the three per-iteration kernels and
+// the per-iteration scalar records.  Every call on a device shares that
+// device's copy; each call initialises what it reads before reading it.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr size_t kScratchStatus = 0;                                     // StepStatus
+constexpr size_t kScratchPartGrad = 256;                                 // [kMaxGrid][8] doubles
+constexpr size_t kScratchPartDir = kScratchPartGrad + 8 * sizeof(double) * kMaxGrid;   // [kMaxGrid][4]
+constexpr size_t kScratchPartNarrow = kScratchPartDir + 4 * sizeof(double) * kMaxGrid; // [kMaxGrid]
+constexpr size_t kScratchScal = kScratchPartNarrow + sizeof(double) * kMaxGrid;        // IterScal[...]
+constexpr int kScratchScalRecords = (int)((kScratchBytes - kScratchScal) / sizeof(IterScal));
+static_assert(sizeof(StepStatus) <= kScratchPartGrad, "step status does not fit its scratch slot");
+static_assert(kScratchScal % alignof(IterScal) == 0, "misaligned scratch records");
+static_assert(kScratchScalRecords - 2 == PNCG_NOALLOC_ITER_MAX, "PNCG_NOALLOC_ITER_MAX does not match the scratch");
+
+// Device address of `scratch` on each device, taken once with that device
+// current (the array's host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -43,6 +79,8 @@ struct pncg_ctx {
   bool own_stream = false;
   bool dev_ready = false;
   int scatter = PNCG_SCATTER_SEGMENTED;   // resolved PNCG_SCATTER_* of the options
+  void* d_static = nullptr;    // this device's `scratch` (pncg_step_dev_noalloc)
+  bool noalloc = false;        // inside pncg_step_dev_noalloc: no device allocation allowed
   int chunk = 16;
   std::string err;
   int state = 0;  // 0 created, 1 mesh, 2 material
@@ -211,6 +249,7 @@ int ensure_device(pncg_ctx* c) {
   if (e != hipSuccess || n <= 0) return fail(c, PNCG_E_HIP, "no HIP device available");
   if (c->device < 0 || c->device >= n) return fail(c, PNCG_E_INVAL, "device ordinal out of range");
   HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, scratch_address(c->device, &c->d_static));
   if (!c->stream) {
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->own_stream = true;
@@ -365,6 +404,8 @@ PairIndex make_pairindex(pncg_ctx* c) {
 // scatter); contents are not kept.
 int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (cap <= c->cand_cap) return PNCG_OK;
+  if (c->noalloc)
+    return fail(c, PNCG_E_CAPACITY, "the candidate list needs larger buffers (a pncg_step_dev call grows them)");
   for (void* p : {(void*)c->d_cand, (void*)c->d_cand_raw, (void*)c->d_cent, (void*)c->d_cact, (void*)c->d_cslot})
     dfree(c, p);
   c->d_cand = c->d_cand_raw = nullptr;
@@ -387,6 +428,7 @@ bool self_contact(const pncg_ctx* c) { return (c->cflags & PNCG_CONTACT_SELF) &&
 // The override lists (pncg_set_candidates_override) as one device list.
 int upload_override(pncg_ctx* c) {
   if (c->ovr_uploaded) return PNCG_OK;
+  if (c->noalloc) return fail(c, PNCG_E_STATE, "internal: the candidate override was not uploaded");
   std::vector<int2> all(c->ovr[0]);
   for (const int2& e : c->ovr[1]) all.push_back(make_int2(e.x, ~e.y));
   dfree(c, c->d_ovr);
@@ -1148,6 +1190,8 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   c->d_count = nullptr; c->d_start = nullptr; c->d_part_cnt = nullptr; c->d_part_off = nullptr;
   // grid entries: start with eight cells per primitive; grown on demand
   if ((rc = alloc_grid(c, 8LL * (nF + nE) + (long long)surf.size() + 4096))) return rc;
+  // the solver list's first capacity, so that steps start without allocating
+  if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * (long long)surf.size())))) return rc;
   HIPCHK(c, hipMemsetAsync(c->d_ncand, 0, 4 * sizeof(long long), c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_inc, inc.data(), sizeof(int) * inc.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_inc_vert, incv.data(), sizeof(int) * incv.size(), hipMemcpyHostToDevice, c->stream));
@@ -1382,7 +1426,11 @@ int pncg_set_candidates_override(pncg_ctx* c, int32_t kind, int64_t n, const int
   c->ovr[kind] = lst;
   c->ovr_set[kind] = true;
   c->ovr_uploaded = false;
-  return PNCG_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = upload_override(c);
+  if (rc) return rc;
+  if ((rc = ensure_cand_cap(c, std::max<long long>(c->n_ovr, 1024)))) return rc;
+  return sync(c);
 }
 
 static int ensure_split(pncg_ctx* c) {
@@ -1450,6 +1498,47 @@ int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, doubl
     if ((rc = grow_solver_buffers(c))) return rc;
   }
   return fail(c, PNCG_E_CAPACITY, "candidate buffers kept overflowing");
+}
+
+int pncg_step_dev_noalloc(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
+                          pncg_stats* st) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !v || !x_out || !v_out) return fail(c, PNCG_E_INVAL, "NULL state pointer");
+  if (!std::isfinite(h) || !(h > 0.0)) return fail(c, PNCG_E_INVAL, "need a finite h > 0");
+  if (c->iter_max > PNCG_NOALLOC_ITER_MAX)
+    return fail(c, PNCG_E_INVAL, "iter_max above PNCG_NOALLOC_ITER_MAX (" + std::to_string(PNCG_NOALLOC_ITER_MAX) + ")");
+  if (c->sflags & PNCG_SPLIT_OBJECTS) return fail(c, PNCG_E_INVAL, "the split step is not allocation-free");
+  if (c->profiling) return fail(c, PNCG_E_STATE, "profiling is on (it creates events)");
+  if (!c->d_static) return fail(c, PNCG_E_STATE, "no device scratch (set_mesh first)");
+  if (c->grid > kMaxGrid) return fail(c, PNCG_E_INVAL, "grid above the scratch partials");
+  HIPCHK(c, hipSetDevice(c->device));
+  // the step's reduction scratch moves to this device's static array for the call
+  unsigned char* base = static_cast<unsigned char*>(c->d_static);
+  StepStatus* status = c->d_status;
+  double *pg = c->d_part_grad, *pd = c->d_part_dir, *pn = c->d_part_narrow;
+  IterScal* scal = c->d_scal;
+  const int scal_cap = c->scal_cap;
+  c->d_status = reinterpret_cast<StepStatus*>(base + kScratchStatus);
+  c->d_part_grad = reinterpret_cast<double*>(base + kScratchPartGrad);
+  c->d_part_dir = reinterpret_cast<double*>(base + kScratchPartDir);
+  c->d_part_narrow = reinterpret_cast<double*>(base + kScratchPartNarrow);
+  c->d_scal = reinterpret_cast<IterScal*>(base + kScratchScal);
+  c->scal_cap = kScratchScalRecords;
+  c->noalloc = true;
+  if (st) std::memset(st, 0, sizeof(*st));
+  rc = c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)
+                                  : step_impl<double>(c, x, v, h, x_out, v_out, st);
+  c->noalloc = false;
+  c->d_status = status;
+  c->d_part_grad = pg;
+  c->d_part_dir = pd;
+  c->d_part_narrow = pn;
+  c->d_scal = scal;
+  c->scal_cap = scal_cap;
+  if (rc == kRestart)
+    return fail(c, PNCG_E_CAPACITY, "the contact buffers are too small for this state (a pncg_step_dev call grows them)");
+  return rc;
 }
 
 int pncg_run_dev(pncg_ctx* c, double* x, double* v, double h, int32_t nsteps, pncg_stats* steps) {
