@@ -304,7 +304,6 @@ __global__ void __launch_bounds__(kSBlock) k_cg_dir(Args<double> A, AdjArgs C, i
 template <int M, bool SEG = false>
 __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, int k) {
   __shared__ double sh[kSWaves * 2];
-  __shared__ double gsh[SEG ? kSWaves * 3 * kWave : 1];
   if (read_stopped(C.status)) return;
   const double4* pk = C.pbuf[k & 1];
   auto pget = [&](int v) -> V3<double> { return ld3(pk, v); };
@@ -315,6 +314,8 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
     const long long idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
+    int2 wr = make_int2(0, 0);
+    if constexpr (SEG) wr = wave_range(A.wrange, (int)w);
     double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (code >= 0) {
       const ElemRec<double> rec = A.elem[code >> 2];
@@ -342,10 +343,12 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
     seg_sum<double>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
     const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
-    double prs[3];
-    if constexpr (SEG) pair_gather<3>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + wave * 3 * kWave);
     if (!vlane) continue;
     const int v = myv;
+    double prs[3] = {0.0, 0.0, 0.0};
+    if constexpr (SEG) {
+      if (wr.x < wr.y) pair_partials_sum<3>(A.coff, A.rp, v, prs);
+    }
     const V3<double> p = pget(v);
     const double m = A.mass[v];
     double hv[3] = {fma(A.h2, s[0], m * p.x), fma(A.h2, s[1], m * p.y), fma(A.h2, s[2], m * p.z)};

@@ -124,13 +124,13 @@ struct pncg_ctx {
   int n_excl_pt = 0, n_excl_ee = 0;
   int2* d_cand = nullptr;
   long long cand_cap = 0;
-  // segmented scatter: the unsorted list, its canonical order's index and
-  // the per-(pair, corner) slots (all sized by cand_cap)
-  int2* d_cand_raw = nullptr;
-  int *d_bcnt = nullptr, *d_boff = nullptr, *d_vcnt = nullptr, *d_coff = nullptr, *d_cent = nullptr,
-      *d_pl_tmp = nullptr;
-  uint8_t* d_cact = nullptr;
-  double* d_cslot = nullptr;
+  // segmented scatter: the list's per-vertex entry index and the run
+  // partials of its pair terms (sized by cand_cap)
+  int *d_vcnt = nullptr, *d_coff = nullptr, *d_cent = nullptr, *d_cent_tmp = nullptr, *d_pl_tmp = nullptr,
+      *d_big = nullptr;
+  unsigned long long* d_ckey_tmp = nullptr;
+  int2 *d_wvert = nullptr, *d_wrange = nullptr;   // per incidence wave: first / last vertex, entry range
+  double* d_rp = nullptr;      // [4 cap][6] run partials of the pair entries
   // explicit candidate lists (pncg_set_candidates_override), kind in the pair
   bool ovr_set[2] = {false, false};
   std::vector<int2> ovr[2];
@@ -291,8 +291,8 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.seg = c->scatter == PNCG_SCATTER_SEGMENTED ? 1 : 0;
   A.coff = c->d_coff;
   A.cent = c->d_cent;
-  A.cact = c->d_cact;
-  A.cslot = c->d_cslot;
+  A.wrange = c->d_wrange;
+  A.rp = c->d_rp;
   A.self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0 ? 1 : 0;
   A.cand = c->d_cand;
   A.ncand = c->d_ncand;
@@ -339,9 +339,9 @@ int list_args(pncg_ctx* c, Args<R>& A) {
   A.cand_cap = c->cand_cap;
   A.coff = c->d_coff;
   A.cent = c->d_cent;
-  A.cact = c->d_cact;
-  A.cslot = c->d_cslot;
-  if (A.self && A.seg && (!A.cand || !A.coff || !A.cent || !A.cact || !A.cslot))
+  A.wrange = c->d_wrange;
+  A.rp = c->d_rp;
+  if (A.self && A.seg && (!A.cand || !A.coff || !A.cent || !A.rp || !A.wrange))
     return fail(c, PNCG_E_STATE, "internal: the candidate list or its pair index is not allocated");
   return PNCG_OK;
 }
@@ -386,15 +386,18 @@ Broad make_broad(pncg_ctx* c) {
 PairIndex make_pairindex(pncg_ctx* c) {
   PairIndex P{};
   P.nV = c->nV;
-  P.nE = c->nE;
   P.tris = c->d_tris;
   P.edges = c->d_edges;
-  P.bcnt = c->d_bcnt;
-  P.boff = c->d_boff;
   P.vcnt = c->d_vcnt;
   P.coff = c->d_coff;
   P.cent = c->d_cent;
+  P.cent_tmp = c->d_cent_tmp;
+  P.ckey_tmp = c->d_ckey_tmp;
+  P.big = c->d_big;
   P.scan_tmp = c->d_pl_tmp;
+  P.wvert = c->d_wvert;
+  P.wrange = c->d_wrange;
+  P.nWaves = c->nWaves;
   P.grid = c->grid;
   return P;
 }
@@ -406,18 +409,19 @@ int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (cap <= c->cand_cap) return PNCG_OK;
   if (c->noalloc)
     return fail(c, PNCG_E_CAPACITY, "the candidate list needs larger buffers (a pncg_step_dev call grows them)");
-  for (void* p : {(void*)c->d_cand, (void*)c->d_cand_raw, (void*)c->d_cent, (void*)c->d_cact, (void*)c->d_cslot})
+  for (void* p : {(void*)c->d_cand, (void*)c->d_cent, (void*)c->d_cent_tmp, (void*)c->d_ckey_tmp, (void*)c->d_rp})
     dfree(c, p);
-  c->d_cand = c->d_cand_raw = nullptr;
-  c->d_cent = nullptr;
-  c->d_cact = nullptr;
-  c->d_cslot = nullptr;
+  c->d_cand = nullptr;
+  c->d_ckey_tmp = nullptr;
+  c->d_cent = c->d_cent_tmp = nullptr;
+  c->d_rp = nullptr;
   c->cand_cap = 0;
   int rc;
   if ((rc = dmalloc(c, &c->d_cand, (size_t)cap))) return rc;
   if (c->scatter == PNCG_SCATTER_SEGMENTED &&
-      ((rc = dmalloc(c, &c->d_cand_raw, (size_t)cap)) || (rc = dmalloc(c, &c->d_cent, 4 * (size_t)cap)) ||
-       (rc = dmalloc(c, &c->d_cact, (size_t)cap)) || (rc = dmalloc(c, &c->d_cslot, 24 * (size_t)cap))))
+      ((rc = dmalloc(c, &c->d_cent, 4 * (size_t)cap)) || (rc = dmalloc(c, &c->d_cent_tmp, 4 * (size_t)cap)) ||
+       (rc = dmalloc(c, &c->d_ckey_tmp, 4 * (size_t)cap)) ||
+       (rc = dmalloc(c, &c->d_rp, 24 * (size_t)cap))))
     return rc;
   c->cand_cap = cap;
   return PNCG_OK;
@@ -442,11 +446,10 @@ int upload_override(pncg_ctx* c) {
   return PNCG_OK;
 }
 
-// With the segmented scatter, put the list in d_cand_raw into canonical
-// order in d_cand and index its corners.
+// With the segmented scatter, index the corner entries of the list in d_cand.
 void finish_list(pncg_ctx* c) {
   if (c->scatter != PNCG_SCATTER_SEGMENTED) return;
-  pairs_canonical(make_pairindex(c), c->d_cand_raw, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
+  pairs_index(make_pairindex(c), c->d_cand, c->d_ncand, c->cand_cap, c->stream);
 }
 
 // The override as the current candidate list (kind in the pair).
@@ -454,8 +457,7 @@ int install_override(pncg_ctx* c) {
   int rc;
   if ((rc = upload_override(c))) return rc;
   if ((rc = ensure_cand_cap(c, std::max<long long>(c->n_ovr, 1024)))) return rc;
-  const bool seg = c->scatter == PNCG_SCATTER_SEGMENTED;
-  pairs_install(c->d_ovr, c->n_ovr, seg ? c->d_cand_raw : c->d_cand, c->d_ncand, &c->d_status->n_cand, c->stream);
+  pairs_install(c->d_ovr, c->n_ovr, c->d_cand, c->d_ncand, &c->d_status->n_cand, c->stream);
   finish_list(c);
   return PNCG_OK;
 }
@@ -496,7 +498,7 @@ __global__ void k_copy_counts(const long long* totals, long long* ncand) {
 // (to size the pair list); the grid is rebuilt larger if its entry capacity
 // was too small.
 int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, int filter_obj, long long* n_total,
-                     long long* n_pt, bool canonical = false) {
+                     long long* n_pt, bool indexed = false) {
   int rc;
   long long n = 0;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -513,10 +515,8 @@ int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, i
   hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, c->stream, (const long long*)c->d_totals, c->d_ncand);
   if ((n > c->cand_cap || c->cand_cap == 0) && (rc = ensure_cand_cap(c, std::max<long long>(n + n / 2, 1024))))
     return rc;
-  const bool seg = canonical && c->scatter == PNCG_SCATTER_SEGMENTED;
-  broad_fill(make_broad(c), x, c->cell, r, filter_d, filter_obj, seg ? c->d_cand_raw : c->d_cand, c->cand_cap,
-             c->stream);
-  if (canonical) finish_list(c);
+  broad_fill(make_broad(c), x, c->cell, r, filter_d, filter_obj, c->d_cand, c->cand_cap, c->stream);
+  if (indexed) finish_list(c);
   if (n_total) *n_total = n;
   if (n_pt) *n_pt = npt;
   return PNCG_OK;
@@ -535,8 +535,7 @@ int build_solver_list(pncg_ctx* c, const double4* x) {
     if ((rc = install_override(c))) return rc;
   } else {
     if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;
-    const bool seg = c->scatter == PNCG_SCATTER_SEGMENTED;
-    broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, seg ? c->d_cand_raw : c->d_cand, c->cand_cap,
+    broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, c->d_cand, c->cand_cap,
                       c->d_ncand, &c->d_status->err, &c->d_status->n_cand, c->stream);
     finish_list(c);
   }
@@ -1151,7 +1150,8 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
-  c->d_cand_raw = nullptr; c->d_cent = nullptr; c->d_cact = nullptr; c->d_cslot = nullptr;
+  c->d_cent = nullptr; c->d_cent_tmp = nullptr; c->d_ckey_tmp = nullptr;
+  c->d_rp = nullptr;
   c->d_ovr = nullptr; c->n_ovr = 0; c->ovr_uploaded = false;
   c->ovr_set[0] = c->ovr_set[1] = false; c->ovr[0].clear(); c->ovr[1].clear();
   c->adj_ready = false; c->d_cgs = nullptr; c->cgs_cap = 0; c->E_uploaded = false;
@@ -1176,10 +1176,22 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
       (rc = dmalloc(c, &c->d_item_cnt, (size_t)nF + nE + surf.size())) ||
       (rc = dmalloc(c, &c->d_item_off, (size_t)nF + nE + surf.size() + 1)) ||
       (rc = dmalloc(c, &c->d_totals, 4)) ||
-      (rc = dmalloc(c, &c->d_bcnt, 2 * ((size_t)nV + nE))) || (rc = dmalloc(c, &c->d_boff, (size_t)nV + nE + 1)) ||
       (rc = dmalloc(c, &c->d_vcnt, 2 * (size_t)nV)) || (rc = dmalloc(c, &c->d_coff, (size_t)nV + 1)) ||
-      (rc = dmalloc(c, &c->d_pl_tmp, ((size_t)nV + nE) / kTileScan + 16)))
+      (rc = dmalloc(c, &c->d_pl_tmp, (size_t)nV / kTileScan + 16)) || (rc = dmalloc(c, &c->d_big, (size_t)nV + 1)) || (rc = dmalloc(c, &c->d_wvert, (size_t)c->nWaves)) ||
+      (rc = dmalloc(c, &c->d_wrange, (size_t)c->nWaves)))
     return rc;
+  {
+    // first and last vertex of every incidence wave (vertices ascend, padding at the end)
+    std::vector<int2> wv(c->nWaves);
+    for (int w = 0; w < c->nWaves; ++w) {
+      int last = incv[(size_t)w * kWave];
+      for (int l = 1; l < kWave; ++l) last = std::max(last, incv[(size_t)w * kWave + l]);
+      wv[w] = make_int2(incv[(size_t)w * kWave], last);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_wvert, wv.data(), sizeof(int2) * wv.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_wrange, 0, sizeof(int2) * wv.size(), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   c->scal_cap = 0;
   c->d_scal = nullptr;
   c->split_ready = false;

@@ -634,18 +634,18 @@ __device__ __forceinline__ void pl_corners(const PairIndex& P, int kind, int a, 
 }
 
 __global__ void __launch_bounds__(kBlock) k_pl_zero(PairIndex P) {
-  const int nb = 2 * (P.nV + P.nE), nv = 2 * P.nV;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) P.bcnt[i] = 0;
+  const int nv = 2 * P.nV;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < nv; i += gridDim.x * kBlock) P.vcnt[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.big[0] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pl_count(PairIndex P, const int2* in, const long long* ncand,
+// corner entries per vertex
+__global__ void __launch_bounds__(kBlock) k_pl_count(PairIndex P, const int2* list, const long long* ncand,
                                                      long long cap) {
   const long long n = min(ncand[0], cap), npt = ncand[1];
   for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
     int kind, a, b;
-    pl_decode(in[q], q, npt, kind, a, b);
-    atomicAdd(&P.bcnt[kind ? P.nV + a : a], 1);
+    pl_decode(list[q], q, npt, kind, a, b);
     int v[4];
     pl_corners(P, kind, a, b, v);
 #pragma unroll
@@ -653,72 +653,108 @@ __global__ void __launch_bounds__(kBlock) k_pl_count(PairIndex P, const int2* in
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pl_scatter(PairIndex P, const int2* in, int2* out,
-                                                       const long long* ncand, long long cap) {
-  const long long n = min(ncand[0], cap), npt = ncand[1];
-  const int nb = P.nV + P.nE;
-  for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
-    int kind, a, b;
-    pl_decode(in[q], q, npt, kind, a, b);
-    const int bk = kind ? P.nV + a : a;
-    const int pos = P.boff[bk] + atomicAdd(&P.bcnt[nb + bk], 1);
-    out[pos] = make_int2(a, kind ? ~b : b);
-  }
+// Content key of pair q: kind, then its two indices.  A vertex belongs to a
+// pair at most once, so the keys of one vertex's entries are distinct, and
+// their order does not depend on the list order.
+__device__ __forceinline__ unsigned long long pair_key(int kind, int a, int b) {
+  return ((unsigned long long)kind << 62) | ((unsigned long long)(unsigned)a << 31) | (unsigned long long)(unsigned)b;
 }
 
-// one thread per first index: insertion sort of its pairs by the second index
-__global__ void __launch_bounds__(kBlock) k_pl_sort(PairIndex P, int2* out) {
-  const int nb = P.nV + P.nE;
-  for (int bk = blockIdx.x * kBlock + threadIdx.x; bk < nb; bk += gridDim.x * kBlock) {
-    const int s0 = P.boff[bk], s1 = P.boff[bk + 1];
-    const bool ee = bk >= P.nV;
-    for (int i = s0 + 1; i < s1; ++i) {
-      const int2 x = out[i];
-      const int kx = ee ? ~x.y : x.y;
-      int j = i - 1;
-      while (j >= s0) {
-        const int2 y = out[j];
-        if ((ee ? ~y.y : y.y) <= kx) break;
-        out[j + 1] = y;
-        --j;
-      }
-      out[j + 1] = x;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_pl_corners(PairIndex P, const int2* out, long long* ncand,
+// entries grouped by vertex (slot ids 4 q + corner and their pairs' keys, in
+// no particular order within a vertex) and the entry range of each
+// incidence wave
+__global__ void __launch_bounds__(kBlock) k_pl_corners(PairIndex P, const int2* list, const long long* ncand,
                                                        long long cap) {
-  const long long n = min(ncand[0], cap);
+  const long long n = min(ncand[0], cap), npt = ncand[1];
   for (long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
     int kind, a, b;
-    pl_decode(out[q], q, -1, kind, a, b);
+    pl_decode(list[q], q, npt, kind, a, b);
+    const unsigned long long key = pair_key(kind, a, b);
     int v[4];
     pl_corners(P, kind, a, b, v);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pos = P.coff[v[i]] + atomicAdd(&P.vcnt[P.nV + v[i]], 1);
-      P.cent[pos] = (int)(4 * q + i);
+      P.cent_tmp[pos] = (int)(4 * q + i);
+      P.ckey_tmp[pos] = key;
+    }
+  }
+  for (int w = blockIdx.x * kBlock + threadIdx.x; w < P.nWaves; w += gridDim.x * kBlock) {
+    const int2 fv = P.wvert[w];
+    P.wrange[w] = make_int2(P.coff[fv.x], P.coff[fv.y + 1]);
+  }
+}
+
+// Each vertex's entries [coff[v], coff[v + 1]) of cent_tmp go to the same
+// range of cent in ascending key order: every entry is written at its rank
+// (the number of smaller keys of the vertex), which depends on the pairs
+// only.  One thread per vertex with at most kRankSmall entries (held in
+// registers); vertices with more are listed in big (count in big[0]) for
+// k_rank_big.
+constexpr int kRankSmall = 16;
+constexpr int kRankLds = 1024;   // keys of a vertex staged in LDS by k_rank_big
+
+__global__ void __launch_bounds__(kBlock) k_rank_small(PairIndex P) {
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < P.nV; v += gridDim.x * kBlock) {
+    const int s0 = P.coff[v], n = P.coff[v + 1] - s0;
+    if (n <= 0) continue;
+    if (n > kRankSmall) {
+      P.big[1 + atomicAdd(&P.big[0], 1)] = v;
+      continue;
+    }
+    int e[kRankSmall];
+    unsigned long long k[kRankSmall];
+#pragma unroll
+    for (int i = 0; i < kRankSmall; ++i)
+      if (i < n) {
+        e[i] = P.cent_tmp[s0 + i];
+        k[i] = P.ckey_tmp[s0 + i];
+      }
+#pragma unroll
+    for (int i = 0; i < kRankSmall; ++i) {
+      if (i >= n) break;
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < kRankSmall; ++j)
+        if (j < n && k[j] < k[i]) ++r;
+      P.cent[s0 + r] = e[i];
     }
   }
 }
 
-// one thread per vertex: insertion sort of its slot ids, then mark the list
-// as kind-in-pair
-__global__ void __launch_bounds__(kBlock) k_pl_csort(PairIndex P, long long* ncand) {
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < P.nV; v += gridDim.x * kBlock) {
-    const int s0 = P.coff[v], s1 = P.coff[v + 1];
-    for (int i = s0 + 1; i < s1; ++i) {
-      const int x = P.cent[i];
-      int j = i - 1;
-      while (j >= s0 && P.cent[j] > x) {
-        P.cent[j + 1] = P.cent[j];
-        --j;
-      }
-      P.cent[j + 1] = x;
+// One wave per listed vertex: its keys are staged in the wave's LDS block
+// (up to kRankLds; beyond that they are read from memory) and each lane
+// ranks entries lane, lane + 64, ... against all of them.
+__global__ void __launch_bounds__(kBlock) k_rank_big(PairIndex P) {
+  __shared__ unsigned long long ks[kBlock / kWave][kRankLds];
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long* kw = ks[threadIdx.x >> 6];
+  const int nbig = P.big[0];
+  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6, nw = (gridDim.x * kBlock) >> 6;
+  for (int w = wid; w < nbig; w += nw) {
+    const int v = P.big[1 + w];
+    const int s0 = P.coff[v], n = P.coff[v + 1] - s0;
+    const bool lds = n <= kRankLds;
+    if (lds) {
+      for (int i = lane; i < n; i += kWave) kw[i] = P.ckey_tmp[s0 + i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    const unsigned long long* kk = lds ? kw : P.ckey_tmp + s0;
+    for (int i0 = 0; i0 < n; i0 += kWave) {
+      const int i = i0 + lane;
+      if (i < n) {
+        const unsigned long long ki = kk[i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += kk[j] < ki ? 1 : 0;
+        P.cent[s0 + r] = P.cent_tmp[s0 + i];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ncand[1] = -1;
 }
 
 __global__ void __launch_bounds__(kBlock) k_pl_install(const int2* src, long long n, int2* out, long long* ncand,
@@ -733,16 +769,13 @@ __global__ void __launch_bounds__(kBlock) k_pl_install(const int2* src, long lon
 
 }  // namespace
 
-void pairs_canonical(const PairIndex& P, const int2* in, int2* out, long long* ncand, long long cap, hipStream_t s) {
-  const int nb = P.nV + P.nE;
+void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s) {
   hipLaunchKernelGGL(k_pl_zero, dim3(P.grid), dim3(kBlock), 0, s, P);
-  hipLaunchKernelGGL(k_pl_count, dim3(P.grid), dim3(kBlock), 0, s, P, in, (const long long*)ncand, cap);
-  scan_exclusive<int>(P.bcnt, nb, P.boff, P.boff + nb, P.scan_tmp, s);
+  hipLaunchKernelGGL(k_pl_count, dim3(P.grid), dim3(kBlock), 0, s, P, list, ncand, cap);
   scan_exclusive<int>(P.vcnt, P.nV, P.coff, P.coff + P.nV, P.scan_tmp, s);
-  hipLaunchKernelGGL(k_pl_scatter, dim3(P.grid), dim3(kBlock), 0, s, P, in, out, (const long long*)ncand, cap);
-  hipLaunchKernelGGL(k_pl_sort, dim3(P.grid), dim3(kBlock), 0, s, P, out);
-  hipLaunchKernelGGL(k_pl_corners, dim3(P.grid), dim3(kBlock), 0, s, P, (const int2*)out, ncand, cap);
-  hipLaunchKernelGGL(k_pl_csort, dim3(P.grid), dim3(kBlock), 0, s, P, ncand);
+  hipLaunchKernelGGL(k_pl_corners, dim3(P.grid), dim3(kBlock), 0, s, P, list, ncand, cap);
+  hipLaunchKernelGGL(k_rank_small, dim3(P.grid), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_rank_big, dim3(P.grid), dim3(kBlock), 0, s, P);
 }
 
 void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s) {

@@ -126,13 +126,13 @@ struct Args {
   R4<R>* p0;               // direction buffers (p_k lives in p[k & 1])
   R4<R>* p1;
   double* acc;             // [nV][8] contact accumulators: g xyz, diag xyz (atomic scatter)
-  // segmented scatter: every (pair, corner) writes a slot, each vertex adds
-  // its slots in the order of its corner entries
+  // segmented scatter: the (pair, corner) entries grouped by vertex are
+  // evaluated 64 to a wave and summed per vertex run into run partials
   int seg;                 // 1: segmented, 0: atomic
   const int* coff;         // [nV + 1] corner entries of each vertex
-  const int* cent;         // [4 cap] slot ids 4 q + corner, per vertex in pair-key order
-  uint8_t* cact;           // [cap] the pair was active at the last narrow phase
-  double* cslot;           // [4 cap][6] gradient xyz, diag xyz (or H p xyz) of each corner
+  const int* cent;         // [4 cap] slot id 4 q + corner of each entry (per vertex in pair-key order)
+  const int2* wrange;      // [nWaves] corner-entry range of each incidence wave's vertices
+  double* rp;              // [4 cap][6] run partials: gradient xyz, diag xyz (or H p xyz)
   // contact
   int self;                // point-triangle / edge-edge barriers on
   const int2* cand;        // candidate pairs: (v, f) point-triangle then (e1, e2) edge-edge

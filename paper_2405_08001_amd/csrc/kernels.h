@@ -79,26 +79,32 @@ void broad_fill(const Broad& B, const double4* x, double cell, double r, double 
 // the pair count to *n_out.
 void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
                        long long* ncand, int* err, long long* n_out, hipStream_t s);
-// Canonical order of a candidate list and the per-vertex index of its
-// (pair, corner) slots, for the segmented scatter of the pair terms.
+// Per-vertex index of the (pair, corner) entries of a candidate list, for the
+// segmented scatter of the pair terms.
 struct PairIndex {
-  int nV, nE;
+  int nV;
   const int* tris;       // [nF][3]
   const int* edges;      // [nE][2]
-  int* bcnt;             // [2 (nV + nE)] pairs per first index (v, or nV + e1), then fill counters
-  int* boff;             // [nV + nE + 1] their offsets
-  int* vcnt;             // [2 nV] corners per vertex, then fill counters
+  int* vcnt;             // [2 nV] entries per vertex, then fill counters
   int* coff;             // [nV + 1] their offsets
-  int* cent;             // [4 cap] slot ids (4 q + corner) grouped by vertex, ascending per vertex
-  int* scan_tmp;         // scan partials, (nV + nE) / 4096 + 2 ints
+  int* cent;             // [4 cap] slot ids (4 q + corner) grouped by vertex, each vertex's in the
+                         // order of its pairs' (kind, first index, second index)
+  int* cent_tmp;         // [4 cap] the same before the per-vertex ordering
+  unsigned long long* ckey_tmp;  // [4 cap] the pair key of each entry of cent_tmp
+  int* big;              // [nV + 1] vertices with more entries than a thread orders ([0] = count)
+  int* scan_tmp;         // scan partials, nV / 4096 + 2 ints
+  // entry range [x, y) of each 64-lane wave of the vertex incidence (its
+  // vertices' entries), so that waves without entries skip the pair sums
+  const int2* wvert;     // [nWaves] first and last vertex of each incidence wave
+  int2* wrange;          // [nWaves]
+  int nWaves;
   int grid;
 };
-// Sort in[0, min(ncand[0], cap)) lexicographically into out: point-triangle
-// (v, f) first, then edge-edge (e1, ~e2) (the kind is taken by position when
-// ncand[1] >= 0, else from the sign of the second index); set ncand[1] = -1
-// (kind in the pair) and build coff / cent for out.  No host
-// synchronisation; deterministic.
-void pairs_canonical(const PairIndex& P, const int2* in, int2* out, long long* ncand, long long cap, hipStream_t s);
+// Build coff / cent for list[0, min(ncand[0], cap)) (kind by position when
+// ncand[1] >= 0, else in the pair) and set each incidence wave's entry
+// range.  The entry order depends on the set of pairs only, not on their
+// order in the list.  No host synchronisation; deterministic.
+void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s);
 // Copy n pairs (kind in the pair) into out, set ncand = {n, -1} and *n_out = n.
 void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s);
 

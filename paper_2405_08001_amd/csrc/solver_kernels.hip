@@ -293,23 +293,121 @@ __device__ __forceinline__ void pair_hess_coefs(const Args<R>& A, double d, doub
   }
 }
 
-// Barrier gradient and diagonal of one active pair (eq8, eq10, eq11) into
-// its corners' slots (segmented scatter) or accumulators (atomic scatter).
+// Calls f(q) for the candidate pairs of this block: a contiguous slice of
+// the list (atomic scatter), or, with the segmented scatter, the pairs named
+// by the corner-0 entries of a slice of the per-vertex entry index, whose
+// order does not depend on the list's order (so sums over pairs are
+// reproducible).
+template <typename R, int BS, typename F>
+__device__ __forceinline__ void for_each_pair(const Args<R>& A, F&& f) {
+  const long long nq = min(A.ncand[0], A.cand_cap);
+  if (A.seg) {
+    const Slice se = block_slice(4 * nq);
+    for (long long j = se.begin + threadIdx.x; j < se.end; j += BS) {
+      const int sl = A.cent[j];
+      if ((sl & 3) == 0) f(sl >> 2);
+    }
+  } else {
+    const Slice sq = block_slice(nq);
+    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += BS) f((int)q);
+  }
+}
+
+// Barrier gradient and diagonal at corner i of an active pair (eq8, eq10,
+// eq11): val = {g xyz, diag xyz}.
 template <typename R>
-__device__ __forceinline__ void pair_grad_diag_out(const Args<R>& A, long long q, const int (&iv)[4],
-                                                   const Closest& c) {
+__device__ __forceinline__ void pair_grad_diag_corner(const Args<R>& A, const Closest& c, int i, double (&val)[6]) {
   const double d = c.d;
   const double cg = A.kappa * barrier_db(d, A.dhat) / d;
   double ca, cb;
   pair_hess_coefs(A, d, ca, cb);
+  const double ci = c.c[i];
+  const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
+  const double dj = cb * ci * ci;
+  val[0] = cg * tx; val[1] = cg * ty; val[2] = cg * tz;
+  val[3] = ca * tx * tx + dj; val[4] = ca * ty * ty + dj; val[5] = ca * tz * tz + dj;
+}
+
+// (H p) at corner i of an active pair and the pair's p^T H p (eq12, eq13):
+// (H p)_i = c_i [ca (t . sp) t + cb sp] with sp = sum_k c_k p_k.
+template <typename R>
+__device__ __forceinline__ double pair_hp_corner(const Args<R>& A, const Closest& c, const int (&iv)[4], int i,
+                                                 double (&val)[3]) {
+  double ca, cb;
+  pair_hess_coefs(A, c.d, ca, cb);
+  V3<double> sp = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sp = sp + c.c[k] * cast3<double>(ldr<R>(A.p0, iv[k]));
+  const double st = dot(sp, c.t);
+  const double ci = c.c[i];
+  val[0] = ci * (ca * st * c.t.x + cb * sp.x);
+  val[1] = ci * (ca * st * c.t.y + cb * sp.y);
+  val[2] = ci * (ca * st * c.t.z + cb * sp.z);
+  return ca * st * st + cb * dot(sp, sp);
+}
+
+// Atomic scatter: the gradient and diagonal of an active pair added to its
+// corners' accumulators.
+template <typename R>
+__device__ __forceinline__ void pair_grad_diag_atomic(const Args<R>& A, const int (&iv)[4], const Closest& c) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const double ci = c.c[i];
-    const double tx = ci * c.t.x, ty = ci * c.t.y, tz = ci * c.t.z;
-    const double dj = cb * ci * ci;
-    const double val[6] = {cg * tx, cg * ty, cg * tz, ca * tx * tx + dj, ca * ty * ty + dj, ca * tz * tz + dj};
-    pair_corner_out<6>(A.seg, A.cslot, A.acc, 4 * q + i, iv[i], val);
+    double val[6];
+    pair_grad_diag_corner(A, c, i, val);
+    double* a = A.acc + 8 * (size_t)iv[i];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) atomicAdd(a + j, val[j]);
   }
+}
+
+// Segmented scatter: the corner entries (grouped by vertex) of this block's
+// 64-entry chunks, one per lane; each lane evaluates its pair at `pos` (the
+// four entries of a pair evaluate it alike) and its corner's terms, a
+// wave-segmented sum reduces each vertex run and the run's first lane
+// stores the run partial in A.rp.  WHAT 0: gradient and diagonal (6 values);
+// WHAT 2: H p (3 values, p in A.p0) and p^T H p counted once per pair.
+// Returns this thread's count of active pairs (WHAT 0) or its p^T H p sum
+// (WHAT 2).
+template <typename R, int WHAT, int BS, typename Pos>
+__device__ __forceinline__ double pair_entries(const Args<R>& A, const Pos& pos) {
+  constexpr int N = WHAT == 0 ? 6 : 3;
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
+  const long long nent = 4 * nq;
+  const Slice sc = block_slice((nent + kWave - 1) / kWave);
+  double acc = 0.0;
+  for (long long m = sc.begin + (threadIdx.x >> 6); m < sc.end; m += BS / kWave) {
+    const long long j = m * kWave + lane;
+    double val[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) val[i] = 0.0;
+    int key = -1 - lane;   // distinct keys for lanes past the end
+    if (j < nent) {
+      const int sl = A.cent[j];
+      const int q = sl >> 2, ci = sl & 3;
+      int iv[4];
+      Closest c;
+      const bool act = pair_closest(A, q, pos, iv, c, npt);
+      key = iv[ci];
+      if (act) {
+        if constexpr (WHAT == 0) {
+          pair_grad_diag_corner(A, c, ci, val);
+          if (ci == 0) acc += 1.0;
+        } else {
+          const double php = pair_hp_corner(A, c, iv, ci, val);
+          if (ci == 0) acc += php;
+        }
+      }
+    }
+    seg_sum_d<N>(key, val);
+    const int up = __shfl_up(key, 1, kWave);
+    if (j < nent && (lane == 0 || up != key)) {
+      double* o = A.rp + 6 * (size_t)j;
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] = val[i];
+    }
+  }
+  return acc;
 }
 
 // First launch of an iteration with self contact: apply the pending update,
@@ -325,17 +423,19 @@ __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) 
   if (fp.materialize) apply_update<R, SPLIT>(A, k, fp, xcur, xprev, pk);
   if (!fp.work) return;
   const auto pos = first_pos<R, SPLIT>(A, k, fp, fp.materialize ? xprev : xcur, pk);
-  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
   double nact = 0.0;
-  const Slice sq = block_slice(nq);
-  for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
-    int iv[4];
-    Closest c;
-    const bool act = pair_closest(A, (int)q, pos, iv, c, npt);
-    if (A.seg) A.cact[q] = act ? 1 : 0;
-    if (!act) continue;
-    nact += 1.0;
-    pair_grad_diag_out(A, q, iv, c);
+  if (A.seg) {
+    nact = pair_entries<R, 0, kSBlock>(A, pos);
+  } else {
+    const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
+    const Slice sq = block_slice(nq);
+    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += kSBlock) {
+      int iv[4];
+      Closest c;
+      if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+      nact += 1.0;
+      pair_grad_diag_atomic(A, iv, c);
+    }
   }
   double v[1] = {nact};
   const int kind[1] = {0};
@@ -408,13 +508,12 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // kGradQuery: writes g and diag to out_g / out_d (float64, [nV][3]).
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
-// SEG: the contact-pair terms come from the segmented slots (pair_gather)
-// instead of the atomic accumulators.
+// SEG: the contact-pair terms come from the run partials of the segmented
+// scatter instead of the atomic accumulators.
 template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, bool SEG = false, int BS = GradBlock<R>::value>
 __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
   __shared__ double sh[NW * 8];
-  __shared__ double gsh[SEG ? NW * 6 * kWave : 1];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
     fp = first_prologue<R, SPLIT, BS>(A, k, mode, sh);
@@ -439,6 +538,8 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
     const int idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
+    int2 wr = make_int2(0, 0);
+    if constexpr (SEG) wr = wave_range(A.wrange, w);
     V3<R> g, dg;
     R s[6];
     if (lane_elem<R, M>(A, code, pos, g, dg)) {
@@ -450,11 +551,13 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
     seg_sum<R>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
     const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
-    double prs[6];
-    if constexpr (SEG) pair_gather<6>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + (threadIdx.x >> 6) * 6 * kWave);
     if (!vlane) continue;
     // this lane is the vertex's first lane
     const int v = myv;
+    double prs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (SEG) {
+      if (wr.x < wr.y) pair_partials_sum<6>(A.coff, A.rp, v, prs);
+    }
     const V3<double> x = pos(v);
     if (MODE == kGradFirst && fp.materialize) st3(xcur, v, x);
     double gd[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
@@ -657,12 +760,11 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   // split: each object's side of the pair with the other side's p left out
   if (A.self) {
     PosReader<R> pos{xk, pk, 0.0, 0};
-    const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
-    const Slice sq = block_slice(nq);
-    for (long long q = sq.begin + threadIdx.x; q < sq.end; q += BS) {
+    const long long npt = A.ncand[1];
+    for_each_pair<R, BS>(A, [&](int q) {
       int iv[4];
       Closest c;
-      if (!pair_closest(A, (int)q, pos, iv, c, npt)) continue;
+      if (!pair_closest(A, q, pos, iv, c, npt)) return;
       double ca, cb;
       pair_hess_coefs(A, c.d, ca, cb);
       if constexpr (SPLIT) {
@@ -697,7 +799,7 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
         const double st = dot(sp, c.t);
         acc_pHp += ca * st * st + cb * dot(sp, sp);
       }
-    }
+    });
   }
   if constexpr (SPLIT) return;
   double v[3] = {acc_pHp, pmv, pmc};
@@ -844,42 +946,46 @@ __global__ void __launch_bounds__(kSBlock) k_load_query(Args<R> A, const double*
 template <typename R, int WHAT>
 __global__ void __launch_bounds__(kSBlock) k_pairs_query(Args<R> A, double* part) {
   __shared__ double sh[kSWaves * 2];
-  const int tid = blockIdx.x * kSBlock + threadIdx.x, stride = gridDim.x * kSBlock;
   PosReader<R> pos{A.x0, A.p0, 0.0, 0};
-  const long long nq = min(A.ncand[0], A.cand_cap), npt = A.ncand[1];
+  const long long npt = A.ncand[1];
   double sum = 0.0;
-  for (long long q = tid; q < nq; q += stride) {
+  for_each_pair<R, kSBlock>(A, [&](int q) {
     int iv[4];
     Closest c;
-    const bool act = pair_closest(A, (int)q, pos, iv, c, npt);
-    if (WHAT != 1 && A.seg) A.cact[q] = act ? 1 : 0;
-    if (!act) continue;
+    if (!pair_closest(A, q, pos, iv, c, npt)) return;
     const double d = c.d;
     if (WHAT == 1) {
       sum += A.kappa * barrier_b(d, A.dhat);
-      continue;
+      return;
     }
     if (WHAT == 0) {
-      pair_grad_diag_out(A, q, iv, c);
+      pair_grad_diag_atomic(A, iv, c);
     } else {
-      double ca, cb;
-      pair_hess_coefs(A, d, ca, cb);
-      V3<double> sp = mk3(0.0, 0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sp = sp + c.c[i] * cast3<double>(ldr<R>(A.p0, iv[i]));
-      const double st = dot(sp, c.t);
-      sum += ca * st * st + cb * dot(sp, sp);
-      // (H p)_i = c_i [ca (t . sp) t + cb sp]
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double ci = c.c[i];
-        const double val[3] = {ci * (ca * st * c.t.x + cb * sp.x), ci * (ca * st * c.t.y + cb * sp.y),
-                               ci * (ca * st * c.t.z + cb * sp.z)};
-        pair_corner_out<3>(A.seg, A.cslot, A.acc, 4 * q + i, iv[i], val);
+        double val[3];
+        const double php = pair_hp_corner(A, c, iv, i, val);
+        if (i == 0) sum += php;
+        double* a = A.acc + 8 * (size_t)iv[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) atomicAdd(a + j, val[j]);
       }
     }
-  }
+  });
   double v[1] = {sum};
+  const int kind[1] = {0};
+  block_reduce<1>(v, kind, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Segmented form of the gradient / H p pair queries at x0 (WHAT 0, 2):
+// run partials into A.rp and per-block partials of the active-pair count or
+// p^T H p.
+template <typename R, int WHAT>
+__global__ void __launch_bounds__(kSBlock) k_pairs_entries(Args<R> A, double* part) {
+  __shared__ double sh[kSWaves * 2];
+  PosReader<R> pos{A.x0, A.p0, 0.0, 0};
+  double v[1] = {pair_entries<R, WHAT, kSBlock>(A, pos)};
   const int kind[1] = {0};
   block_reduce<1>(v, kind, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -923,7 +1029,6 @@ __global__ void __launch_bounds__(kSBlock) k_energy(Args<R> A, double* part) {
 template <typename R, int M, bool SEG = false>
 __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, double* part) {
   __shared__ double sh[kSWaves * 2];
-  __shared__ double gsh[SEG ? kSWaves * 3 * kWave : 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = (blockIdx.x * kSBlock + threadIdx.x) >> 6;
   const int nw = (gridDim.x * kSBlock) >> 6;
@@ -932,6 +1037,8 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
     const int idx = w * kWave + lane;
     const int code = A.inc[idx];
     const int myv = A.inc_vert[idx];
+    int2 wr = make_int2(0, 0);
+    if constexpr (SEG) wr = wave_range(A.wrange, w);
     R s[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (code >= 0) {
       const int e = code >> 2, a = code & 3;
@@ -949,10 +1056,12 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
     seg_sum<R>(myv, s);
     const int upv = __shfl_up(myv, 1, kWave);
     const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
-    double prs[3];
-    if constexpr (SEG) pair_gather<3>(A.coff, A.cent, A.cact, A.cslot, myv, vlane, prs, gsh + (threadIdx.x >> 6) * 3 * kWave);
     if (!vlane) continue;
     const int v = myv;
+    double prs[3] = {0.0, 0.0, 0.0};
+    if constexpr (SEG) {
+      if (wr.x < wr.y) pair_partials_sum<3>(A.coff, A.rp, v, prs);
+    }
     V3<R> pr = ldr<R>(A.p0, v);
     const double p3[3] = {double(pr.x), double(pr.y), double(pr.z)};
     double hv[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
@@ -1101,7 +1210,10 @@ void launch_load_query(const Args<R>& A, const double* x, const double* xt, cons
 }
 template <typename R>
 void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s) {
-  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  if (A.self && A.seg)
+    hipLaunchKernelGGL((k_pairs_entries<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  else if (A.self)
+    hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
   PNCG_BY_SCATTER(A.self && A.seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradQuery, false, M_, S_>), dim3(A.grid),
                                             dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d)));
 }
@@ -1114,14 +1226,17 @@ void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
 }
 template <typename R>
 void launch_query_hvp(const Args<R>& A, double* hp, double* out, hipStream_t s) {
-  if (A.self) hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  if (A.self) launch_pairs_hvp<R>(A, s);
   PNCG_BY_SCATTER(A.self && A.seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_hvp<R, M_, S_>), dim3(A.grid), dim3(kSBlock), 0, s, A, hp, A.part_dir)));
   // pair p^T H p is already inside H p at the vertices, so only k_hvp's partials are summed
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSBlock), 0, s, A.part_dir, A.grid, (const double*)nullptr, 0, out);
 }
 template <typename R>
 void launch_pairs_hvp(const Args<R>& A, hipStream_t s) {
-  hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  if (A.seg)
+    hipLaunchKernelGGL((k_pairs_entries<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
+  else
+    hipLaunchKernelGGL((k_pairs_query<R, 2>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
 }
 template <typename R>
 void launch_audit(const Args<R>& A, double* part, hipStream_t s) {

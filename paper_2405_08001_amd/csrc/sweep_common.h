@@ -165,77 +165,50 @@ __device__ __forceinline__ void seg_sum(int myv, R (&s)[6]) {
   }
 }
 
-// ------------------------------------------------- segmented pair gather
-// Sum of the first N values of the (pair, corner) slots of the active pairs
-// that touch this lane's vertex, in the fixed order of the vertex's corner
-// entries.  Called by every lane of a wave of the vertex-centric incidence
-// (vertices in increasing order, none straddling a wave, padding at the end);
-// `vlane` marks the lane that owns its vertex's total.  The wave's vertices
-// own one contiguous entry range, which the wave reads 64 entries at a time
-// (one per lane) into its LDS block `lds` ([N][64] doubles); each owning lane
-// then adds its own entries in order.
+// Entry range of incidence wave w (wave-uniform) by a scalar load, so that
+// waiting for it does not wait for the wave's outstanding vector memory
+// operations.  The range is written by an earlier launch.
+__device__ __forceinline__ int2 wave_range(const int2* wrange, int w) {
+  typedef const __attribute__((address_space(4))) int* ConstIntPtr;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const ConstIntPtr p = (ConstIntPtr)(const void*)(wrange + wu);
+  return make_int2(p[0], p[1]);
+}
+
+// ------------------------------------------------- segmented pair sums
+// The corner entries of the candidate pairs are grouped by vertex (each
+// vertex's entries in pair-key order) and evaluated 64 to a wave; a
+// wave-segmented sum leaves, at the first entry of every run of one vertex
+// inside a 64-entry chunk, the run's total (the run partial).  A vertex with
+// entries [c0, c1) adds the partials of the chunks it touches, in chunk
+// order: rp at max(c0, 64 k) for k = c0 / 64 ... (c1 - 1) / 64.
 template <int N>
-__device__ __forceinline__ void pair_gather(const int* coff, const int* cent, const uint8_t* cact,
-                                            const double* cslot, int myv, bool vlane, double (&out)[N],
-                                            double* lds) {
-  const int lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ void pair_partials_sum(const int* coff, const double* rp, int v, double (&out)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) out[i] = 0.0;
-  const unsigned long long valid = __ballot(myv >= 0);
-  if (!valid) return;
-  const int last = 63 - __clzll(valid);
-  const int vfirst = __shfl(myv, 0, kWave), vlast = __shfl(myv, last, kWave);
-  const int j0 = coff[vfirst], j1 = coff[vlast + 1];
-  if (j0 >= j1) return;
-  int my0 = 0, my1 = 0;
-  if (vlane) {
-    my0 = coff[myv];
-    my1 = coff[myv + 1];
-  }
-  for (int base = j0; base < j1; base += kWave) {
-    const int j = base + lane;
-    double e[N];
+  const int c0 = coff[v], c1 = coff[v + 1];
+  if (c0 >= c1) return;
+  for (int k = c0 >> 6; k * kWave < c1; ++k) {
+    const double* p = rp + 6 * (size_t)max(c0, k * kWave);
 #pragma unroll
-    for (int i = 0; i < N; ++i) e[i] = 0.0;
-    if (j < j1) {
-      const int s = cent[j];
-      if (cact[s >> 2]) {
-        const double* sl = cslot + 6 * (size_t)s;
-#pragma unroll
-        for (int i = 0; i < N; ++i) e[i] = sl[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) lds[i * kWave + lane] = e[i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (vlane) {
-      const int t0 = max(my0, base) - base, t1 = min(my1, base + kWave) - base;
-      for (int t = t0; t < t1; ++t) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) out[i] += lds[i * kWave + t];
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = 0; i < N; ++i) out[i] += p[i];
   }
 }
 
-// Slot values of one active pair corner (segmented scatter) or atomic adds
-// into the vertex's accumulator (atomic scatter): N values.
+// Wave-segmented sum of N doubles over runs of equal `key` (runs contiguous
+// within the wave); afterwards a run's first lane holds its total.
 template <int N>
-__device__ __forceinline__ void pair_corner_out(int seg, double* cslot, double* acc, long long slot, int v,
-                                                const double (&val)[N]) {
-  if (seg) {
-    double* sl = cslot + 6 * (size_t)slot;
+__device__ __forceinline__ void seg_sum_d(int key, double (&s)[N]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int ok = __shfl_down(key, off, kWave);
+    double o[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) sl[i] = val[i];
-  } else {
-    double* a = acc + 8 * (size_t)v;
+    for (int i = 0; i < N; ++i) o[i] = __shfl_down(s[i], off, kWave);
+    if (lane + off < kWave && ok == key) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) atomicAdd(a + i, val[i]);
+      for (int i = 0; i < N; ++i) s[i] += o[i];
+    }
   }
 }
 
