@@ -4,19 +4,29 @@
 Workload: the ~110k-tet pile (24 voxelised spheres and tori dropped into a
 0.4 m box; synthetic, seeded; dhat = 5e-4 m, h = 1/30 s, at most 25 PNCG
 iterations per frame, dE tolerance 1e-3), stepped in the mixed float32 /
-float64 form, with the plain float64 form timed on the same frames for
-comparison.  W untimed warm-up frames bring the shapes into contact; the
-timed region is K frames.  The primary value is PNCG iterations per second
-(summed over the K frames); ms per frame is reported beside it.
+float64 form.  The pile first falls for S untimed frames (default 150:
+input preparation, so that the timed frames are those of a pile at rest on
+its floor and on itself, frames S+W .. S+W+K of the configured 200), then W
+untimed warm-up frames, then K timed frames in one pncg_run_dev call.  The
+primary value is PNCG iterations per second over the K frames; ms per frame
+is reported beside it.  The same K frames are then run again from the saved
+state through one pncg_step_dev call per frame, and again with per-launch
+HIP events (profiling): the segmented pair scatter makes all three passes
+follow the same trajectory bit for bit.
 
 One JSON line is printed.  Besides the throughput it carries:
-  roofline      the dominant kernel's algorithmic bytes per launch over its
-                average launch time (HIP events on the library's stream,
-                from a separate profiled pass), against 8 TB/s
-  iter_roofline the whole iteration's algorithmic bytes (per-tet, per-vertex,
-                per-contact byte model) times iterations/s, against 8 TB/s
-  cpu_baseline  the float64 CPU oracle timed on a bounded sample of the same
-                workload (one PNCG iteration from the state after warm-up)
+  roofline      the dominant kernel's algorithmic bytes per launch (the
+                per-tet / per-vertex / per-pair byte model) over its average
+                launch time: from HIP events on the library's stream in the
+                profiled pass, and from the rocprofv3 summary committed in
+                profiles/ (when it was made from the current kernel sources)
+  iter_roofline the whole iteration's algorithmic bytes times iterations/s
+  fp64          the plain float64 form over the same frames
+  packed        the contact-rich packed pile (the same 24 shapes stacked with
+                sub-dhat gaps, ~25k point-triangle / edge-edge pairs active)
+  cpu_baseline  the float64 CPU oracle on bounded samples: pile iterations
+                (headline), batched scene steps over the host's cores, and one
+                adjoint step of the 30,000-tet bar
   batched       256 independent scenes (500-8000 tets each, 721k tets in
                 all) stepped together by the batched kernel, several steps per
                 captured graph: scene-steps/s and the kernel's byte rate
@@ -37,26 +47,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
-# algorithmic bytes (compulsory traffic, each array touched once per pass)
+# Algorithmic bytes (compulsory traffic: each array touched once per pass),
+# per tet, per vertex, per active point-triangle / edge-edge pair and per
+# candidate pair, for one PNCG iteration: two element passes (index 16 B,
+# D_m^-1 36 / 72 B, V mu and V lam 8 / 16 B), the vertex arrays of the
+# gradient pass (x, xt, m read; g, diag written), of the direction pass (g,
+# g_prev, diag, p_prev read; p written), of the curvature pass (x, p) and of
+# the update (x, p read; x written); a contact record written and read.
 BYTES = {
-    # per tet, per vertex, per active contact, per candidate, for one iteration
     "iter": {"mixed": (120, 232, 144, 8), "fp64": (208, 344, 144, 8)},
 }
-# per-launch algorithmic bytes of each kernel: per tet, per vertex, per candidate
+# The same model split over the kernels of one iteration (per tet, per vertex,
+# per active pair, per candidate).
 KERNEL_BYTES = {
-    # dir: tet record; x (24), P g, p_prev, p_new, mass (8); candidate pair (8)
-    "dir": {"mixed": (60, 24 + 12 + 12 + 12 + 8, 8), "fp64": (104, 24 + 24 + 24 + 24 + 8, 8)},
-    # grad: tet record; x, xt, mass, g_prev, p_prev, g, P g, contact accumulators (48)
-    "grad": {"mixed": (60, 24 + 24 + 8 + 12 * 4 + 48, 0), "fp64": (104, 24 + 24 + 8 + 24 * 4 + 48, 0)},
-    # narrow: pending update (x_prev, p, x) per vertex; candidate pair (8)
-    "narrow": {"mixed": (0, 24 + 12 + 24, 8), "fp64": (0, 24 + 24 + 24, 8)},
+    # grad: element pass (60 / 104 B per tet); per vertex x, xt (24 each), m
+    # (8), g_prev and p_prev read and g and P g written (4 vectors of 12 / 24
+    # B); per active pair the read half of its contact record (72 B)
+    "grad": {"mixed": (60, 24 + 24 + 8 + 12 * 4, 72, 0), "fp64": (104, 24 + 24 + 8 + 24 * 4, 72, 0)},
+    # dir: element pass; per vertex x (24), P g, p_prev, p_new (12 / 24 each),
+    # mass (8); candidate pair (8)
+    "dir": {"mixed": (60, 24 + 12 + 12 + 12 + 8, 0, 8), "fp64": (104, 24 + 24 + 24 + 24 + 8, 0, 8)},
+    # narrow: pending update (x_prev, p read, x written) per vertex; the
+    # written half of each active pair's record (72 B); candidate pair (8)
+    "narrow": {"mixed": (0, 24 + 12 + 24, 72, 8), "fp64": (0, 24 + 24 + 24, 72, 8)},
 }
+SETTLE_FRAMES = 150        # frames the pile falls before the warm-up and timed frames
 
 
 # kernels of the mixed single-scene path, by the name rocprofv3 records
 # the Neo-Hookean, unsplit instantiations the pile runs (template arguments:
 # real type, sweep mode, split, model, ...)
-KERNEL_NAMES = {"grad": "k_grad<float, 1, false, 0,", "dir": "k_dir<float, false, 0,", "narrow": "k_narrow<float, false>"}
+KERNEL_NAMES = {"grad": "k_grad<float, 1, false, 0, true,", "dir": "k_dir<float, false, 0,",
+                "narrow": "k_narrow<float, false>"}
+KERNEL_TIMES = os.path.join(ROOT, "profiles", "kernel_times.json")
 CALIB_BYTES = 256 << 20          # the calibration copy reads and writes this many bytes
 SOLVER_SOURCES = ("solver_kernels.hip", "sweep_common.h", "device_math.h", "internal.h")
 
@@ -159,49 +182,61 @@ def _torch_stream():
     return h or None
 
 
-def run(sc, precision, warmup, steps, profile_frames, model="nh"):
-    """W warm-up frames, then K timed frames in one pncg_run_dev call (the
-    state stays on the device and no host round trip separates the steps);
-    then K frames by separate pncg_step_dev calls from Python, for
-    comparison, and the profiled frames."""
+def run(sc, precision, settle, warmup, steps, model="nh", profile=True, per_call=True):
+    """S settle frames and W warm-up frames (untimed), then K timed frames in
+    one pncg_run_dev call (the state stays on the device and no host round
+    trip separates the steps); then the same K frames from the saved state
+    through one pncg_step_dev call per frame from Python, and again with
+    per-launch HIP events (profiling on)."""
     import torch
     ctx = setup_ctx(sc, precision, model)
     dev = torch.device("cuda:0")
     x = torch.tensor(sc.x0, dtype=torch.float64, device=dev)
     v = torch.tensor(sc.v0, dtype=torch.float64, device=dev)
-    if warmup > 0:
-        ctx.pncg_run_dev(x, v, sc.h, warmup)
+    if settle + warmup > 0:
+        ctx.pncg_run_dev(x, v, sc.h, settle + warmup)
+    xs, vs = x.clone(), v.clone()
     state = (x.cpu().numpy().copy(), v.cpu().numpy().copy())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sts, _ = ctx.pncg_run_dev(x, v, sc.h, steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    x_end = x.cpu().numpy().copy()
     iters = sum(st["iters"] for st in sts)
     act = sum(st["n_active"] for st in sts)
     cand = sum(st["n_candidates"] for st in sts)
-    # the same number of frames through one Python call per step
-    x2, v2 = torch.empty_like(x), torch.empty_like(v)
-    it_pc = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st = ctx.pncg_step_dev(x, v, sc.h, x2, v2)
-        x, x2, v, v2 = x2, x, v2, v
-        it_pc += st["iters"]
-    torch.cuda.synchronize()
-    dt_pc = time.perf_counter() - t0
-    # profiled pass (events around every launch) on further frames
-    ctx.pncg_set_profiling(True)
-    if profile_frames > 0:
-        ctx.pncg_run_dev(x, v, sc.h, profile_frames)
-    prof = ctx.pncg_get_profile()
-    ctx.pncg_set_profiling(False)
-    dmin, jmin = ctx.pncg_min_distance(x.cpu().numpy())
+    reb = sum(st["rebuilds"] for st in sts)
+    out = dict(seconds=dt, iters=iters, frames=steps, mean_active=act / steps, mean_cand=cand / steps,
+               rebuilds_per_frame=reb / steps, state=state, stats=sts)
+    if per_call:
+        # the same frames through one Python call per step
+        x.copy_(xs)
+        v.copy_(vs)
+        x2, v2 = torch.empty_like(x), torch.empty_like(v)
+        it_pc = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = ctx.pncg_step_dev(x, v, sc.h, x2, v2)
+            x, x2, v, v2 = x2, x, v2, v
+            it_pc += st["iters"]
+        torch.cuda.synchronize()
+        dt_pc = time.perf_counter() - t0
+        out["per_call"] = {"iters_per_s": round(it_pc / dt_pc, 1), "ms_per_frame": round(1e3 * dt_pc / steps, 4),
+                           "same_trajectory": bool(np.array_equal(x.cpu().numpy(), x_end))}
+    if profile:
+        # the same frames with HIP events around every launch
+        x.copy_(xs)
+        v.copy_(vs)
+        ctx.pncg_set_profiling(True)
+        ctx.pncg_run_dev(x, v, sc.h, steps)
+        out["prof"] = ctx.pncg_get_profile()
+        ctx.pncg_set_profiling(False)
+        out["prof_same_trajectory"] = bool(np.array_equal(x.cpu().numpy(), x_end))
+    out["dmin"], out["jmin"] = ctx.pncg_min_distance(x_end)
     ctx.close()
-    return dict(seconds=dt, iters=iters, frames=steps, mean_active=act / steps, mean_cand=cand / steps,
-                prof=prof, dmin=dmin, jmin=jmin, state=state,
-                per_call={"iters_per_s": round(it_pc / dt_pc, 1), "ms_per_frame": round(1e3 * dt_pc / steps, 4)})
+    return out
 
 
 def run_host_io(sc, state, frames=20):
@@ -331,25 +366,25 @@ def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
     return out
 
 
-def run_materials(sc, warmup=10, steps=30, profile_frames=5, models=("snh", "arap", "fcr"), batched=True,
+def run_materials(sc, warmup=0, steps=30, models=("snh", "arap", "fcr"), batched=True,
                   adjoint_model="fcr"):
     """The pile as configured under each other material model (mixed form):
     iteration rate, frame time, iterations per frame, and the sweep's
     roofline (its algorithmic bytes do not depend on the model); the
     256-scene batch under each model (10 graph-captured steps); and the
     differentiable 30,000-tet rollout under one corotated model."""
-    out = {"frames_warmup": warmup, "frames_timed": steps}
-    kt, kv, kq = KERNEL_BYTES["grad"]["mixed"]
+    out = {"frames_settle": SETTLE_FRAMES, "frames_warmup": warmup, "frames_timed": steps}
+    kt, kv, ka, kq = KERNEL_BYTES["grad"]["mixed"]
     for model in models:
         try:
-            r = run(sc, "mixed", warmup, steps, profile_frames, model=model)
+            r = run(sc, "mixed", SETTLE_FRAMES, warmup, steps, model=model, per_call=False)
         except Exception as e:  # a model whose trajectory leaves its domain
             out[model] = {"error": str(e)}
             continue
         ips = r["iters"] / r["seconds"]
         prof = {k: v for k, v in r["prof"].items() if v[1] > 0}
         gus = prof["grad"][0] / prof["grad"][1]
-        gb = kt * sc.nT + kv * sc.nV + kq * r["mean_cand"]
+        gb = kt * sc.nT + kv * sc.nV + ka * r["mean_active"] + kq * r["mean_cand"]
         out[model] = {"iters_per_s": round(ips, 1), "ms_per_frame": round(1e3 * r["seconds"] / r["frames"], 4),
                       "iters_per_frame": round(r["iters"] / r["frames"], 2),
                       "grad_us": round(gus, 3), "dir_us": round(prof["dir"][0] / prof["dir"][1], 3),
@@ -409,33 +444,10 @@ def run_dhat_strategy(pile, warmup=10, fractions=(0.3, 0.5, 0.7), budgets=(10, 2
     return out
 
 
-def cpu_baseline(sc, state, budget_iters=1):
-    """The float64 oracle, single-threaded, on one PNCG iteration from the
-    same state (the rest-pose exclusion set of this scene is empty, so it is
-    skipped in the oracle's setup)."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:      # pragma: no cover
-        threadpool_limits = None
-    from oracle import pncg, problem
-    prob = problem.Problem.from_scene(sc, rest_exclude=False)
-    x, v = state
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
-        t0 = time.perf_counter()
-        _, _, st = pncg.step(prob, x, v, sc.h, iter_max=budget_iters, eps=0.0, term="delta_e")
-        dt = time.perf_counter() - t0
-    finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
-    return dict(value=st.iters / dt, unit="iters/s", cores=1, kind="oracle",
-                sample=f"{st.iters} PNCG iteration(s) of the 110k-tet pile from the state after warm-up "
-                       f"(float64 NumPy oracle, 1 thread, {dt:.1f} s)")
-
-
-def run_batched(steps, warmup, model="nh"):
+def run_batched(steps, warmup, model="nh", state_out=None):
     """The 256-scene batch, mixed precision: W eager steps (the scenes fall
-    onto their planes), then K steps as one captured graph."""
+    onto their planes), then K steps as one captured graph.  state_out: a
+    directory that receives the state after the warm-up steps."""
     import torch
     import paper_2405_08001_amd as P
     import scenes
@@ -451,6 +463,9 @@ def run_batched(steps, warmup, model="nh"):
     x = torch.tensor(b["x"], dtype=torch.float64, device=dev)
     v = torch.tensor(b["v"], dtype=torch.float64, device=dev)
     bt.pncg_batch_run(x, v, s0.h, warmup)
+    if state_out:
+        np.savez(os.path.join(state_out, "batch_state.npz"), x=x.cpu().numpy(), v=v.cpu().numpy(),
+                 vert_off=np.asarray(b["vert_off"]))
     block = bt.pncg_batch_autotune(x, v, s0.h, 2)     # on the state the timed steps start from
     cfg = bt.pncg_batch_get_config()
     _, _, tot0 = bt.pncg_batch_stats()
@@ -525,13 +540,153 @@ def run_adjoint(steps=30, checkpoint=5, model="nh"):
             "loss": float(loss.detach()), "grad_norm": float(E.grad.norm()), "dtype": "f64"}
 
 
+def kernel_times_from(stats_csv, command):
+    """profiles/kernel_times.json from a rocprofv3 --stats kernel statistics
+    CSV: average and total duration and call count per kernel name, with the
+    solver sources' hash and the command that made it."""
+    import csv
+    rows = {}
+    with open(stats_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = r.get("Name") or r.get("KernelName") or r.get("Kernel_Name")
+            calls = int(r.get("Calls") or r.get("Count") or 0)
+            total = float(r.get("TotalDurationNs") or r.get("Total_Duration_Ns") or 0.0)
+            rows[name] = {"calls": calls, "avg_us": round(total / max(calls, 1) / 1e3, 3),
+                          "total_us": round(total / 1e3, 1)}
+    out = {"source_sha256": solver_source_hash(), "command": command, "kernels": rows}
+    with open(KERNEL_TIMES, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def rocprof_avg_us(kern):
+    """Average rocprofv3 duration of the kernel of KERNEL_NAMES[kern] from
+    profiles/kernel_times.json, if that file was made from the current
+    solver sources; else None."""
+    try:
+        kt = json.load(open(KERNEL_TIMES))
+    except (OSError, ValueError):
+        return None
+    if kt.get("source_sha256") != solver_source_hash():
+        return None
+    pat = KERNEL_NAMES.get(kern)
+    hits = [v for k, v in kt.get("kernels", {}).items() if pat and pat in k]
+    if len(hits) != 1:
+        return None
+    return hits[0]["avg_us"], kt.get("command")
+
+
+def kernel_roofline(kern, prof, sc, r, precision="mixed"):
+    """Dominant-kernel roofline: algorithmic bytes per launch (KERNEL_BYTES
+    with the frames' mean active pairs and candidates) over the average
+    launch time from the profiled pass's HIP events, and over the rocprofv3
+    average when profiles/kernel_times.json matches the sources."""
+    us = prof[kern][0] / prof[kern][1]
+    kt, kv, ka, kq = KERNEL_BYTES[kern][precision]
+    kbytes = kt * sc.nT + kv * sc.nV + ka * r["mean_active"] + kq * r["mean_cand"]
+    achieved = kbytes / (us * 1e-6)
+    out = {"bound": "hbm", "kernel": kern, "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "bytes_per_launch": int(kbytes),
+           "avg_launch_us": round(us, 3), "timing": "HIP events around each launch on the library's stream"}
+    rp = rocprof_avg_us(kern) if precision == "mixed" else None
+    if rp is not None:
+        out["avg_launch_us_rocprof"] = rp[0]
+        out["frac_rocprof"] = round(kbytes / (rp[0] * 1e-6) / HBM_PEAK, 4)
+        out["rocprof_command"] = rp[1]
+    return out
+
+
+def summarize(sc, r, precision):
+    ips = r["iters"] / r["seconds"]
+    bt, bv, ba, bq = BYTES["iter"][precision]
+    bytes_iter = bt * sc.nT + bv * sc.nV + ba * r["mean_active"] + bq * r["mean_cand"]
+    out = {"iters_per_s": round(ips, 1), "ms_per_frame": round(1e3 * r["seconds"] / r["frames"], 4),
+           "us_per_iter": round(1e6 / ips, 3), "mean_iters_per_frame": round(r["iters"] / r["frames"], 2),
+           "mean_active_pairs": round(r["mean_active"], 1), "mean_candidates": round(r["mean_cand"], 1),
+           "rebuilds_per_frame": round(r["rebuilds_per_frame"], 2),
+           "iter_roofline": {"bytes_per_iter": int(bytes_iter), "achieved_GBps": round(bytes_iter * ips / 1e9, 1),
+                             "frac": round(bytes_iter * ips / HBM_PEAK, 4)},
+           "min_distance_after": r["dmin"], "min_detF_after": r["jmin"]}
+    if "per_call" in r:
+        out["per_call"] = r["per_call"]
+    if "prof" in r:
+        prof = {k: v for k, v in r["prof"].items() if v[1] > 0}
+        out["kernels_us_avg"] = {k: round(v[0] / v[1], 3) for k, v in prof.items()}
+        out["kernels_launches"] = {k: v[1] for k, v in prof.items()}
+        out["profiled_same_trajectory"] = r["prof_same_trajectory"]
+    return out
+
+
+def cpu_baselines(workdir, n_pile_iters=3, n_batch_scenes=16, cores=8):
+    """Run in a child process (no GPU): the float64 oracle on bounded
+    samples of the three workloads, from states the GPU run saved in
+    workdir."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:      # pragma: no cover
+        pass
+    import multiprocessing as mp
+    import scenes
+    from oracle import adjoint, pncg, problem
+    out = {}
+    # pile: n PNCG iterations of the step from the state the timed frames start from
+    sc = scenes.pile_scene()
+    st = np.load(os.path.join(workdir, "pile_state.npy"))
+    prob = problem.Problem.from_scene(sc, rest_exclude=False)
+    t0 = time.perf_counter()
+    _, _, stt = pncg.step(prob, st[0], st[1], sc.h, iter_max=n_pile_iters, eps=0.0, term="delta_e")
+    dt = time.perf_counter() - t0
+    out["pile"] = {"value": round(stt.iters / dt, 4), "unit": "iters/s", "cores": 1, "kind": "oracle",
+                   "seconds": round(dt, 2), "iters": stt.iters}
+    # batched: one step of each of the first n scenes from the GPU state, over `cores` processes
+    b = np.load(os.path.join(workdir, "batch_state.npz"))
+    scs = scenes.batched_scenes()[:n_batch_scenes]
+    jobs = [(i, b["x"][b["vert_off"][i]:b["vert_off"][i + 1]], b["v"][b["vert_off"][i]:b["vert_off"][i + 1]])
+            for i in range(n_batch_scenes)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        iters = pool.map(_cpu_batch_scene, jobs)
+    dt = time.perf_counter() - t0
+    out["batched"] = {"value": round(n_batch_scenes / dt, 3), "unit": "scene-steps/s", "cores": cores,
+                      "kind": "oracle", "seconds": round(dt, 2), "iters": int(sum(iters)),
+                      "sample": f"one step of each of the first {n_batch_scenes} of the 256 scenes, "
+                                f"from the batch's state after its warm-up steps"}
+    # adjoint: one implicit-differentiation step of the 30,000-tet bar at a converged first step
+    dsc = scenes.diff_bar_scene(seed=4)
+    dp = problem.Problem.from_scene(dsc)
+    x1, _ = adjoint.newton_solve(dp, dsc.x0, dsc.v0, dsc.h)
+    xbar = np.random.default_rng(6).standard_normal(x1.shape)
+    t0 = time.perf_counter()
+    adjoint.step_adjoint(dp, x1, dsc.h, xbar, np.zeros_like(xbar))
+    dt = time.perf_counter() - t0
+    out["adjoint"] = {"value": round(1e3 * dt, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
+                      "sample": "one adjoint step (assembled Hessian, sparse direct solve, modulus gradient) "
+                                "of the 30,000-tet bar at its converged first step"}
+    return out
+
+
+def _cpu_batch_scene(job):
+    import scenes
+    from oracle import pncg, problem
+    i, x, v = job
+    s = scenes.batched_scenes()[i]
+    p = problem.Problem.from_scene(s)
+    _, _, st = pncg.step(p, x, v, s.h, iter_max=s.iter_max, eps=s.eps, term="delta_e")
+    return st.iters
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60, help="timed frames")
-    ap.add_argument("--warmup", type=int, default=10, help="untimed frames before timing")
-    ap.add_argument("--profile-frames", type=int, default=10)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--steps", type=int, default=50, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed frames after the settle frames")
+    ap.add_argument("--settle", type=int, default=SETTLE_FRAMES,
+                    help="frames the pile falls before the warm-up frames (input preparation)")
+    ap.add_argument("--packed-frames", type=int, default=10, help="frames of the packed pile from rest")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison runs")
+    ap.add_argument("--no-packed", action="store_true", help="skip the contact-rich packed pile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-scene batched run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable rollout")
@@ -539,11 +694,16 @@ def main():
     ap.add_argument("--no-dhat-strategy", action="store_true", help="skip the larger-dhat comparison")
     ap.add_argument("--no-split", action="store_true", help="skip the per-object splitting comparison")
     ap.add_argument("--no-materials", action="store_true", help="skip the pile and batch under the other material models")
+    ap.add_argument("--headline-only", action="store_true", help="only the mixed pile (for kernel profiles)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference dispatch for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calibrate-copy run into profiles/traffic.json")
+    ap.add_argument("--kernel-times-from", nargs=2, metavar=("STATS_CSV", "COMMAND"),
+                    help="no GPU run: turn a rocprofv3 --stats kernel statistics CSV into "
+                         "profiles/kernel_times.json")
+    ap.add_argument("--cpu-baselines", metavar="DIR", help=argparse.SUPPRESS)
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--batched-warmup", type=int, default=10)
     args = ap.parse_args()
@@ -551,10 +711,20 @@ def main():
         print(json.dumps(traffic_from_csv(args.traffic_from[0], args.traffic_from[1],
                                           os.path.join(ROOT, "profiles", "traffic.json"))))
         return
+    if args.kernel_times_from:
+        print(json.dumps(kernel_times_from(*args.kernel_times_from)))
+        return
+    if args.cpu_baselines:
+        with open(os.path.join(args.cpu_baselines, "cpu.json"), "w") as fh:
+            json.dump(cpu_baselines(args.cpu_baselines), fh)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is one scene or one batch)", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_fp64 = args.no_packed = args.no_cpu_baseline = args.no_batched = args.no_adjoint = True
+        args.no_beta_ablation = args.no_dhat_strategy = args.no_split = args.no_materials = True
 
     import torch
     if not torch.cuda.is_available():
@@ -571,24 +741,19 @@ def main():
 
     res = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        log(f"running {prec}: warmup {args.warmup}, timed {args.steps}")
-        res[prec] = run(sc, prec, args.warmup, args.steps, args.profile_frames)
+        log(f"running {prec}: settle {args.settle}, warmup {args.warmup}, timed {args.steps}")
+        res[prec] = run(sc, prec, args.settle, args.warmup, args.steps)
         r = res[prec]
         log(f"  {prec}: {r['iters']} iterations in {r['seconds'] * 1e3:.1f} ms "
-            f"({r['iters'] / r['seconds']:.0f} it/s), dmin={r['dmin']:.3e} jmin={r['jmin']:.3f}")
+            f"({r['iters'] / r['seconds']:.0f} it/s), active {r['mean_active']:.1f}, dmin={r['dmin']:.3e}")
 
     m = res["mixed"]
     ips = m["iters"] / m["seconds"]
     ms_frame = 1e3 * m["seconds"] / m["frames"]
-    bt, bv, ba, bq = BYTES["iter"]["mixed"]
-    bytes_iter = bt * sc.nT + bv * sc.nV + ba * m["mean_active"] + bq * m["mean_cand"]
-    # dominant kernel of the profiled pass
+    head = summarize(sc, m, "mixed")
     prof = {k: v for k, v in m["prof"].items() if v[1] > 0}
     kern = max((k for k in prof if k in KERNEL_BYTES), key=lambda k: prof[k][0])
-    avg_us = prof[kern][0] / prof[kern][1]
-    kt, kv, kq = KERNEL_BYTES[kern]["mixed"]
-    kbytes = kt * sc.nT + kv * sc.nV + kq * m["mean_cand"]
-    achieved = kbytes / (avg_us * 1e-6) / 1e9
+    roof = kernel_roofline(kern, prof, sc, m)
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
@@ -598,6 +763,8 @@ def main():
                 traffic = tj.get("pile", {}).get(kern)
         except (OSError, ValueError):
             traffic = None
+    roof["traffic"] = traffic
+    first = args.settle + args.warmup
     out = {
         "metric": "PNCG iterations/s, 110k-tet pile, mixed float32/float64",
         "value": round(ips, 1),
@@ -613,48 +780,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": "pile-110k", "tets": sc.nT, "vertices": sc.nV, "h": sc.h,
                    "iter_max": sc.iter_max, "eps": sc.eps, "dhat": sc.dhat,
-                   "frames_timed": args.steps, "frames_warmup": args.warmup,
-                   "mean_iters_per_frame": round(m["iters"] / m["frames"], 2),
-                   "mean_active_pairs": round(m["mean_active"], 1),
-                   "mean_candidates": round(m["mean_cand"], 1)},
+                   "frames": f"{first}-{first + args.steps} of the drop (settle {args.settle}, warm-up {args.warmup})",
+                   "scatter": "segmented (deterministic)",
+                   "mean_iters_per_frame": head["mean_iters_per_frame"],
+                   "mean_active_pairs": head["mean_active_pairs"],
+                   "mean_candidates": head["mean_candidates"]},
         "ms_per_frame": round(ms_frame, 4),
-        "per_call": m["per_call"],
-        "us_per_iter": round(1e6 / ips, 3),
-        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": round(achieved * 1e9 / HBM_PEAK, 4),
-                     "bytes_per_launch": int(kbytes), "avg_launch_us": round(avg_us, 3),
-                     "traffic": traffic},
-        "iter_roofline": {"bytes_per_iter": int(bytes_iter),
-                          "achieved_GBps": round(bytes_iter * ips / 1e9, 1),
-                          "frac": round(bytes_iter * ips / HBM_PEAK, 4)},
-        "kernels_us_avg": {k: round(v[0] / v[1], 3) for k, v in prof.items()},
-        "kernels_launches": {k: v[1] for k, v in prof.items()},
+        "per_call": head.get("per_call"),
+        "us_per_iter": head["us_per_iter"],
+        "roofline": roof,
+        "iter_roofline": head["iter_roofline"],
+        "kernels_us_avg": head.get("kernels_us_avg"),
+        "kernels_launches": head.get("kernels_launches"),
+        "profiled_same_trajectory": head.get("profiled_same_trajectory"),
+        "rebuilds_per_frame": head["rebuilds_per_frame"],
         "min_distance_after": m["dmin"],
         "min_detF_after": m["jmin"],
     }
     if "fp64" in res:
         f = res["fp64"]
-        fips = f["iters"] / f["seconds"]
-        out["fp64"] = {"iters_per_s": round(fips, 1), "ms_per_frame": round(1e3 * f["seconds"] / f["frames"], 4),
-                       "us_per_iter": round(1e6 / fips, 3)}
-        t8, v8, a8, q8 = BYTES["iter"]["fp64"]
-        b8 = t8 * sc.nT + v8 * sc.nV + a8 * f["mean_active"] + q8 * f["mean_cand"]
-        out["fp64"]["iter_roofline"] = {"bytes_per_iter": int(b8), "achieved_GBps": round(b8 * fips / 1e9, 1),
-                                        "frac": round(b8 * fips / HBM_PEAK, 4)}
+        out["fp64"] = summarize(sc, f, "fp64")
         fprof = {k: v for k, v in f["prof"].items() if v[1] > 0}
         if "grad" in fprof:
-            gus = fprof["grad"][0] / fprof["grad"][1]
-            kt, kv, kq = KERNEL_BYTES["grad"]["fp64"]
-            gb = kt * sc.nT + kv * sc.nV + kq * f["mean_cand"]
-            out["fp64"]["grad_roofline"] = {"achieved": round(gb / (gus * 1e-6) / 1e9, 1), "avg_launch_us": round(gus, 3),
-                                            "bytes_per_launch": int(gb), "frac": round(gb / (gus * 1e-6) / HBM_PEAK, 4)}
-        out["mixed_vs_fp64_speedup"] = round(ips / fips, 3)
+            out["fp64"]["grad_roofline"] = kernel_roofline("grad", fprof, sc, f, "fp64")
+        out["mixed_vs_fp64_speedup"] = round(ips / (f["iters"] / f["seconds"]), 3)
+    if not args.no_packed:
+        pk = scenes.packed_pile_scene()
+        out["packed"] = {"workload": "pile-110k packed (24 shapes stacked with 0.3 dhat gaps, from rest)",
+                         "frames": args.packed_frames}
+        for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+            log(f"packed pile {prec}: {args.packed_frames} frames from rest ...")
+            r = run(pk, prec, 0, 0, args.packed_frames)
+            out["packed"][prec] = summarize(pk, r, prec)
+            pprof = {k: v for k, v in r["prof"].items() if v[1] > 0}
+            out["packed"][prec]["grad_roofline"] = kernel_roofline("grad", pprof, pk, r, prec)
+            log(f"  {out['packed'][prec]['iters_per_s']} it/s, active {out['packed'][prec]['mean_active_pairs']}")
+    if not args.no_cpu_baseline:
+        import tempfile
+        workdir = tempfile.mkdtemp(prefix="pncg_bench_")
+        np.save(os.path.join(workdir, "pile_state.npy"), np.stack(m["state"]))
     log("pile through host arrays (PCIe-inclusive) ...")
     out["host_io"] = run_host_io(sc, m["state"])
     log(f"  {out['host_io']['iters_per_s']} it/s, {out['host_io']['ms_per_frame']} ms/frame")
     if not args.no_batched:
         log("batched: 256 scenes ...")
-        out["batched"] = run_batched(args.batched_steps, args.batched_warmup)
+        out["batched"] = run_batched(args.batched_steps, args.batched_warmup,
+                                     state_out=None if args.no_cpu_baseline else workdir)
         log(f"  {out['batched']['scene_steps_per_s']} scene-steps/s")
     if not args.no_adjoint:
         log("adjoint: 30,000-tet bar, 30 steps ...")
@@ -678,9 +849,24 @@ def main():
         log("larger-dhat strategy on the pile ...")
         out["dhat_strategy"] = run_dhat_strategy(sc)
         log("  " + ", ".join(f"{k} {v.get('rel_error', v.get('error'))}" for k, v in out["dhat_strategy"]["dhat"].items()))
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on one iteration ...")
-        out["cpu_baseline"] = cpu_baseline(sc, m["state"])
+    if not args.no_cpu_baseline and not args.no_batched:
+        log("timing the CPU oracle on bounded samples (child process, no GPU) ...")
+        import subprocess
+        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baselines", workdir],
+                            capture_output=True, text=True)
+        if cp.returncode == 0:
+            cb = json.load(open(os.path.join(workdir, "cpu.json")))
+            pile = cb["pile"]
+            ipf = head["mean_iters_per_frame"]
+            out["cpu_baseline"] = {
+                "value": pile["value"], "unit": "iters/s", "cores": pile["cores"], "kind": "oracle",
+                "sample": f"{pile['iters']} PNCG iterations of the step from the state the timed frames start "
+                          f"from (float64 NumPy oracle, 1 thread, {pile['seconds']} s); at the GPU's "
+                          f"{ipf} iterations per frame that is {ipf / pile['value']:.0f} s per frame "
+                          f"(extrapolated, not timed)",
+                "batched": cb["batched"], "adjoint": cb["adjoint"]}
+        else:
+            out["cpu_baseline"] = {"error": cp.stderr[-2000:]}
     print(json.dumps(out), flush=True)
 
 

@@ -318,9 +318,12 @@ int pncg_step_dev_noalloc(pncg_ctx* ctx, const double* x_dev, const double* v_de
  * (each exactly as pncg_step_dev with the outputs written over the
  * inputs), without returning to the caller in between: a simulation loop
  * with no per-step host round trip.  steps (nullable) receives one
- * pncg_stats per step, [nsteps].  Returns the first error (the state then
- * holds the last completed step), else PNCG_W_MAXITER if any step hit the
- * iteration cap, else PNCG_OK.  E_INVAL for nsteps < 1 or a NULL state. */
+ * pncg_stats per step, [nsteps].  Returns the first error, else
+ * PNCG_W_MAXITER if any step hit the iteration cap, else PNCG_OK.  After
+ * E_PENETRATION, E_INVERTED or E_CAPACITY the state holds the last
+ * completed step; after E_NONFINITE (found as the failed step writes its
+ * result) it may hold that non-finite result.  E_INVAL for nsteps < 1 or a
+ * NULL state. */
 int pncg_run_dev(pncg_ctx* ctx, double* x_dev, double* v_dev, double h,
                  int32_t nsteps, pncg_stats* steps);
 
@@ -384,9 +387,15 @@ int pncg_get_profile(pncg_ctx* ctx, double* total_us, int64_t* launches);
  * the optimality condition G(x^{t+1}) = 0.  For a loss L with adjoints
  * xbar = dL/dx^{t+1}, vbar = dL/dv^{t+1} ([nV][3]):
  *     H lambda = xbar + vbar / h   (H = Hessian of equation E at x1:
- *              inertia, exact Neo-Hookean Hessian (Sec. 3.1), plane barrier
- *              kappa b''(d) n n^T, pair barrier as the solver's pair Hessian
- *              model; prescribed rows removed)
+ *              inertia, the exact Hessian of the context's elastic density
+ *              (Sec. 3.1), plane barrier kappa b''(d) n n^T, and for
+ *              point-triangle / edge-edge pairs the solver's pair Hessian
+ *              model: the PSD projection of equation eq9 unless
+ *              PNCG_BARRIER_FULL, with frozen closest-point coefficients
+ *              either way; prescribed rows removed)
+ * With active point-triangle or edge-edge pairs that model is not the
+ * exact Hessian of equation E, so the result is the adjoint of the
+ * model, not the exact derivative; with planes only it is exact.
  *     xbar_t = M lambda - vbar / h          (= dL/dx^t)   [nV][3]
  *     vbar_t = h M lambda                   (= dL/dv^t)   [nV][3]
  *     Ebar[e] -= lambda . dG/dE_e           (dL/dE_e, ACCUMULATED) [nT]

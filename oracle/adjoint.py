@@ -103,11 +103,15 @@ def trajectory(prob, x0, v0, h, steps, tol=1e-10):
     return xs, vs
 
 
-def step_adjoint(prob, x1, h, xbar, vbar):
+def step_adjoint(prob, x1, h, xbar, vbar, pair_hessian="full"):
     """One backward step at the converged x^{t+1} = x1, given the loss
     adjoints xbar = dL/dx^{t+1}, vbar = dL/dv^{t+1}: returns
-    (dL/dx^t, dL/dv^t, this step's contribution to dL/dE, lambda)."""
-    H = prob.hessian_matrix(x1, h, mode="full")
+    (dL/dx^t, dL/dv^t, this step's contribution to dL/dE, lambda).
+    pair_hessian: the point-triangle / edge-edge barrier Hessian in H,
+    "full" (equation eq9 with frozen closest-point coefficients) or "psd" (its
+    projection, the solver's model); planes and elements are exact either
+    way."""
+    H = prob.hessian_matrix(x1, h, mode=pair_hessian)
     rhs = (np.asarray(xbar, dtype=np.float64) + np.asarray(vbar, dtype=np.float64) / h).copy()
     rhs[~prob.free] = 0.0
     lam = spla.spsolve(H.tocsc(), rhs.ravel()).reshape(-1, 3)

@@ -13,12 +13,13 @@ oriented (``det[X1-X0, X2-X0, X3-X0] > 0``).
 from .mesh import (hex_grid, surface_of, voxel_mesh, merge_meshes, Scene,
                    rotation_matrix)
 from .configs import (cube_scene, twisted_bar_scene, stacked_bars_scene, twist_targets, pile_scene,
+                      packed_pile_scene,
                       batched_scenes, pack_batch, diff_bar_scene, small_contact_scene,
                       tiny_scene)
 
 __all__ = [
     "hex_grid", "surface_of", "voxel_mesh", "merge_meshes", "Scene",
     "rotation_matrix", "cube_scene", "twisted_bar_scene", "stacked_bars_scene", "twist_targets",
-    "pile_scene", "batched_scenes", "pack_batch", "diff_bar_scene", "small_contact_scene",
+    "pile_scene", "packed_pile_scene", "batched_scenes", "pack_batch", "diff_bar_scene", "small_contact_scene",
     "tiny_scene",
 ]

@@ -153,6 +153,72 @@ def _pile_masks(rng, pitch, n_shapes):
     return masks
 
 
+def _pile_pitch(seed, n_shapes, target_tets):
+    """Voxel pitch at which the pile's shapes total target_tets (within 3 %),
+    by bisection on the cell count."""
+    def count(p):
+        return 6 * sum(int(m.sum()) for m, _ in _pile_masks(np.random.default_rng(seed), p, n_shapes))
+    lo, hi = 0.003, 0.02
+    for _ in range(25):
+        mid = 0.5 * (lo + hi)
+        if count(mid) > target_tets:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def packed_pile_scene(seed=2, n_shapes=24, target_tets=110_000, box=0.4, gap_frac=0.3, dhat=5e-4):
+    """A contact-rich state of the pile workload: the same 24 voxelised
+    shapes (the pile's masks and pitch, so the same tet and vertex counts;
+    interior vertices jittered by U[-0.1,0.1]*pitch), unrotated and stacked in
+    four columns inside the 0.4 m box, each turned by a random angle about the
+    vertical axis: spheres in two columns, tori (lying flat) in the other two.  Each shape rests on the one below, or on the
+    floor, with a gap of gap_frac * dhat between the flat voxel facets that
+    face each other, so every facing pair of facets has its vertices, edges
+    and triangles within dhat: thousands of point-triangle and edge-edge
+    pairs and the plane contacts of the bottom shapes are active in the rest
+    state, which is also the start state (zero velocity).  E per shape is
+    log-uniform in [1e4, 1e6], nu = 0.4; the other settings are the pile's."""
+    pitch = _pile_pitch(seed, n_shapes, target_tets)
+    masks = _pile_masks(np.random.default_rng(seed), pitch, n_shapes)
+    rng = np.random.default_rng(seed + 1000)
+    gap = gap_frac * dhat
+    cols = {0: (0.1 * box / 0.4, 0.1 * box / 0.4), 1: (0.3 * box / 0.4, 0.1 * box / 0.4),
+            2: (0.1 * box / 0.4, 0.3 * box / 0.4), 3: (0.3 * box / 0.4, 0.3 * box / 0.4)}
+    top = {k: 0.0 for k in cols}
+    parts, Es = [], []
+    n_sph = n_tor = 0
+    for s, (mask, half) in enumerate(masks):
+        X, T = voxel_mesh(mask, pitch, origin=-np.asarray(half))
+        _, _, sv = surface_of(T)
+        interior = np.setdiff1d(np.arange(X.shape[0]), sv)
+        X[interior] += rng.uniform(-0.1 * pitch, 0.1 * pitch, size=(interior.size, 3))
+        # a random turn about the vertical axis: facets stay horizontal, but
+        # the lattices of facing facets no longer line up vertex on vertex
+        X = X @ rotation_matrix([0.0, 0.0, 1.0], rng.uniform(0.0, 0.5 * np.pi)).T
+        if s % 2 == 0:          # spheres: columns 0 and 3
+            col = 0 if n_sph % 2 == 0 else 3
+            n_sph += 1
+        else:                   # tori: columns 1 and 2
+            col = 1 if n_tor % 2 == 0 else 2
+            n_tor += 1
+        cx, cy = cols[col]
+        z0 = top[col] + gap
+        X = X + np.array([cx, cy, z0 - X[:, 2].min()])
+        top[col] = float(X[:, 2].max())
+        parts.append((X, T))
+        Es.append(float(np.exp(rng.uniform(np.log(1e4), np.log(1e6)))))
+    X, tets, oid = merge_meshes(parts)
+    E = np.concatenate([np.full(T.shape[0], e) for (_, T), e in zip(parts, Es)])
+    planes = np.array([[0, 0, 1, 0.0], [1, 0, 0, 0.0], [-1, 0, 0, -box],
+                       [0, 1, 0, 0.0], [0, -1, 0, -box]], dtype=np.float64)
+    return _scene(X, tets, E=E, nu=0.4, rho=1000.0, planes=planes, dhat=dhat,
+                  kappa=1e4, h=1.0 / 30.0, object_id=oid, self_contact=True,
+                  name="pile-packed", iter_max=25, eps=1e-3, cell=0.0,
+                  meta={"pitch": pitch, "n_shapes": n_shapes, "gap": gap})
+
+
 def pile_scene(seed=2, n_shapes=24, target_tets=110_000, pitch=None, box=0.4,
                gap=2e-3):
     """Voxelised spheres and tori stacked in a box of side ``box``.
@@ -165,17 +231,8 @@ def pile_scene(seed=2, n_shapes=24, target_tets=110_000, pitch=None, box=0.4,
     every shape already placed, so shapes meet the floor and each other within
     a few frames.  E per shape is log-uniform in [1e4, 1e6]; nu=0.4.
     """
-    def count(p):
-        return 6 * sum(int(m.sum()) for m, _ in _pile_masks(np.random.default_rng(seed), p, n_shapes))
     if pitch is None:
-        lo, hi = 0.003, 0.02
-        for _ in range(25):
-            mid = 0.5 * (lo + hi)
-            if count(mid) > target_tets:
-                lo = mid
-            else:
-                hi = mid
-        pitch = 0.5 * (lo + hi)
+        pitch = _pile_pitch(seed, n_shapes, target_tets)
     rng = np.random.default_rng(seed)
     masks = _pile_masks(rng, pitch, n_shapes)
     placed = []

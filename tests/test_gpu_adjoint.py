@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import scenes
-from helpers import make_ctx, make_problem, rel
+from helpers import elem, make_ctx, make_problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -185,3 +185,38 @@ def test_gradient_matches_central_differences_16_directions():
         assert err <= 1e-4
     _say(f"  worst {worst:.1e}; {time.perf_counter() - t_start:.1f} s, "
          f"forward iterations per step {np.mean([s['iters'] for s in sim.forward_stats]):.0f}")
+
+
+@pytest.mark.parametrize("scatter", [2, 1])
+def test_adjoint_step_with_self_contact_matches_oracle(scatter):
+    """Point-triangle, edge-edge and plane barriers active (the pressed cube
+    stack): the adjoint's linear solve H lambda = xbar + vbar / h on the
+    device (CG with the pair H p of the segmented or the atomic scatter)
+    against the oracle's sparse direct solve with the same pair Hessian model
+    (the solver's PSD projection, reading S7), element by element."""
+    from oracle import adjoint
+    sc = scenes.small_contact_scene()
+    x1 = sc.X.copy()
+    top = sc.object_id == 1
+    x1[top, 2] -= 5.5e-4
+    x1[~top, 2] -= 3e-4
+    # a deformed state (at the rest shape dG/dE vanishes and Ebar is only rounding)
+    x1 += np.random.default_rng(10).uniform(-3e-5, 3e-5, x1.shape)
+    P = make_problem(sc)
+    a = P.active_set(x1)
+    assert np.sum(a.kind == 0) > 0 and np.sum(a.kind == 1) > 0 and len(a.pd) > 0
+    rng = np.random.default_rng(9)
+    xbar = rng.standard_normal(x1.shape)
+    vbar = rng.standard_normal(x1.shape)
+    xo, vo, Eo, lo = adjoint.step_adjoint(P, x1, sc.h, xbar, vbar, pair_hessian="psd")
+    ctx = make_ctx(sc, 0, scatter=scatter)
+    xg, vg, Eg, st = ctx.pncg_adjoint_step(x1, sc.h, xbar, vbar, cg_tol=1e-13, cg_max=20000)
+    _say(f"self-contact adjoint scatter={scatter}: cg {st['cg_iters']} res {st['rel_residual']:.1e} "
+         f"xbar {elem(xg, xo):.2e} vbar {elem(vg, vo):.2e} Ebar {elem(Eg, Eo):.2e}")
+    assert st["reason"] == 0
+    # the stiff barriers make H ill-conditioned (thousands of CG iterations):
+    # a 1e-13 residual leaves lambda accurate to about 1e-9
+    assert elem(xg, xo) <= 1e-8 and elem(vg, vo) <= 1e-8 and elem(Eg, Eo) <= 1e-8
+    # and the pair Hessian matters: the full (unprojected) model gives another lambda
+    xf, _, _, _ = adjoint.step_adjoint(P, x1, sc.h, xbar, vbar, pair_hessian="full")
+    assert elem(xf, xo) > 1e-6
