@@ -350,6 +350,19 @@ int pncg_hvp(pncg_ctx* ctx, const double* x, const double* p, double h,
 int pncg_candidates(pncg_ctx* ctx, const double* x, int32_t kind,
                     int32_t* pairs, int64_t cap, int64_t* n);
 
+/* The solver's own pair list at x (the constraint set of Algorithm 1 with
+ * the list skin of pncg_set_tuning): point-triangle or edge-edge candidates
+ * by the inflated-AABB test with r = dhat + skin whose closest distance
+ * (Sec. 3.2, float64) is below dhat + skin, after topology and rest-pose
+ * exclusions, built by the same kernels a step uses for its list (a
+ * candidates override set with pncg_set_candidates_override is ignored
+ * here).  Sorted lexicographically, pairs [cap][2], edge-edge pairs as
+ * (e1, e2) with e1 < e2; *n receives the count, and if it exceeds cap the
+ * call returns E_CAPACITY and writes nothing.  Empty without
+ * PNCG_CONTACT_SELF.  E_INVAL for another kind. */
+int pncg_solver_pairs(pncg_ctx* ctx, const double* x, int32_t kind,
+                      int32_t* pairs, int64_t cap, int64_t* n);
+
 /* Penetration audit (Sec. 6: discrete collision check per frame): smallest
  * distance over all non-excluded point-triangle, edge-edge and
  * surface-vertex/plane pairs within 10 dhat, and smallest det F. */

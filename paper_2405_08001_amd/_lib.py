@@ -35,7 +35,7 @@ CODE_NAMES = {0: "OK", 1: "W_MAXITER", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP"
               -5: "E_PENETRATION", -6: "E_INVERTED", -7: "E_NONFINITE", -8: "E_CAPACITY", -9: "E_INDEFINITE"}
 EXPORTS = ("pncg_create", "pncg_destroy", "pncg_last_error", "pncg_set_mesh", "pncg_set_material",
            "pncg_set_contact", "pncg_set_solver", "pncg_set_dirichlet", "pncg_step", "pncg_step_dev",
-           "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_min_distance",
+           "pncg_energy", "pncg_gradient", "pncg_hvp", "pncg_candidates", "pncg_solver_pairs", "pncg_min_distance",
            "pncg_set_profiling", "pncg_get_profile", "pncg_adjoint_step", "pncg_adjoint_step_dev",
            "pncg_set_tuning", "pncg_mean_boundary_edge", "pncg_set_adjoint_warm_start",
            "pncg_batch_create", "pncg_batch_destroy", "pncg_batch_last_error", "pncg_batch_set_params",
@@ -101,6 +101,7 @@ def _load():
         "pncg_gradient": (I32, [P, P, P, D, P, P]),
         "pncg_hvp": (I32, [P, P, P, D, P, P]),
         "pncg_candidates": (I32, [P, P, I32, P, I64, C.POINTER(I64)]),
+        "pncg_solver_pairs": (I32, [P, P, I32, P, I64, C.POINTER(I64)]),
         "pncg_min_distance": (I32, [P, P, P, P]),
         "pncg_set_profiling": (I32, [P, I32]),
         "pncg_get_profile": (I32, [P, P, P]),
@@ -317,6 +318,16 @@ class Context:
             self._check(rc)
         out = np.empty((max(n.value, 1), 2), dtype=np.int32)
         self._check(_L.pncg_candidates(self._h, _ptr(x), int(kind), _ptr(out), out.shape[0], C.byref(n)))
+        return out[:n.value]
+
+    def pncg_solver_pairs(self, x, kind):
+        x = _f64(x, (self.nV, 3))
+        n = C.c_int64()
+        rc = _L.pncg_solver_pairs(self._h, _ptr(x), int(kind), None, 0, C.byref(n))
+        if rc < 0 and rc != E_CAPACITY:
+            self._check(rc)
+        out = np.empty((max(n.value, 1), 2), dtype=np.int32)
+        self._check(_L.pncg_solver_pairs(self._h, _ptr(x), int(kind), _ptr(out), out.shape[0], C.byref(n)))
         return out[:n.value]
 
     def pncg_min_distance(self, x):

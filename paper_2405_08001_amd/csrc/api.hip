@@ -1652,6 +1652,48 @@ int pncg_candidates(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, 
   return PNCG_OK;
 }
 
+int pncg_solver_pairs(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs, int64_t cap, int64_t* n) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!x || !n || cap < 0 || (cap > 0 && !pairs)) return fail(c, PNCG_E_INVAL, "bad arguments");
+  if (kind != PNCG_KIND_PT && kind != PNCG_KIND_EE) return fail(c, PNCG_E_INVAL, "kind must be PNCG_KIND_PT or _EE");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = stage_positions(c, x))) return rc;
+  std::vector<int2> all;
+  if ((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0) {
+    if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;
+    long long cnt[2] = {0, 0};
+    for (int attempt = 0;; ++attempt) {
+      broad_solver_list(make_broad(c), c->d_x0, c->cell, c->dhat + c->skin, c->d_cand, c->cand_cap, c->d_ncand,
+                        &c->d_status->err, &c->d_status->n_cand, c->stream);
+      HIPCHK(c, hipMemcpyAsync(&cnt[0], c->d_totals, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(&cnt[1], c->d_ncand, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+      if ((rc = sync(c))) return rc;
+      if (cnt[0] <= c->ent_cap && cnt[1] <= c->cand_cap) break;
+      if (attempt == 2) return fail(c, PNCG_E_NOMEM, "the solver's list did not fit after growing its buffers");
+      if (cnt[0] > c->ent_cap && (rc = alloc_grid(c, cnt[0] + cnt[0] / 2))) return rc;
+      if (cnt[1] > c->cand_cap && (rc = ensure_cand_cap(c, cnt[1] + cnt[1] / 2 + 1024))) return rc;
+    }
+    all.resize((size_t)cnt[1]);
+    if (cnt[1]) HIPCHK(c, hipMemcpyAsync(all.data(), c->d_cand, sizeof(int2) * cnt[1], hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync(c))) return rc;
+  }
+  // the kind is in the pair: (v, f) point-triangle, (e1, ~e2) edge-edge
+  std::vector<int2> out;
+  for (const int2& p : all) {
+    if (kind == PNCG_KIND_PT && p.y >= 0) out.push_back(p);
+    if (kind == PNCG_KIND_EE && p.y < 0) out.push_back(make_int2(p.x, ~p.y));
+  }
+  std::sort(out.begin(), out.end(), [](const int2& p, const int2& q) { return p.x < q.x || (p.x == q.x && p.y < q.y); });
+  *n = (int64_t)out.size();
+  if ((int64_t)out.size() > cap) return fail(c, PNCG_E_CAPACITY, "pairs buffer too small; *n holds the size needed");
+  for (size_t i = 0; i < out.size(); ++i) {
+    pairs[2 * i] = out[i].x;
+    pairs[2 * i + 1] = out[i].y;
+  }
+  return PNCG_OK;
+}
+
 int pncg_set_profiling(pncg_ctx* c, int32_t on) {
   if (!c) return PNCG_E_INVAL;
   c->profiling = on != 0;

@@ -397,6 +397,42 @@ __device__ __forceinline__ void edge_pairs(const Broad& B, const PairCtx& P, con
   }
 }
 
+// Edge-edge test of two slots of one bucket, the pair reported once: e1 is
+// the edge with the smaller item id, whose record takes the first place in
+// the exact box test, the reporting-cell test and the distance (the same
+// evaluation as edge_pairs from e1's side).  Emits (e1, ~e2).
+template <typename Rec>
+__device__ __forceinline__ bool edge_slot_pair_test(const Broad& B, const PairCtx& P, const Rec& R, int s, int t,
+                                                    int2& out) {
+  const int ebase = B.nSV + B.nF;
+  const unsigned long long key = R.key(s);
+  if (R.key(t) != key) return false;
+  int sa = s, sb = t;
+  if (R.item(t) < R.item(s)) {
+    sa = t;
+    sb = s;
+  }
+  const int4 idA = R.ids(sa), idB = R.ids(sb);
+  if (idA.x == idB.x || idA.x == idB.y || idA.y == idB.x || idA.y == idB.y) return false;
+  const V3<double> a0 = R.lo(sa), a1 = R.hi(sa), b0 = R.lo(sb), b1 = R.hi(sb);
+  const V3<double> loA = vmin3(a0, a1), hiA = vmax3(a0, a1), lo = vmin3(b0, b1), hi = vmax3(b0, b1);
+  const double r = P.r, q = 0.5 * P.r + kEdgeMargin;
+  if (!((loA.x - r) <= hi.x && (loA.y - r) <= hi.y && (loA.z - r) <= hi.z)) return false;
+  if (!(lo.x <= (hiA.x + r) && lo.y <= (hiA.y + r) && lo.z <= (hiA.z + r))) return false;
+  const V3<double> corner = mk3(fmax(loA.x - q, lo.x - q), fmax(loA.y - q, lo.y - q), fmax(loA.z - q, lo.z - q));
+  const int3 cc = cell_of(corner, P.inv);
+  if (cell_key(cc.x, cc.y, cc.z) != key) return false;
+  const int e1 = R.item(sa) - ebase, e2 = R.item(sb) - ebase;
+  if (P.filter_d >= 0.0) {
+    if (P.filter_obj && B.oid[idA.x] != B.oid[idB.x]) return false;
+    if (!(closest_ee(a0, a1, b0, b1).d < P.filter_d)) return false;
+  }
+  const unsigned long long pk = ((unsigned long long)(unsigned)e1 << 32) | (unsigned)e2;
+  if (B.n_excl_ee && in_sorted(B.excl_ee, B.n_excl_ee, pk)) return false;
+  out = make_int2(e1, ~e2);
+  return true;
+}
+
 // Load the edge buckets covering slots [S, S + kBlock) into LDS; returns the
 // first slot of the span, or -1 if the span does not fit.
 __device__ __forceinline__ int load_span(const Broad& B, SlotSpan& L, long long S, long long E) {
@@ -480,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_fill(Broad B, PairCtx P, int2*
 // block (edge-edge), in no particular order; the kind is in the pair:
 // (v, f) point-triangle, (e1, ~e2) edge-edge.  counter counts every pair
 // found, also those past cap (the caller checks it against cap).
-constexpr int kEmitBuf = 4;
+constexpr int kEbuf = 4 * kBlock;   // edge-edge pairs buffered per block before one counter update
 
 __device__ __forceinline__ int block_excl_scan(int v, int& total, int* sh) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
@@ -501,8 +537,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int& total, int* sh) {
 __global__ void __launch_bounds__(kBlock) k_pairs_emit(Broad B, PairCtx P, int2* out, long long cap,
                                                       unsigned long long* counter) {
   __shared__ SlotSpan L;
-  __shared__ int2 buf[kBlock * kEmitBuf];
+  __shared__ int2 ebuf[kEbuf];
+  __shared__ int soff[kBlock + 1];
   __shared__ int ssum[kBlock / kWave];
+  __shared__ int ecount;
   __shared__ unsigned long long sbase;
   const int lane = threadIdx.x & (kWave - 1);
   const long long e0 = B.start[B.tsize >> 1], e1 = B.start[B.tsize];
@@ -531,30 +569,55 @@ __global__ void __launch_bounds__(kBlock) k_pairs_emit(Broad B, PairCtx P, int2*
       }
     }
   }
-  // edge-edge: a block takes kBlock consecutive edge slots with their buckets in LDS
+  // edge-edge: a block takes kBlock consecutive edge slots with their
+  // buckets in LDS and enumerates the pairs (s, t), t a later slot of s's
+  // bucket, spread evenly over its threads (pair i of the block goes to
+  // thread i mod kBlock), so that a long bucket does not hold up a wave
   for (long long S = e0 + (long long)blockIdx.x * kBlock; S < e1; S += (long long)gridDim.x * kBlock) {
     const long long s = S + threadIdx.x;
-    const int base = load_span(B, L, S, min(S + (long long)kBlock, e1));
+    const long long Send = min(S + (long long)kBlock, e1);
+    const int base = load_span(B, L, S, Send);
     int c = 0;
-    if (s < e1)
-      edge_slot_pairs(B, P, L, base, (int)s, [&](int2 pr) {
-        if (c < kEmitBuf) buf[threadIdx.x * kEmitBuf + c] = make_int2(pr.x, ~pr.y);
-        ++c;
-      });
+    if (s < e1) c = B.start[hash_key(B.bkt_key[s], B.tsize, true) + 1] - (int)s - 1;
     int total;
     const int before = block_excl_scan(c, total, ssum);
-    if (threadIdx.x == 0) sbase = total ? atomicAdd(counter, (unsigned long long)total) : 0ull;
+    soff[threadIdx.x] = before;
+    if (threadIdx.x == 0) {
+      soff[kBlock] = total;
+      ecount = 0;
+    }
     __syncthreads();
-    const unsigned long long o = sbase + before;
-    for (int i = 0; i < c && i < kEmitBuf; ++i)
-      if ((long long)(o + i) < cap) out[o + i] = buf[threadIdx.x * kEmitBuf + i];
-    if (c > kEmitBuf) {
-      // more pairs than the buffer holds: enumerate again for the rest
-      int j = 0;
-      edge_slot_pairs(B, P, L, base, (int)s, [&](int2 pr) {
-        if (j >= kEmitBuf && (long long)(o + j) < cap) out[o + j] = make_int2(pr.x, ~pr.y);
-        ++j;
-      });
+    for (int r0 = 0; r0 < total; r0 += kBlock) {
+      const int i = r0 + threadIdx.x;
+      if (i < total) {
+        // the slot whose pairs hold index i: largest j with soff[j] <= i
+        int lo = 0, hi = kBlock;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (soff[mid] <= i) lo = mid; else hi = mid;
+        }
+        const int sa = (int)S + lo, sb = sa + 1 + (i - soff[lo]);
+        int2 pr;
+        const bool hit = base >= 0 ? edge_slot_pair_test(B, P, LdsRec{L, base}, sa, sb, pr)
+                                   : edge_slot_pair_test(B, P, GlobalRec{B}, sa, sb, pr);
+        if (hit) ebuf[atomicAdd(&ecount, 1)] = pr;
+      }
+      __syncthreads();
+      // every thread reads the count before any thread changes it again, so
+      // the flush decision is the same in the whole block
+      const int n = ecount;
+      __syncthreads();
+      // flush when another round could overflow the buffer, and at the end
+      if (n > kEbuf - kBlock || r0 + kBlock >= total) {
+        if (threadIdx.x == 0) {
+          sbase = n ? atomicAdd(counter, (unsigned long long)n) : 0ull;
+          ecount = 0;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += kBlock)
+          if ((long long)(sbase + j) < cap) out[sbase + j] = ebuf[j];
+        __syncthreads();
+      }
     }
     __syncthreads();
   }

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenes
-from helpers import make_ctx, make_problem, rel
+from helpers import check_solver_pairs, make_ctx, make_problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +95,11 @@ def test_candidates_bit_exact(which):
     assert np.array_equal(g_pg, pg), (len(g_pg), len(pg))
     if which != "cube":
         assert len(pt) > 0 and len(ee) > 0
+    # the solver's own list (distance-filtered, built by the step's kernels)
+    ctx.pncg_set_tuning(skin=2.0 * sc.dhat)
+    n_pt, n_ee = check_solver_pairs(ctx, P, x, 3.0 * sc.dhat)
+    if which == "bar":
+        assert n_pt > 0 and n_ee > 0
 
 
 def _cube_drop():
@@ -526,6 +531,25 @@ def test_pile_candidates_bit_exact_full_size():
     assert np.array_equal(g_pt, pt)
     assert np.array_equal(g_ee, ee)
     assert np.array_equal(g_pg, pg)
+
+
+def test_pile_solver_list_matches_oracle_full_size():
+    """The solver's own pair list (built by the step's kernels: candidates
+    within dhat + skin kept by their closest distance) on the squashed
+    110k-tet pile equals the oracle's at full size.  With a skin of 9 dhat
+    the list holds about 73k point-triangle and 209k edge-edge pairs, many
+    between neighbouring primitives of one surface, so the cell buckets are
+    long."""
+    _say("pile solver list (squashed)")
+    sc, P = _pile()
+    x = sc.x0.copy()
+    x[:, 2] *= 0.4
+    ctx = make_ctx(sc, 1)
+    skin = 9.0 * sc.dhat
+    ctx.pncg_set_tuning(skin=skin)
+    n_pt, n_ee = check_solver_pairs(ctx, P, x, sc.dhat + skin)
+    _say(f"  pt {n_pt} ee {n_ee}")
+    assert n_pt > 10000 and n_ee > 10000
 
 
 @pytest.mark.parametrize("precision", [1, 0])
