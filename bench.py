@@ -60,10 +60,12 @@ BYTES = {
 # The same model split over the kernels of one iteration (per tet, per vertex,
 # per active pair, per candidate).
 KERNEL_BYTES = {
-    # grad: element pass (60 / 104 B per tet); per vertex x, xt (24 each), m
-    # (8), g_prev and p_prev read and g and P g written (4 vectors of 12 / 24
-    # B); per active pair the read half of its contact record (72 B)
-    "grad": {"mixed": (60, 24 + 24 + 8 + 12 * 4, 72, 0), "fp64": (104, 24 + 24 + 8 + 24 * 4, 72, 0)},
+    # grad (first launch of an iteration, with the pair pass and the pending
+    # update folded in): element pass (60 / 104 B per tet); per vertex x_prev
+    # read and x written (24 each), xt (24), m (8), g_prev and p read and g
+    # and P g written (4 vectors of 12 / 24 B); per active pair its contact
+    # record written and read (144 B); per candidate the pair (8 B)
+    "grad": {"mixed": (60, 24 + 24 + 24 + 8 + 12 * 4, 144, 8), "fp64": (104, 24 + 24 + 24 + 8 + 24 * 4, 144, 8)},
     # dir: element pass; per vertex x (24), P g, p_prev, p_new (12 / 24 each),
     # mass (8); candidate pair (8)
     "dir": {"mixed": (60, 24 + 12 + 12 + 12 + 8, 0, 8), "fp64": (104, 24 + 24 + 24 + 24 + 8, 0, 8)},
@@ -77,7 +79,7 @@ SETTLE_FRAMES = 150        # frames the pile falls before the warm-up and timed 
 # kernels of the mixed single-scene path, by the name rocprofv3 records
 # the Neo-Hookean, unsplit instantiations the pile runs (template arguments:
 # real type, sweep mode, split, model, ...)
-KERNEL_NAMES = {"grad": "k_grad<float, 1, false, 0, true,", "dir": "k_dir<float, false, 0,",
+KERNEL_NAMES = {"grad": "k_grad<float, 0, false, 0, true,", "dir": "k_dir<float, false, 0,",
                 "narrow": "k_narrow<float, false>"}
 KERNEL_TIMES = os.path.join(ROOT, "profiles", "kernel_times.json")
 CALIB_BYTES = 256 << 20          # the calibration copy reads and writes this many bytes

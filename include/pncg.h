@@ -373,8 +373,11 @@ int pncg_min_distance(pncg_ctx* ctx, const double* x, double* dmin,
  * launch a step makes is bracketed by HIP events recorded on the context's
  * stream; durations are summed per kind:
  *   PNCG_PROF_NARROW  first launch of an iteration with self contact
- *                     (update + pair gradient/diagonal)
- *   PNCG_PROF_GRAD    element gradient/diag sweep + dot products
+ *                     under the atomic scatter or with
+ *                     PNCG_SPLIT_OBJECTS (update + pair gradient/diagonal)
+ *   PNCG_PROF_GRAD    element gradient/diag sweep + dot products (with the
+ *                     segmented scatter and one step size, also the update
+ *                     and the pair pass, which run inside it)
  *   PNCG_PROF_DIR     direction + p^T H p sweep
  *   PNCG_PROF_REBUILD candidate-list rebuild (hash build + pair queries,
  *                     including its host synchronisation)

@@ -11,7 +11,12 @@ unconstrained stationary point lies in the domain it is the minimiser,
 otherwise the minimum lies on the boundary, i.e. on one of the triangle's
 three edges (PT) or on one of the four sides s=0, s=1, u=0, u=1 of the
 parameter square (EE), each a clamped point-segment projection.  On exact
-ties the first case in that order wins.
+ties the first case in that order wins (ties="first"); ties="last" takes the
+last, an equally valid choice.  Ties occur where the closest points are not
+unique (parallel overlapping edges, a point equidistant from two triangle
+edges): there the distance is the same either way but the coefficients c,
+and so the barrier gradient's split over the four vertices, are not, and a
+test can measure how far that choice alone moves a result.
 
 Readings: a zero-area triangle is an input error; two edges count as parallel
 (no interior stationary point) when (d1.d1)(d2.d2) - (d1.d2)^2 <=
@@ -39,7 +44,17 @@ def point_segment(p, a, b):
     return tau, t
 
 
-def point_triangle(x0, x1, x2, x3):
+def _pick(d2, ties):
+    """Index of the smallest candidate per pair: the first of equal ones, or
+    the last (ties="last")."""
+    if ties == "first":
+        return np.argmin(d2, axis=0)
+    if ties == "last":
+        return d2.shape[0] - 1 - np.argmin(d2[::-1], axis=0)
+    raise ValueError(f"ties must be 'first' or 'last', not {ties!r}")
+
+
+def point_triangle(x0, x1, x2, x3, ties="first"):
     """Vectorised over n pairs (arrays (n,3)).  Returns c (n,4), t (n,3), d (n,)."""
     x0, x1, x2, x3 = (np.asarray(v, dtype=np.float64).reshape(-1, 3) for v in (x0, x1, x2, x3))
     n = x0.shape[0]
@@ -68,14 +83,14 @@ def point_triangle(x0, x1, x2, x3):
         Tt[k] = t
     d2 = np.einsum("kni,kni->kn", Tt, Tt)
     d2[0, ~inside] = np.inf
-    pick = np.argmin(d2, axis=0)
+    pick = _pick(d2, ties)
     idx = np.arange(n)
     c = C[pick, idx]
     t = Tt[pick, idx]
     return c, t, np.sqrt(_dot(t, t))
 
 
-def edge_edge(x0, x1, x2, x3):
+def edge_edge(x0, x1, x2, x3, ties="first"):
     """Vectorised over n pairs.  Returns c (n,4), t (n,3), d (n,)."""
     x0, x1, x2, x3 = (np.asarray(v, dtype=np.float64).reshape(-1, 3) for v in (x0, x1, x2, x3))
     n = x0.shape[0]
@@ -104,7 +119,7 @@ def edge_edge(x0, x1, x2, x3):
     Tt = r[None] + S[..., None] * d1[None] - U[..., None] * d2[None]
     dd = np.einsum("kni,kni->kn", Tt, Tt)
     dd[0, ~inside] = np.inf
-    pick = np.argmin(dd, axis=0)
+    pick = _pick(dd, ties)
     idx = np.arange(n)
     s, u = S[pick, idx], U[pick, idx]
     t = Tt[pick, idx]

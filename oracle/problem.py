@@ -53,7 +53,7 @@ class Problem:
 
     def __init__(self, X, tets, tris, edges, E, nu, rho, planes, dhat, kappa,
                  self_contact=False, fixed=None, barrier_mode="psd",
-                 rest_exclude=True, gravity=(0.0, 0.0, -9.8), object_id=None, model="nh"):
+                 rest_exclude=True, gravity=(0.0, 0.0, -9.8), object_id=None, model="nh", ties="first"):
         self.X = np.asarray(X, dtype=np.float64)
         self.tets = np.asarray(tets, dtype=np.int64)
         self.tris = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
@@ -73,6 +73,7 @@ class Problem:
         self.free = np.ones(self.nV, dtype=bool)
         self.free[self.fixed] = False
         self.barrier_mode = barrier_mode
+        self.ties = ties          # closest points on exact ties (see distance)
         self.gravity = np.asarray(gravity, dtype=np.float64)
         self.surf_verts = np.unique(self.tris.reshape(-1)) if len(self.tris) else np.zeros(0, np.int64)
         self.object_id = (np.zeros(self.nV, np.int64) if object_id is None
@@ -141,12 +142,12 @@ class Problem:
         if len(pt):
             f = self.tris[pt[:, 1]]
             idx = np.stack([pt[:, 0], f[:, 0], f[:, 1], f[:, 2]], axis=1).astype(np.int64)
-            c, t, d = distance.point_triangle(*(x[idx[:, i]] for i in range(4)))
+            c, t, d = distance.point_triangle(*(x[idx[:, i]] for i in range(4)), ties=self.ties)
             kinds.append(np.zeros(len(d), np.int64)); idxs.append(idx); cs.append(c); ts.append(t); ds.append(d)
         if len(ee):
             ea, eb = self.edges[ee[:, 0]], self.edges[ee[:, 1]]
             idx = np.stack([ea[:, 0], ea[:, 1], eb[:, 0], eb[:, 1]], axis=1).astype(np.int64)
-            c, t, d = distance.edge_edge(*(x[idx[:, i]] for i in range(4)))
+            c, t, d = distance.edge_edge(*(x[idx[:, i]] for i in range(4)), ties=self.ties)
             kinds.append(np.ones(len(d), np.int64)); idxs.append(idx); cs.append(c); ts.append(t); ds.append(d)
         if kinds:
             kind = np.concatenate(kinds); idx = np.concatenate(idxs); c = np.concatenate(cs)

@@ -131,6 +131,7 @@ struct pncg_ctx {
   unsigned long long* d_ckey_tmp = nullptr;
   int2 *d_wvert = nullptr, *d_wrange = nullptr;   // per incidence wave: first / last vertex, entry range
   double* d_rp = nullptr;      // [4 cap][6] run partials of the pair entries
+  int4* d_pv = nullptr;        // [cap] corner vertices of each pair
   // explicit candidate lists (pncg_set_candidates_override), kind in the pair
   bool ovr_set[2] = {false, false};
   std::vector<int2> ovr[2];
@@ -293,6 +294,7 @@ Args<R> make_args(pncg_ctx* c, double h) {
   A.cent = c->d_cent;
   A.wrange = c->d_wrange;
   A.rp = c->d_rp;
+  A.pv = A.seg ? c->d_pv : nullptr;
   A.self = (c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0 ? 1 : 0;
   A.cand = c->d_cand;
   A.ncand = c->d_ncand;
@@ -341,7 +343,8 @@ int list_args(pncg_ctx* c, Args<R>& A) {
   A.cent = c->d_cent;
   A.wrange = c->d_wrange;
   A.rp = c->d_rp;
-  if (A.self && A.seg && (!A.cand || !A.coff || !A.cent || !A.rp || !A.wrange))
+  A.pv = A.seg ? c->d_pv : nullptr;
+  if (A.self && A.seg && (!A.cand || !A.coff || !A.cent || !A.rp || !A.wrange || !A.pv))
     return fail(c, PNCG_E_STATE, "internal: the candidate list or its pair index is not allocated");
   return PNCG_OK;
 }
@@ -393,6 +396,7 @@ PairIndex make_pairindex(pncg_ctx* c) {
   P.cent = c->d_cent;
   P.cent_tmp = c->d_cent_tmp;
   P.ckey_tmp = c->d_ckey_tmp;
+  P.pv = c->d_pv;
   P.big = c->d_big;
   P.scan_tmp = c->d_pl_tmp;
   P.wvert = c->d_wvert;
@@ -409,9 +413,11 @@ int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (cap <= c->cand_cap) return PNCG_OK;
   if (c->noalloc)
     return fail(c, PNCG_E_CAPACITY, "the candidate list needs larger buffers (a pncg_step_dev call grows them)");
-  for (void* p : {(void*)c->d_cand, (void*)c->d_cent, (void*)c->d_cent_tmp, (void*)c->d_ckey_tmp, (void*)c->d_rp})
+  for (void* p : {(void*)c->d_cand, (void*)c->d_cent, (void*)c->d_cent_tmp, (void*)c->d_ckey_tmp, (void*)c->d_rp,
+                  (void*)c->d_pv})
     dfree(c, p);
   c->d_cand = nullptr;
+  c->d_pv = nullptr;
   c->d_ckey_tmp = nullptr;
   c->d_cent = c->d_cent_tmp = nullptr;
   c->d_rp = nullptr;
@@ -421,7 +427,7 @@ int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (c->scatter == PNCG_SCATTER_SEGMENTED &&
       ((rc = dmalloc(c, &c->d_cent, 4 * (size_t)cap)) || (rc = dmalloc(c, &c->d_cent_tmp, 4 * (size_t)cap)) ||
        (rc = dmalloc(c, &c->d_ckey_tmp, 4 * (size_t)cap)) ||
-       (rc = dmalloc(c, &c->d_rp, 24 * (size_t)cap))))
+       (rc = dmalloc(c, &c->d_rp, 24 * (size_t)cap)) || (rc = dmalloc(c, &c->d_pv, (size_t)cap))))
     return rc;
   c->cand_cap = cap;
   return PNCG_OK;
@@ -663,7 +669,8 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   };
   // Enqueue iterations [k0, k0 + m) (the last launch of the cap finishes the
   // step); returns the end of the chunk.
-  const int kind_first = A.self ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
+  const bool fused = fused_pairs(A);
+  const int kind_first = (A.self && !fused) ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
   // A chunk that reaches the cap ends the step whatever happens before it
   // (unless a pause comes first), so the output kernel goes right behind it;
   // it reads the final iteration from the device status, and a later one
@@ -690,7 +697,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
       }
       launch_iteration_first<R>(A, j, (j == k0) ? mode0 : 0, c->stream);
       prof_end(c, e);
-      if (A.self) {
+      if (A.self && !fused) {
         e = prof_begin(c, PNCG_PROF_GRAD);
         launch_iteration_grad<R>(A, j, c->stream);
         prof_end(c, e);
@@ -1152,6 +1159,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
   c->d_cent = nullptr; c->d_cent_tmp = nullptr; c->d_ckey_tmp = nullptr;
   c->d_rp = nullptr;
+  c->d_pv = nullptr;
   c->d_ovr = nullptr; c->n_ovr = 0; c->ovr_uploaded = false;
   c->ovr_set[0] = c->ovr_set[1] = false; c->ovr[0].clear(); c->ovr[1].clear();
   c->adj_ready = false; c->d_cgs = nullptr; c->cgs_cap = 0; c->E_uploaded = false;

@@ -711,6 +711,7 @@ __global__ void __launch_bounds__(kBlock) k_pl_count(PairIndex P, const int2* li
     pl_decode(list[q], q, npt, kind, a, b);
     int v[4];
     pl_corners(P, kind, a, b, v);
+    P.pv[q] = make_int4(v[0], v[1], v[2], kind == 0 ? v[3] : ~v[3]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) atomicAdd(&P.vcnt[v[i]], 1);
   }

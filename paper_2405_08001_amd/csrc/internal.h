@@ -133,6 +133,8 @@ struct Args {
   const int* cent;         // [4 cap] slot id 4 q + corner of each entry (per vertex in pair-key order)
   const int2* wrange;      // [nWaves] corner-entry range of each incidence wave's vertices
   double* rp;              // [4 cap][6] run partials: gradient xyz, diag xyz (or H p xyz)
+  const int4* pv;          // [cap] corner vertices of each pair (segmented scatter; NULL otherwise),
+                           // edge-edge pairs with ~v3 in w
   // contact
   int self;                // point-triangle / edge-edge barriers on
   const int2* cand;        // candidate pairs: (v, f) point-triangle then (e1, e2) edge-edge
@@ -183,6 +185,14 @@ struct Args {
 
 // Runs CALL with the constexpr S_ set to whether the pair terms use the
 // segmented slots.
+// With the segmented scatter and one step size for the whole scene, the
+// pair pass runs inside the first launch of the gradient sweep (two launches
+// per iteration); otherwise it is a launch of its own.
+template <typename R>
+inline bool fused_pairs(const Args<R>& A) {
+  return A.self && A.seg && !A.split;
+}
+
 #define PNCG_BY_SCATTER(seg, CALL) \
   do {                             \
     if (seg) {                     \

@@ -91,6 +91,8 @@ struct PairIndex {
                          // order of its pairs' (kind, first index, second index)
   int* cent_tmp;         // [4 cap] the same before the per-vertex ordering
   unsigned long long* ckey_tmp;  // [4 cap] the pair key of each entry of cent_tmp
+  int4* pv;              // [cap] the four vertices of pair q in narrow-phase order; edge-edge
+                         // pairs store ~v3 in w (the kind is the sign of w)
   int* big;              // [nV + 1] vertices with more entries than a thread orders ([0] = count)
   int* scan_tmp;         // scan partials, nV / 4096 + 2 ints
   // entry range [x, y) of each 64-lane wave of the vertex incidence (its

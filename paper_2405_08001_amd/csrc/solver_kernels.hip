@@ -2,9 +2,13 @@
 // query kernels built from the same pieces.
 //
 // One iteration k is two launches (three with point-triangle / edge-edge
-// contact):
-//   [narrow]  candidate pairs at x_k -> barrier gradient and diagonal,
-//             scattered with float64 atomics into per-vertex accumulators
+// contact under the atomic scatter or with one step size per object):
+//   [narrow]  candidate pairs at x_k -> barrier gradient and diagonal, as
+//             float64 atomics into per-vertex accumulators or as run
+//             partials of the per-vertex entry index (segmented scatter);
+//             with the segmented scatter and one step size the pass runs
+//             inside the first grad launch, each block evaluating the
+//             entries of its own vertices before its sweep
 //   grad      vertex-centric element sweep: every lane evaluates one
 //             (tet, corner) incidence, a wave-segmented sum gives each
 //             vertex its complete gradient and diag(H) without atomics;
@@ -254,8 +258,22 @@ __device__ __forceinline__ void apply_update(const Args<R>& A, int k, const Firs
 template <typename R, typename Pos>
 __device__ __forceinline__ bool pair_closest(const Args<R>& A, int q, const Pos& pos, int (&iv)[4], Closest& c,
                                              long long npt) {
-  int2 pr = A.cand[q];
   V3<double> X[4];
+  if (A.pv) {
+    // the pair index holds the corner vertices: one load fewer on the way
+    // to the positions
+    const int4 w = A.pv[q];
+    iv[0] = w.x; iv[1] = w.y; iv[2] = w.z; iv[3] = w.w >= 0 ? w.w : ~w.w;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = pos(iv[i]);
+    c = w.w >= 0 ? closest_pt(X[0], X[1], X[2], X[3]) : closest_ee(X[0], X[1], X[2], X[3]);
+    if (!(c.d > 0.0)) {
+      raise_err(A.status, kErrPenetration);
+      return false;
+    }
+    return c.d < A.dhat;
+  }
+  int2 pr = A.cand[q];
   // kind: by position in a sorted list (npt >= 0), or in the pair itself
   // (npt < 0: edge-edge pairs are stored as (e1, ~e2))
   if (npt >= 0 ? q < npt : pr.y >= 0) {
@@ -443,6 +461,50 @@ __global__ void __launch_bounds__(kSBlock) k_narrow(Args<R> A, int k, int mode) 
   if (threadIdx.x == 0) A.part_narrow[blockIdx.x] = v[0];
 }
 
+// The pair pass folded into the first launch of the sweep (segmented
+// scatter, unsplit step): the corner entries of this block's vertices,
+// [wrange[first wave].x, wrange[last wave].y), evaluated at `pos` 64 to a
+// wave in the 64-entry chunks of the global entry index that pair_entries
+// uses, so every run partial is the same number it computes.  Entries of
+// another block's vertices in a shared chunk are left out: their runs are
+// that block's.  Returns this thread's count of active pairs (each pair
+// counted at its corner-0 entry, which lies in exactly one block).
+template <typename R, int BS, typename Pos>
+__device__ __forceinline__ double block_pair_entries(const Args<R>& A, const Pos& pos, const Slice& swv) {
+  if (swv.begin >= swv.end) return 0.0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long npt = A.ncand[1];
+  const int e0 = A.wrange[swv.begin].x, e1 = A.wrange[swv.end - 1].y;
+  double acc = 0.0;
+  if (e0 >= e1) return 0.0;
+  for (int m = (e0 >> 6) + (int)(threadIdx.x >> 6); m <= ((e1 - 1) >> 6); m += BS / kWave) {
+    const int j = m * kWave + lane;
+    const bool mine = j >= e0 && j < e1;
+    double val[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int key = -1 - lane;   // distinct keys for lanes outside the range
+    if (mine) {
+      const int sl = A.cent[j];
+      const int q = sl >> 2, ci = sl & 3;
+      int iv[4];
+      Closest c;
+      const bool act = pair_closest(A, q, pos, iv, c, npt);
+      key = iv[ci];
+      if (act) {
+        pair_grad_diag_corner(A, c, ci, val);
+        if (ci == 0) acc += 1.0;
+      }
+    }
+    seg_sum_d<6>(key, val);
+    const int up = __shfl_up(key, 1, kWave);
+    if (mine && (lane == 0 || up != key)) {
+      double* o = A.rp + 6 * (size_t)j;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) o[i] = val[i];
+    }
+  }
+  return acc;
+}
+
 // ---------------------------------------------------- vertex-centric sweep
 enum GradMode { kGradFirst = 0, kGradDirect = 1, kGradQuery = 2 };
 
@@ -509,10 +571,13 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // SPLIT: the beta dot products go per vertex to vdots (reduced per object
 // by k_objred_grad) instead of into the block partials.
 // SEG: the contact-pair terms come from the run partials of the segmented
-// scatter instead of the atomic accumulators.
+// scatter instead of the atomic accumulators.  With kGradFirst (self
+// contact, unsplit) the launch also computes those partials for its own
+// vertices first (block_pair_entries), so an iteration is two launches.
 template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, bool SEG = false, int BS = GradBlock<R>::value>
 __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
+  constexpr bool FUSED = MODE == kGradFirst && SEG;
   __shared__ double sh[NW * 8];
   FirstPro fp{0.0, 0, 1};
   if (MODE == kGradFirst) {
@@ -533,6 +598,11 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
   }
   if (!fp.work) return;
   const auto pos = first_pos<R, SPLIT>(A, k, fp, fp.materialize ? xprev : xcur, pk);
+  double nact = 0.0;
+  if constexpr (FUSED) {
+    nact = block_pair_entries<R, BS>(A, pos, swv);
+    __syncthreads();   // the block's run partials are in A.rp before its vertex lanes read them
+  }
   double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int w = (int)swv.begin + (threadIdx.x >> 6); w < swv.end; w += NW) {
     const int idx = w * kWave + lane;
@@ -563,7 +633,7 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
     double gd[3] = {A.h2 * double(s[0]), A.h2 * double(s[1]), A.h2 * double(s[2])};
     double dd[3] = {A.h2 * double(s[3]), A.h2 * double(s[4]), A.h2 * double(s[5])};
     vertex_terms(A, v, x, gd, dd, dots[6], MODE != kGradQuery, SEG ? prs : nullptr);
-    if (MODE == kGradDirect && A.self && (A.vflag[v] & kSurface)) {
+    if ((MODE == kGradDirect || FUSED) && A.self && (A.vflag[v] & kSurface)) {
       const V3<double> xb = ld3(A.xbuild, v);
       const double ex = x.x - xb.x, ey = x.y - xb.y, ez = x.z - xb.z;
       dots[7] = fmax(dots[7], sqrt(ex * ex + ey * ey + ez * ez));
@@ -622,6 +692,12 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) A.part_grad[blockIdx.x * 8 + i] = dots[i];
+  }
+  if constexpr (FUSED) {
+    double v[1] = {nact};
+    const int kind1[1] = {0};
+    block_reduce<1, BS>(v, kind1, sh);
+    if (threadIdx.x == 0) A.part_narrow[blockIdx.x] = v[0];
   }
 }
 
@@ -1161,7 +1237,11 @@ void launch_predict(const Args<R>& A, const double* x, const double* v, double3 
 // beta reduction and the direction part with the per-object alpha reduction.
 template <typename R>
 void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
-  if (A.self) {
+  if (fused_pairs(A)) {
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, false, M_, true>), dim3(A.grid),
+                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              (double*)nullptr));
+  } else if (A.self) {
     if (A.split)
       hipLaunchKernelGGL((k_narrow<R, true>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
     else

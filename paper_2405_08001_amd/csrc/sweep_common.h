@@ -42,13 +42,16 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kind)[N
   __syncthreads();
 }
 
-// Re-reduce the per-block partials [n][stride] of the previous launch.
+// Re-reduce the per-block partials [n][stride] of the previous launch.  The
+// first kSBlock threads take partials j, j + kSBlock, ... whatever the
+// block size, so launches of any block size reach the same bits.
 template <int N, int BS = kSBlock>
 __device__ __forceinline__ void reduce_partials(const double* part, int stride, int n, const int (&kind)[N],
                                                 double (&out)[N], double* sh) {
+  static_assert(BS >= kSBlock, "reduce_partials needs at least kSBlock threads");
 #pragma unroll
-  for (int i = 0; i < N; ++i) out[i] = kind[i] ? 0.0 : 0.0;
-  for (int j = threadIdx.x; j < n; j += BS) {
+  for (int i = 0; i < N; ++i) out[i] = 0.0;
+  for (int j = threadIdx.x; threadIdx.x < kSBlock && j < n; j += kSBlock) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       double v = part[j * stride + i];

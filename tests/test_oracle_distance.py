@@ -103,6 +103,41 @@ def test_parallel_edges():
     np.testing.assert_allclose(c[0], [0, 1, -1, 0], atol=1e-14)
 
 
+def test_ties_pick_another_valid_closest_pair():
+    # overlapping parallel edges have a segment of closest-point pairs: both
+    # tie rules return the separation as distance and a valid pair (c in
+    # range, t = sum c_i x_i), but not the same pair
+    x0, x1 = np.array([0, 0, 0.0]), np.array([1, 0, 0.0])
+    x2, x3 = np.array([0.5, 0.2, 0.0]), np.array([1.5, 0.2, 0.0])
+    X = [v[None] for v in (x0, x1, x2, x3)]
+    c1, t1, d1 = distance.edge_edge(*X, ties="first")
+    c2, t2, d2 = distance.edge_edge(*X, ties="last")
+    assert d1[0] == pytest.approx(0.2, rel=1e-15) and d2[0] == pytest.approx(0.2, rel=1e-15)
+    for c, t in ((c1, t1), (c2, t2)):
+        assert 0 <= c[0, 1] <= 1 and -1 <= c[0, 3] <= 0
+        np.testing.assert_allclose(t[0], c[0, 0] * x0 + c[0, 1] * x1 + c[0, 2] * x2 + c[0, 3] * x3, atol=1e-15)
+    assert not np.allclose(c1, c2)
+    # the tied sides are s = 1 (x1 against edge 2, at its middle) and u = 0
+    # (x2 against edge 1, at its middle): first takes s = 1, last u = 0
+    np.testing.assert_allclose(c1[0], [0, 1, -0.5, -0.5], atol=1e-15)
+    np.testing.assert_allclose(c2[0], [0.5, 0.5, -1, 0], atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ties_agree_where_the_closest_point_is_unique(seed):
+    # random pairs: the closest point is unique, so both rules give the same
+    # distance and coefficients (a vertex closest point reached from two
+    # sides may differ in t by rounding only)
+    rng = np.random.default_rng(seed)
+    X = [rng.standard_normal((200, 3)) for _ in range(4)]
+    for fn in (distance.edge_edge, distance.point_triangle):
+        ca, ta, da = fn(*X, ties="first")
+        cb, tb, db = fn(*X, ties="last")
+        assert np.array_equal(da, db)
+        assert np.array_equal(ca, cb)
+        np.testing.assert_allclose(ta, tb, rtol=0, atol=1e-14)
+
+
 def test_degenerate_triangle_raises():
     x = np.array([[0, 0, 1.0], [0, 0, 0], [1, 0, 0], [2, 0, 0]])
     with pytest.raises(distance.DegenerateTriangle):
