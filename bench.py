@@ -173,6 +173,8 @@ def setup_ctx(sc, precision, model="nh"):
     ctx.pncg_set_contact(sc.dhat, sc.kappa, sc.cell, sc.planes,
                          (P.CONTACT_SELF if sc.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
     ctx.pncg_set_solver(sc.iter_max, sc.eps, P.TERM_DELTA_E, sc.gravity, 0)
+    if len(sc.fixed):
+        ctx.pncg_set_dirichlet(sc.fixed, sc.X[sc.fixed])
     return ctx
 
 
@@ -281,7 +283,10 @@ def _solve_once(sc, prec, x0, v0, iters, eps, term, flags=0, dhat=None):
     return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
 
 
-def _reference(sc, x0, v0, dhat=None, tol=1e-7, cap=5000, flags=None):
+REF_TOL = 1e-7       # a study's reference minimiser: ||g|| <= REF_TOL ||g_0||
+
+
+def _reference(sc, x0, v0, dhat=None, tol=REF_TOL, cap=20000, flags=None):
     """x* of the step from (x0, v0): float64 Dai-Kou to ||g|| <= tol ||g_0||
     (at most cap iterations) and how far it got.  Scenes of several objects
     are solved split by object (Sec. 5.2), which reaches the minimiser where
@@ -290,8 +295,9 @@ def _reference(sc, x0, v0, dhat=None, tol=1e-7, cap=5000, flags=None):
     if flags is None:
         flags = P.SPLIT_OBJECTS if len(np.unique(sc.object_id)) > 1 else 0
     xs, _, sref, _ = _solve_once(sc, "fp64", x0, v0, cap, tol, P.TERM_GRAD_REL, flags, dhat)
-    return xs, {"reference_iters": int(sref["iters"]),
-                "reference_grad_ratio": float(f"{sref['g_norm'] / sref['g0_norm']:.3e}")}
+    ratio = sref["g_norm"] / sref["g0_norm"]
+    return xs, {"reference_iters": int(sref["iters"]), "reference_grad_ratio": float(f"{ratio:.3e}"),
+                "reference_converged": bool(ratio <= tol)}
 
 
 def _convergence(sc, prec, x0, v0, budgets, flags, dhat, xs):
@@ -308,63 +314,69 @@ def _convergence(sc, prec, x0, v0, budgets, flags, dhat, xs):
     return {"rel_error": errs, "iters_per_s": round(ips, 1), "active_pairs": int(act)}
 
 
-def run_beta_ablation(pile, pile_state, budgets=(10, 25, 50, 100)):
-    """The beta rules of the ablation (Sec. 7.1), re-run on synthetic scenes:
-    the error after K iterations of one step against the step's minimiser
-    (float64 Dai-Kou to ||g|| <= 1e-7 ||g_0||, at most 5,000 iterations),
-    for the pile (mixed, from the state after warm-up) and the cube resting
-    on its floor (float64, after 12 steps)."""
+def _study_cases():
+    """Contact states for the convergence studies whose step minimiser the
+    float64 reference reaches (||g|| <= 1e-7 ||g_0||; a case whose reference
+    falls short reports no errors): the cube resting on its floor after 12
+    steps (plane barriers), the stacked cubes with the top one moving down
+    into its sub-dhat gap (point-triangle, edge-edge and plane barriers), and
+    the stacked bars (30,720 tets, about 5,400 pairs active at the start)."""
     import paper_2405_08001_amd as P
     import scenes
     cube = scenes.cube_scene()
     x, v = cube.x0.copy(), cube.v0.copy()
     for _ in range(12):
         x, v, _, _ = _solve_once(cube, "fp64", x, v, 2000, cube.eps, P.TERM_GRAD_REL)
-    cases = {"cube": (cube, "fp64", x, v), "pile": (pile, "mixed", pile_state[0], pile_state[1])}
+    stack = scenes.small_contact_scene()
+    sv = np.zeros_like(stack.X)
+    sv[stack.object_id == 1, 2] = -0.05
+    bars = scenes.stacked_bars_scene()
+    return {"cube-resting": (cube, x, v), "stacked-cubes": (stack, stack.X.copy(), sv),
+            "stacked-bars": (bars, bars.x0.copy(), bars.v0.copy())}
+
+
+def _study(sc, prec, x0, v0, budgets, runs, dhat=None):
+    """The reference of one case, then the error curve of each named run
+    (flags) if the reference converged."""
+    xs, ref = _reference(sc, x0, v0, dhat)
+    res = {"precision": prec, "budgets": list(budgets), "reference_tol": REF_TOL}
+    res.update(ref)
+    if not ref["reference_converged"]:
+        res["note"] = "reference not converged: no errors reported"
+        return res
+    for name, flag in runs.items():
+        res[name] = _convergence(sc, prec, x0, v0, budgets, flag, dhat, xs)
+    return res
+
+
+def run_beta_ablation(budgets=(25, 100, 400, 1600)):
+    """The beta rules of the ablation (Sec. 7.1) on synthetic contact states:
+    the error after K iterations of one step against the step's minimiser,
+    float64, for each rule."""
+    import paper_2405_08001_amd as P
     out = {}
-    for name, (sc, prec, x0, v0) in cases.items():
-        xs, ref = _reference(sc, x0, v0)
-        res = {"precision": prec, "budgets": list(budgets), "reference_tol": 1e-7, "rules": {}}
-        res.update(ref)
-        for rule, flag in P.BETA_RULES.items():
-            res["rules"][rule] = _convergence(sc, prec, x0, v0, budgets, flag, None, xs)
-        out[name] = res
+    for name, (sc, x0, v0) in _study_cases().items():
+        r = _study(sc, "fp64", x0, v0, budgets, dict(P.BETA_RULES))
+        out[name] = {"reference": {k: r[k] for k in ("reference_iters", "reference_grad_ratio",
+                                                     "reference_converged")},
+                     "rules": {k: r[k] for k in P.BETA_RULES if k in r}}
+        if "note" in r:
+            out[name]["note"] = r["note"]
     return out
 
 
-def run_split(pile, pile_state, budgets=(10, 25, 50, 100)):
-    """Splitting computation (Sec. 5.2) on the pile (24 objects), mixed, from
-    the state after warm-up: the error after K iterations against the step's
-    minimiser (the same energy either way), split and unsplit, and the
-    iteration rate of each over 10 frames as configured.  The minimiser is
-    taken from the split float64 solve, which gets much closer to it."""
-    import torch
+def run_split(budgets=(25, 100, 400, 1600)):
+    """Splitting computation (Sec. 5.2) on the two-object contact states:
+    the error after K iterations against the step's minimiser (the same
+    energy either way), split and unsplit, float64 and mixed."""
     import paper_2405_08001_amd as P
-    dev = torch.device("cuda:0")
-    xs, ref = _reference(pile, pile_state[0], pile_state[1])
-    out = {"budgets": list(budgets), "objects": int(len(np.unique(pile.object_id))), "reference_tol": 1e-7}
-    out.update(ref)
-    for name, flag in (("unsplit", 0), ("split", P.SPLIT_OBJECTS)):
-        r = _convergence(pile, "mixed", pile_state[0], pile_state[1], budgets, flag, None, xs)
-        ctx = setup_ctx(pile, "mixed")
-        ctx.pncg_set_solver(pile.iter_max, pile.eps, P.TERM_DELTA_E, pile.gravity, flag)
-        x = torch.tensor(pile_state[0], device=dev)
-        v = torch.tensor(pile_state[1], device=dev)
-        x2, v2 = torch.empty_like(x), torch.empty_like(v)
-        its = reb = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            st = ctx.pncg_step_dev(x, v, pile.h, x2, v2)
-            its += st["iters"]
-            reb += st["rebuilds"]
-            x, x2, v, v2 = x2, x, v2, v
-        torch.cuda.synchronize()
-        r["frames_iters_per_s"] = round(its / (time.perf_counter() - t0), 1)
-        r["frames_iters_per_frame"] = round(its / 10, 2)
-        r["frames_rebuilds_per_frame"] = round(reb / 10, 2)
-        ctx.close()
-        out[name] = r
+    out = {"budgets": list(budgets), "reference_tol": REF_TOL}
+    for name, (sc, x0, v0) in _study_cases().items():
+        if len(np.unique(sc.object_id)) < 2:
+            continue
+        for prec in ("fp64", "mixed"):
+            out[f"{name}/{prec}"] = _study(sc, prec, x0, v0, budgets,
+                                            {"unsplit": 0, "split": P.SPLIT_OBJECTS})
     return out
 
 
@@ -403,45 +415,36 @@ def run_materials(sc, warmup=0, steps=30, models=("snh", "arap", "fcr"), batched
     return out
 
 
-def run_dhat_strategy(pile, warmup=10, fractions=(0.3, 0.5, 0.7), budgets=(10, 25, 50, 100)):
-    """The larger-dhat strategy (Sec. 5.1) on the pile, mixed: dhat at
-    30/50/70 % of the mean boundary edge (same-object pairs closer than
-    1.5 dhat at rest excluded) against the configured dhat.  Each runs its
-    own warm-up frames from the initial state with its dhat (the strategy is
-    a setting of the whole simulation), then one step is measured against
-    its own minimiser (the problem changes with dhat)."""
-    import torch
+def run_dhat_strategy(fractions=(0.3, 0.5, 0.7), budgets=(25, 100, 400, 1600)):
+    """The larger-dhat strategy (Sec. 5.1) on the stacked cubes, float64:
+    dhat at 30/50/70 % of the mean boundary edge (same-object pairs closer
+    than 1.5 dhat at rest excluded) against the configured dhat.  The
+    strategy is a setting of the whole simulation, so each dhat gets the
+    contact state it would keep: the cubes stacked with a gap of 0.4 dhat,
+    the lower one 0.4 dhat above the floor, the upper one moving down at
+    5 cm/s; one step from there against its own minimiser (the problem
+    changes with dhat)."""
     import paper_2405_08001_amd as P
-    dev = torch.device("cuda:0")
-    ctx = setup_ctx(pile, "mixed")
+    import scenes
+    base = scenes.small_contact_scene()
+    ctx = setup_ctx(base, "fp64")
     lbar = ctx.pncg_mean_boundary_edge()
     ctx.close()
-    out = {"mean_boundary_edge": lbar, "budgets": list(budgets), "reference_tol": 1e-7, "warmup_frames": warmup,
-           "dhat": {}}
-    for label, dh in [("configured", pile.dhat)] + [(f"{f:.1f}*edge", f * lbar) for f in fractions]:
-        r = {"dhat": dh}
+    out = {"scene": "stacked-cubes, gaps 0.4 dhat", "mean_boundary_edge": lbar, "budgets": list(budgets),
+           "reference_tol": REF_TOL, "dhat": {}}
+    for label, dh in [("configured", base.dhat)] + [(f"{f:.1f}*edge", f * lbar) for f in fractions]:
+        sc = scenes.small_contact_scene(gap=0.4 * dh, dhat=dh)
+        x0 = sc.X.copy()
+        x0[:, 2] += 0.4 * dh - x0[:, 2].min()
+        v0 = np.zeros_like(x0)
+        v0[sc.object_id == 1, 2] = -0.05
         try:
-            ctx = setup_ctx(pile, "mixed")
-            ctx.pncg_set_contact(dh, pile.kappa, 0.0, pile.planes,
-                                 (P.CONTACT_SELF if pile.self_contact else 0) | P.CONTACT_REST_EXCLUDE)
-            x = torch.tensor(pile.x0, device=dev)
-            v = torch.tensor(pile.v0, device=dev)
-            x2, v2 = torch.empty_like(x), torch.empty_like(v)
-            its = 0
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(warmup):
-                its += ctx.pncg_step_dev(x, v, pile.h, x2, v2)["iters"]
-                x, x2, v, v2 = x2, x, v2, v
-            torch.cuda.synchronize()
-            r["warmup_iters_per_s"] = round(its / (time.perf_counter() - t0), 1)
-            ctx.close()
-            x0, v0 = x.cpu().numpy(), v.cpu().numpy()
-            xs, ref = _reference(pile, x0, v0, dh)
-            r.update(_convergence(pile, "mixed", x0, v0, budgets, 0, dh, xs))
-            r.update(ref)
+            r = _study(sc, "fp64", x0, v0, budgets, {"pncg": 0}, dh)
+            r["dhat"] = dh
+            if "pncg" in r:
+                r.update(r.pop("pncg"))
         except P.PncgError as e:      # e.g. a tet inverted on the way (no inversion guard, reading S4)
-            r["error"] = str(e)
+            r = {"dhat": dh, "error": str(e)}
         out["dhat"][label] = r
     return out
 
@@ -839,18 +842,23 @@ def main():
         log("  " + ", ".join(f"{k} {v.get('iters_per_s', v.get('error'))}" for k, v in out["materials"].items()
                              if isinstance(v, dict)))
     if not args.no_beta_ablation:
-        log("beta rules: pile and cube ...")
-        out["beta_ablation"] = run_beta_ablation(sc, m["state"])
+        log("beta rules on the study states ...")
+        out["beta_ablation"] = run_beta_ablation()
         for case, r in out["beta_ablation"].items():
-            log(f"  {case}: " + ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
+            log(f"  {case}: reference {r['reference']}; " +
+                ", ".join(f"{k} {v['rel_error']}" for k, v in r["rules"].items()))
     if not args.no_split:
-        log("splitting computation on the pile ...")
-        out["split"] = run_split(sc, m["state"])
-        log(f"  unsplit {out['split']['unsplit']['rel_error']} split {out['split']['split']['rel_error']}")
+        log("splitting computation on the two-object states ...")
+        out["split"] = run_split()
+        for case, r in out["split"].items():
+            if isinstance(r, dict):
+                log(f"  {case}: ratio {r['reference_grad_ratio']} unsplit {r.get('unsplit', {}).get('rel_error')} "
+                    f"split {r.get('split', {}).get('rel_error')}")
     if not args.no_dhat_strategy:
-        log("larger-dhat strategy on the pile ...")
-        out["dhat_strategy"] = run_dhat_strategy(sc)
-        log("  " + ", ".join(f"{k} {v.get('rel_error', v.get('error'))}" for k, v in out["dhat_strategy"]["dhat"].items()))
+        log("larger-dhat strategy on the stacked cubes ...")
+        out["dhat_strategy"] = run_dhat_strategy()
+        log("  " + ", ".join(f"{k} {v.get('rel_error', v.get('error', v.get('note')))}"
+                             for k, v in out["dhat_strategy"]["dhat"].items()))
     if not args.no_cpu_baseline and not args.no_batched:
         log("timing the CPU oracle on bounded samples (child process, no GPU) ...")
         import subprocess

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import scenes
-from helpers import make_ctx, make_problem, rel
+from helpers import elem, make_ctx, make_problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -311,15 +311,17 @@ def test_batch_autotune_keeps_state_and_result():
         bt.pncg_batch_set_block(300)
 
 
-def test_batch_full_size_sampled_scenes():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_full_size_sampled_scenes(precision):
     """The 256-scene batch (about 720k tets) in one launch: all scenes end
     feasible, and four sampled scenes (the largest, the smallest and two
-    others) match the oracle after 3 fixed iterations."""
+    others) match the oracle after 3 fixed iterations, as a whole and
+    element by element."""
     from oracle import pncg
     scs = scenes.batched_scenes()
-    _say(f"full batch: {len(scs)} scenes, {sum(s.nT for s in scs)} tets")
+    _say(f"full batch precision={precision}: {len(scs)} scenes, {sum(s.nT for s in scs)} tets")
     xs, vs = _states(scs, 6)
-    bt, b = _make_batch(scs, 0, 3, 0.0, "delta_e")
+    bt, b = _make_batch(scs, precision, 3, 0.0, "delta_e")
     xg, _ = _step(bt, np.concatenate(xs), np.concatenate(vs), scs[0].h)
     it, _, _ = bt.pncg_batch_stats()
     assert np.all(it == 3)
@@ -327,10 +329,48 @@ def test_batch_full_size_sampled_scenes():
     assert np.all(xg[:, 2] > 0.0)
     sizes = np.array([s.nT for s in scs])
     picks = [int(np.argmax(sizes)), int(np.argmin(sizes)), 17, 128]
+    bx, bdx = (1e-12, 1e-9) if precision == 0 else (1e-6, 1e-3)
     for i in picks:
         s = scs[i]
         xo, _, st = pncg.step(make_problem(s), xs[i], vs[i], s.h, iter_max=3, eps=0.0, term="delta_e")
         sl = slice(off[i], off[i + 1])
         rx, rdx = rel(xg[sl], xo), rel(xg[sl] - xs[i], xo - xs[i])
-        _say(f"  scene {i} ({s.nT} tets): rel_x={rx:.3e} rel_dx={rdx:.3e}")
-        assert rx <= 1e-12 and rdx <= 1e-9
+        edx = elem(xg[sl] - xs[i], xo - xs[i])
+        _say(f"  scene {i} ({s.nT} tets): rel_x={rx:.3e} rel_dx={rdx:.3e} elem_dx={edx:.3e}")
+        assert rx <= bx and rdx <= bdx and edx <= bdx
+
+
+def test_batch_full_size_configured_step_mixed():
+    """The 256-scene batch as the benchmark runs it (mixed, at most 100
+    iterations, each scene stops at dE < 1e-3 dE_0 on its own): three
+    sampled scenes against the oracle's configured step.  float32 element
+    arithmetic perturbs each iteration by about 2^-24 relative, so the bar is
+    4x the oracle's own spread under a 2^-24 relative perturbation of the
+    start state (the same envelope as the 12-iteration mixed test), with
+    1e-6 / 1e-3 as the floor."""
+    from oracle import pncg
+    scs = scenes.batched_scenes()
+    s0 = scs[0]
+    xs, vs = _states(scs, 7)
+    bt, b = _make_batch(scs, 1, s0.iter_max, s0.eps, "delta_e")
+    xg, _ = _step(bt, np.concatenate(xs), np.concatenate(vs), s0.h)
+    it, rs, _ = bt.pncg_batch_stats()
+    off = b["vert_off"]
+    _say(f"full batch configured (iter_max {s0.iter_max}, eps {s0.eps}): iterations {int(it.min())}-{int(it.max())}, "
+         f"mean {float(it.mean()):.1f}")
+    assert np.all(xg[:, 2] > 0.0)
+    sizes = np.array([s.nT for s in scs])
+    for i in (int(np.argmin(sizes)), 17, 128):
+        s = scs[i]
+        P = make_problem(s)
+        xo, _, st = pncg.step(P, xs[i], vs[i], s.h, iter_max=s.iter_max, eps=s.eps, term="delta_e")
+        xq = xs[i] * (1.0 + 2.0 ** -24)
+        xp, _, sp = pncg.step(P, xq, vs[i], s.h, iter_max=s.iter_max, eps=s.eps, term="delta_e")
+        bx = max(1e-6, 4.0 * rel(xp, xo))
+        bdx = max(1e-3, 4.0 * rel(xp - xq, xo - xs[i]))
+        sl = slice(off[i], off[i + 1])
+        rx, rdx = rel(xg[sl], xo), rel(xg[sl] - xs[i], xo - xs[i])
+        _say(f"  scene {i} ({s.nT} tets): iters {it[i]}/{st.iters} (perturbed {sp.iters}) rel_x={rx:.3e} "
+             f"(bar {bx:.1e}) rel_dx={rdx:.3e} (bar {bdx:.1e})")
+        assert rs[i] == {"delta_e": 0, "grad_rel": 1, "iter_max": 2}[st.reason]
+        assert rx <= bx and rdx <= bdx

@@ -216,6 +216,47 @@ def test_mean_boundary_edge_matches_numpy():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_larger_dhat_with_rest_exclusion(precision):
+    """Sec. 5.1's larger-dhat strategy on the stacked cubes: dhat = 0.5 x the
+    mean boundary edge (about 5 mm against a 0.4 mm gap).  Within each cube,
+    pairs closer than 1.5 dhat in the rest shape are excluded, a non-empty
+    set at this dhat; the exact candidate lists at rest (where the exclusion
+    removes every same-cube neighbour) and at a squeezed state equal the
+    oracle's bit for bit, and two fixed iterations of the step from rest
+    match the oracle."""
+    import paper_2405_08001_amd as L
+    from oracle import pncg
+    base = scenes.small_contact_scene()
+    lbar = float(np.mean(np.linalg.norm(base.X[base.edges[:, 0]] - base.X[base.edges[:, 1]], axis=1)))
+    dhat = 0.5 * lbar
+    sc = scenes.small_contact_scene(dhat=dhat)
+    P = make_problem(sc)
+    _say(f"larger dhat {dhat:.3e} (mean boundary edge {lbar:.3e}) precision={precision}: "
+         f"excluded PT {len(P.excl_pt)} EE {len(P.excl_ee)}")
+    assert len(P.excl_pt) > 100 and len(P.excl_ee) > 100
+    ctx = make_ctx(sc, precision, iter_max=2, eps=0.0, term="delta_e", cell=2.0 * dhat)
+    squeezed = sc.X.copy()
+    squeezed[:, 2] *= 0.97
+    for x in (sc.X, squeezed):
+        pt, ee, pg = P.candidate_lists(x)
+        g_pt = ctx.pncg_candidates(x, L.KIND_PT)
+        g_ee = ctx.pncg_candidates(x, L.KIND_EE)
+        g_pg = ctx.pncg_candidates(x, L.KIND_PG)
+        _say(f"  candidates PT {len(g_pt)}/{len(pt)} EE {len(g_ee)}/{len(ee)} PG {len(g_pg)}/{len(pg)}")
+        assert len(pt) > 0 and len(ee) > 0
+        assert np.array_equal(g_pt, pt) and np.array_equal(g_ee, ee) and np.array_equal(g_pg, pg)
+    v0 = np.zeros_like(sc.X)
+    xo, vo, st = pncg.step(P, sc.X, v0, sc.h, iter_max=2, eps=0.0, term="delta_e")
+    xg, vg, sg = ctx.pncg_step(sc.X, v0, sc.h)
+    rx, rdx = rel(xg, xo), rel(xg - sc.X, xo - sc.X)
+    _say(f"  step: iters {sg['iters']}/{st.iters} active {sg['n_active']} rel_x={rx:.3e} rel_dx={rdx:.3e}")
+    assert sg["iters"] == st.iters == 2
+    assert sg["n_active"] > 0
+    assert rx <= (1e-12 if precision == 0 else 1e-6)
+    assert rdx <= (1e-9 if precision == 0 else 1e-3)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("rule", ["fr", "prp", "cd", "hz"])
 @pytest.mark.parametrize("which", ["cube", "stack"])
 def test_beta_rules_match_oracle(which, rule, precision):
