@@ -163,7 +163,7 @@ struct pncg_ctx {
   long long *d_item_cnt = nullptr, *d_item_off = nullptr;
   long long ent_cap = 0;
   unsigned long long *d_ent_key = nullptr, *d_bkt_key = nullptr;
-  int *d_ent_item = nullptr, *d_bkt_item = nullptr;
+  int *d_ent_item = nullptr, *d_bkt_item = nullptr, *d_ent_rank = nullptr;
   double4 *d_bkt_lo = nullptr, *d_bkt_hi = nullptr;
   int4* d_bkt_ids = nullptr;
   long long *d_part_cnt = nullptr, *d_part_off = nullptr, *d_totals = nullptr;
@@ -370,6 +370,7 @@ Broad make_broad(pncg_ctx* c) {
   B.ent_cap = c->ent_cap;
   B.ent_key = c->d_ent_key;
   B.ent_item = c->d_ent_item;
+  B.ent_rank = c->d_ent_rank;
   B.bkt_key = c->d_bkt_key;
   B.bkt_item = c->d_bkt_item;
   B.bkt_lo = c->d_bkt_lo;
@@ -472,7 +473,8 @@ int install_override(pncg_ctx* c) {
 // work arrays that depend on it.
 int alloc_grid(pncg_ctx* c, long long ent) {
   int rc;
-  for (void* p : {(void*)c->d_ent_key, (void*)c->d_ent_item, (void*)c->d_bkt_key, (void*)c->d_bkt_item,
+  for (void* p : {(void*)c->d_ent_key, (void*)c->d_ent_item, (void*)c->d_ent_rank, (void*)c->d_bkt_key,
+                  (void*)c->d_bkt_item,
                   (void*)c->d_bkt_lo, (void*)c->d_bkt_hi, (void*)c->d_bkt_ids, (void*)c->d_count,
                   (void*)c->d_start, (void*)c->d_part_cnt, (void*)c->d_part_off})
     dfree(c, p);
@@ -482,6 +484,7 @@ int alloc_grid(pncg_ctx* c, long long ent) {
   c->tsize = ts;
   c->work_cap = (long long)c->nSV + c->ent_cap;
   if ((rc = dmalloc(c, &c->d_ent_key, c->ent_cap)) || (rc = dmalloc(c, &c->d_ent_item, c->ent_cap)) ||
+      (rc = dmalloc(c, &c->d_ent_rank, c->ent_cap)) ||
       (rc = dmalloc(c, &c->d_bkt_key, c->ent_cap)) || (rc = dmalloc(c, &c->d_bkt_item, c->ent_cap)) ||
       (rc = dmalloc(c, &c->d_bkt_lo, c->ent_cap)) || (rc = dmalloc(c, &c->d_bkt_hi, c->ent_cap)) ||
       (rc = dmalloc(c, &c->d_bkt_ids, c->ent_cap)) ||
@@ -1206,6 +1209,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   c->oscal_cap = 0;
   c->d_oscal = nullptr;
   c->d_ent_key = nullptr; c->d_ent_item = nullptr; c->d_bkt_key = nullptr; c->d_bkt_item = nullptr;
+  c->d_ent_rank = nullptr;
   c->d_bkt_lo = nullptr; c->d_bkt_hi = nullptr; c->d_bkt_ids = nullptr;
   c->d_count = nullptr; c->d_start = nullptr; c->d_part_cnt = nullptr; c->d_part_off = nullptr;
   // grid entries: start with eight cells per primitive; grown on demand

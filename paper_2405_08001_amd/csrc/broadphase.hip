@@ -213,12 +213,13 @@ __global__ void __launch_bounds__(kBlock) k_emit(Broad B, const double4* x, doub
           const unsigned long long k = cell_key(cx, cy, cz);
           B.ent_key[o] = k;
           B.ent_item[o] = B.nSV + i;
-          atomicAdd(&B.count[hash_key(k, B.tsize, i >= B.nF)], 1);
+          B.ent_rank[o] = atomicAdd(&B.count[hash_key(k, B.tsize, i >= B.nF)], 1);
         }
   }
 }
 
-// Group the entries by bucket and store each entry's full record there.
+// Group the entries by bucket and store each entry's full record there: its
+// slot is the bucket's start plus the rank k_emit's counter gave it.
 __global__ void __launch_bounds__(kBlock) k_bucket_fill(Broad B, const double4* x) {
   const long long n = min(B.totals[0], B.ent_cap);
   const int vbase = B.nSV, ebase = B.nSV + B.nF;
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_fill(Broad B, const double4* 
     const unsigned long long k = B.ent_key[j];
     const int it = B.ent_item[j];
     const unsigned h = hash_key(k, B.tsize, it >= B.nSV + B.nF);
-    const int slot = B.start[h] + atomicAdd(&B.count[h], 1);
+    const int slot = B.start[h] + B.ent_rank[j];
     double4 lo, hi;
     int4 ids = make_int4(-1, -1, -1, 0);
     if (it < vbase) {
@@ -264,12 +265,13 @@ struct PairCtx {
   int filter_obj;
 };
 
-// Records of a contiguous run of bucket slots held in LDS.
+// Records of a contiguous run of edge bucket slots held in LDS (an edge has
+// two vertex ids; 34 KB, so that four blocks fit a compute unit).
 constexpr int kSpan = 512;
 struct SlotSpan {
   unsigned long long key[kSpan];
   int item[kSpan];
-  int4 ids[kSpan];
+  int2 ids[kSpan];
   double lo[3][kSpan];
   double hi[3][kSpan];
 };
@@ -280,7 +282,10 @@ struct LdsRec {
   int base;
   __device__ __forceinline__ unsigned long long key(int t) const { return L.key[t - base]; }
   __device__ __forceinline__ int item(int t) const { return L.item[t - base]; }
-  __device__ __forceinline__ int4 ids(int t) const { return L.ids[t - base]; }
+  __device__ __forceinline__ int4 ids(int t) const {
+    const int2 i = L.ids[t - base];
+    return make_int4(i.x, i.y, -1, 0);
+  }
   __device__ __forceinline__ V3<double> lo(int t) const {
     return mk3(L.lo[0][t - base], L.lo[1][t - base], L.lo[2][t - base]);
   }
@@ -443,7 +448,8 @@ __device__ __forceinline__ int load_span(const Broad& B, SlotSpan& L, long long 
     for (int t = threadIdx.x; t < hi - lo; t += kBlock) {
       L.key[t] = B.bkt_key[lo + t];
       L.item[t] = B.bkt_item[lo + t];
-      L.ids[t] = B.bkt_ids[lo + t];
+      const int4 id = B.bkt_ids[lo + t];
+      L.ids[t] = make_int2(id.x, id.y);
       const double4 a = B.bkt_lo[lo + t], b = B.bkt_hi[lo + t];
       L.lo[0][t] = a.x; L.lo[1][t] = a.y; L.lo[2][t] = a.z;
       L.hi[0][t] = b.x; L.hi[1][t] = b.y; L.hi[2][t] = b.z;
@@ -516,7 +522,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_fill(Broad B, PairCtx P, int2*
 // block (edge-edge), in no particular order; the kind is in the pair:
 // (v, f) point-triangle, (e1, ~e2) edge-edge.  counter counts every pair
 // found, also those past cap (the caller checks it against cap).
-constexpr int kEbuf = 4 * kBlock;   // edge-edge pairs buffered per block before one counter update
+constexpr int kEbuf = 2 * kBlock;   // edge-edge pairs buffered per block before one counter update
 
 __device__ __forceinline__ int block_excl_scan(int v, int& total, int* sh) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
@@ -786,38 +792,27 @@ __global__ void __launch_bounds__(kBlock) k_rank_small(PairIndex P) {
   }
 }
 
-// One wave per listed vertex: its keys are staged in the wave's LDS block
-// (up to kRankLds; beyond that they are read from memory) and each lane
-// ranks entries lane, lane + 64, ... against all of them.
+// One block per listed vertex: its keys are staged in LDS (up to kRankLds;
+// beyond that they are read from memory) and each thread ranks entries
+// tid, tid + kBlock, ... against all of them.
 __global__ void __launch_bounds__(kBlock) k_rank_big(PairIndex P) {
-  __shared__ unsigned long long ks[kBlock / kWave][kRankLds];
-  const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long* kw = ks[threadIdx.x >> 6];
+  __shared__ unsigned long long ks[kRankLds];
   const int nbig = P.big[0];
-  const int wid = (blockIdx.x * kBlock + threadIdx.x) >> 6, nw = (gridDim.x * kBlock) >> 6;
-  for (int w = wid; w < nbig; w += nw) {
+  for (int w = blockIdx.x; w < nbig; w += gridDim.x) {
     const int v = P.big[1 + w];
     const int s0 = P.coff[v], n = P.coff[v + 1] - s0;
     const bool lds = n <= kRankLds;
-    if (lds) {
-      for (int i = lane; i < n; i += kWave) kw[i] = P.ckey_tmp[s0 + i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lds)
+      for (int i = threadIdx.x; i < n; i += kBlock) ks[i] = P.ckey_tmp[s0 + i];
+    __syncthreads();
+    const unsigned long long* kk = lds ? ks : P.ckey_tmp + s0;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      const unsigned long long ki = kk[i];
+      int r = 0;
+      for (int j = 0; j < n; ++j) r += kk[j] < ki ? 1 : 0;
+      P.cent[s0 + r] = P.cent_tmp[s0 + i];
     }
-    const unsigned long long* kk = lds ? kw : P.ckey_tmp + s0;
-    for (int i0 = 0; i0 < n; i0 += kWave) {
-      const int i = i0 + lane;
-      if (i < n) {
-        const unsigned long long ki = kk[i];
-        int r = 0;
-        for (int j = 0; j < n; ++j) r += kk[j] < ki ? 1 : 0;
-        P.cent[s0 + r] = P.cent_tmp[s0 + i];
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
   }
 }
 
@@ -856,7 +851,6 @@ void broad_build_count(const Broad& B, const double4* x, double cell, double r, 
   scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
   hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
   scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
-  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
   hipLaunchKernelGGL(k_bucket_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x);
   PairCtx P{x, inv, r, filter_d, filter_obj};
   const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
@@ -882,7 +876,6 @@ void broad_solver_list(const Broad& B, const double4* x, double cell, double r, 
   scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
   hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
   scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
-  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
   hipLaunchKernelGGL(k_bucket_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x);
   PairCtx P{x, inv, r, r, 0};
   const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);

@@ -44,6 +44,7 @@ struct Broad {
   long long ent_cap;
   unsigned long long* ent_key;   // [ent_cap]
   int* ent_item;                 // [ent_cap]
+  int* ent_rank;                 // [ent_cap] place of the entry in its bucket (its bucket count before it)
   unsigned long long* bkt_key;   // [ent_cap] records grouped by bucket
   int* bkt_item;                 // [ent_cap]
   double4* bkt_lo;               // [ent_cap] vertex: position; triangle: inflated box (lo, hi); edge: its two end points (box = their min, max)
