@@ -93,36 +93,18 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* in, long long n
   }
 }
 
-// exclusive scan of nb block sums in place (one block, nb <= kBlock * 16)
+// out[j] = exclusive prefix of in[j]; *total = sum (written by the last
+// block).  Each block first adds up the sums of the blocks before it (bsum,
+// from k_scan_reduce) in a fixed order, which takes the place of a separate
+// launch that scans bsum.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_top(T* bsum, int nb) {
+__global__ void __launch_bounds__(kBlock) k_scan_down(const T* in, long long n, const T* bsum, T* out, T* total) {
   __shared__ T sh[kBlock];
-  const int per = (nb + kBlock - 1) / kBlock;
-  const int b0 = threadIdx.x * per;
-  T s = 0;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) s += bsum[b0 + i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {
-    T v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
-  }
-  T run = sh[threadIdx.x] - s;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) {
-      T v = bsum[b0 + i];
-      bsum[b0 + i] = run;
-      run += v;
-    }
-}
-
-// out[j] = exclusive prefix of in[j]; *total = sum (written by the last block)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_down(const T* in, long long n, const T* boff, T* out, T* total) {
-  __shared__ T sh[kBlock];
+  __shared__ T sw[kBlock / kWave];
+  T pre = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) pre += bsum[b];
+  for (int o = kWave / 2; o > 0; o >>= 1) pre += __shfl_down(pre, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) sw[threadIdx.x / kWave] = pre;
   const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * 16;
   T v[16];
   T s = 0;
@@ -134,13 +116,16 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const T* in, long long n, 
   }
   sh[threadIdx.x] = s;
   __syncthreads();
+  T boff = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) boff += sw[w];
   for (int o = 1; o < kBlock; o <<= 1) {
     T u = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
     __syncthreads();
     sh[threadIdx.x] += u;
     __syncthreads();
   }
-  T run = boff[blockIdx.x] + sh[threadIdx.x] - s;
+  T run = boff + sh[threadIdx.x] - s;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     long long j = base + i;
@@ -154,7 +139,6 @@ template <typename T>
 void scan_exclusive(const T* in, long long n, T* out, T* total, T* scratch, hipStream_t s) {
   const int nb = (int)((n + kTile - 1) / kTile);
   hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kBlock), 0, s, in, n, scratch);
-  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kBlock), 0, s, scratch, nb);
   hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(kBlock), 0, s, in, n, (const T*)scratch, out, total);
 }
 
