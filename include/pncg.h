@@ -148,6 +148,13 @@ typedef struct {
   void*   stream;      /* hipStream_t to run on; NULL = a stream the context creates */
   int32_t scatter;     /* PNCG_SCATTER_*; 0 = AUTO */
   int32_t chunk;       /* iterations launched between host status reads; 0 = default */
+  int32_t graphs;      /* 0: the candidate-list rebuild of a step is captured once
+                          as a HIP graph and replayed (one host call instead of
+                          about twenty launches; re-captured when a buffer it
+                          uses is reallocated); 1: its kernels are launched one
+                          by one.  Results are the same bits either way; the
+                          allocation-free step always launches them one by
+                          one.  Ignored by pncg_batch_create. */
 } pncg_opts;
 
 typedef struct {

@@ -54,7 +54,7 @@ class PncgError(RuntimeError):
 
 class pncg_opts(C.Structure):
     _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("stream", C.c_void_p),
-                ("scatter", C.c_int32), ("chunk", C.c_int32)]
+                ("scatter", C.c_int32), ("chunk", C.c_int32), ("graphs", C.c_int32)]
 
 
 class pncg_stats(C.Structure):
@@ -148,8 +148,8 @@ def _ptr(a):
 class Context:
     """One libpncg context (a device, a precision, a mesh)."""
 
-    def __init__(self, device=0, precision=FP64, stream=None, chunk=0, scatter=SCATTER_AUTO):
-        opts = pncg_opts(device, precision, stream, scatter, chunk)
+    def __init__(self, device=0, precision=FP64, stream=None, chunk=0, scatter=SCATTER_AUTO, graphs=True):
+        opts = pncg_opts(device, precision, stream, scatter, chunk, 0 if graphs else 1)
         self._stream = int(stream or 0)
         h = C.c_void_p()
         rc = _L.pncg_create(C.byref(h), C.byref(opts))
@@ -428,7 +428,7 @@ class Batch:
         if E.shape != (nT,) or nu.shape != (nT,) or rho.shape != (nT,):
             raise ValueError("E, nu, rho need one value per tet")
         pl = None if planes is None else _f64(planes).reshape(S, 4)
-        opts = pncg_opts(device, precision, stream, 0, 0)
+        opts = pncg_opts(device, precision, stream, 0, 0, 0)
         self._stream = int(stream or 0)
         h = C.c_void_p()
         rc = _L.pncg_batch_create(C.byref(h), C.byref(opts), S, _ptr(vert_off), _ptr(X), _ptr(tet_off), _ptr(tets),

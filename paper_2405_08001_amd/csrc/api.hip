@@ -82,6 +82,12 @@ struct pncg_ctx {
   void* d_static = nullptr;    // this device's `scratch` (pncg_step_dev_noalloc)
   bool noalloc = false;        // inside pncg_step_dev_noalloc: no device allocation allowed
   int chunk = 16;
+  bool graphs = true;                      // rebuilds replayed from captured graphs
+  long long last_ncand = 0;                // size of the last solver list the host has read
+  struct RebuildGraph {
+    hipGraphExec_t exec = nullptr;
+    unsigned char key[sizeof(Broad) + sizeof(PairIndex) + 8 * sizeof(void*) + 4 * sizeof(double)] = {};
+  } rgraph[2];                             // by the buffer the list is built from (x0, x1)
   std::string err;
   int state = 0;  // 0 created, 1 mesh, 2 material
 
@@ -232,7 +238,15 @@ void dfree(pncg_ctx* c, void* p) {
   (void)hipFree(p);
 }
 
+void drop_graphs(pncg_ctx* c) {
+  for (auto& g : c->rgraph) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+}
+
 void free_all(pncg_ctx* c) {
+  drop_graphs(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->h_status) (void)hipHostFree(c->h_status);
@@ -414,6 +428,7 @@ int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (cap <= c->cand_cap) return PNCG_OK;
   if (c->noalloc)
     return fail(c, PNCG_E_CAPACITY, "the candidate list needs larger buffers (a pncg_step_dev call grows them)");
+  drop_graphs(c);
   for (void* p : {(void*)c->d_cand, (void*)c->d_cent, (void*)c->d_cent_tmp, (void*)c->d_ckey_tmp, (void*)c->d_rp,
                   (void*)c->d_pv})
     dfree(c, p);
@@ -473,6 +488,7 @@ int install_override(pncg_ctx* c) {
 // work arrays that depend on it.
 int alloc_grid(pncg_ctx* c, long long ent) {
   int rc;
+  drop_graphs(c);
   for (void* p : {(void*)c->d_ent_key, (void*)c->d_ent_item, (void*)c->d_ent_rank, (void*)c->d_bkt_key,
                   (void*)c->d_bkt_item,
                   (void*)c->d_bkt_lo, (void*)c->d_bkt_hi, (void*)c->d_bkt_ids, (void*)c->d_count,
@@ -542,13 +558,49 @@ int build_solver_list(pncg_ctx* c, const double4* x) {
   int rc;
   if (c->ovr_set[0] || c->ovr_set[1]) {
     if ((rc = install_override(c))) return rc;
-  } else {
-    if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;
-    broad_solver_list(make_broad(c), x, c->cell, c->dhat + c->skin, c->d_cand, c->cand_cap,
-                      c->d_ncand, &c->d_status->err, &c->d_status->n_cand, c->stream);
-    finish_list(c);
+    copy_positions(c->d_xbuild, x, c->nV, c->stream);
+    return PNCG_OK;
   }
-  HIPCHK(c, hipMemcpyAsync(c->d_xbuild, x, sizeof(double4) * c->nV, hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;
+  const Broad B = make_broad(c);
+  const PairIndex P = make_pairindex(c);
+  const double r = c->dhat + c->skin;
+  auto enqueue = [&]() {
+    broad_solver_list(B, x, c->cell, r, c->d_cand, c->cand_cap, c->d_ncand, &c->d_status->err,
+                      &c->d_status->n_cand, c->stream);
+    if (c->scatter == PNCG_SCATTER_SEGMENTED) pairs_index(P, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
+    copy_positions(c->d_xbuild, x, c->nV, c->stream);
+  };
+  if (!c->graphs || c->noalloc) {
+    enqueue();
+    return PNCG_OK;
+  }
+  // Everything the launches take by value or by address, as one byte image:
+  // a graph is replayed only while all of it is unchanged.
+  auto& g = c->rgraph[x == c->d_x1 ? 1 : 0];
+  unsigned char key[sizeof g.key] = {};
+  const void* ptrs[8] = {x, c->d_cand, c->d_ncand, c->d_status, c->d_xbuild, c->stream, nullptr, nullptr};
+  const double vals[4] = {c->cell, r, (double)c->cand_cap, (double)c->scatter};
+  std::memcpy(key, &B, sizeof B);
+  std::memcpy(key + sizeof B, &P, sizeof P);
+  std::memcpy(key + sizeof B + sizeof P, ptrs, sizeof ptrs);
+  std::memcpy(key + sizeof B + sizeof P + sizeof ptrs, vals, sizeof vals);
+  if (!g.exec || std::memcmp(key, g.key, sizeof key) != 0) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    enqueue();
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      return fail(c, PNCG_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    std::memcpy(g.key, key, sizeof key);
+  }
+  HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
   return PNCG_OK;
 }
 
@@ -672,8 +724,6 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   };
   // Enqueue iterations [k0, k0 + m) (the last launch of the cap finishes the
   // step); returns the end of the chunk.
-  const bool fused = fused_pairs(A);
-  const int kind_first = (A.self && !fused) ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
   // A chunk that reaches the cap ends the step whatever happens before it
   // (unless a pause comes first), so the output kernel goes right behind it;
   // it reads the final iteration from the device status, and a later one
@@ -689,6 +739,11 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
                            !overlap(v_out, v_dev);
   bool last_is_final = false;
   auto launch_chunk = [&](int k0, int m, int mode0) {
+    // fold the pair pass into the sweep while the last list had at most one
+    // corner entry per vertex on average (sparse contact)
+    A.fuse = 4 * c->last_ncand <= (long long)c->nV ? 1 : 0;
+    const bool fused = fused_pairs(A);
+    const int kind_first = (A.self && !fused) ? PNCG_PROF_NARROW : PNCG_PROF_GRAD;
     const int kend = std::min(k0 + m, c->iter_max + 1);
     last_is_final = false;
     for (int j = k0; j < kend; ++j) {
@@ -740,6 +795,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     }
     if ((rc = wait_status(c, cur))) return bail(rc);
     const StepStatus s = c->h_status[cur];
+    if (A.self) c->last_ncand = s.n_cand;
     if (s.err & kErrCapacity) return bail(kRestart);
     if ((rc = check_status_err(c, s))) return bail(rc);
     if (s.stopped) break;
@@ -1074,6 +1130,12 @@ int pncg_create(pncg_ctx** out, const pncg_opts* o) {
       g_create_error = "scatter must be PNCG_SCATTER_AUTO, _ATOMIC or _SEGMENTED";
       return PNCG_E_INVAL;
     }
+    if (o->graphs != 0 && o->graphs != 1) {
+      delete c;
+      g_create_error = "graphs must be 0 or 1";
+      return PNCG_E_INVAL;
+    }
+    c->graphs = o->graphs == 0;
     c->scatter = o->scatter == PNCG_SCATTER_ATOMIC ? PNCG_SCATTER_ATOMIC : PNCG_SCATTER_SEGMENTED;
     c->device = o->device;
     c->precision = o->precision;
@@ -1157,6 +1219,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   HIPCHK(c, hipSetDevice(c->device));
   // (re)allocate device state
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;

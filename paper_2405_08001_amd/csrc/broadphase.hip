@@ -821,6 +821,15 @@ void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, l
   hipLaunchKernelGGL(k_rank_big, dim3(P.grid), dim3(kBlock), 0, s, P);
 }
 
+__global__ void __launch_bounds__(kBlock) k_copy_positions(double4* dst, const double4* src, int n) {
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) dst[v] = src[v];
+}
+
+void copy_positions(double4* dst, const double4* src, int n, hipStream_t s) {
+  const int g = std::min((n + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_copy_positions, dim3(std::max(g, 1)), dim3(kBlock), 0, s, dst, src, n);
+}
+
 void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s) {
   const int g = (int)std::min<long long>(std::max<long long>((n + kBlock - 1) / kBlock, 1), 1024);
   hipLaunchKernelGGL(k_pl_install, dim3(g), dim3(kBlock), 0, s, src, n, out, ncand, n_out);

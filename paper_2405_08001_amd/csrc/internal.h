@@ -129,6 +129,7 @@ struct Args {
   // segmented scatter: the (pair, corner) entries grouped by vertex are
   // evaluated 64 to a wave and summed per vertex run into run partials
   int seg;                 // 1: segmented, 0: atomic
+  int fuse;                // 1: the pair pass runs inside the first sweep launch (see fused_pairs)
   const int* coff;         // [nV + 1] corner entries of each vertex
   const int* cent;         // [4 cap] slot id 4 q + corner of each entry (per vertex in pair-key order)
   const int2* wrange;      // [nWaves] corner-entry range of each incidence wave's vertices
@@ -186,11 +187,15 @@ struct Args {
 // Runs CALL with the constexpr S_ set to whether the pair terms use the
 // segmented slots.
 // With the segmented scatter and one step size for the whole scene, the
-// pair pass runs inside the first launch of the gradient sweep (two launches
-// per iteration); otherwise it is a launch of its own.
+// pair pass can run inside the first launch of the gradient sweep (two
+// launches per iteration): each block evaluates the entries of its own
+// vertices.  That pays while contact is sparse; where entries crowd onto a
+// few blocks' vertices the separate, evenly split pass is faster, so the
+// host sets A.fuse per chunk from the size of the last list.  Both forms
+// give the same bits.
 template <typename R>
 inline bool fused_pairs(const Args<R>& A) {
-  return A.self && A.seg && !A.split;
+  return A.self && A.seg && !A.split && A.fuse;
 }
 
 #define PNCG_BY_SCATTER(seg, CALL) \

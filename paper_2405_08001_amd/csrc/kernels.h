@@ -109,6 +109,8 @@ struct PairIndex {
 // order in the list.  No host synchronisation; deterministic.
 void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s);
 // Copy n pairs (kind in the pair) into out, set ncand = {n, -1} and *n_out = n.
+// dst[v] = src[v] for v < n (the list's build positions).
+void copy_positions(double4* dst, const double4* src, int n, hipStream_t s);
 void pairs_install(const int2* src, long long n, int2* out, long long* ncand, long long* n_out, hipStream_t s);
 
 // Plane candidates ((n0 x0 + n1 x1) + n2 x2) - o <= r for surface vertices.

@@ -4,9 +4,10 @@ import numpy as np
 
 
 def make_ctx(sc, precision=0, barrier_full=False, alpha_component=False, iter_max=None, eps=None, term=None,
-             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False, model="nh", scatter=0):
+             rest_exclude=True, chunk=0, cell=None, beta="dk", split=False, model="nh", scatter=0,
+             graphs=True):
     import paper_2405_08001_amd as P
-    ctx = P.Context(0, precision, chunk=chunk, scatter=scatter)
+    ctx = P.Context(0, precision, chunk=chunk, scatter=scatter, graphs=graphs)
     if model != "nh":
         ctx.pncg_set_model(model)
     ctx.pncg_set_mesh(sc.X, sc.tets, sc.tris, sc.edges, sc.object_id)

@@ -66,6 +66,18 @@ def test_create_rejects_bad_scatter_mode():
         P.Context(0, P.MIXED, scatter=ok).close()
 
 
+def test_create_rejects_bad_graphs_flag():
+    import ctypes as C
+    import paper_2405_08001_amd as P
+    from paper_2405_08001_amd import _lib
+    h = C.c_void_p()
+    for bad in (-1, 2):
+        opts = _lib.pncg_opts(0, P.FP64, None, 0, 0, bad)
+        assert _lib._L.pncg_create(C.byref(h), C.byref(opts)) == P.E_INVAL
+    for graphs in (True, False):
+        P.Context(0, P.MIXED, graphs=graphs).close()
+
+
 def test_candidates_override_needs_a_mesh():
     import paper_2405_08001_amd as P
     c = _ctx()

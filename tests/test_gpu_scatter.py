@@ -73,6 +73,36 @@ def test_segmented_steps_are_bit_reproducible(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_graph_rebuilds_equal_eager_rebuilds(precision):
+    """The candidate-list rebuild replayed from a captured HIP graph against
+    the same kernels launched one by one: the falling stack for four steps
+    of 12 iterations (several rebuilds per step, from both position
+    buffers, with the step's own eager launches, host status reads and
+    synchronisations between the replays), then four more steps through
+    pncg_run_dev on the same contexts: identical bits and statistics after
+    every step."""
+    _say(f"graph vs eager rebuilds precision={precision}")
+    import torch
+    sc, x0, v0 = _stack_drop()
+    cg = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG, graphs=True)
+    ce = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG, graphs=False)
+    xg, vg, xe, ve = x0, v0, x0, v0
+    for i in range(4):
+        xg, vg, sg = cg.pncg_step(xg, vg, sc.h)
+        xe, ve, se = ce.pncg_step(xe, ve, sc.h)
+        _say(f"  step {i}: rebuilds {sg['rebuilds']} active {sg['n_active']}")
+        assert np.array_equal(xg, xe) and np.array_equal(vg, ve) and sg == se
+    dev = torch.device("cuda:0")
+    tg = [torch.tensor(a, device=dev) for a in (xg, vg)]
+    te = [torch.tensor(a, device=dev) for a in (xe, ve)]
+    sg, _ = cg.pncg_run_dev(tg[0], tg[1], sc.h, 4)
+    se, _ = ce.pncg_run_dev(te[0], te[1], sc.h, 4)
+    assert sum(s["rebuilds"] for s in sg) >= 4
+    assert sg == se
+    assert torch.equal(tg[0], te[0]) and torch.equal(tg[1], te[1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_atomic_and_segmented_scatter_agree(precision):
     """Queries at a pressed stack and 12 fixed iterations of a step: both
     scatter modes against the oracle at the parity bars, and against each
