@@ -283,21 +283,22 @@ def _solve_once(sc, prec, x0, v0, iters, eps, term, flags=0, dhat=None):
     return xo.cpu().numpy(), vo.cpu().numpy(), st, dt
 
 
-REF_TOL = 1e-7       # a study's reference minimiser: ||g|| <= REF_TOL ||g_0||
+REF_TOL = 1e-11      # a study's reference minimiser: ||g|| <= REF_TOL ||g_0|| ...
+REF_OK = 1e-9        # ... or, where rounding stops it short, at least this
 
 
-def _reference(sc, x0, v0, dhat=None, tol=REF_TOL, cap=20000, flags=None):
+def _reference(sc, x0, v0, dhat=None, tol=REF_TOL, cap=60000, flags=0):
     """x* of the step from (x0, v0): float64 Dai-Kou to ||g|| <= tol ||g_0||
-    (at most cap iterations) and how far it got.  Scenes of several objects
-    are solved split by object (Sec. 5.2), which reaches the minimiser where
-    the unsplit iteration stalls; the minimiser is the same."""
+    (at most cap iterations) and how far it got.  A looser gradient rule is
+    not enough on contact steps: at 1e-7 the unsplit and the split solves of
+    the stacked cubes stop 24 % (relative to |x* - x^t|) apart, at 1e-11
+    2e-4 apart, so the studies use 1e-11 (the unsplit iteration gets there
+    in far fewer iterations than the split one)."""
     import paper_2405_08001_amd as P
-    if flags is None:
-        flags = P.SPLIT_OBJECTS if len(np.unique(sc.object_id)) > 1 else 0
     xs, _, sref, _ = _solve_once(sc, "fp64", x0, v0, cap, tol, P.TERM_GRAD_REL, flags, dhat)
     ratio = sref["g_norm"] / sref["g0_norm"]
     return xs, {"reference_iters": int(sref["iters"]), "reference_grad_ratio": float(f"{ratio:.3e}"),
-                "reference_converged": bool(ratio <= tol)}
+                "reference_converged": bool(ratio <= REF_OK)}
 
 
 def _convergence(sc, prec, x0, v0, budgets, flags, dhat, xs):
@@ -316,8 +317,8 @@ def _convergence(sc, prec, x0, v0, budgets, flags, dhat, xs):
 
 def _study_cases():
     """Contact states for the convergence studies whose step minimiser the
-    float64 reference reaches (||g|| <= 1e-7 ||g_0||; a case whose reference
-    falls short reports no errors): the cube resting on its floor after 12
+    float64 reference reaches (||g|| <= 1e-11 ||g_0||, or 1e-9 where rounding
+    stops it; a case whose reference falls short reports no errors): the cube resting on its floor after 12
     steps (plane barriers), the stacked cubes with the top one moving down
     into its sub-dhat gap (point-triangle, edge-edge and plane barriers), and
     the stacked bars (30,720 tets, about 5,400 pairs active at the start)."""
@@ -339,7 +340,7 @@ def _study(sc, prec, x0, v0, budgets, runs, dhat=None):
     """The reference of one case, then the error curve of each named run
     (flags) if the reference converged."""
     xs, ref = _reference(sc, x0, v0, dhat)
-    res = {"precision": prec, "budgets": list(budgets), "reference_tol": REF_TOL}
+    res = {"precision": prec, "budgets": list(budgets), "reference_tol": REF_TOL, "reference_ok": REF_OK}
     res.update(ref)
     if not ref["reference_converged"]:
         res["note"] = "reference not converged: no errors reported"
