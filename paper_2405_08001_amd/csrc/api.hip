@@ -84,6 +84,8 @@ struct pncg_ctx {
   int chunk = 16;
   bool graphs = true;                      // rebuilds replayed from captured graphs
   long long last_ncand = 0;                // size of the last solver list the host has read
+  bool list_valid = false;                 // d_cand / xbuild hold the solver list of the last step
+  double last_D_end = 0.0;                 // its displacement bound from the build at that step's end
   struct RebuildGraph {
     hipGraphExec_t exec = nullptr;
     unsigned char key[sizeof(Broad) + sizeof(PairIndex) + 8 * sizeof(void*) + 4 * sizeof(double)] = {};
@@ -429,6 +431,7 @@ int ensure_cand_cap(pncg_ctx* c, long long cap) {
   if (c->noalloc)
     return fail(c, PNCG_E_CAPACITY, "the candidate list needs larger buffers (a pncg_step_dev call grows them)");
   drop_graphs(c);
+  c->list_valid = false;
   for (void* p : {(void*)c->d_cand, (void*)c->d_cent, (void*)c->d_cent_tmp, (void*)c->d_ckey_tmp, (void*)c->d_rp,
                   (void*)c->d_pv})
     dfree(c, p);
@@ -477,6 +480,7 @@ void finish_list(pncg_ctx* c) {
 // The override as the current candidate list (kind in the pair).
 int install_override(pncg_ctx* c) {
   int rc;
+  c->list_valid = false;
   if ((rc = upload_override(c))) return rc;
   if ((rc = ensure_cand_cap(c, std::max<long long>(c->n_ovr, 1024)))) return rc;
   pairs_install(c->d_ovr, c->n_ovr, c->d_cand, c->d_ncand, &c->d_status->n_cand, c->stream);
@@ -525,6 +529,7 @@ __global__ void k_copy_counts(const long long* totals, long long* ncand) {
 int build_candidates(pncg_ctx* c, const double4* x, double r, double filter_d, int filter_obj, long long* n_total,
                      long long* n_pt, bool indexed = false) {
   int rc;
+  c->list_valid = false;   // the candidate buffer no longer holds the solver's list
   long long n = 0;
   for (int attempt = 0; attempt < 3; ++attempt) {
     Broad B = make_broad(c);
@@ -693,26 +698,36 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
               pncg_stats* st) {
   Args<R> A = make_args<R>(c, h);
   const double3 grav = make_double3(c->grav[0], c->grav[1], c->grav[2]);
+  // The solver's list: pairs within dhat + skin at the build positions (a
+  // pair's distance changes by at most twice the per-vertex displacement,
+  // which stays below skin / 2 until the next build).  A step may start on
+  // the list the previous step of this context left, if that step ended
+  // with at most a quarter of the skin used: the predictor then measures x_0
+  // against the list's build positions and iteration 0 pauses for a rebuild
+  // if the list no longer covers x_0 (the caller may pass any state).
+  const bool carry = A.self && c->list_valid && !(c->ovr_set[0] || c->ovr_set[1]) &&
+                     c->last_D_end <= 0.25 * c->skin;
+  c->list_valid = false;
+  A.carry = carry ? 1 : 0;
   int ev = prof_begin(c, PNCG_PROF_PREDICT);
   launch_predict<R>(A, x_dev, v_dev, grav, c->stream);
   prof_end(c, ev);
   int rebuilds = 0;
-  // the solver's list: pairs within dhat + skin at the build positions (a
-  // pair's distance changes by at most twice the per-vertex displacement,
-  // which stays below skin / 2 until the next build)
   int rc;
   if (A.self) {
-    ev = prof_begin(c, PNCG_PROF_REBUILD);
-    if ((rc = build_solver_list(c, c->d_x0))) return rc;
-    prof_end(c, ev);
-    ++rebuilds;
+    if (!carry) {
+      ev = prof_begin(c, PNCG_PROF_REBUILD);
+      if ((rc = build_solver_list(c, c->d_x0))) return rc;
+      prof_end(c, ev);
+      ++rebuilds;
+    }
     if ((rc = list_args(c, A))) return rc;
   }
   // With self contact the chunk length is chosen so that the displacement
   // bound is expected to stay inside half the skin (observed growth per
   // iteration, starting from the worst case dhat / 2); the device pauses the
   // chunk if the prediction fails.
-  double D = 0.0, rate = 0.5 * c->dhat;
+  double D = carry ? c->last_D_end : 0.0, rate = 0.5 * c->dhat;
   auto chunk_len = [&](double Dpred) {
     int m = c->chunk;
     if (A.self) {
@@ -833,6 +848,11 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   if ((rc = read_status(c))) return rc;
   const StepStatus s = *c->h_status;
   if ((rc = check_status_err(c, s))) return rc;
+  if (A.self) {
+    // the list and its build positions stay for the next step
+    c->list_valid = true;
+    c->last_D_end = s.D;
+  }
   if (st) {
     st->iters = s.iters;
     st->reason = s.reason;
@@ -1220,6 +1240,7 @@ int pncg_set_mesh(pncg_ctx* c, int32_t nV, const double* X, int32_t nT, const in
   // (re)allocate device state
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   drop_graphs(c);
+  c->list_valid = false;
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->d_elem = nullptr; c->d_cand = nullptr; c->cand_cap = 0;
@@ -1324,6 +1345,7 @@ int pncg_set_contact(pncg_ctx* c, double dhat, double kappa, double cell, int32_
   if (!std::isfinite(dhat) || !std::isfinite(kappa) || !std::isfinite(cell) || !(dhat > 0.0) || kappa < 0.0 ||
       cell < 0.0)
     return fail(c, PNCG_E_INVAL, "need dhat > 0, kappa >= 0, cell >= 0");
+  c->list_valid = false;
   if (nP < 0 || nP > kMaxPlanes || (nP > 0 && !planes)) return fail(c, PNCG_E_INVAL, "0 <= nP <= 8 planes");
   if (flags & ~3u) return fail(c, PNCG_E_INVAL, "unknown contact flag");
   Planes P{};
@@ -1446,6 +1468,7 @@ int pncg_set_tuning(pncg_ctx* c, double skin, int32_t chunk) {
   if (c->state < 2) return fail(c, PNCG_E_STATE, "set_mesh and set_material must come first");
   if (!std::isfinite(skin) || skin < 0.0 || chunk < 0) return fail(c, PNCG_E_INVAL, "need skin >= 0, chunk >= 0");
   c->skin_user = skin;
+  c->list_valid = false;
   c->skin = skin > 0.0 ? skin : default_skin(c->dhat, c->lmean);
   if (c->cell_user <= 0.0 && c->lmean > 0.0) c->cell = std::max(1.5 * c->lmean, c->dhat + c->skin);
   else if (c->cell_user <= 0.0) c->cell = c->dhat + c->skin;
@@ -1476,6 +1499,7 @@ int pncg_set_dirichlet(pncg_ctx* c, int32_t n, const int32_t* idx, const double*
 int pncg_set_candidates_override(pncg_ctx* c, int32_t kind, int64_t n, const int32_t* pairs) {
   if (!c) return PNCG_E_INVAL;
   if (c->state < 1) return fail(c, PNCG_E_STATE, "set_mesh must come first");
+  c->list_valid = false;
   if (n < 0) {
     c->ovr_set[0] = c->ovr_set[1] = false;
     c->ovr[0].clear();
@@ -1734,6 +1758,7 @@ int pncg_solver_pairs(pncg_ctx* c, const double* x, int32_t kind, int32_t* pairs
   if (kind != PNCG_KIND_PT && kind != PNCG_KIND_EE) return fail(c, PNCG_E_INVAL, "kind must be PNCG_KIND_PT or _EE");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = stage_positions(c, x))) return rc;
+  c->list_valid = false;
   std::vector<int2> all;
   if ((c->cflags & PNCG_CONTACT_SELF) && c->nF + c->nE > 0) {
     if ((rc = ensure_cand_cap(c, std::max<long long>(4096, 2LL * c->nSV)))) return rc;

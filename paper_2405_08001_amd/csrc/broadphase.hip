@@ -183,22 +183,40 @@ __global__ void __launch_bounds__(kBlock) k_items(Broad B, const double4* x, dou
   }
 }
 
+// Entries of item i, one per cell of its culling box (z fastest, then y,
+// then x), at item_off[i] on.  The bucket counters are bumped eight cells at
+// a time, so that a thread has eight atomics in flight instead of waiting
+// for each rank before the next.
 __global__ void __launch_bounds__(kBlock) k_emit(Broad B, const double4* x, double inv, double r) {
+  constexpr int kBatch = 8;
   const int n = B.nF + B.nE;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     V3<double> cl, ch;
     cull_box(B, i, r, cl, ch);
     const int3 c0 = cell_of(cl, inv), c1 = cell_of(ch, inv);
-    long long o = B.item_off[i];
-    for (int cx = c0.x; cx <= c1.x; ++cx)
-      for (int cy = c0.y; cy <= c1.y; ++cy)
-        for (int cz = c0.z; cz <= c1.z; ++cz, ++o) {
-          if (o >= B.ent_cap) break;
+    const int nz = c1.z - c0.z + 1, nyz = (c1.y - c0.y + 1) * nz;
+    const long long ncell = (long long)(c1.x - c0.x + 1) * nyz;
+    const long long o = B.item_off[i];
+    const long long m = min(ncell, B.ent_cap - o);   // entries past the capacity are not written
+    const bool edge = i >= B.nF;
+    for (long long t0 = 0; t0 < m; t0 += kBatch) {
+      int rank[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const long long t = t0 + j;
+        if (t < m) {
+          const int cx = c0.x + (int)(t / nyz), rem = (int)(t % nyz);
+          const int cy = c0.y + rem / nz, cz = c0.z + rem % nz;
           const unsigned long long k = cell_key(cx, cy, cz);
-          B.ent_key[o] = k;
-          B.ent_item[o] = B.nSV + i;
-          B.ent_rank[o] = atomicAdd(&B.count[hash_key(k, B.tsize, i >= B.nF)], 1);
+          B.ent_key[o + t] = k;
+          B.ent_item[o + t] = B.nSV + i;
+          rank[j] = atomicAdd(&B.count[hash_key(k, B.tsize, edge)], 1);
         }
+      }
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j)
+        if (t0 + j < m) B.ent_rank[o + t0 + j] = rank[j];
+    }
   }
 }
 

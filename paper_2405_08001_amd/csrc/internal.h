@@ -130,6 +130,9 @@ struct Args {
   // evaluated 64 to a wave and summed per vertex run into run partials
   int seg;                 // 1: segmented, 0: atomic
   int fuse;                // 1: the pair pass runs inside the first sweep launch (see fused_pairs)
+  int carry;               // 1: the step starts on the list of an earlier step (k_predict measures
+                           // how far x_0 is from its build positions; iteration 0 pauses for a
+                           // rebuild if that exceeds half the skin)
   const int* coff;         // [nV + 1] corner entries of each vertex
   const int* cent;         // [4 cap] slot id 4 q + corner of each entry (per vertex in pair-key order)
   const int2* wrange;      // [nWaves] corner-entry range of each incidence wave's vertices

@@ -56,9 +56,13 @@ __device__ __forceinline__ R4<R>* pbuf(const Args<R>& A, int k) { return (k & 1)
 
 // --------------------------------------------------------------- predict
 // xt = x^t + h v^t + h^2 g (Sec. 3); x_0 = x^t with prescribed vertices at
-// their targets (Algorithm 1, first line).
+// their targets (Algorithm 1, first line).  With A.carry, each block also
+// leaves in part_dir[4 b + 3] the largest distance of its surface vertices
+// from the positions the current candidate list was built at.
 template <typename R>
 __global__ void __launch_bounds__(kSBlock) k_predict(Args<R> A, const double* x_in, const double* v_in, double3 grav) {
+  __shared__ double sh[kSWaves];
+  double dmax = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     StepStatus* s = A.status;
     s->stopped = 0; s->final_k = 0; s->iters = 0; s->reason = 2; s->paused_at = -1; s->err = 0;
@@ -82,6 +86,21 @@ __global__ void __launch_bounds__(kSBlock) k_predict(Args<R> A, const double* x_
     if (A.self) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) A.acc[8 * v + j] = 0.0;
+      if (A.carry && (A.vflag[v] & kSurface)) {
+        const V3<double> xb = ld3(A.xbuild, v);
+        const double ex = x.x - xb.x, ey = x.y - xb.y, ez = x.z - xb.z;
+        dmax = fmax(dmax, sqrt(ex * ex + ey * ey + ez * ez));
+      }
+    }
+  }
+  if (A.self && A.carry) {
+    dmax = wave_max(dmax);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = sh[0];
+      for (int w = 1; w < kSWaves; ++w) m = fmax(m, sh[w]);
+      A.part_dir[4 * blockIdx.x + 3] = m;
     }
   }
 }
@@ -131,15 +150,28 @@ __device__ FirstPro first_prologue(const Args<R>& A, int k, int mode, double* sh
   FirstPro fp{0.0, 0, 1};
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   if (k == 0 || mode == kModeResume) {
+    // a step that starts on an earlier step's list first checks that x_0 is
+    // within half the skin of the list's build positions, else it pauses
+    // here for a rebuild at x_0 (and resumes at iteration 0)
+    double D0 = 0.0;
+    int pause = 0;
+    if (k == 0 && mode == kModeNormal && A.self && A.carry) {
+      const int kind[1] = {1};
+      double r[1];
+      reduce_partials<1, BS>(A.part_dir + 3, 4, A.grid, kind, r, sh);
+      D0 = r[0];
+      pause = D0 > 0.5 * A.skin ? 1 : 0;
+    }
     if (leader) {
       IterScal& s = A.scal[k];
       if (k == 0) {
         s.alpha = 0; s.dE = 0; s.dE0 = 0; s.a_up = 0;
       }
-      s.D = 0; s.stop = 0; s.pause = 0;
-      A.status->paused_at = -1;
-      A.status->D = 0.0;
+      s.D = 0; s.stop = 0; s.pause = pause;
+      A.status->paused_at = pause ? 0 : -1;
+      A.status->D = D0;
     }
+    if (pause) fp.work = 0;
     return fp;
   }
   const IterScal prev = A.scal[k - 1];
