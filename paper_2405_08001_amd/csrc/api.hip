@@ -741,17 +741,11 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
   // step); returns the end of the chunk.
   // A chunk that reaches the cap ends the step whatever happens before it
   // (unless a pause comes first), so the output kernel goes right behind it;
-  // it reads the final iteration from the device status, and a later one
-  // supersedes it if the step resumes.  Not when an output overlaps an
-  // input: a capacity rerun of the step reads the inputs again.
-  const size_t n3 = 3 * (size_t)c->nV;
-  auto overlap = [n3](const double* a, const double* b) {
-    const uintptr_t ua = reinterpret_cast<uintptr_t>(a), ub = reinterpret_cast<uintptr_t>(b);
-    const uintptr_t len = n3 * sizeof(double);
-    return ua < ub + len && ub < ua + len;
-  };
-  const bool early_final = !overlap(x_out, x_dev) && !overlap(x_out, v_dev) && !overlap(v_out, x_dev) &&
-                           !overlap(v_out, v_dev);
+  // it reads the final iteration from the device status and writes only if
+  // the step has stopped without an error (so outputs that alias the inputs,
+  // which a capacity rerun reads again, stay intact), and a later one
+  // supersedes it if the step resumes.
+  const bool early_final = true;
   bool last_is_final = false;
   auto launch_chunk = [&](int k0, int m, int mode0) {
     // fold the pair pass into the sweep while the last list had at most one

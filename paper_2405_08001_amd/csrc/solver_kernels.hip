@@ -1015,8 +1015,14 @@ __global__ void __launch_bounds__(kSBlock) k_objred_dir(Args<R> A, int k) {
 }
 
 // --------------------------------------------------------------- finalize
+// x^{t+1} and v^{t+1} (Sec. 3) from the final iteration, written only once
+// the step has stopped without an error: the host may queue this launch
+// behind the chunk that reaches the iteration cap before it knows whether
+// the step pauses first or fails, and the outputs may be the step's own
+// inputs, which a failed or paused step must leave untouched.
 template <typename R>
 __global__ void __launch_bounds__(kSBlock) k_finalize(Args<R> A, double* x_out, double* v_out) {
+  if (!A.status->stopped || A.status->err) return;
   const int fk = A.status->final_k;
   const double4* xf = xbuf(A, fk);
   const double ih = 1.0 / A.h;
