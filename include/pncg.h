@@ -329,8 +329,10 @@ int pncg_step_dev_noalloc(pncg_ctx* ctx, const double* x_dev, const double* v_de
  * PNCG_W_MAXITER if any step hit the iteration cap, else PNCG_OK.  After
  * E_PENETRATION, E_INVERTED or E_CAPACITY the state holds the last
  * completed step; after E_NONFINITE (found as the failed step writes its
- * result) it may hold that non-finite result.  E_INVAL for nsteps < 1 or a
- * NULL state. */
+ * result, or as the next step reads it: the host waits only for the end of
+ * the last step, the steps before it run back to back) it may hold that
+ * non-finite result, and the statistics of the step that produced it are
+ * reported as if it had succeeded.  E_INVAL for nsteps < 1 or a NULL state. */
 int pncg_run_dev(pncg_ctx* ctx, double* x_dev, double* v_dev, double h,
                  int32_t nsteps, pncg_stats* steps);
 

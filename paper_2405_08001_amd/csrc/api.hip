@@ -693,9 +693,14 @@ int read_status(pncg_ctx* c) {
 }
 
 // ------------------------------------------------------------------ step
+// sync_end = false (the steps of pncg_run_dev but its last): the step ends as
+// soon as a chunk's status shows the stop, with the output kernel queued and
+// no further host wait, so that the next step's launches follow at once; its
+// statistics are the stopping status.  A non-finite result, which only the
+// output kernel would flag, is then found by the next step's predictor.
 template <typename R>
 int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, double* x_out, double* v_out,
-              pncg_stats* st) {
+              pncg_stats* st, bool sync_end = true) {
   Args<R> A = make_args<R>(c, h);
   const double3 grav = make_double3(c->grav[0], c->grav[1], c->grav[2]);
   // The solver's list: pairs within dhat + skin at the build positions (a
@@ -794,7 +799,8 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     return code;
   };
   int k = 0, cur = 0;
-  int kend = launch_chunk(0, chunk_len(0.0), 0 /*kModeNormal*/);
+  StepStatus last_s{};
+  int kend = launch_chunk(0, chunk_len(D), 0 /*kModeNormal*/);
   if ((rc = enqueue_status(c, cur))) return rc;
   while (true) {
     int kn = -1;
@@ -804,6 +810,7 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     }
     if ((rc = wait_status(c, cur))) return bail(rc);
     const StepStatus s = c->h_status[cur];
+    last_s = s;
     if (A.self) c->last_ncand = s.n_cand;
     if (s.err & kErrCapacity) return bail(kRestart);
     if ((rc = check_status_err(c, s))) return bail(rc);
@@ -839,9 +846,12 @@ int step_impl(pncg_ctx* c, const double* x_dev, const double* v_dev, double h, d
     launch_finalize<R>(A, x_out, v_out, c->stream);
     prof_end(c, ev);
   }
-  if ((rc = read_status(c))) return rc;
-  const StepStatus s = *c->h_status;
-  if ((rc = check_status_err(c, s))) return rc;
+  StepStatus s = last_s;
+  if (sync_end) {
+    if ((rc = read_status(c))) return rc;
+    s = *c->h_status;
+    if ((rc = check_status_err(c, s))) return rc;
+  }
   if (A.self) {
     // the list and its build positions stay for the next step
     c->list_valid = true;
@@ -1587,8 +1597,8 @@ static int ensure_scal(pncg_ctx* c) {
   return PNCG_OK;
 }
 
-int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
-                  pncg_stats* st) {
+static int step_dev(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
+                    pncg_stats* st, bool sync_end) {
   int rc = ready(c);
   if (rc) return rc;
   if (!x || !v || !x_out || !v_out) return fail(c, PNCG_E_INVAL, "NULL state pointer");
@@ -1597,12 +1607,17 @@ int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, doubl
   if ((rc = ensure_scal(c)) || (rc = ensure_split(c))) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (st) std::memset(st, 0, sizeof(*st));
-    rc = c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st)
-                                    : step_impl<double>(c, x, v, h, x_out, v_out, st);
+    rc = c->precision == PNCG_MIXED ? step_impl<float>(c, x, v, h, x_out, v_out, st, sync_end)
+                                    : step_impl<double>(c, x, v, h, x_out, v_out, st, sync_end);
     if (rc != kRestart) return rc;
     if ((rc = grow_solver_buffers(c))) return rc;
   }
   return fail(c, PNCG_E_CAPACITY, "candidate buffers kept overflowing");
+}
+
+int pncg_step_dev(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
+                  pncg_stats* st) {
+  return step_dev(c, x, v, h, x_out, v_out, st, true);
 }
 
 int pncg_step_dev_noalloc(pncg_ctx* c, const double* x, const double* v, double h, double* x_out, double* v_out,
@@ -1653,8 +1668,9 @@ int pncg_run_dev(pncg_ctx* c, double* x, double* v, double h, int32_t nsteps, pn
   if (nsteps < 1) return fail(c, PNCG_E_INVAL, "need nsteps >= 1");
   int out = PNCG_OK;
   for (int i = 0; i < nsteps; ++i) {
-    // in place: the predictor reads (x, v) before the step writes them
-    rc = pncg_step_dev(c, x, v, h, x, v, steps ? steps + i : nullptr);
+    // in place: the predictor reads (x, v) before the step writes them; the
+    // host waits for the end of the last step only
+    rc = step_dev(c, x, v, h, x, v, steps ? steps + i : nullptr, i == nsteps - 1);
     if (rc < 0) return rc;
     out = std::max(out, rc);
   }
