@@ -570,11 +570,11 @@ int build_solver_list(pncg_ctx* c, const double4* x) {
   const Broad B = make_broad(c);
   const PairIndex P = make_pairindex(c);
   const double r = c->dhat + c->skin;
+  const bool seg = c->scatter == PNCG_SCATTER_SEGMENTED;
   auto enqueue = [&]() {
     broad_solver_list(B, x, c->cell, r, c->d_cand, c->cand_cap, c->d_ncand, &c->d_status->err,
-                      &c->d_status->n_cand, c->stream);
-    if (c->scatter == PNCG_SCATTER_SEGMENTED) pairs_index(P, c->d_cand, c->d_ncand, c->cand_cap, c->stream);
-    copy_positions(c->d_xbuild, x, c->nV, c->stream);
+                      &c->d_status->n_cand, c->stream, seg ? &P : nullptr, c->d_xbuild);
+    if (seg) pairs_index(P, c->d_cand, c->d_ncand, c->cand_cap, c->stream, true);
   };
   if (!c->graphs || c->noalloc) {
     enqueue();

@@ -143,9 +143,6 @@ void scan_exclusive(const T* in, long long n, T* out, T* total, T* scratch, hipS
 }
 
 // ------------------------------------------------------------ grid build
-__global__ void __launch_bounds__(kBlock) k_zero_int(int* a, int n) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) a[i] = 0;
-}
 
 // culling box of primitive i (0..nF-1 triangles, nF.. edges): what is
 // inserted into the grid
@@ -159,7 +156,15 @@ __device__ __forceinline__ void cull_box(const Broad& B, int i, double r, V3<dou
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_items(Broad B, const double4* x, double inv, double r) {
+// Boxes and cell counts of the items; also zeroes the bucket counters (which
+// k_emit bumps next) and, given a list counter, empties the list.
+__global__ void __launch_bounds__(kBlock) k_items(Broad B, const double4* x, double inv, double r,
+                                                  long long* ncand) {
+  for (int h = blockIdx.x * kBlock + threadIdx.x; h < B.tsize; h += gridDim.x * kBlock) B.count[h] = 0;
+  if (ncand && blockIdx.x == 0 && threadIdx.x == 0) {
+    ncand[0] = 0;
+    ncand[1] = -1;
+  }
   const int n = B.nF + B.nE;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     V3<double> lo, hi;
@@ -632,19 +637,23 @@ __global__ void __launch_bounds__(kBlock) k_pairs_emit(Broad B, PairCtx P, int2*
 }
 
 // ncand[0] = 0 (the counter), ncand[1] = -1 (the kind is in the pair)
-__global__ void k_list_reset(long long* ncand) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ncand[0] = 0;
-    ncand[1] = -1;
-  }
-}
 
-// Flags a grid or list that did not fit (the list is then incomplete).
-__global__ void k_list_check(Broad B, const long long* ncand, long long cap, int* err, long long* n_out) {
+// Flags a grid or list that did not fit (the list is then incomplete) and
+// records the list size; with a pair index (vcnt non-null) also zeroes its
+// per-vertex counters, and with xbuild copies the build positions.
+__global__ void __launch_bounds__(kBlock) k_list_check(Broad B, const long long* ncand, long long cap, int* err,
+                                                       long long* n_out, int* vcnt, int* big, int nV,
+                                                       double4* xbuild, const double4* x) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (B.totals[0] > B.ent_cap || ncand[0] > cap) atomicOr(err, kErrCapacity);
     *n_out = ncand[0];
+    if (big) big[0] = 0;
   }
+  const int stride = gridDim.x * kBlock;
+  if (vcnt)
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < 2 * nV; i += stride) vcnt[i] = 0;
+  if (xbuild)
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < nV; v += stride) xbuild[v] = x[v];
 }
 
 // totals[2] = number of point-triangle pairs = offset of the first edge-edge slot
@@ -830,8 +839,9 @@ __global__ void __launch_bounds__(kBlock) k_pl_install(const int2* src, long lon
 
 }  // namespace
 
-void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_pl_zero, dim3(P.grid), dim3(kBlock), 0, s, P);
+void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s,
+                 bool zeroed) {
+  if (!zeroed) hipLaunchKernelGGL(k_pl_zero, dim3(P.grid), dim3(kBlock), 0, s, P);
   hipLaunchKernelGGL(k_pl_count, dim3(P.grid), dim3(kBlock), 0, s, P, list, ncand, cap);
   scan_exclusive<int>(P.vcnt, P.nV, P.coff, P.coff + P.nV, P.scan_tmp, s);
   hipLaunchKernelGGL(k_pl_corners, dim3(P.grid), dim3(kBlock), 0, s, P, list, ncand, cap);
@@ -857,8 +867,7 @@ void broad_build_count(const Broad& B, const double4* x, double cell, double r, 
                        hipStream_t s) {
   const double inv = 1.0 / cell;
   const int n = B.nF + B.nE;
-  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
-  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r, (long long*)nullptr);
   scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
   hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
   scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
@@ -878,20 +887,20 @@ void broad_fill(const Broad& B, const double4* x, double cell, double r, double 
 }
 
 void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
-                       long long* ncand, int* err, long long* n_out, hipStream_t s) {
+                       long long* ncand, int* err, long long* n_out, hipStream_t s, const PairIndex* P,
+                       double4* xbuild) {
   const double inv = 1.0 / cell;
   const int n = B.nF + B.nE;
-  hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, s, ncand);
-  hipLaunchKernelGGL(k_zero_int, dim3(B.grid), dim3(kBlock), 0, s, B.count, B.tsize);
-  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
+  hipLaunchKernelGGL(k_items, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r, ncand);
   scan_exclusive<long long>(B.item_cnt, n, B.item_off, B.totals, B.part_off + B.work_cap, s);
   hipLaunchKernelGGL(k_emit, dim3(B.grid), dim3(kBlock), 0, s, B, x, inv, r);
   scan_exclusive<int>(B.count, B.tsize, B.start, B.start + B.tsize, (int*)(B.part_off + B.work_cap), s);
   hipLaunchKernelGGL(k_bucket_fill, dim3(B.grid), dim3(kBlock), 0, s, B, x);
-  PairCtx P{x, inv, r, r, 0};
+  PairCtx PC{x, inv, r, r, 0};
   const int nb = (int)std::min<long long>((B.ent_cap + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(k_pairs_emit, dim3(nb), dim3(kBlock), 0, s, B, P, out, cap, (unsigned long long*)ncand);
-  hipLaunchKernelGGL(k_list_check, dim3(1), dim3(64), 0, s, B, (const long long*)ncand, cap, err, n_out);
+  hipLaunchKernelGGL(k_pairs_emit, dim3(nb), dim3(kBlock), 0, s, B, PC, out, cap, (unsigned long long*)ncand);
+  hipLaunchKernelGGL(k_list_check, dim3((P || xbuild) ? B.grid : 1), dim3(kBlock), 0, s, B, (const long long*)ncand,
+                     cap, err, n_out, P ? P->vcnt : nullptr, P ? P->big : nullptr, B.nV, xbuild, x);
 }
 
 void plane_candidates(const Broad& B, const double4* x, const Planes& planes, double r, int2* out, long long* n,

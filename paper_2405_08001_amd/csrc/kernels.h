@@ -77,9 +77,13 @@ void broad_fill(const Broad& B, const double4* x, double cell, double r, double 
 // (v, f) point-triangle, (e1, ~e2) edge-edge; ncand[0] = pairs found,
 // ncand[1] = -1).  Sets kErrCapacity in *err if the grid entries or the
 // pairs exceeded their capacity (the list is then incomplete), and copies
-// the pair count to *n_out.
+// the pair count to *n_out.  With P its launch also zeroes the pair index's
+// counters (pairs_index is then called with zeroed = true), and with xbuild
+// it copies x there (the list's build positions).
+struct PairIndex;
 void broad_solver_list(const Broad& B, const double4* x, double cell, double r, int2* out, long long cap,
-                       long long* ncand, int* err, long long* n_out, hipStream_t s);
+                       long long* ncand, int* err, long long* n_out, hipStream_t s, const PairIndex* P = nullptr,
+                       double4* xbuild = nullptr);
 // Per-vertex index of the (pair, corner) entries of a candidate list, for the
 // segmented scatter of the pair terms.
 struct PairIndex {
@@ -107,7 +111,8 @@ struct PairIndex {
 // ncand[1] >= 0, else in the pair) and set each incidence wave's entry
 // range.  The entry order depends on the set of pairs only, not on their
 // order in the list.  No host synchronisation; deterministic.
-void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s);
+void pairs_index(const PairIndex& P, const int2* list, const long long* ncand, long long cap, hipStream_t s,
+                 bool zeroed = false);
 // Copy n pairs (kind in the pair) into out, set ncand = {n, -1} and *n_out = n.
 // dst[v] = src[v] for v < n (the list's build positions).
 void copy_positions(double4* dst, const double4* src, int n, hipStream_t s);
