@@ -383,6 +383,25 @@ def test_in_place_step_after_capacity_rerun(K):
         assert np.array_equal(xb, xa) and np.array_equal(vb, va)
 
 
+def test_failed_in_place_step_leaves_the_state():
+    """A step whose start state has vertices below the floor plane fails
+    with E_PENETRATION; the in-place state (outputs aliasing the inputs, as
+    pncg_run_dev uses) is left as it was."""
+    import torch
+    import paper_2405_08001_amd as P
+    sc, x0, v0 = _stack_drop()
+    x = x0.copy()
+    x[:, 2] -= x[:, 2].min() + 1e-3          # the lowest vertices 1 mm below the floor
+    dev = torch.device("cuda:0")
+    xt, vt = torch.tensor(x, device=dev), torch.tensor(v0, device=dev)
+    ctx = make_ctx(sc, 0, iter_max=12, eps=0.0, term="delta_e")
+    with pytest.raises(P.PncgError) as e:
+        ctx.pncg_run_dev(xt, vt, sc.h, 2)
+    _say(f"start below the floor: {e.value}")
+    assert e.value.code == P.E_PENETRATION
+    assert np.array_equal(xt.cpu().numpy(), x) and np.array_equal(vt.cpu().numpy(), v0)
+
+
 def _run_pair(sc, x0, v0, precision, n, **kw):
     """(state, stats) after n steps by pncg_run_dev (in place) and by n
     separate pncg_step_dev calls, each on a fresh context."""

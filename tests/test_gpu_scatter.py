@@ -103,6 +103,41 @@ def test_graph_rebuilds_equal_eager_rebuilds(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_carried_list_is_checked_at_the_step_start(precision):
+    """A step may start on the previous step's candidate list.  (a) After
+    steps from the falling stack, a step on the same context from a state
+    far from the list's build positions (the stack back at its start) must
+    pause at iteration 0, rebuild, and give the bits of a fresh context.
+    (b) A step that continues from where the context stopped keeps the
+    list (fewer rebuilds than the fresh context needs) and matches the
+    fresh context's step to the rounding of the pair sums' grouping."""
+    _say(f"carried list precision={precision}")
+    sc, x0, v0 = _stack_drop()
+    ctx = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    x, v = x0, v0
+    for _ in range(3):
+        x, v, _ = ctx.pncg_step(x, v, sc.h)
+    # (a) back to the start state: the carried list no longer covers x_0
+    xa, va, sa = ctx.pncg_step(x0, v0, sc.h)
+    fresh = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    xf, vf, sf = fresh.pncg_step(x0, v0, sc.h)
+    _say(f"  restart from x0: rebuilds {sa['rebuilds']}/{sf['rebuilds']}")
+    assert np.array_equal(xa, xf) and np.array_equal(va, vf) and sa == sf
+    # (b) a resting stack barely moves: the next step keeps the list
+    rest = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    xr, vr = sc.X.copy(), np.zeros_like(sc.X)
+    xr, vr, s1 = rest.pncg_step(xr, vr, sc.h)
+    x2, v2, s2 = rest.pncg_step(xr, vr, sc.h)
+    fresh2 = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    x3, v3, s3 = fresh2.pncg_step(xr, vr, sc.h)
+    _say(f"  resting stack: rebuilds carried {s2['rebuilds']} fresh {s3['rebuilds']}, "
+         f"rel_x {rel(x2, x3):.2e} rel_dx {rel(x2 - xr, x3 - xr):.2e}")
+    assert s2["rebuilds"] < s3["rebuilds"]
+    assert s2["iters"] == s3["iters"] and s2["n_active"] == s3["n_active"] > 0
+    assert rel(x2, x3) <= (1e-12 if precision == 0 else 1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_atomic_and_segmented_scatter_agree(precision):
     """Queries at a pressed stack and 12 fixed iterations of a step: both
     scatter modes against the oracle at the parity bars, and against each
