@@ -108,9 +108,10 @@ def test_carried_list_is_checked_at_the_step_start(precision):
     steps from the falling stack, a step on the same context from a state
     far from the list's build positions (the stack back at its start) must
     pause at iteration 0, rebuild, and give the bits of a fresh context.
-    (b) A step that continues from where the context stopped keeps the
-    list (fewer rebuilds than the fresh context needs) and matches the
-    fresh context's step to the rounding of the pair sums' grouping."""
+    (b) A one-iteration step that continues from where the context stopped
+    keeps the list (no rebuild, where a fresh context builds one) and
+    matches the fresh context's step to the rounding of the pair sums'
+    grouping."""
     _say(f"carried list precision={precision}")
     sc, x0, v0 = _stack_drop()
     ctx = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
@@ -123,12 +124,13 @@ def test_carried_list_is_checked_at_the_step_start(precision):
     xf, vf, sf = fresh.pncg_step(x0, v0, sc.h)
     _say(f"  restart from x0: rebuilds {sa['rebuilds']}/{sf['rebuilds']}")
     assert np.array_equal(xa, xf) and np.array_equal(va, vf) and sa == sf
-    # (b) a resting stack barely moves: the next step keeps the list
-    rest = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    # (b) one-iteration steps of the resting stack move every vertex by at
+    # most dhat / 2, under a quarter of the skin: the next step keeps the list
+    rest = make_ctx(sc, precision, iter_max=1, eps=0.0, term="delta_e", scatter=SEG)
     xr, vr = sc.X.copy(), np.zeros_like(sc.X)
     xr, vr, s1 = rest.pncg_step(xr, vr, sc.h)
     x2, v2, s2 = rest.pncg_step(xr, vr, sc.h)
-    fresh2 = make_ctx(sc, precision, iter_max=12, eps=0.0, term="delta_e", scatter=SEG)
+    fresh2 = make_ctx(sc, precision, iter_max=1, eps=0.0, term="delta_e", scatter=SEG)
     x3, v3, s3 = fresh2.pncg_step(xr, vr, sc.h)
     _say(f"  resting stack: rebuilds carried {s2['rebuilds']} fresh {s3['rebuilds']}, "
          f"rel_x {rel(x2, x3):.2e} rel_dx {rel(x2 - xr, x3 - xr):.2e}")
