@@ -10,13 +10,44 @@ namespace pncg {
 constexpr int kSWaves = kSBlock / kWave;
 
 // ------------------------------------------------------------- reductions
+// Lane moves by DPP (data-parallel primitives: the VALU reads another
+// lane's register).  CTRL: 0x111 + s - 1 shifts right by s within each row
+// of 16 lanes; 0x142 / 0x143 broadcast lane 15 / 31 into the next row(s).
+// Lanes that ROW_MASK leaves out, or whose source lies outside the row,
+// receive `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double old, double v) {
+  const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum and maximum over the 64 lanes of a full wave, in a fixed order (a
+// prefix scan within each row of 16, then the row totals carried upward);
+// every lane receives the result.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
-  return v;
+  v += dpp_move<0x111, 0xf>(0.0, v);
+  v += dpp_move<0x112, 0xf>(0.0, v);
+  v += dpp_move<0x114, 0xf>(0.0, v);
+  v += dpp_move<0x118, 0xf>(0.0, v);
+  v += dpp_move<0x142, 0xa>(0.0, v);
+  v += dpp_move<0x143, 0xc>(0.0, v);
+  return from_lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
-  return v;
+  v = fmax(v, dpp_move<0x111, 0xf>(v, v));
+  v = fmax(v, dpp_move<0x112, 0xf>(v, v));
+  v = fmax(v, dpp_move<0x114, 0xf>(v, v));
+  v = fmax(v, dpp_move<0x118, 0xf>(v, v));
+  v = fmax(v, dpp_move<0x142, 0xa>(v, v));
+  v = fmax(v, dpp_move<0x143, 0xc>(v, v));
+  return from_lane63(v);
 }
 
 // Sum (kind 0) or max (kind 1) of N per-thread values over a block of BS
@@ -51,11 +82,21 @@ __device__ __forceinline__ void reduce_partials(const double* part, int stride, 
   static_assert(BS >= kSBlock, "reduce_partials needs at least kSBlock threads");
 #pragma unroll
   for (int i = 0; i < N; ++i) out[i] = 0.0;
-  for (int j = threadIdx.x; threadIdx.x < kSBlock && j < n; j += kSBlock) {
+  // Two partials per step, both loaded before either is added, so that the
+  // usual grid (at most 2 kSBlock partials) costs one round trip; the
+  // additions keep the order j, j + kSBlock, j + 2 kSBlock, ...
+  for (int j = threadIdx.x; threadIdx.x < kSBlock && j < n; j += 2 * kSBlock) {
+    const bool two = j + kSBlock < n;
+    double a[N], b[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double v = part[j * stride + i];
-      out[i] = kind[i] ? fmax(out[i], v) : out[i] + v;
+    for (int i = 0; i < N; ++i) a[i] = part[j * stride + i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = two ? part[(j + kSBlock) * stride + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = kind[i] ? fmax(out[i], a[i]) : out[i] + a[i];
+    if (two) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) out[i] = kind[i] ? fmax(out[i], b[i]) : out[i] + b[i];
     }
   }
   block_reduce<N, BS>(out, kind, sh);
