@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kSBlock) k_adj_init(Args<double> A, AdjArgs C,
 //   alpha = r.z / p.q;  z_k = z_{k-1} - alpha w_{k-1};
 //   r_k.z_k = r.z - alpha (r.w + q.z) + alpha^2 q.w;
 //   beta = r_k.z_k / r.z;  p_k = z_k + beta p_{k-1},
-// z_k and p_k formed on the fly at every corner; each vertex's first lane
+// z_k and p_k formed on the fly at every corner; each vertex's last lane
 // applies H and stores p_k, {z_k, D q_k} and lambda_k = lambda_{k-1} + alpha
 // p_{k-1} (lambda in place: only that lane touches it), and adds the partials
 // of launch k, with r_k = diag z_k (the residual itself is not stored).
@@ -222,9 +222,7 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_fused(Args<double> A, AdjArgs C
         raise_err(A.status, kErrInverted);
       }
     }
-    seg_sum<double>(myv, s);
-    const int upv = __shfl_up(myv, 1, kWave);
-    if (myv < 0 || (lane > 0 && upv == myv)) continue;
+    if (!seg_sum(myv, s) || myv < 0) continue;
     const int v = myv;
     const V3<double> z = zget(v);
     const V3<double> pp = k > 0 ? ld3(pprev, v) : mk3(0.0, 0.0, 0.0);
@@ -340,9 +338,7 @@ __global__ void __launch_bounds__(kSBlock) k_cg_hv(Args<double> A, AdjArgs C, in
         raise_err(A.status, kErrInverted);
       }
     }
-    seg_sum<double>(myv, s);
-    const int upv = __shfl_up(myv, 1, kWave);
-    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    const bool vlane = seg_sum(myv, s) && myv >= 0;
     if (!vlane) continue;
     const int v = myv;
     double prs[3] = {0.0, 0.0, 0.0};

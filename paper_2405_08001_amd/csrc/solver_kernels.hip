@@ -413,7 +413,7 @@ __device__ __forceinline__ void pair_grad_diag_atomic(const Args<R>& A, const in
 // Segmented scatter: the corner entries (grouped by vertex) of this block's
 // 64-entry chunks, one per lane; each lane evaluates its pair at `pos` (the
 // four entries of a pair evaluate it alike) and its corner's terms, a
-// wave-segmented sum reduces each vertex run and the run's first lane
+// wave-segmented sum reduces each vertex run and the run's last lane
 // stores the run partial in A.rp.  WHAT 0: gradient and diagonal (6 values);
 // WHAT 2: H p (3 values, p in A.p0) and p^T H p counted once per pair.
 // Returns this thread's count of active pairs (WHAT 0) or its p^T H p sum
@@ -449,9 +449,8 @@ __device__ __forceinline__ double pair_entries(const Args<R>& A, const Pos& pos)
         }
       }
     }
-    seg_sum_d<N>(key, val);
-    const int up = __shfl_up(key, 1, kWave);
-    if (j < nent && (lane == 0 || up != key)) {
+    const bool last = seg_sum(key, val);
+    if (j < nent && last) {
       double* o = A.rp + 6 * (size_t)j;
 #pragma unroll
       for (int i = 0; i < N; ++i) o[i] = val[i];
@@ -526,9 +525,8 @@ __device__ __forceinline__ double block_pair_entries(const Args<R>& A, const Pos
         if (ci == 0) acc += 1.0;
       }
     }
-    seg_sum_d<6>(key, val);
-    const int up = __shfl_up(key, 1, kWave);
-    if (mine && (lane == 0 || up != key)) {
+    const bool last = seg_sum(key, val);
+    if (mine && last) {
       double* o = A.rp + 6 * (size_t)j;
 #pragma unroll
       for (int i = 0; i < 6; ++i) o[i] = val[i];
@@ -650,11 +648,9 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
 #pragma unroll
       for (int i = 0; i < 6; ++i) s[i] = R(0);
     }
-    seg_sum<R>(myv, s);
-    const int upv = __shfl_up(myv, 1, kWave);
-    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    const bool vlane = seg_sum(myv, s) && myv >= 0;
     if (!vlane) continue;
-    // this lane is the vertex's first lane
+    // this lane is the vertex's last lane
     const int v = myv;
     double prs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (SEG) {
@@ -1167,9 +1163,7 @@ __global__ void __launch_bounds__(kSBlock) k_hvp(Args<R> A, double* out_hp, doub
         raise_err(A.status, kErrInverted);
       }
     }
-    seg_sum<R>(myv, s);
-    const int upv = __shfl_up(myv, 1, kWave);
-    const bool vlane = myv >= 0 && (lane == 0 || upv != myv);
+    const bool vlane = seg_sum(myv, s) && myv >= 0;
     if (!vlane) continue;
     const int v = myv;
     double prs[3] = {0.0, 0.0, 0.0};

@@ -2,6 +2,7 @@
 // wave / block reductions, wave-segmented sums, padded-vector loads and
 // stores, the direction update, plane distances and lazy position reads.
 #pragma once
+#include <climits>
 
 #include "internal.h"
 
@@ -15,6 +16,10 @@ constexpr int kSWaves = kSBlock / kWave;
 // of 16 lanes; 0x142 / 0x143 broadcast lane 15 / 31 into the next row(s).
 // Lanes that ROW_MASK leaves out, or whose source lies outside the row,
 // receive `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_move(double old, double v) {
   const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
@@ -192,21 +197,37 @@ struct PosReader {
 };
 
 
-// Wave-segmented suffix sum: lanes of one vertex are contiguous inside a
-// wave; afterwards the vertex's first lane holds the segment total.
-template <typename R>
-__device__ __forceinline__ void seg_sum(int myv, R (&s)[6]) {
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int off = 1; off < kWave; off <<= 1) {
-    int ov = __shfl_down(myv, off, kWave);
-    R o[6];
+// One step of the segmented sum: every lane adds the value that the DPP
+// move brings from its source lane if that lane holds the same key (lanes
+// without a source get a key no lane holds).
+template <int CTRL, int ROW_MASK, typename T, int N>
+__device__ __forceinline__ void seg_step(int key, T (&s)[N]) {
+  const int ok = __builtin_amdgcn_update_dpp(INT_MIN, key, CTRL, ROW_MASK, 0xf, false);
+  T o[N];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) o[i] = __shfl_down(s[i], off, kWave);
-    if (lane + off < kWave && ov == myv) {
+  for (int i = 0; i < N; ++i) o[i] = dpp_move<CTRL, ROW_MASK>(T(0), s[i]);
+  if (ok == key) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) s[i] += o[i];
-    }
+    for (int i = 0; i < N; ++i) s[i] += o[i];
   }
+}
+// Wave-segmented sums over runs of equal `key` (each run contiguous within
+// the wave; call with the whole wave active): an inclusive scan within each
+// row of 16 lanes (shifts by 1, 2, 4, 8), then each row in turn adds the
+// last lane of the row below it where the run continues.  Afterwards the
+// last lane of every run holds the run's total, in a fixed order of
+// additions; returns true on that lane.
+template <typename T, int N>
+__device__ __forceinline__ bool seg_sum(int key, T (&s)[N]) {
+  seg_step<0x111, 0xf>(key, s);
+  seg_step<0x112, 0xf>(key, s);
+  seg_step<0x114, 0xf>(key, s);
+  seg_step<0x118, 0xf>(key, s);
+  seg_step<0x142, 0x2>(key, s);
+  seg_step<0x142, 0x4>(key, s);
+  seg_step<0x142, 0x8>(key, s);
+  const int next = __shfl_down(key, 1, kWave);
+  return (threadIdx.x & (kWave - 1)) == kWave - 1 || next != key;
 }
 
 // Entry range of incidence wave w (wave-uniform) by a scalar load, so that
@@ -222,10 +243,10 @@ __device__ __forceinline__ int2 wave_range(const int2* wrange, int w) {
 // ------------------------------------------------- segmented pair sums
 // The corner entries of the candidate pairs are grouped by vertex (each
 // vertex's entries in pair-key order) and evaluated 64 to a wave; a
-// wave-segmented sum leaves, at the first entry of every run of one vertex
+// wave-segmented sum leaves, at the last entry of every run of one vertex
 // inside a 64-entry chunk, the run's total (the run partial).  A vertex with
 // entries [c0, c1) adds the partials of the chunks it touches, in chunk
-// order: rp at max(c0, 64 k) for k = c0 / 64 ... (c1 - 1) / 64.
+// order: rp at min(c1, 64 (k + 1)) - 1 for k = c0 / 64 ... (c1 - 1) / 64.
 template <int N>
 __device__ __forceinline__ void pair_partials_sum(const int* coff, const double* rp, int v, double (&out)[N]) {
 #pragma unroll
@@ -233,26 +254,9 @@ __device__ __forceinline__ void pair_partials_sum(const int* coff, const double*
   const int c0 = coff[v], c1 = coff[v + 1];
   if (c0 >= c1) return;
   for (int k = c0 >> 6; k * kWave < c1; ++k) {
-    const double* p = rp + 6 * (size_t)max(c0, k * kWave);
+    const double* p = rp + 6 * (size_t)(min(c1, (k + 1) * kWave) - 1);
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] += p[i];
-  }
-}
-
-// Wave-segmented sum of N doubles over runs of equal `key` (runs contiguous
-// within the wave); afterwards a run's first lane holds its total.
-template <int N>
-__device__ __forceinline__ void seg_sum_d(int key, double (&s)[N]) {
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int ok = __shfl_down(key, off, kWave);
-    double o[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) o[i] = __shfl_down(s[i], off, kWave);
-    if (lane + off < kWave && ok == key) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) s[i] += o[i];
-    }
   }
 }
 
