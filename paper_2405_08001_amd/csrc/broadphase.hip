@@ -331,14 +331,19 @@ __device__ __forceinline__ bool vertex_slot_pair(const Broad& B, const PairCtx& 
   return true;
 }
 
+// Exclusive prefix sum over a full wave by DPP lane moves: an inclusive
+// scan within each row of 16 lanes (shifts by 1, 2, 4, 8), then lane 15 of
+// rows 0 and 2 added to rows 1 and 3, then lane 31 to rows 2 and 3; the
+// total is lane 63's.
 __device__ __forceinline__ int wave_excl_scan(int v, int& total) {
-  const int lane = threadIdx.x & (kWave - 1);
   int x = v;
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int u = __shfl_up(x, o, kWave);
-    if (lane >= o) x += u;
-  }
-  total = __shfl(x, kWave - 1, kWave);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+  total = __builtin_amdgcn_readlane(x, kWave - 1);
   return x - v;
 }
 

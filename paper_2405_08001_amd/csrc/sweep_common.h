@@ -226,8 +226,9 @@ __device__ __forceinline__ bool seg_sum(int key, T (&s)[N]) {
   seg_step<0x142, 0x2>(key, s);
   seg_step<0x142, 0x4>(key, s);
   seg_step<0x142, 0x8>(key, s);
-  const int next = __shfl_down(key, 1, kWave);
-  return (threadIdx.x & (kWave - 1)) == kWave - 1 || next != key;
+  // the next lane's key (wave_shl:1); lane 63 has none
+  const int next = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x130, 0xf, 0xf, false);
+  return next != key;
 }
 
 // Entry range of incidence wave w (wave-uniform) by a scalar load, so that
