@@ -37,12 +37,14 @@ namespace pncg {
 // Threads per block of the vertex-centric sweep: it is latency bound and
 // gains from more resident waves per compute unit than the 256-thread blocks
 // of the other kernels give (the grid, and so the number of partials, stays
-// the same).  Measured on the 110k-tet pile: float 384 (19.1 us; 512 needs a
-// register cap that spills), double 512 with four waves per SIMD (21.8 us;
-// 384 took 32 us).  The direction kernel measured slower at 512.
+// the same).  Measured on the 110k-tet pile: float 448 (seven waves, about
+// 115 VGPRs, so two blocks hold 14 waves of a compute unit: 24.2 us against
+// 25.4 us at 384; 512 needs 131 VGPRs and drops to three waves per SIMD),
+// double 512 with four waves per SIMD (21.8 us; 384 took 32 us).  The
+// direction kernel measured slower at 512.
 template <typename R>
 struct GradBlock {
-  static constexpr int value = 384, min_waves = 1;
+  static constexpr int value = 448, min_waves = 1;
 };
 template <>
 struct GradBlock<double> {
