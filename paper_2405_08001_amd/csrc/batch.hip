@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(BS) k_batch_step(BatchArgs<R> A, const double*
             atomicOr(A.err, kErrInverted);
           }
         }
-        if (!seg_sum(myv, sv) || myv < 0) continue;
+        if (!seg_sum_shfl(myv, sv) || myv < 0) continue;
         const int v = myv;
         const V3<double> x = X(v), xt = ld3(A.xt, v);
         const double m = A.mass[v];
