@@ -734,8 +734,14 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
 // ------------------------------------------------------ direction + pHp
 // SPLIT: beta per object (from k_objred_grad), and the p^T H p terms go
 // per tet, per vertex and per object (pairs) for k_objred_dir.
-template <typename R, bool SPLIT = false, int M = kModelNH, int BS = kSBlock>
+// Threads per block of the direction kernel: the first kSBlock threads take
+// the tets while the waves beyond them take the vertices, so that the two
+// passes' memory round trips overlap instead of adding up.
+constexpr int kDirBlock = 384;
+
+template <typename R, bool SPLIT = false, int M = kModelNH, int BS = kDirBlock>
 __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
+  static_assert(BS > kSBlock, "k_dir: waves beyond the tet threads take the vertices");
   __shared__ double sh[BS / kWave * 8];
   const IterScal s = A.scal[k];
   if (s.stop || s.pause) return;
@@ -812,7 +818,8 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   // tets: element p^T H p with p recomputed at the four corners
   double el = 0.0;
   const Slice st = block_slice(A.nT);
-  for (int e = (int)st.begin + threadIdx.x; e < st.end; e += BS) {
+  const bool tet_thread = threadIdx.x < kSBlock;
+  for (int e = (int)st.begin + threadIdx.x; tet_thread && e < st.end; e += kSBlock) {
     const ElemRec<R> rec = A.elem[e];
     const R rb = beta_of(rec.v[0]);      // a tet lies in one object
     V3<R> P[4];
@@ -834,7 +841,7 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
   const Slice sv = block_slice(A.nV);
-  for (int v = (int)sv.begin + threadIdx.x; v < sv.end; v += BS) {
+  for (int v = (int)sv.begin + (int)threadIdx.x - kSBlock; !tet_thread && v < sv.end; v += BS - kSBlock) {
     V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), beta_of(v));
     str<R>(pn, v, p);
     const double px = p.x, py = p.y, pz = p.z;
@@ -1308,10 +1315,10 @@ void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
 template <typename R>
 void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, true, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, k));
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, true, M_>), dim3(A.grid), dim3(kDirBlock), 0, s, A, k));
     hipLaunchKernelGGL(k_objred_dir<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, false, M_>), dim3(A.grid), dim3(kSBlock), 0, s, A, k));
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, false, M_>), dim3(A.grid), dim3(kDirBlock), 0, s, A, k));
   }
 }
 template <typename R>
