@@ -265,7 +265,8 @@ int pncg_set_candidates_override(pncg_ctx* ctx, int32_t kind, int64_t n, const i
  * the library (cell = 0), it becomes max(1.5 x mean surface edge, dhat + skin).
  * chunk > 0: iterations launched between reads of the device status (0
  * keeps the current value; default 16).  Call after pncg_set_contact, which
- * keeps a skin set here. */
+ * keeps a skin set here.  The call also drops a candidate list carried from
+ * an earlier step (see pncg_step), so the next step builds its own. */
 int pncg_set_tuning(pncg_ctx* ctx, double skin, int32_t chunk);
 
 /* Mean rest length of the surface edges given to pncg_set_mesh (0 if
@@ -291,7 +292,12 @@ int pncg_set_dirichlet(pncg_ctx* ctx, int32_t n, const int32_t* idx,
  * x_out, v_out [nV][3] receive x^{t+1} and v^{t+1}; st (nullable) the step
  * statistics.  Returns PNCG_W_MAXITER if the cap was hit, E_PENETRATION /
  * E_INVERTED / E_NONFINITE if the input or the result is infeasible.
- * x_out may alias x and v_out may alias v. */
+ * x_out may alias x and v_out may alias v.  With self contact a step may
+ * start on the candidate list the previous step of this context left, if
+ * that list still covers x (checked on the device; otherwise the step
+ * rebuilds it at x); the result then differs from a fresh list's only in
+ * the rounding order of the pair sums.  For bit-identical replays from a
+ * saved state, drop the list first (pncg_set_tuning). */
 int pncg_step(pncg_ctx* ctx, const double* x, const double* v, double h,
               double* x_out, double* v_out, pncg_stats* st);
 

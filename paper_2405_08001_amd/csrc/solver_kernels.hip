@@ -734,14 +734,21 @@ __global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A,
 // ------------------------------------------------------ direction + pHp
 // SPLIT: beta per object (from k_objred_grad), and the p^T H p terms go
 // per tet, per vertex and per object (pairs) for k_objred_dir.
-// Threads per block of the direction kernel: the first kSBlock threads take
-// the tets while the waves beyond them take the vertices, so that the two
-// passes' memory round trips overlap instead of adding up.
-constexpr int kDirBlock = 384;
+// Threads per block of the direction kernel.  With more than kSBlock, the
+// first kSBlock threads take the tets while the waves beyond them take the
+// vertices, so that the two passes' memory round trips overlap instead of
+// adding up (pile: 12.6 -> 12.3 us float, 14.7 -> 14.3 us float64).  The
+// float64 corotated instantiation keeps kSBlock threads doing both passes:
+// with the split it measured 17.4 against 10.9 us on the 30,000-tet bar.
+template <typename R, int M>
+struct DirBlock {
+  static constexpr int value = (sizeof(R) == sizeof(double) && M == kModelCorot) ? kSBlock : 384;
+};
 
-template <typename R, bool SPLIT = false, int M = kModelNH, int BS = kDirBlock>
+template <typename R, bool SPLIT = false, int M = kModelNH, int BS = DirBlock<R, M>::value>
 __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
-  static_assert(BS > kSBlock, "k_dir: waves beyond the tet threads take the vertices");
+  static_assert(BS >= kSBlock, "k_dir needs at least kSBlock threads");
+  constexpr bool kSplitPasses = BS > kSBlock;
   __shared__ double sh[BS / kWave * 8];
   const IterScal s = A.scal[k];
   if (s.stop || s.pause) return;
@@ -818,7 +825,7 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   // tets: element p^T H p with p recomputed at the four corners
   double el = 0.0;
   const Slice st = block_slice(A.nT);
-  const bool tet_thread = threadIdx.x < kSBlock;
+  const bool tet_thread = !kSplitPasses || threadIdx.x < kSBlock;
   for (int e = (int)st.begin + threadIdx.x; tet_thread && e < st.end; e += kSBlock) {
     const ElemRec<R> rec = A.elem[e];
     const R rb = beta_of(rec.v[0]);      // a tet lies in one object
@@ -841,7 +848,9 @@ __global__ void __launch_bounds__(BS) k_dir(Args<R> A, int k) {
   acc_pHp += A.h2 * el;
   // vertices: store p_{k+1}; inertia and plane parts of p^T H p; |p| maxima
   const Slice sv = block_slice(A.nV);
-  for (int v = (int)sv.begin + (int)threadIdx.x - kSBlock; !tet_thread && v < sv.end; v += BS - kSBlock) {
+  const bool vert_thread = !kSplitPasses || !tet_thread;
+  const int vt = kSplitPasses ? (int)threadIdx.x - kSBlock : (int)threadIdx.x;
+  for (int v = (int)sv.begin + vt; vert_thread && v < sv.end; v += kSplitPasses ? BS - kSBlock : BS) {
     V3<R> p = direction(ldr<R>(A.pg, v), ldr<R>(pk, v), beta_of(v));
     str<R>(pn, v, p);
     const double px = p.x, py = p.y, pz = p.z;
@@ -1315,10 +1324,10 @@ void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
 template <typename R>
 void launch_iteration_dir(const Args<R>& A, int k, hipStream_t s) {
   if (A.split) {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, true, M_>), dim3(A.grid), dim3(kDirBlock), 0, s, A, k));
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, true, M_>), dim3(A.grid), dim3(DirBlock<R, M_>::value), 0, s, A, k));
     hipLaunchKernelGGL(k_objred_dir<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
-    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, false, M_>), dim3(A.grid), dim3(kDirBlock), 0, s, A, k));
+    PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_dir<R, false, M_>), dim3(A.grid), dim3(DirBlock<R, M_>::value), 0, s, A, k));
   }
 }
 template <typename R>
