@@ -157,6 +157,63 @@ def calibration_copy():
     torch.cuda.synchronize()
 
 
+def _clocks():
+    """Host clocks (ns) that a profiler's timestamps may use, to mark a window."""
+    out = {"monotonic": time.monotonic_ns()}
+    for name in ("CLOCK_BOOTTIME", "CLOCK_MONOTONIC_RAW"):
+        if hasattr(time, name):
+            out[name.lower()] = time.clock_gettime_ns(getattr(time, name))
+    return out
+
+
+def trace_gaps(trace_csv, window_json, top=12):
+    """Device busy and idle time inside the timed window of a headline run,
+    from a rocprofv3 --kernel-trace CSV and the window bench.py wrote with
+    --window-out: the host clock whose window holds the most solver
+    launches is taken as the trace's time base.  Returns the span, the sum
+    of kernel durations, the idle share, idle per frame and per iteration,
+    and the largest gaps by the pair of kernels around them."""
+    import csv
+    import re
+    win = json.load(open(window_json))
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+
+    def short(n):
+        n = n.replace("void ", "").replace("(anonymous namespace)::", "")
+        i = n.find("(")
+        return re.sub(r"pncg::", "", n[:i] if i > 0 else n)
+
+    best = None
+    for clock in win["start"]:
+        t0, t1 = win["start"][clock], win["end"][clock]
+        sel = [r for r in rows if int(r["Start_Timestamp"]) >= t0 and int(r["End_Timestamp"]) <= t1]
+        n = sum(1 for r in sel if "k_grad" in r["Kernel_Name"])
+        if best is None or n > best[0]:
+            best = (n, clock, sel)
+    n_grad, clock, sel = best
+    if len(sel) < 2:
+        raise SystemExit("no kernel of the trace falls inside the window")
+    span = int(sel[-1]["End_Timestamp"]) - int(sel[0]["Start_Timestamp"])
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sel)
+    gaps = {}
+    for a, b in zip(sel, sel[1:]):
+        g = max(int(b["Start_Timestamp"]) - int(a["End_Timestamp"]), 0)
+        key = short(a["Kernel_Name"]) + " -> " + short(b["Kernel_Name"])
+        c = gaps.setdefault(key, [0, 0])
+        c[0] += 1
+        c[1] += g
+    idle = span - busy
+    top_gaps = sorted(gaps.items(), key=lambda kv: -kv[1][1])[:top]
+    return {"clock": clock, "kernels": len(sel), "grad_launches": n_grad, "frames": win["frames"],
+            "iters": win["iters"], "span_us": round(span / 1e3, 1), "busy_us": round(busy / 1e3, 1),
+            "idle_frac": round(idle / span, 4), "idle_us_per_frame": round(idle / 1e3 / win["frames"], 1),
+            "idle_us_per_iter": round(idle / 1e3 / max(win["iters"], 1), 2),
+            "us_per_iter": round(span / 1e3 / max(win["iters"], 1), 2),
+            "top_gaps": [{"between": k, "count": c, "total_us": round(t / 1e3, 1), "mean_us": round(t / 1e3 / c, 2)}
+                         for k, (c, t) in top_gaps]}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -206,17 +263,20 @@ def run(sc, precision, settle, warmup, steps, model="nh", profile=True, per_call
     # the same trajectory bit for bit
     ctx.pncg_set_tuning(0.0, 0)
     torch.cuda.synchronize()
+    clocks0 = _clocks()
     t0 = time.perf_counter()
     sts, _ = ctx.pncg_run_dev(x, v, sc.h, steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    clocks1 = _clocks()
     x_end = x.cpu().numpy().copy()
     iters = sum(st["iters"] for st in sts)
     act = sum(st["n_active"] for st in sts)
     cand = sum(st["n_candidates"] for st in sts)
     reb = sum(st["rebuilds"] for st in sts)
     out = dict(seconds=dt, iters=iters, frames=steps, mean_active=act / steps, mean_cand=cand / steps,
-               rebuilds_per_frame=reb / steps, state=state, stats=sts)
+               rebuilds_per_frame=reb / steps, state=state, stats=sts,
+               window={"start": clocks0, "end": clocks1, "frames": steps, "iters": iters})
     if per_call:
         # the same frames through one Python call per step
         x.copy_(xs)
@@ -715,6 +775,11 @@ def main():
     ap.add_argument("--kernel-times-from", nargs=2, metavar=("STATS_CSV", "COMMAND"),
                     help="no GPU run: turn a rocprofv3 --stats kernel statistics CSV into "
                          "profiles/kernel_times.json")
+    ap.add_argument("--window-out", metavar="JSON",
+                    help="write the host-clock window of the mixed pile's timed frames (for --trace-gaps-from)")
+    ap.add_argument("--trace-gaps-from", nargs=2, metavar=("TRACE_CSV", "WINDOW_JSON"),
+                    help="no GPU run: device busy and idle time inside the timed window of a rocprofv3 "
+                         "--kernel-trace CSV")
     ap.add_argument("--cpu-baselines", metavar="DIR", help=argparse.SUPPRESS)
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--batched-warmup", type=int, default=10)
@@ -725,6 +790,9 @@ def main():
         return
     if args.kernel_times_from:
         print(json.dumps(kernel_times_from(*args.kernel_times_from)))
+        return
+    if args.trace_gaps_from:
+        print(json.dumps(trace_gaps(*args.trace_gaps_from), indent=1))
         return
     if args.cpu_baselines:
         with open(os.path.join(args.cpu_baselines, "cpu.json"), "w") as fh:
@@ -756,6 +824,9 @@ def main():
         log(f"running {prec}: settle {args.settle}, warmup {args.warmup}, timed {args.steps}")
         res[prec] = run(sc, prec, args.settle, args.warmup, args.steps)
         r = res[prec]
+        if args.window_out and prec == "mixed":
+            with open(args.window_out, "w") as fh:
+                json.dump(r["window"], fh)
         log(f"  {prec}: {r['iters']} iterations in {r['seconds'] * 1e3:.1f} ms "
             f"({r['iters'] / r['seconds']:.0f} it/s), active {r['mean_active']:.1f}, dmin={r['dmin']:.3e}")
 
