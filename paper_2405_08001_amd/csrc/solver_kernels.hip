@@ -39,16 +39,16 @@ namespace pncg {
 // of the other kernels give (the grid, and so the number of partials, stays
 // the same).  Measured on the 110k-tet pile: float 448 (seven waves, about
 // 115 VGPRs, so two blocks hold 14 waves of a compute unit: 24.2 us against
-// 25.4 us at 384; 512 needs 131 VGPRs and drops to three waves per SIMD),
-// double 512 with four waves per SIMD (21.8 us; 384 took 32 us).  The
-// direction kernel measured slower at 512.
+// 25.4 us at 384; 512 needs 131 VGPRs and drops to three waves per SIMD).
+// Double 448 too (122 VGPRs, no spill; 512 with a four-wave cap spilled
+// 16 B per lane): the 30,000-tet bar's forward step 13.6 -> 13.1 ms.
 template <typename R>
 struct GradBlock {
   static constexpr int value = 448, min_waves = 1;
 };
 template <>
 struct GradBlock<double> {
-  static constexpr int value = 512, min_waves = 4;
+  static constexpr int value = 448, min_waves = 1;
 };
 
 template <typename R>
