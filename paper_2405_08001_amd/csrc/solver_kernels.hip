@@ -41,14 +41,17 @@ namespace pncg {
 // 115 VGPRs, so two blocks hold 14 waves of a compute unit: 24.2 us against
 // 25.4 us at 384; 512 needs 131 VGPRs and drops to three waves per SIMD).
 // Double 448 too (122 VGPRs, no spill; 512 with a four-wave cap spilled
-// 16 B per lane): the 30,000-tet bar's forward step 13.6 -> 13.1 ms.
-template <typename R>
+// 16 B per lane): the 30,000-tet bar's forward step 13.6 -> 13.1 ms; except
+// the corotated model (below).
+template <typename R, int M>
 struct GradBlock {
   static constexpr int value = 448, min_waves = 1;
 };
+// The float64 corotated sweep needs 134-156 VGPRs: at 448 threads one block
+// fills a compute unit; 512 threads capped at four waves per SIMD keep two.
 template <>
-struct GradBlock<double> {
-  static constexpr int value = 448, min_waves = 1;
+struct GradBlock<double, kModelCorot> {
+  static constexpr int value = 512, min_waves = 4;
 };
 
 template <typename R>
@@ -606,8 +609,8 @@ __device__ __forceinline__ void vertex_terms(const Args<R>& A, int v, V3<double>
 // scatter instead of the atomic accumulators.  With kGradFirst (self
 // contact, unsplit) the launch also computes those partials for its own
 // vertices first (block_pair_entries), so an iteration is two launches.
-template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, bool SEG = false, int BS = GradBlock<R>::value>
-__global__ void __launch_bounds__(BS, GradBlock<R>::min_waves) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
+template <typename R, int MODE, bool SPLIT = false, int M = kModelNH, bool SEG = false, int BS = GradBlock<R, M>::value>
+__global__ void __launch_bounds__(BS, (GradBlock<R, M>::min_waves)) k_grad(Args<R> A, int k, int mode, double* out_g, double* out_d) {
   constexpr int NW = BS / kWave;
   constexpr bool FUSED = MODE == kGradFirst && SEG;
   __shared__ double sh[NW * 8];
@@ -1289,7 +1292,7 @@ template <typename R>
 void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
   if (fused_pairs(A)) {
     PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, false, M_, true>), dim3(A.grid),
-                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              dim3(GradBlock<R, M_>::value), 0, s, A, k, mode, (double*)nullptr,
                                               (double*)nullptr));
   } else if (A.self) {
     if (A.split)
@@ -1298,12 +1301,12 @@ void launch_iteration_first(const Args<R>& A, int k, int mode, hipStream_t s) {
       hipLaunchKernelGGL((k_narrow<R, false>), dim3(A.grid), dim3(kSBlock), 0, s, A, k, mode);
   } else if (A.split) {
     PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, true, M_>), dim3(A.grid),
-                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              dim3(GradBlock<R, M_>::value), 0, s, A, k, mode, (double*)nullptr,
                                               (double*)nullptr));
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
     PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradFirst, false, M_>), dim3(A.grid),
-                                              dim3(GradBlock<R>::value), 0, s, A, k, mode, (double*)nullptr,
+                                              dim3(GradBlock<R, M_>::value), 0, s, A, k, mode, (double*)nullptr,
                                               (double*)nullptr));
   }
 }
@@ -1312,12 +1315,12 @@ void launch_iteration_grad(const Args<R>& A, int k, hipStream_t s) {
   const bool seg = A.self && A.seg;
   if (A.split) {
     PNCG_BY_SCATTER(seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, true, M_, S_>), dim3(A.grid),
-                                              dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
+                                              dim3(GradBlock<R, M_>::value), 0, s, A, k, 0, (double*)nullptr,
                                               (double*)nullptr)));
     hipLaunchKernelGGL(k_objred_grad<R>, dim3(A.nObj), dim3(kSBlock), 0, s, A, k);
   } else {
     PNCG_BY_SCATTER(seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradDirect, false, M_, S_>), dim3(A.grid),
-                                              dim3(GradBlock<R>::value), 0, s, A, k, 0, (double*)nullptr,
+                                              dim3(GradBlock<R, M_>::value), 0, s, A, k, 0, (double*)nullptr,
                                               (double*)nullptr)));
   }
 }
@@ -1345,7 +1348,7 @@ void launch_query_gradient(const Args<R>& A, double* g, double* d, hipStream_t s
   else if (A.self)
     hipLaunchKernelGGL((k_pairs_query<R, 0>), dim3(A.grid), dim3(kSBlock), 0, s, A, A.part_narrow);
   PNCG_BY_SCATTER(A.self && A.seg, PNCG_BY_MODEL(A.model, hipLaunchKernelGGL((k_grad<R, kGradQuery, false, M_, S_>), dim3(A.grid),
-                                            dim3(GradBlock<R>::value), 0, s, A, 0, 0, g, d)));
+                                            dim3(GradBlock<R, M_>::value), 0, s, A, 0, 0, g, d)));
 }
 template <typename R>
 void launch_query_energy(const Args<R>& A, double* out, hipStream_t s) {
